@@ -1,0 +1,211 @@
+/*
+ * iffd.h -- C ABI of the MI355X (gfx950) implementation of the Isogeometric
+ * Fast Fourier-based Diagonalization (IFFD) preconditioner of Montardini,
+ * Takacs and Tani (arXiv 2512.20269), with the matrix-free Kronecker-sum
+ * Galerkin operator, preconditioned conjugate gradients, and the classical
+ * dense Fast Diagonalization (FD) as a baseline.
+ *
+ * Problem (Sections 2 and 3 of the paper): Poisson on [0,1]^d, d in {2,3},
+ * homogeneous Dirichlet conditions on every face, tensor-product B-splines
+ * of degree p and maximal smoothness C^{p-1} on a uniform grid of n elements
+ * per direction.  Per direction the reduced spline space has dimension
+ * m = n + p - 2; a coefficient vector has N = m^d entries.
+ *
+ * Conventions that hold for every entry point
+ *   Layout     a d-dimensional coefficient tensor is stored C-contiguous with
+ *              direction 1 fastest: entry (i_1, .., i_d), 0-based, sits at
+ *              i_1 + m i_2 + m^2 i_3 (the lexicographic order of the tensor
+ *              basis, Section 2).  A batch of nrhs vectors is nrhs such
+ *              tensors back to back ([nrhs][m]^d).
+ *   Memory     pointers named d_* are device pointers (hipMalloc'd memory of
+ *              the current device, e.g. a torch CUDA tensor's data_ptr()),
+ *              h_* are host pointers.  The library never allocates device
+ *              memory: table, workspace and state sizes are queried from the
+ *              plan and the caller owns every buffer.  The plan owns only its
+ *              host-side struct and records the table pointer given to
+ *              iffd_plan_setup; the table buffer must outlive the plan's use.
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = the null
+ *              stream).  Work is enqueued asynchronously unless stated.
+ *   Errors     0 = success, > 0 = warning, < 0 = error (codes below).  All
+ *              arguments are validated before anything is launched; an error
+ *              leaves device buffers untouched.  iffd_last_error() returns a
+ *              thread-local message describing the last failure.
+ *   Threads    a plan is immutable after iffd_plan_setup and may be used from
+ *              several host threads / streams at once, each with its own
+ *              workspace or state buffer.
+ */
+#ifndef IFFD_H
+#define IFFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define IFFD_OK               0
+#define IFFD_W_NOT_CONVERGED  1   /* PCG stopped at maxit above the tolerance */
+#define IFFD_E_INVAL         -1   /* bad argument: null pointer, d, n, p, nrhs  */
+#define IFFD_E_UNSUPPORTED   -2   /* valid problem outside the built kernels   */
+#define IFFD_E_HIP           -3   /* a HIP runtime call failed                 */
+#define IFFD_E_BREAKDOWN     -4   /* PCG breakdown: p.Ap <= 0, r.z <= 0, NaN   */
+#define IFFD_E_WORKSPACE     -5   /* workspace / table / state buffer too small */
+#define IFFD_E_STATE         -6   /* plan not set up, or used with wrong method */
+
+/* ---- options ----------------------------------------------------------- */
+#define IFFD_METHOD_FFT       0   /* IFFD: sine transforms + O(p) outlier block */
+#define IFFD_METHOD_DENSE_FD  1   /* classical FD: dense m x m eigenvectors     */
+
+#define IFFD_PREC_F64         0   /* preconditioner arithmetic in FP64          */
+#define IFFD_PREC_F32         1   /* preconditioner arithmetic in FP32; inputs,
+                                     outputs and all Krylov work stay FP64      */
+
+typedef struct iffd_plan iffd_plan;
+
+typedef struct {
+  int method;       /* IFFD_METHOD_*                                           */
+  int apply_prec;   /* IFFD_PREC_*                                             */
+  int max_rhs;      /* largest batch (nrhs) the workspaces are sized for, >= 1 */
+} iffd_opts;        /* NULL opts = {IFFD_METHOD_FFT, IFFD_PREC_F32, 1}         */
+
+typedef struct {
+  int d, n, p;
+  int m;            /* n + p - 2                                               */
+  int n_reg;        /* dim of the regular subspace: n-1 (p odd), n (p even)    */
+  int n_out;        /* dim of the outlier subspace: p-1 (p odd), p-2 (p even)  */
+  int fft_len;      /* complex FFT length used per pair of lines (2n); 0 for FD*/
+  int method, apply_prec, max_rhs;
+  int64_t N;        /* m^d                                                     */
+  size_t table_bytes;      /* device buffer for iffd_plan_setup               */
+  size_t apply_ws_bytes;   /* workspace for iffd_precond_apply(nrhs=max_rhs)  */
+  size_t pcg_ws_bytes;     /* workspace for iffd_pcg_solve(nrhs=max_rhs)      */
+  size_t state_bytes_per_slot; /* device state per slot of the stepped PCG    */
+  size_t state_bytes_fixed;    /* plus this once per state buffer             */
+} iffd_plan_info;
+
+typedef struct {
+  int iterations;          /* solution updates until ||r_k|| <= rtol ||f||    */
+  int converged;           /* 1 if the tolerance was reached                  */
+  int status;              /* IFFD_OK, IFFD_W_NOT_CONVERGED or IFFD_E_BREAKDOWN */
+  double relres;           /* ||r_k||_2 / ||f||_2, recursively updated residual */
+  double relres_true;      /* ||f - A u_k||_2 / ||f||_2 recomputed at exit     */
+  double lanczos_lmin;     /* extreme eigenvalue estimates of P^{-1} A from   */
+  double lanczos_lmax;     /*   the CG-Lanczos tridiagonal matrix              */
+  double kappa_est;        /* lanczos_lmax / lanczos_lmin                      */
+} iffd_pcg_stats;
+
+/* ---- plan ---------------------------------------------------------------
+ * iffd_plan_create: host-only.  Builds the univariate spline data for
+ * S_{p,h,{0,1}} (Section 2): knots, banded K and M (Section 3), and, for
+ * IFFD, the splitting S = S^reg (+) S^out (Section 4, eq:splitting) in the
+ * special basis of Section 6 (boundary blocks V_reg,0 / V_reg,1), the
+ * outlier basis V_out (L2-orthogonal to S^reg), the normalisation
+ * Dt = diag(U^T V_reg^T M V_reg U)^{1/2} and the regular eigenvalues
+ * (eq:Lambda reg2); for DENSE_FD, the full FP64 eigendecomposition of the
+ * pencil (K, M) (eq:eigendecomposition).  Valid range: d in {2,3},
+ * 1 <= p <= 8, n > p (the paper's standing assumption), m^d*max_rhs < 2^31
+ * per pass; IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 256
+ * (IFFD_E_UNSUPPORTED otherwise).  *out receives the plan (NULL on error). */
+int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
+
+/* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan. */
+int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info);
+
+/* Uploads the plan's tables into the caller's device buffer d_tables
+ * (>= info.table_bytes bytes, 256-byte aligned), solves the small outlier
+ * pencil (V_out^T K V_out, V_out^T M V_out) (eq:eigendecomposition_out) in
+ * FP64 on the device, and synchronizes `stream` once.  Must be called before
+ * any compute entry point; may be called again with another buffer. */
+int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* stream);
+
+/* Copies host-side plan data for inspection (tests, diagnostics).  `what`:
+ *   0 lam_t  (m doubles: regular eigenvalues then outlier eigenvalues; for FD
+ *            the m eigenvalues of (K,M)), 1 Dt (n_reg doubles),
+ *   2 K band, 3 M band (m*(2p+1) doubles, row i holds columns i-p..i+p),
+ *   4 V_reg,0 ((p-1)*floor(p/2) doubles, row-major), 5 V_reg,1 (same),
+ *   6 Vt_out (n_out*m doubles: rows = Q_out-rotated outlier basis vectors,
+ *            available after iffd_plan_setup; syncs `stream`).
+ * `count` is the capacity of h_out in doubles; returns IFFD_E_WORKSPACE if
+ * too small. */
+int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream);
+
+void iffd_plan_destroy(iffd_plan* plan);
+
+/* ---- compute ------------------------------------------------------------
+ * z = P^{-1} r for nrhs right-hand sides (1 <= nrhs <= max_rhs), with
+ *   IFFD:  P^{-1} = (Qt x .. x Qt)(sum_k Lt_k)^{-1}(Qt^T x .. x Qt^T)
+ *          (eq:preconditioner), Qt = [V_reg U Dt^{-1}, V_out Q_out]
+ *          (Sections 4 and 6), applied as d forward line transforms (boundary
+ *          fold, sine transform by FFT, outlier dot products), a diagonal
+ *          scaling, and d backward line transforms;
+ *   FD:    the same with the dense eigenvectors of (K, M) (eq:exact_
+ *          diagonalization), i.e. z = Ahat^{-1} r, by MFMA mode products.
+ * d_r and d_z: [nrhs][m]^d FP64, must not overlap.  d_ws: >= apply_ws_bytes
+ * for max_rhs (scaled by nrhs/max_rhs is enough), 256-byte aligned; may be
+ * NULL when apply_ws_bytes is 0. */
+int iffd_precond_apply(const iffd_plan* plan, const double* d_r, double* d_z, int nrhs,
+                       void* d_ws, size_t ws_bytes, void* stream);
+
+/* y = Ahat x, Ahat = sum_k M x .. x K (slot k) x .. x M (eq:system_matrix and
+ * its 3-term analogue), FP64, matrix-free by sum factorization with the
+ * banded 1-D matrices.  d_x, d_y: [nrhs][m]^d FP64, must not overlap. */
+int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs,
+                     void* stream);
+
+/* Solves Ahat u = f for nrhs right-hand sides by PCG with this plan's
+ * preconditioner (Section 3), zero initial guess, stopping when
+ * ||r_k||_2 <= rtol ||f||_2 for the recursively updated residual (protocol of
+ * Section 7; the norm is the reading documented with the oracle) or after
+ * maxit iterations.  All vectors, inner products and scalars are FP64 on the
+ * device; the host polls convergence flags every `check_every` iterations
+ * (<= 0: every iteration).  h_stats: nrhs entries (may be NULL).  Returns the
+ * worst status over the batch.  d_ws >= pcg_ws_bytes (for max_rhs). */
+int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nrhs,
+                   double rtol, int maxit, int check_every, iffd_pcg_stats* h_stats,
+                   void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---- stepped PCG on resident state (continuous batching) -----------------
+ * A state buffer holds `nslots` independent PCG solves of one plan: bytes =
+ * state_bytes_fixed + nslots * state_bytes_per_slot.  Slots are independent:
+ * a slot's arithmetic does not depend on the other slots (no cross-slot
+ * reduction, fixed reduction order), so its result is the same alone or in a
+ * batch.  All calls are asynchronous on `stream`. */
+
+/* Zeroes the state (every slot free).  Must be called once per buffer. */
+int iffd_pcg_state_init(const iffd_plan* plan, void* d_state, size_t state_bytes, int nslots,
+                        void* stream);
+
+/* Starts solves in the listed slots: copies f (count vectors, [count][m]^d
+ * FP64) into the slots, sets x = 0, r = f, z = P^{-1} r, p = z, and marks them
+ * active with tolerance rtol and iteration limit maxit.  h_slots: count slot
+ * indices (host array), distinct, each < nslots. */
+int iffd_pcg_begin(const iffd_plan* plan, void* d_state, int nslots, const int* h_slots,
+                   int count, const double* d_f, double rtol, int maxit, void* stream);
+
+/* Runs k PCG iterations on every active slot of the state (inactive and
+ * free slots are skipped).  Capturable in a HIP graph. */
+int iffd_pcg_iterate(const iffd_plan* plan, void* d_state, int nslots, int k, void* stream);
+
+/* Enqueues a copy of the per-slot status into pinned or pageable host memory
+ * h_out (nslots records of 4 doubles: active, converged-or-status code,
+ * iterations, relres) and synchronizes `stream`. */
+int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double* h_out,
+                  void* stream);
+
+/* Copies the current iterate of slot `slot` into d_u ([m]^d FP64) and frees
+ * the slot.  Asynchronous. */
+int iffd_pcg_take(const iffd_plan* plan, void* d_state, int nslots, int slot, double* d_u,
+                  void* stream);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+const char* iffd_status_string(int status);
+const char* iffd_last_error(void);
+/* 1 if the HIP device visible as current is gfx950, 0 otherwise. */
+int iffd_device_ok(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFFD_H */

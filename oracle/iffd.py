@@ -36,6 +36,15 @@ Route B (the structured factorization of Sections 5 and 6)
     basis of range(V_reg)'s Euclidean complement; (L_out, Q_out) by Jacobi on
     the out pencil (eq:eigendecomposition_out).
 
+Accuracy of the two routes.  Both are FP64.  Route A diagonalizes the full
+projected pencil with Cholesky + Jacobi, whose eigenvalues carry absolute
+errors of order eps * ||L^{-1} Ktilde L^{-T}|| ~ eps * n^2; the small
+eigenvalues, which dominate P^{-1} r, therefore lose relative accuracy as n
+grows (A and B differ by ~7e-12 at n = 192).  Route B's regular eigenvalues
+are Rayleigh quotients of exactly known modes and keep full relative
+accuracy, so it is the reference for comparisons at large n; the two routes
+are checked against each other (and against brute force) at small n.
+
 Application (eq:preconditioner, eq:exact_diagonalization)
     z = (Qt x .. x Qt) (sum_k Lt_k)^{-1} (Qt^T x .. x Qt^T) r, with Qt^T
     applied first (the order the inverse requires), by explicit dense

@@ -1,0 +1,270 @@
+"""Python binding of libiffd (include/iffd.h): the IFFD preconditioner of
+Montardini, Takacs and Tani (arXiv 2512.20269) on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libiffd.so.  PyTorch supplies device memory (tensors) and streams.
+The library must have been built (``python -m paper_2512_20269_amd.build``);
+importing this package without it raises immediately.
+
+    import torch, paper_2512_20269_amd as iffd
+    plan = iffd.Plan(d=3, n=128, p=3, precision="f32")
+    z = plan.apply(r)                    # z = P^{-1} r, r: float64 [m]^d on cuda
+    y = plan.matvec(x)                   # y = Ahat x
+    u, stats = plan.solve(f, rtol=1e-8)  # PCG
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiffd.so")
+
+OK, W_NOT_CONVERGED = 0, 1
+E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
+METHOD_FFT, METHOD_DENSE_FD = 0, 1
+PREC_F64, PREC_F32 = 0, 1
+
+TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
+
+
+class IffdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"iffd error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("apply_prec", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("p", ctypes.c_int), ("m", ctypes.c_int),
+                ("n_reg", ctypes.c_int), ("n_out", ctypes.c_int), ("fft_len", ctypes.c_int),
+                ("method", ctypes.c_int), ("apply_prec", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("N", ctypes.c_int64), ("table_bytes", ctypes.c_size_t),
+                ("apply_ws_bytes", ctypes.c_size_t), ("pcg_ws_bytes", ctypes.c_size_t),
+                ("state_bytes_per_slot", ctypes.c_size_t), ("state_bytes_fixed", ctypes.c_size_t)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("status", ctypes.c_int),
+                ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("lanczos_lmin", ctypes.c_double), ("lanczos_lmax", ctypes.c_double),
+                ("kappa_est", ctypes.c_double)]
+
+
+# name -> (restype, argtypes), exactly the declarations of include/iffd.h
+_P, _I, _D, _Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "iffd_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, ctypes.POINTER(_Opts)]),
+    "iffd_plan_query": (_I, [_P, ctypes.POINTER(_Info)]),
+    "iffd_plan_setup": (_I, [_P, _P, _Z, _P]),
+    "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
+    "iffd_plan_destroy": (None, [_P]),
+    "iffd_precond_apply": (_I, [_P, _P, _P, _I, _P, _Z, _P]),
+    "iffd_kron_matvec": (_I, [_P, _P, _P, _I, _P]),
+    "iffd_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_Stats), _P, _Z, _P]),
+    "iffd_pcg_state_init": (_I, [_P, _P, _Z, _I, _P]),
+    "iffd_pcg_begin": (_I, [_P, _P, _I, ctypes.POINTER(_I), _I, _P, _D, _I, _P]),
+    "iffd_pcg_iterate": (_I, [_P, _P, _I, _I, _P]),
+    "iffd_pcg_poll": (_I, [_P, _P, _I, _P, _P]),
+    "iffd_pcg_take": (_I, [_P, _P, _I, _I, _P, _P]),
+    "iffd_status_string": (ctypes.c_char_p, [_I]),
+    "iffd_last_error": (ctypes.c_char_p, []),
+    "iffd_device_ok": (_I, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2512_20269_amd.build` (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int, what: str = "") -> int:
+    if rc < 0:
+        raise IffdError(rc, f"{what}: {lib.iffd_last_error().decode()}")
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, shape, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if tuple(t.shape[-len(shape):]) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape})")
+
+
+class Plan:
+    """One (d, n, p) problem with its device tables, workspace and PCG state.
+
+    method: "fft" (IFFD) or "dense" (classical FD); precision: "f32" or "f64"
+    for the preconditioner arithmetic (vectors and Krylov work are FP64)."""
+
+    def __init__(self, d: int, n: int, p: int, method: str = "fft", precision: str = "f32",
+                 max_rhs: int = 1, device=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda")
+        opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
+                     PREC_F32 if precision == "f32" else PREC_F64, max_rhs)
+        h = ctypes.c_void_p()
+        _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
+        self._h = h
+        info = _Info()
+        _check(lib.iffd_plan_query(h, ctypes.byref(info)), "plan_query")
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.d, self.n, self.p, self.m = d, n, p, info.m
+        self.N, self.max_rhs = info.N, max_rhs
+        self.method, self.precision = method, precision
+        self.shape = (self.m,) * d
+        with torch.cuda.device(self.device):
+            self.tables = torch.empty(info.table_bytes, dtype=torch.uint8, device=self.device)
+            assert self.tables.data_ptr() % 256 == 0
+            _check(lib.iffd_plan_setup(h, _ptr(self.tables), info.table_bytes, _stream()),
+                   "plan_setup")
+            self._ws = torch.empty(max(info.apply_ws_bytes, 256), dtype=torch.uint8,
+                                   device=self.device)
+        self._pcg_ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.iffd_plan_destroy(h)
+            self._h = None
+
+    # ---- tables ----------------------------------------------------------
+    def read_table(self, what: int) -> np.ndarray:
+        cap = 4 * self.m * (2 * self.p + 1) + 8 * self.m + 64
+        buf = np.zeros(cap)
+        _check(lib.iffd_plan_read(self._h, what, buf.ctypes.data_as(ctypes.c_void_p), cap,
+                                  _stream()), "plan_read")
+        sizes = {TABLE_LAM: self.m, TABLE_DT: self.info["n_reg"],
+                 TABLE_KBAND: self.m * (2 * self.p + 1), TABLE_MBAND: self.m * (2 * self.p + 1),
+                 TABLE_V0: (self.p - 1) * (self.p // 2), TABLE_V1: (self.p - 1) * (self.p // 2),
+                 TABLE_VT: self.info["n_out"] * self.m}
+        return buf[:sizes[what]].copy()
+
+    # ---- compute ----------------------------------------------------------
+    def _batch(self, x, name):
+        torch = _torch()
+        _need(x, self.shape, torch.float64, name)
+        nrhs = 1 if x.dim() == self.d else int(np.prod(x.shape[:-self.d]))
+        if nrhs > self.max_rhs:
+            raise ValueError(f"{name}: {nrhs} right-hand sides exceed max_rhs={self.max_rhs}")
+        return nrhs
+
+    def apply(self, r, out=None, stream=None):
+        """z = P^{-1} r (FP64 in/out, batch = leading dims)."""
+        torch = _torch()
+        nrhs = self._batch(r, "r")
+        z = out if out is not None else torch.empty_like(r)
+        _need(z, self.shape, torch.float64, "out")
+        _check(lib.iffd_precond_apply(self._h, _ptr(r), _ptr(z), nrhs, _ptr(self._ws),
+                                      self._ws.numel(), _stream(stream)), "precond_apply")
+        return z
+
+    def matvec(self, x, out=None, stream=None):
+        """y = Ahat x."""
+        torch = _torch()
+        nrhs = self._batch(x, "x")
+        y = out if out is not None else torch.empty_like(x)
+        _need(y, self.shape, torch.float64, "out")
+        _check(lib.iffd_kron_matvec(self._h, _ptr(x), _ptr(y), nrhs, _stream(stream)),
+               "kron_matvec")
+        return y
+
+    def solve(self, f, rtol: float = 1e-8, maxit: int = 500, check_every: int = 1, out=None,
+              stream=None):
+        """PCG for Ahat u = f; returns (u, [stats dict per right-hand side])."""
+        torch = _torch()
+        nrhs = self._batch(f, "f")
+        u = out if out is not None else torch.empty_like(f)
+        if self._pcg_ws is None:
+            self._pcg_ws = torch.empty(self.info["pcg_ws_bytes"], dtype=torch.uint8,
+                                       device=self.device)
+        st = (_Stats * nrhs)()
+        rc = lib.iffd_pcg_solve(self._h, _ptr(f), _ptr(u), nrhs, rtol, maxit, check_every, st,
+                                _ptr(self._pcg_ws), self._pcg_ws.numel(), _stream(stream))
+        if rc < 0 and rc != E_BREAKDOWN:
+            _check(rc, "pcg_solve")
+        stats = [{f_: getattr(s, f_) for f_, _ in _Stats._fields_} for s in st]
+        return u, stats
+
+
+class PcgState:
+    """Resident Krylov state for `nslots` solves of one plan (stepped PCG).
+
+    Slots are independent: begin() starts solves in free slots, iterate()
+    advances every active slot, poll() reports per-slot progress, take()
+    copies a solution out and frees its slot."""
+
+    def __init__(self, plan: Plan, nslots: int, stream=None):
+        torch = _torch()
+        if nslots > plan.max_rhs:
+            raise ValueError("nslots exceeds the plan's max_rhs")
+        self.plan, self.nslots = plan, nslots
+        nbytes = plan.info["state_bytes_fixed"] + nslots * plan.info["state_bytes_per_slot"]
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=plan.device)
+        _check(lib.iffd_pcg_state_init(plan._h, _ptr(self.buf), nbytes, nslots, _stream(stream)),
+               "pcg_state_init")
+
+    def begin(self, slots, f, rtol: float = 1e-8, maxit: int = 500, stream=None):
+        torch = _torch()
+        slots = list(slots)
+        _need(f, self.plan.shape, torch.float64, "f")
+        arr = (ctypes.c_int * len(slots))(*slots)
+        _check(lib.iffd_pcg_begin(self.plan._h, _ptr(self.buf), self.nslots, arr, len(slots),
+                                  _ptr(f), rtol, maxit, _stream(stream)), "pcg_begin")
+
+    def iterate(self, k: int = 1, stream=None):
+        _check(lib.iffd_pcg_iterate(self.plan._h, _ptr(self.buf), self.nslots, k,
+                                    _stream(stream)), "pcg_iterate")
+
+    def poll(self, stream=None) -> np.ndarray:
+        """(nslots, 4): active, status (-100 = free slot), iterations, relres."""
+        out = np.zeros((self.nslots, 4))
+        _check(lib.iffd_pcg_poll(self.plan._h, _ptr(self.buf), self.nslots,
+                                 out.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "pcg_poll")
+        return out
+
+    def take(self, slot: int, out=None, stream=None):
+        torch = _torch()
+        u = out if out is not None else torch.empty(self.plan.shape, dtype=torch.float64,
+                                                    device=self.plan.device)
+        _check(lib.iffd_pcg_take(self.plan._h, _ptr(self.buf), self.nslots, slot, _ptr(u),
+                                 _stream(stream)), "pcg_take")
+        return u
+
+
+def device_ok() -> bool:
+    return bool(lib.iffd_device_ok())

@@ -1,0 +1,437 @@
+// C ABI (include/iffd.h): argument validation, table upload and the host
+// side of the PCG loop.  All arithmetic on vectors runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "pcg_state.h"
+#include "plan.h"
+
+namespace iffd {
+hipError_t state_init(const Plan& P, char* st, int nslots, hipStream_t s);
+hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots, int count,
+                         const double* f, double rtol, int maxit, hipStream_t s);
+hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream_t s);
+hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u, hipStream_t s);
+hipError_t residual_norms_dev(const Plan& P, const double* f, const double* y, double* tmp,
+                              double* part, int nrhs, hipStream_t s);
+}  // namespace iffd
+
+using namespace iffd;
+
+struct iffd_plan {
+  Plan P;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return IFFD_E_HIP;
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255) == 0; }
+
+// eigenvalues of a small symmetric tridiagonal matrix (diag a, off b) by
+// cyclic Jacobi on the dense form; used for the CG-Lanczos estimate.
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lmin,
+                      double& lmax) {
+  const int k = (int)a.size();
+  std::vector<double> A((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    A[(size_t)i * k + i] = a[i];
+    if (i + 1 < k) A[(size_t)i * k + i + 1] = A[(size_t)(i + 1) * k + i] = b[i];
+  }
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    bool rot = false;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        double apq = A[(size_t)p * k + q], app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
+        if (std::fabs(apq) <= std::max(eps * std::sqrt(std::fabs(app * aqq)), 1e-300)) continue;
+        rot = true;
+        double th = (aqq - app) / (2 * apq);
+        double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int j = 0; j < k; ++j) {
+          double x = A[(size_t)p * k + j], y = A[(size_t)q * k + j];
+          A[(size_t)p * k + j] = c * x - s * y;
+          A[(size_t)q * k + j] = s * x + c * y;
+        }
+        for (int j = 0; j < k; ++j) {
+          double x = A[(size_t)j * k + p], y = A[(size_t)j * k + q];
+          A[(size_t)j * k + p] = c * x - s * y;
+          A[(size_t)j * k + q] = s * x + c * y;
+        }
+      }
+    if (!rot) break;
+  }
+  lmin = 1e300;
+  lmax = -1e300;
+  for (int i = 0; i < k; ++i) {
+    lmin = std::min(lmin, A[(size_t)i * k + i]);
+    lmax = std::max(lmax, A[(size_t)i * k + i]);
+  }
+}
+
+template <typename T>
+void put(std::vector<char>& buf, size_t off, const std::vector<double>& v) {
+  T* d = reinterpret_cast<T*>(buf.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) d[i] = (T)v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* iffd_last_error(void) { return g_err.c_str(); }
+
+const char* iffd_status_string(int s) {
+  switch (s) {
+    case IFFD_OK: return "ok";
+    case IFFD_W_NOT_CONVERGED: return "not converged";
+    case IFFD_E_INVAL: return "invalid argument";
+    case IFFD_E_UNSUPPORTED: return "unsupported";
+    case IFFD_E_HIP: return "HIP error";
+    case IFFD_E_BREAKDOWN: return "PCG breakdown";
+    case IFFD_E_WORKSPACE: return "buffer too small";
+    case IFFD_E_STATE: return "plan not ready";
+    default: return "unknown status";
+  }
+}
+
+int iffd_device_ok(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts) {
+  if (!out) return fail(IFFD_E_INVAL, "out is null");
+  *out = nullptr;
+  iffd_plan* pl = new iffd_plan();
+  std::string err;
+  int rc = build_plan(pl->P, d, n, p, opts, err);
+  if (rc != IFFD_OK) {
+    delete pl;
+    return fail(rc, err);
+  }
+  *out = pl;
+  return IFFD_OK;
+}
+
+void iffd_plan_destroy(iffd_plan* plan) { delete plan; }
+
+int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info) {
+  if (!plan || !info) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  info->d = P.d; info->n = P.n; info->p = P.p; info->m = P.m;
+  info->n_reg = P.method == IFFD_METHOD_FFT ? P.n_reg : P.m;
+  info->n_out = P.method == IFFD_METHOD_FFT ? P.n_out : 0;
+  info->fft_len = P.method == IFFD_METHOD_FFT ? P.L : 0;
+  info->method = P.method; info->apply_prec = P.prec; info->max_rhs = P.max_rhs;
+  info->N = P.N;
+  info->table_bytes = P.lay.total;
+  info->apply_ws_bytes = apply_ws_bytes(P, P.max_rhs);
+  info->pcg_ws_bytes = state_layout(P, P.max_rhs).total;
+  const StateLayout one = state_layout(P, 1);
+  info->state_bytes_per_slot = one.per_slot;
+  info->state_bytes_fixed = one.fixed;
+  return IFFD_OK;
+}
+
+int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* stream) {
+  if (!plan || !d_tables) return fail(IFFD_E_INVAL, "null argument");
+  Plan& P = plan->P;
+  if (table_bytes < P.lay.total) return fail(IFFD_E_WORKSPACE, "table buffer too small");
+  if (!aligned256(d_tables)) return fail(IFFD_E_INVAL, "table buffer must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const TableLayout& t = P.lay;
+  std::vector<char> buf(t.total, 0);
+  put<double>(buf, t.lam64, P.lam);
+  put<double>(buf, t.s64, P.s);
+  put<double>(buf, t.v0_64, P.V0);
+  put<double>(buf, t.v1_64, P.V1);
+  put<double>(buf, t.twl64, P.twl);
+  put<double>(buf, t.twp64, P.twp);
+  put<double>(buf, t.kb64, P.Kb);
+  put<double>(buf, t.mb64, P.Mb);
+  put<double>(buf, t.kc64, P.Kc);
+  put<double>(buf, t.mc64, P.Mc);
+  put<double>(buf, t.ao64, P.Ao);
+  put<double>(buf, t.bo64, P.Bo);
+  put<double>(buf, t.vout64, P.Vout);
+  put<float>(buf, t.lam32, P.lam);
+  put<float>(buf, t.s32, P.s);
+  put<float>(buf, t.v0_32, P.V0);
+  put<float>(buf, t.v1_32, P.V1);
+  put<float>(buf, t.twl32, P.twl);
+  put<float>(buf, t.twp32, P.twp);
+  if (P.method == IFFD_METHOD_DENSE_FD) {
+    const int m = P.m;
+    std::vector<double> QT((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) QT[(size_t)j * m + i] = P.Qfd[(size_t)i * m + j];
+    put<double>(buf, t.qfd64, P.Qfd);
+    put<double>(buf, t.qtfd64, QT);
+    put<double>(buf, t.lamfd64, P.lamfd);
+    put<float>(buf, t.qfd32, P.Qfd);
+    put<float>(buf, t.qtfd32, QT);
+    put<float>(buf, t.lamfd32, P.lamfd);
+  }
+  hipError_t e = hipMemcpyAsync(d_tables, buf.data(), t.total, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  P.d_tables = (char*)d_tables;
+  P.table_bytes = table_bytes;
+  if (P.method == IFFD_METHOD_FFT) {
+    e = launch_setup_outliers(P, s);
+    if (e != hipSuccess) return hip_fail(e, "outlier setup");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "setup sync");
+  if (P.method == IFFD_METHOD_FFT && P.n_out > 0) {
+    std::vector<double> lam(P.m), vt((size_t)P.n_out * P.m);
+    e = hipMemcpy(lam.data(), (char*)d_tables + t.lam64, 8 * P.m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(vt.data(), (char*)d_tables + t.vt64, 8 * vt.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "setup readback");
+    for (int k = P.n_reg; k < P.m; ++k) P.lam[k] = lam[k];
+    P.Vt = vt;
+  }
+  P.ready = true;
+  return IFFD_OK;
+}
+
+int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream) {
+  (void)stream;
+  if (!plan || !h_out) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  const std::vector<double>* v = nullptr;
+  switch (what) {
+    case 0: v = &P.lam; break;
+    case 1: v = &P.Dt; break;
+    case 2: v = &P.Kb; break;
+    case 3: v = &P.Mb; break;
+    case 4: v = &P.V0; break;
+    case 5: v = &P.V1; break;
+    case 6:
+      if (!P.ready) return fail(IFFD_E_STATE, "Vt is available after iffd_plan_setup");
+      v = &P.Vt;
+      break;
+    default: return fail(IFFD_E_INVAL, "unknown table id");
+  }
+  if (count < v->size()) return fail(IFFD_E_WORKSPACE, "output array too small");
+  std::copy(v->begin(), v->end(), h_out);
+  return IFFD_OK;
+}
+
+int iffd_precond_apply(const iffd_plan* plan, const double* d_r, double* d_z, int nrhs, void* d_ws,
+                       size_t ws_bytes, void* stream) {
+  if (!plan || !d_r || !d_z) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(IFFD_E_INVAL, "nrhs out of range");
+  if ((const void*)d_r == (const void*)d_z) return fail(IFFD_E_INVAL, "r and z must not alias");
+  const size_t need = apply_ws_bytes(P, nrhs);
+  if (need && (!d_ws || ws_bytes < need)) return fail(IFFD_E_WORKSPACE, "apply workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = (P.method == IFFD_METHOD_FFT)
+                     ? launch_iffd_apply(P, d_r, d_z, nrhs, d_ws, nullptr, 0, s)
+                     : launch_fd_apply(P, d_r, d_z, nrhs, d_ws, nullptr, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "precond_apply launch");
+  return IFFD_OK;
+}
+
+int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs, void* stream) {
+  if (!plan || !d_x || !d_y) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(IFFD_E_INVAL, "nrhs out of range");
+  if ((const void*)d_x == (const void*)d_y) return fail(IFFD_E_INVAL, "x and y must not alias");
+  hipError_t e = launch_matvec(P, d_x, d_y, nrhs, nullptr, 0, nullptr, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "kron_matvec launch");
+  return IFFD_OK;
+}
+
+// ---- stepped PCG -------------------------------------------------------------
+
+int iffd_pcg_state_init(const iffd_plan* plan, void* d_state, size_t state_bytes, int nslots,
+                        void* stream) {
+  if (!plan || !d_state) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (nslots < 1) return fail(IFFD_E_INVAL, "nslots must be >= 1");
+  if (!aligned256(d_state)) return fail(IFFD_E_INVAL, "state must be 256-byte aligned");
+  if (state_bytes < state_layout(P, nslots).total) return fail(IFFD_E_WORKSPACE, "state buffer too small");
+  hipError_t e = state_init(P, (char*)d_state, nslots, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "state init");
+  return IFFD_OK;
+}
+
+int iffd_pcg_begin(const iffd_plan* plan, void* d_state, int nslots, const int* h_slots, int count,
+                   const double* d_f, double rtol, int maxit, void* stream) {
+  if (!plan || !d_state || !h_slots || !d_f) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (count < 1 || count > nslots) return fail(IFFD_E_INVAL, "bad slot count");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(IFFD_E_INVAL, "bad rtol / maxit");
+  std::vector<char> seen(nslots, 0);
+  for (int k = 0; k < count; ++k) {
+    if (h_slots[k] < 0 || h_slots[k] >= nslots || seen[h_slots[k]])
+      return fail(IFFD_E_INVAL, "slot indices must be distinct and < nslots");
+    seen[h_slots[k]] = 1;
+  }
+  if (P.method == IFFD_METHOD_FFT || P.method == IFFD_METHOD_DENSE_FD) {
+    if (nslots > P.max_rhs) return fail(IFFD_E_INVAL, "nslots exceeds the plan's max_rhs");
+  }
+  hipError_t e = pcg_begin_dev(P, (char*)d_state, nslots, h_slots, count, d_f, rtol, maxit,
+                               (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pcg begin");
+  return IFFD_OK;
+}
+
+int iffd_pcg_iterate(const iffd_plan* plan, void* d_state, int nslots, int k, void* stream) {
+  if (!plan || !d_state) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (nslots < 1 || nslots > P.max_rhs || k < 0) return fail(IFFD_E_INVAL, "bad nslots / k");
+  hipError_t e = pcg_iterate_dev(P, (char*)d_state, nslots, k, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pcg iterate");
+  return IFFD_OK;
+}
+
+int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double* h_out,
+                  void* stream) {
+  if (!plan || !d_state || !h_out) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  const StateLayout L = state_layout(P, nslots);
+  std::vector<double> sc((size_t)nslots * kScal);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(sc.data(), (const char*)d_state + L.scal, 8 * sc.size(),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "pcg poll");
+  for (int i = 0; i < nslots; ++i) {
+    const double* r = &sc[(size_t)i * kScal];
+    h_out[4 * i + 0] = r[S_ACTIVE];
+    h_out[4 * i + 1] = r[S_USED] != 0.0 ? r[S_STATUS] : -100.0;
+    h_out[4 * i + 2] = r[S_IT];
+    h_out[4 * i + 3] = r[S_RELRES];
+  }
+  return IFFD_OK;
+}
+
+int iffd_pcg_take(const iffd_plan* plan, void* d_state, int nslots, int slot, double* d_u,
+                  void* stream) {
+  if (!plan || !d_state || !d_u) return fail(IFFD_E_INVAL, "null argument");
+  if (slot < 0 || slot >= nslots) return fail(IFFD_E_INVAL, "slot out of range");
+  hipError_t e = pcg_take_dev(plan->P, (char*)d_state, nslots, slot, d_u, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pcg take");
+  return IFFD_OK;
+}
+
+int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nrhs, double rtol,
+                   int maxit, int check_every, iffd_pcg_stats* h_stats, void* d_ws,
+                   size_t ws_bytes, void* stream) {
+  if (!plan || !d_f || !d_u || !d_ws) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(IFFD_E_INVAL, "nrhs out of range");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(IFFD_E_INVAL, "bad rtol / maxit");
+  const StateLayout L = state_layout(P, nrhs);
+  if (ws_bytes < L.total) return fail(IFFD_E_WORKSPACE, "pcg workspace too small");
+  if (!aligned256(d_ws)) return fail(IFFD_E_INVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* st = (char*)d_ws;
+  int rc = iffd_pcg_state_init(plan, d_ws, ws_bytes, nrhs, stream);
+  if (rc != IFFD_OK) return rc;
+  std::vector<int> slots(nrhs);
+  for (int k = 0; k < nrhs; ++k) slots[k] = k;
+  rc = iffd_pcg_begin(plan, d_ws, nrhs, slots.data(), nrhs, d_f, rtol, maxit, stream);
+  if (rc != IFFD_OK) return rc;
+  const int step = check_every > 0 ? check_every : 1;
+  std::vector<double> poll((size_t)4 * nrhs);
+  int done_it = 0;
+  while (true) {
+    rc = iffd_pcg_poll(plan, d_ws, nrhs, poll.data(), stream);
+    if (rc != IFFD_OK) return rc;
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) any = any || poll[4 * k] != 0.0;
+    if (!any || done_it >= maxit) break;
+    const int kk = std::min(step, maxit - done_it);
+    hipError_t e = pcg_iterate_dev(P, st, nrhs, kk, s);
+    if (e != hipSuccess) return hip_fail(e, "pcg iterate");
+    done_it += kk;
+  }
+  // solution out, true residual
+  double* x = (double*)(st + L.x);
+  double* qz = (double*)(st + L.qz);
+  double* r = (double*)(st + L.r);
+  double* part = (double*)(st + L.part);
+  hipError_t e = hipMemcpyAsync(d_u, x, 8 * (size_t)P.N * nrhs, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copy solution");
+  e = launch_matvec(P, d_u, qz, nrhs, nullptr, 0, nullptr, 0, s);
+  if (e == hipSuccess) e = residual_norms_dev(P, d_f, qz, r, part, nrhs, s);
+  if (e != hipSuccess) return hip_fail(e, "true residual");
+  const int nb = pcg_blocks(P);
+  std::vector<double> parts((size_t)nrhs * nb), sc((size_t)nrhs * kScal),
+      hist((size_t)nrhs * kHist * 2);
+  e = hipMemcpyAsync(parts.data(), part, 8 * parts.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sc.data(), st + L.scal, 8 * sc.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hist.data(), st + L.hist, 8 * hist.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stats readback");
+  int worst = IFFD_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const double* rec = &sc[(size_t)k * kScal];
+    double rr = 0.0;
+    for (int i = 0; i < nb; ++i) rr += parts[(size_t)k * nb + i];
+    const int status = (int)rec[S_STATUS];
+    if (status < 0) worst = std::min(worst, status);
+    else if (worst >= 0) worst = std::max(worst, status);
+    if (h_stats) {
+      iffd_pcg_stats& S = h_stats[k];
+      S.iterations = (int)rec[S_IT];
+      S.converged = rec[S_CONV] != 0.0;
+      S.status = status;
+      S.relres = rec[S_RELRES];
+      S.relres_true = rec[S_FF] > 0 ? std::sqrt(rr / rec[S_FF]) : 0.0;
+      // CG-Lanczos: T_jj = 1/a_j + b_{j-1}/a_{j-1}, T_j,j+1 = sqrt(b_j)/a_j
+      const int kl = std::min(S.iterations, kHist);
+      S.lanczos_lmin = S.lanczos_lmax = S.kappa_est = 0.0;
+      if (kl >= 1) {
+        const double* h = &hist[(size_t)k * kHist * 2];
+        std::vector<double> a(kl), b(kl > 1 ? kl - 1 : 0);
+        for (int j = 0; j < kl; ++j) {
+          a[j] = 1.0 / h[2 * j];
+          if (j > 0) a[j] += h[2 * (j - 1) + 1] / h[2 * (j - 1)];
+          if (j + 1 < kl) b[j] = std::sqrt(h[2 * j + 1]) / h[2 * j];
+        }
+        double lmin, lmax;
+        tridiag_extremes(a, b, lmin, lmax);
+        S.lanczos_lmin = lmin;
+        S.lanczos_lmax = lmax;
+        S.kappa_est = lmin > 0 ? lmax / lmin : 0.0;
+      }
+    }
+  }
+  return worst;
+}
+
+}  // extern "C"

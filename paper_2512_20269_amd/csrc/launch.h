@@ -1,0 +1,35 @@
+// Host-side launchers of the HIP kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace iffd {
+
+enum PassMode { PASS_FWD = 0, PASS_BWD = 1, PASS_MID = 2 };
+enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
+
+// One IFFD line pass along `axis` (1-based; direction 1 = fastest) of the
+// [nrhs][m]^d tensor.  Tin/Tout: ELEM_*; compute precision = plan.prec.
+// active: optional per-RHS flags (stride `active_stride` doubles; 0 = skip).
+hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
+                            void* out, int nrhs, const double* active, int active_stride,
+                            hipStream_t s);
+
+// Full IFFD apply z = P^{-1} r (FP64 in/out), ws = apply workspace.
+hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
+                             const double* active, int active_stride, hipStream_t s);
+
+// Dense FD apply (MFMA mode products).
+hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
+                           const double* active, int active_stride, hipStream_t s);
+
+// Outlier pencil eigensolve + table completion (FP64, on device).
+hipError_t launch_setup_outliers(const Plan& P, hipStream_t s);
+
+// y = Ahat x; optional fused partial dot sums part[b][blk] = sum p.y over a block.
+hipError_t launch_matvec(const Plan& P, const double* x, double* y, int nrhs, double* part,
+                         int npart, const double* active, int active_stride, hipStream_t s);
+
+}  // namespace iffd

@@ -1,0 +1,385 @@
+// Preconditioned conjugate gradients on gfx950, FP64 (Section 3; protocol of
+// Section 7: zero initial guess, stop at ||r_k|| <= rtol ||f||).
+//
+// Each slot is an independent solve.  Scalars live on the device in a record
+// of 16 doubles per slot, so the iteration never waits for the host and can
+// be captured in a HIP graph.  Inner products are reduced in two fixed-order
+// steps (per-block partials, then one sum per slot), so a slot's arithmetic
+// never depends on the other slots of the batch.
+//
+// One iteration, per active slot:
+//   q = A p, pq = p.q (fused in the operator)      -> reduce pq
+//   alpha = rz / pq; x += alpha p; r -= alpha q; rr -> reduce rr, test
+//   z = P^{-1} r; rz' = r.z                        -> reduce rz'
+//   beta = rz'/rz; p = z + beta p
+// rz alternates between two record entries by iteration parity so that no
+// kernel reads a value another block of the same kernel overwrites.
+#include "launch.h"
+#include "pcg_state.h"
+
+namespace iffd {
+
+constexpr int VT = 256;  // threads per block of the vector kernels
+
+// slot list of one begin call, passed by value (no device allocation)
+constexpr int kBeginMax = 64;
+struct BeginSlots {
+  int count;
+  int slot[kBeginMax];
+};
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < VT / 64; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ void chunk(int N, int nblk, int blk, int& lo, int& hi) {
+  const int c = (N + nblk - 1) / nblk;
+  lo = min(N, blk * c);
+  hi = min(N, lo + c);
+}
+
+// part[slot][blk] = sum a.b over the block's chunk; flags: slots to do
+__global__ void __launch_bounds__(VT)
+dot_partials(const double* __restrict__ a, const double* __restrict__ b, int N, int nblk,
+             double* __restrict__ part, const double* __restrict__ scal, int flag) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
+  if (scal && scal[(size_t)slot * kScal + flag] == 0.0) return;
+  int lo, hi;
+  chunk(N, nblk, blk, lo, hi);
+  const double* ar = a + (size_t)slot * N;
+  const double* br = b + (size_t)slot * N;
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += VT) s += ar[i] * br[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
+}
+
+// sum of a slot's partials in index order
+__device__ __forceinline__ double psum(const double* part, int nblk, int slot) {
+  const double* p = part + (size_t)slot * nblk;
+  double s = 0.0;
+  for (int i = 0; i < nblk; ++i) s += p[i];
+  return s;
+}
+
+// one thread per slot: pq = sum of partials; alpha = rz / pq; breakdown test
+__global__ void pcg_alpha(double* scal, const double* part, int npart_used, int npart, int nslots) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double* pp = part + (size_t)slot * npart;
+  double pq = 0.0;
+  for (int i = 0; i < npart_used; ++i) pq += pp[i];
+  const int it = (int)sc[S_IT];
+  const double rz = sc[S_RZ0 + (it & 1)];
+  if (!(pq > 0.0) || !(rz > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+    sc[S_ACTIVE] = 0.0;
+    sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
+    return;
+  }
+  sc[S_ALPHA] = rz / pq;
+}
+
+// x += alpha p; r -= alpha q; partial r.r
+__global__ void __launch_bounds__(VT)
+pcg_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+              const double* __restrict__ q, int N, int nblk, const double* __restrict__ scal,
+              double* __restrict__ part) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
+  const double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double alpha = sc[S_ALPHA];
+  int lo, hi;
+  chunk(N, nblk, blk, lo, hi);
+  const size_t o = (size_t)slot * N;
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += VT) {
+    x[o + i] += alpha * p[o + i];
+    const double rv = r[o + i] - alpha * q[o + i];
+    r[o + i] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
+}
+
+// one thread per slot: iteration count, residual test, history
+__global__ void pcg_check(double* scal, double* hist, const double* part, int nblk, int nslots) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double rr = psum(part, nblk, slot);
+  const int it = (int)sc[S_IT] + 1;
+  sc[S_IT] = it;
+  if (it - 1 < kHist) hist[((size_t)slot * kHist + it - 1) * 2] = sc[S_ALPHA];
+  const double rel = sqrt(rr / sc[S_FF]);
+  sc[S_RELRES] = rel;
+  if (!isfinite(rr)) {
+    sc[S_ACTIVE] = 0.0;
+    sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
+  } else if (rel <= sc[S_TOL]) {
+    sc[S_ACTIVE] = 0.0;
+    sc[S_CONV] = 1.0;
+    sc[S_STATUS] = (double)IFFD_OK;
+  } else if (it >= (int)sc[S_MAXIT]) {
+    sc[S_ACTIVE] = 0.0;
+    sc[S_STATUS] = (double)IFFD_W_NOT_CONVERGED;
+  }
+}
+
+// one thread per slot: rz' = sum of partials, beta = rz'/rz
+__global__ void pcg_beta(double* scal, double* hist, const double* part, int nblk, int nslots) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double rzn = psum(part, nblk, slot);
+  const int it = (int)sc[S_IT];  // already counts this iteration
+  const double rzo = sc[S_RZ0 + ((it - 1) & 1)];
+  if (!(rzn > 0.0) || !isfinite(rzn)) {
+    sc[S_ACTIVE] = 0.0;
+    sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
+    return;
+  }
+  const double beta = rzn / rzo;
+  sc[S_BETA] = beta;
+  sc[S_RZ0 + (it & 1)] = rzn;
+  if (it - 1 < kHist) hist[((size_t)slot * kHist + it - 1) * 2 + 1] = beta;
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(VT)
+pcg_update_p(double* __restrict__ p, const double* __restrict__ z, int N, int nblk,
+             const double* __restrict__ scal) {
+  const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
+  const double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double beta = sc[S_BETA];
+  int lo, hi;
+  chunk(N, nblk, blk, lo, hi);
+  const size_t o = (size_t)slot * N;
+  for (int i = lo + threadIdx.x; i < hi; i += VT) p[o + i] = z[o + i] + beta * p[o + i];
+}
+
+// begin: x = 0, r = f (f packed [count][N], slot list), partial f.f
+__global__ void __launch_bounds__(VT)
+pcg_begin_copy(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ f,
+               BeginSlots slots, int N, int nblk, double* __restrict__ part) {
+  __shared__ double red[VT / 64];
+  const int k = blockIdx.x / nblk, blk = blockIdx.x - k * nblk;
+  const int slot = slots.slot[k];
+  int lo, hi;
+  chunk(N, nblk, blk, lo, hi);
+  const size_t o = (size_t)slot * N;
+  const double* fk = f + (size_t)k * N;
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += VT) {
+    const double v = fk[i];
+    x[o + i] = 0.0;
+    r[o + i] = v;
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
+}
+
+// begin scalars (one thread per started slot)
+__global__ void pcg_begin_scal(double* scal, const double* part, int nblk, BeginSlots slots,
+                               double rtol, int maxit) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= slots.count) return;
+  const int slot = slots.slot[k];
+  double* sc = scal + (size_t)slot * kScal;
+  for (int i = 0; i < kScal; ++i) sc[i] = 0.0;
+  const double ff = psum(part, nblk, slot);
+  sc[S_FF] = ff;
+  sc[S_TOL] = rtol;
+  sc[S_MAXIT] = maxit;
+  sc[S_USED] = 1.0;
+  sc[S_RELRES] = ff > 0 ? 1.0 : 0.0;
+  if (!isfinite(ff)) {  // NaN / Inf right-hand side
+    sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
+    sc[S_RELRES] = ff;
+  } else if (ff > 0.0 && maxit > 0) {
+    sc[S_NEW] = 1.0;
+  } else {
+    sc[S_CONV] = ff > 0.0 ? 0.0 : 1.0;
+    sc[S_STATUS] = ff > 0.0 ? (double)IFFD_W_NOT_CONVERGED : (double)IFFD_OK;
+  }
+}
+
+// p = z for the started slots
+__global__ void __launch_bounds__(VT)
+pcg_begin_p(double* __restrict__ p, const double* __restrict__ z, int N, int nblk,
+            const double* __restrict__ scal) {
+  const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
+  if (scal[(size_t)slot * kScal + S_NEW] == 0.0) return;
+  int lo, hi;
+  chunk(N, nblk, blk, lo, hi);
+  const size_t o = (size_t)slot * N;
+  for (int i = lo + threadIdx.x; i < hi; i += VT) p[o + i] = z[o + i];
+}
+
+__global__ void pcg_begin_finish(double* scal, const double* part, int nblk, int nslots) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  double* sc = scal + (size_t)slot * kScal;
+  if (sc[S_NEW] == 0.0) return;
+  const double rz = psum(part, nblk, slot);
+  sc[S_NEW] = 0.0;
+  if (!(rz > 0.0) || !isfinite(rz)) {
+    sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
+    return;
+  }
+  sc[S_RZ0] = rz;
+  sc[S_ACTIVE] = 1.0;
+}
+
+// zero a byte range with a plain fill kernel (graph-safe, unlike memset nodes)
+__global__ void fill_zero(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// u = x[slot]; mark the slot free
+__global__ void pcg_take_kernel(const double* __restrict__ x, double* __restrict__ u, int N,
+                                int slot, double* scal) {
+  const size_t o = (size_t)slot * N;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    u[i] = x[o + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* sc = scal + (size_t)slot * kScal;
+    sc[S_USED] = 0.0;
+    sc[S_ACTIVE] = 0.0;
+  }
+}
+
+// r = f - y (for the true residual), per slot
+__global__ void __launch_bounds__(VT)
+axpby_res(double* __restrict__ out, const double* __restrict__ f, const double* __restrict__ y,
+          size_t n) {
+  for (size_t i = (size_t)blockIdx.x * VT + threadIdx.x; i < n; i += (size_t)gridDim.x * VT)
+    out[i] = f[i] - y[i];
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+hipError_t state_init(const Plan& P, char* st, int nslots, hipStream_t s) {
+  const StateLayout L = state_layout(P, nslots);
+  const size_t n = (L.part - L.scal) / 8;  // scalars + history
+  hipLaunchKernelGGL(fill_zero, dim3(64), dim3(256), 0, s, (double*)(st + L.scal), n);
+  return hipGetLastError();
+}
+
+hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots, int count,
+                         const double* f, double rtol, int maxit, hipStream_t s) {
+  if (count > kBeginMax) {
+    for (int c0 = 0; c0 < count; c0 += kBeginMax) {
+      hipError_t e = pcg_begin_dev(P, st, nslots, h_slots + c0, count - c0 < kBeginMax ? count - c0 : kBeginMax,
+                                   f + (size_t)c0 * P.N, rtol, maxit, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  BeginSlots bs;
+  bs.count = count;
+  for (int k = 0; k < kBeginMax; ++k) bs.slot[k] = k < count ? h_slots[k] : 0;
+  const StateLayout L = state_layout(P, nslots);
+  const int N = (int)P.N, nb = L.npart;
+  double* scal = (double*)(st + L.scal);
+  double* part = (double*)(st + L.part);
+  double* x = (double*)(st + L.x);
+  double* r = (double*)(st + L.r);
+  double* p = (double*)(st + L.p);
+  double* qz = (double*)(st + L.qz);
+  hipLaunchKernelGGL(pcg_begin_copy, dim3(count * nb), dim3(VT), 0, s, x, r, f, bs, N, nb, part);
+  hipLaunchKernelGGL(pcg_begin_scal, dim3(1), dim3(64), 0, s, scal, part, nb, bs, rtol, maxit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // z = P^{-1} r for the new slots only
+  e = (P.method == IFFD_METHOD_FFT)
+          ? launch_iffd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s)
+          : launch_fd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
+                     (int)S_NEW);
+  hipLaunchKernelGGL(pcg_begin_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
+  hipLaunchKernelGGL(pcg_begin_finish, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, part, nb,
+                     nslots);
+  return hipGetLastError();
+}
+
+hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream_t s) {
+  const StateLayout L = state_layout(P, nslots);
+  const int N = (int)P.N, nb = L.npart;
+  double* scal = (double*)(st + L.scal);
+  double* hist = (double*)(st + L.hist);
+  double* part = (double*)(st + L.part);
+  double* part2 = part + (size_t)nslots * nb;
+  double* x = (double*)(st + L.x);
+  double* r = (double*)(st + L.r);
+  double* p = (double*)(st + L.p);
+  double* qz = (double*)(st + L.qz);
+  void* ws = L.ws ? st + L.ws : nullptr;
+  const int nmv = matvec_blocks(P);
+  for (int it = 0; it < k; ++it) {
+    hipError_t e = launch_matvec(P, p, qz, nslots, part2, nb, scal + S_ACTIVE, kScal, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pcg_alpha, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, part2, nmv, nb, nslots);
+    hipLaunchKernelGGL(pcg_update_xr, dim3(nslots * nb), dim3(VT), 0, s, x, r, p, qz, N, nb, scal, part);
+    hipLaunchKernelGGL(pcg_check, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, hist, part, nb, nslots);
+    e = (P.method == IFFD_METHOD_FFT)
+            ? launch_iffd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s)
+            : launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
+                       (int)S_ACTIVE);
+    hipLaunchKernelGGL(pcg_beta, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, hist, part, nb, nslots);
+    hipLaunchKernelGGL(pcg_update_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u, hipStream_t s) {
+  const StateLayout L = state_layout(P, nslots);
+  hipLaunchKernelGGL(pcg_take_kernel, dim3(256), dim3(256), 0, s, (const double*)(st + L.x), u,
+                     (int)P.N, slot, (double*)(st + L.scal));
+  return hipGetLastError();
+}
+
+// norms of f - y for nrhs vectors (true residual): out[k] = ||f_k - y_k||^2
+hipError_t residual_norms_dev(const Plan& P, const double* f, const double* y, double* tmp,
+                              double* part, int nrhs, hipStream_t s) {
+  const int N = (int)P.N, nb = pcg_blocks(P);
+  hipLaunchKernelGGL(axpby_res, dim3(1024), dim3(VT), 0, s, tmp, f, y, (size_t)N * nrhs);
+  hipLaunchKernelGGL(dot_partials, dim3(nrhs * nb), dim3(VT), 0, s, tmp, tmp, N, nb, part,
+                     (const double*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t dot_partials_dev(const Plan& P, const double* a, const double* b, double* part, int nrhs,
+                            hipStream_t s) {
+  const int N = (int)P.N, nb = pcg_blocks(P);
+  hipLaunchKernelGGL(dot_partials, dim3(nrhs * nb), dim3(VT), 0, s, a, b, N, nb, part,
+                     (const double*)nullptr, 0);
+  return hipGetLastError();
+}
+
+}  // namespace iffd

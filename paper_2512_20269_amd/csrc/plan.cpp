@@ -1,0 +1,649 @@
+// Host-side FP64 construction of the univariate IFFD / FD factors.
+//
+// Everything here runs once per plan (not on the timed path).  The
+// construction follows the paper:
+//   Section 2   p-open uniform knot vector, B-splines, Dirichlet reduction
+//               (the first and last B-spline are dropped, m = n + p - 2);
+//   Section 3   1-D stiffness K and mass M (banded, half-bandwidth p);
+//   Section 4   splitting S = S^reg (+) S^out; V_reg has the block structure
+//               blkdiag(V_reg,0, I, V_reg,1); S^out is the L2-orthogonal
+//               complement, spanned by M^{-1} W with W spanning the Euclidean
+//               complement of range(V_reg) (so V_reg^T M V_out = 0);
+//   Section 6   the special basis (eq:special_basis_dirichlet): reflected
+//               cardinal B-splines at the ends, plain ones inside, for which
+//               Q_reg = U Dt^{-1} with U = [sin(x_i alpha_j)] (Table 1) and
+//               Dt = diag(U^T V_reg^T M V_reg U)^{1/2};
+//   eq:Lambda reg2  regular eigenvalues as Rayleigh quotients of the modes.
+// The small outlier pencil is solved later on the device (setup kernel).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace iffd {
+namespace {
+
+constexpr long double kPi = 3.141592653589793238462643383279502884L;
+
+// ---------------------------------------------------------------------------
+// B-spline evaluation on a knot vector U (de Boor / Piegl-Tiller triangle).
+// ---------------------------------------------------------------------------
+
+int find_span(int nb, int p, double u, const std::vector<double>& U) {
+  // span s in [p, nb-1] with U[s] <= u < U[s+1]; the right end belongs to
+  // the last non-empty span
+  if (u >= U[nb]) return nb - 1;
+  int lo = p, hi = nb;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (u < U[mid]) hi = mid; else lo = mid;
+  }
+  return lo;
+}
+
+// values (ders[0][j]) and first derivatives (ders[1][j]) of the p+1 B-splines
+// N_{s-p+j}, j = 0..p, that are non-zero on span s.
+void basis_and_derivative(int s, double u, int p, const std::vector<double>& U,
+                          std::vector<double>& val, std::vector<double>& der) {
+  std::vector<double> left(p + 1), right(p + 1);
+  // ndu[j][r]: upper triangle = basis values of increasing degree,
+  // lower triangle = knot differences
+  std::vector<std::vector<double>> ndu(p + 1, std::vector<double>(p + 1, 0.0));
+  ndu[0][0] = 1.0;
+  for (int j = 1; j <= p; ++j) {
+    left[j] = u - U[s + 1 - j];
+    right[j] = U[s + j] - u;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      ndu[j][r] = right[r + 1] + left[j - r];
+      double t = ndu[r][j - 1] / ndu[j][r];
+      ndu[r][j] = saved + right[r + 1] * t;
+      saved = left[j - r] * t;
+    }
+    ndu[j][j] = saved;
+  }
+  val.assign(p + 1, 0.0);
+  der.assign(p + 1, 0.0);
+  for (int j = 0; j <= p; ++j) val[j] = ndu[j][p];
+  if (p == 0) return;
+  // derivative from the degree p-1 values: N'_{i,p} = p N_{i,p-1}/(U_{i+p}-U_i)
+  //                                               - p N_{i+1,p-1}/(U_{i+p+1}-U_{i+1})
+  // ndu[j][p-1], j = 0..p-1, are N_{s-p+1+j, p-1}.
+  for (int j = 0; j <= p; ++j) {
+    int i = s - p + j;  // global index of the degree-p function
+    double a = 0.0, b = 0.0;
+    if (j >= 1) {        // N_{i,p-1} = ndu[j-1][p-1]
+      double den = U[i + p] - U[i];
+      if (den > 0) a = ndu[j - 1][p - 1] / den;
+    }
+    if (j <= p - 1) {    // N_{i+1,p-1} = ndu[j][p-1]
+      double den = U[i + p + 1] - U[i + 1];
+      if (den > 0) b = ndu[j][p - 1] / den;
+    }
+    der[j] = p * (a - b);
+  }
+}
+
+// Gauss-Legendre rule on [-1,1] with q points (Newton on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(q);
+  w.resize(q);
+  for (int i = 0; i < q; ++i) {
+    long double z = std::cos(kPi * (i + 0.75L) / (q + 0.5L));
+    long double dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = z; p0 = 1; }
+      dp = q * (z * p1 - p0) / (z * z - 1);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs((double)dz) < 1e-19) break;
+    }
+    // recompute the derivative at the converged node
+    long double p0 = 1, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = q * (z * p1 - p0) / (z * z - 1);
+    x[i] = (double)z;
+    w[i] = (double)(2 / ((1 - z * z) * dp * dp));
+  }
+}
+
+// Symmetric cardinal B-spline of degree p centred at 0 (support of width
+// p+1), by the Cox-de Boor recursion on the uniform knots k - (p+1)/2.
+double cardinal(int p, double t) {
+  std::vector<double> N(p + 1);
+  double t0 = -(p + 1) / 2.0;
+  for (int i = 0; i <= p; ++i) {
+    double a = t0 + i;
+    N[i] = (t >= a && t < a + 1) ? 1.0 : 0.0;
+  }
+  for (int q = 1; q <= p; ++q)
+    for (int i = 0; i + q <= p; ++i) {
+      double a = t0 + i;
+      N[i] = ((t - a) * N[i] + (a + q + 1 - t) * N[i + 1]) / q;
+    }
+  return N[0];
+}
+
+// Dense LU with partial pivoting; solves A X = B in place (A n x n, B n x k),
+// both row-major.  Returns false if singular.
+bool lu_solve(int n, std::vector<double> A, std::vector<double>& B, int k) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
+      for (int j = 0; j < k; ++j) std::swap(B[c * k + j], B[piv * k + j]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = A[r * n + c] / A[c * n + c];
+      if (f == 0.0) continue;
+      for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+      for (int j = 0; j < k; ++j) B[r * k + j] -= f * B[c * k + j];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c)
+    for (int j = 0; j < k; ++j) {
+      double s = B[c * k + j];
+      for (int q = c + 1; q < n; ++q) s -= A[c * n + q] * B[q * k + j];
+      B[c * k + j] = s / A[c * n + c];
+    }
+  return true;
+}
+
+// Cyclic Jacobi for a dense symmetric n x n matrix A (row-major, destroyed).
+// On return w holds the eigenvalues and V (row-major, column j = eigenvector
+// j), both unsorted.
+void jacobi(int n, std::vector<double>& A, std::vector<double>& V, std::vector<double>& w) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[(size_t)p * n + q];
+        double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        if (std::fabs(apq) <= std::max(eps * std::sqrt(std::fabs(app * aqq)), 1e-300)) continue;
+        rotated = true;
+        double th = (aqq - app) / (2 * apq);
+        double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          double a = A[(size_t)p * n + k], b = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * a - s * b;
+          A[(size_t)q * n + k] = s * a + c * b;
+        }
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          double a = A[(size_t)k * n + p], b = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * a - s * b;
+          A[(size_t)k * n + q] = s * a + c * b;
+          double va = V[(size_t)k * n + p], vb = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * va - s * vb;
+          V[(size_t)k * n + q] = s * va + c * vb;
+        }
+      }
+    if (!rotated) break;
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+}  // namespace
+
+bool fft_len_supported(int L) {
+  static const int ok[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+  for (int v : ok)
+    if (v == L) return true;
+  return false;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void compute_layout(Plan& P) {
+  TableLayout& t = P.lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  const int m = P.m, bw = 2 * P.p + 1, nb = (P.p - 1) * P.half;
+  const bool fd = P.method == IFFD_METHOD_DENSE_FD;
+  const size_t mm = fd ? (size_t)m * m : 1;
+  t.lam64 = take(8 * m);
+  t.s64 = take(8 * m);
+  t.v0_64 = take(8 * nb);
+  t.v1_64 = take(8 * nb);
+  t.vt64 = take(8 * (size_t)P.n_out * m);
+  t.twl64 = take(16 * (size_t)std::max(P.L, 1));
+  t.twp64 = take(16 * (size_t)(P.n + 1));
+  t.kb64 = take(8 * (size_t)m * bw);
+  t.mb64 = take(8 * (size_t)m * bw);
+  t.ao64 = take(8 * (size_t)P.n_out * P.n_out);
+  t.bo64 = take(8 * (size_t)P.n_out * P.n_out);
+  t.vout64 = take(8 * (size_t)P.n_out * m);
+  t.qfd64 = take(8 * mm);
+  t.qtfd64 = take(8 * mm);
+  t.lamfd64 = take(8 * m);
+  t.kc64 = take(8 * (size_t)std::max(P.crows, 1) * bw);
+  t.mc64 = take(8 * (size_t)std::max(P.crows, 1) * bw);
+  t.lam32 = take(4 * m);
+  t.s32 = take(4 * m);
+  t.v0_32 = take(4 * nb);
+  t.v1_32 = take(4 * nb);
+  t.vt32 = take(4 * (size_t)P.n_out * m);
+  t.twl32 = take(8 * (size_t)std::max(P.L, 1));
+  t.twp32 = take(8 * (size_t)(P.n + 1));
+  t.qfd32 = take(4 * mm);
+  t.qtfd32 = take(4 * mm);
+  t.lamfd32 = take(4 * m);
+  t.total = off;
+}
+
+int pcg_blocks(const Plan& P) {
+  // partial sums per slot: one per 1024 elements, capped
+  int64_t b = (P.N + 1023) / 1024;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+}
+
+size_t apply_ws_bytes(const Plan& P, int nrhs) {
+  if (P.prec == IFFD_PREC_F32) return align256((size_t)4 * P.N * nrhs);
+  if (P.method == IFFD_METHOD_DENSE_FD) return align256((size_t)8 * P.N * nrhs);
+  return 0;
+}
+
+StateLayout state_layout(const Plan& P, int nslots) {
+  StateLayout s{};
+  s.npart = std::max(pcg_blocks(P), matvec_blocks(P));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  s.scal = take((size_t)nslots * 16 * 8);
+  s.hist = take((size_t)nslots * kHist * 2 * 8);
+  s.part = take((size_t)3 * nslots * s.npart * 8);
+  s.x = take((size_t)nslots * P.N * 8);
+  s.r = take((size_t)nslots * P.N * 8);
+  s.p = take((size_t)nslots * P.N * 8);
+  s.qz = take((size_t)nslots * P.N * 8);
+  size_t ws = apply_ws_bytes(P, nslots);
+  s.ws = ws ? take(ws) : 0;
+  s.total = off;
+  // linear in nslots up to alignment: report a safe per-slot bound
+  s.per_slot = align256(16 * 8) + align256(kHist * 16) + align256((size_t)3 * s.npart * 8) +
+               4 * align256((size_t)P.N * 8) + apply_ws_bytes(P, 1) + 8 * 256;
+  s.fixed = 4096;
+  return s;
+}
+
+int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string& err) {
+  if (d != 2 && d != 3) { err = "d must be 2 or 3"; return IFFD_E_INVAL; }
+  if (p < 1 || p > 8) { err = "p must be in 1..8"; return IFFD_E_INVAL; }
+  if (n <= p) { err = "n must exceed p"; return IFFD_E_INVAL; }
+  if (n > 4096) { err = "n too large"; return IFFD_E_INVAL; }
+  P.d = d; P.n = n; P.p = p;
+  P.m = n + p - 2;
+  P.n_reg = (p % 2) ? n - 1 : n;
+  P.n_out = (p % 2) ? p - 1 : p - 2;
+  P.half = p / 2;
+  if (opts) {
+    P.method = opts->method;
+    P.prec = opts->apply_prec;
+    P.max_rhs = opts->max_rhs;
+  }
+  if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
+  if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64) { err = "bad apply_prec"; return IFFD_E_INVAL; }
+  if (P.max_rhs < 1) { err = "max_rhs must be >= 1"; return IFFD_E_INVAL; }
+  P.N = 1;
+  for (int k = 0; k < d; ++k) P.N *= P.m;
+  if (P.N * (int64_t)P.max_rhs >= (int64_t(1) << 31)) { err = "problem too large for 32-bit indexing"; return IFFD_E_UNSUPPORTED; }
+  if (P.method == IFFD_METHOD_FFT) {
+    if (p < 2) { err = "IFFD needs p >= 2 (p = 1 has no outlier split; use DENSE_FD)"; return IFFD_E_UNSUPPORTED; }
+    P.L = 2 * n;
+    if (!fft_len_supported(P.L)) { err = "n must be 2^a or 3*2^a with 8 <= n <= 256 for the FFT kernels"; return IFFD_E_UNSUPPORTED; }
+  }
+  const int m = P.m, bw = 2 * p + 1, nb = n + p;  // nb: full basis size
+  const double h = 1.0 / n;
+
+  // --- knots and 1-D matrices (Sections 2, 3) -----------------------------
+  std::vector<double> U(n + 2 * p + 1);
+  for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
+  for (int k = 1; k < n; ++k) U[p + k] = (double)k / n;
+  std::vector<double> gx, gw;
+  gauss_legendre(p + 1, gx, gw);
+  std::vector<double> Kf((size_t)nb * bw, 0.0), Mf((size_t)nb * bw, 0.0);  // full, banded
+  std::vector<double> val, der;
+  for (int e = 0; e < n; ++e) {
+    const int s = p + e;  // knot span of element e
+    const double a = e * h;
+    for (int g = 0; g < p + 1; ++g) {
+      double x = a + 0.5 * h * (gx[g] + 1.0), wq = 0.5 * h * gw[g];
+      basis_and_derivative(s, x, p, U, val, der);
+      for (int i = 0; i <= p; ++i)
+        for (int j = 0; j <= p; ++j) {
+          int gi = s - p + i, gj = s - p + j;
+          Mf[(size_t)gi * bw + (gj - gi + p)] += wq * val[i] * val[j];
+          Kf[(size_t)gi * bw + (gj - gi + p)] += wq * der[i] * der[j];
+        }
+    }
+  }
+  // Dirichlet reduction: drop B_0 and B_{nb-1}; reduced row i = full row i+1
+  P.Kb.assign((size_t)m * bw, 0.0);
+  P.Mb.assign((size_t)m * bw, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int o = 0; o < bw; ++o) {
+      int j = i + o - p;  // reduced column
+      if (j < 0 || j >= m) continue;
+      P.Kb[(size_t)i * bw + o] = Kf[(size_t)(i + 1) * bw + o];
+      P.Mb[(size_t)i * bw + o] = Mf[(size_t)(i + 1) * bw + o];
+    }
+
+  // compact band tables: rows 0..nbr-1 and m-nbr..m-1 are special, the rows
+  // in between equal the interior (Toeplitz) stencil
+  P.nbr = 2 * p - 1;
+  P.crows = (m > 2 * P.nbr + 1) ? 2 * P.nbr + 1 : m;
+  P.Kc.assign((size_t)P.crows * bw, 0.0);
+  P.Mc.assign((size_t)P.crows * bw, 0.0);
+  for (int cr = 0; cr < P.crows; ++cr) {
+    int i;
+    if (P.crows == m) i = cr;
+    else if (cr < P.nbr) i = cr;
+    else if (cr == P.nbr) i = m / 2;
+    else i = m - P.nbr + (cr - P.nbr - 1);
+    for (int o = 0; o < bw; ++o) {
+      P.Kc[(size_t)cr * bw + o] = P.Kb[(size_t)i * bw + o];
+      P.Mc[(size_t)cr * bw + o] = P.Mb[(size_t)i * bw + o];
+    }
+  }
+  if (P.crows < m) {  // the interior rows must all match the stencil row
+    const int mid = m / 2;
+    for (int i = P.nbr; i < m - P.nbr; ++i)
+      for (int o = 0; o < bw; ++o) {
+        double a = P.Kb[(size_t)i * bw + o], b = P.Kb[(size_t)mid * bw + o];
+        double c = P.Mb[(size_t)i * bw + o], d = P.Mb[(size_t)mid * bw + o];
+        if (std::fabs(a - b) > 1e-12 * std::fabs(P.Kb[(size_t)mid * bw + p]) ||
+            std::fabs(c - d) > 1e-12 * std::fabs(P.Mb[(size_t)mid * bw + p])) {
+          err = "interior rows of K/M are not Toeplitz";
+          return IFFD_E_INVAL;
+        }
+      }
+  }
+
+  P.lam.assign(m, 0.0);
+  P.s.assign(m, 1.0);
+
+  if (P.method == IFFD_METHOD_DENSE_FD) {
+    // full generalized eigendecomposition of (K, M): M = L L^T, C = L^-1 K L^-T
+    std::vector<double> L((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+      for (int i = j; i < std::min(m, j + p + 1); ++i) {
+        double sum = P.Mb[(size_t)i * bw + (j - i + p)];
+        for (int k = std::max(0, i - p); k < j; ++k) sum -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+        if (i == j) {
+          if (!(sum > 0)) { err = "mass matrix not SPD"; return IFFD_E_INVAL; }
+          L[(size_t)j * m + j] = std::sqrt(sum);
+        } else {
+          L[(size_t)i * m + j] = sum / L[(size_t)j * m + j];
+        }
+      }
+    }
+    // X = L^{-1} K (dense), then C = X L^{-T} = (L^{-1} X^T)^T
+    std::vector<double> Kd((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int o = 0; o < bw; ++o) {
+        int j = i + o - p;
+        if (j >= 0 && j < m) Kd[(size_t)i * m + j] = P.Kb[(size_t)i * bw + o];
+      }
+    auto lower_solve_cols = [&](std::vector<double>& B) {  // B <- L^{-1} B (m x m)
+      for (int c = 0; c < m; ++c)
+        for (int i = 0; i < m; ++i) {
+          double sum = B[(size_t)i * m + c];
+          for (int k = std::max(0, i - p); k < i; ++k) sum -= L[(size_t)i * m + k] * B[(size_t)k * m + c];
+          B[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
+        }
+    };
+    lower_solve_cols(Kd);
+    std::vector<double> T((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) T[(size_t)i * m + j] = Kd[(size_t)j * m + i];
+    lower_solve_cols(T);
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) {
+        double a = 0.5 * (T[(size_t)i * m + j] + T[(size_t)j * m + i]);
+        T[(size_t)i * m + j] = T[(size_t)j * m + i] = a;
+      }
+    std::vector<double> Z, w;
+    jacobi(m, T, Z, w);
+    // Q = L^{-T} Z (back substitution on each column)
+    std::vector<double> Q = Z;
+    for (int c = 0; c < m; ++c)
+      for (int i = m - 1; i >= 0; --i) {
+        double sum = Q[(size_t)i * m + c];
+        for (int k = i + 1; k < std::min(m, i + p + 1); ++k) sum -= L[(size_t)k * m + i] * Q[(size_t)k * m + c];
+        Q[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
+      }
+    std::vector<int> ord(m);
+    for (int i = 0; i < m; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
+    P.Qfd.assign((size_t)m * m, 0.0);
+    P.lamfd.assign(m, 0.0);
+    for (int j = 0; j < m; ++j) {
+      P.lamfd[j] = w[ord[j]];
+      for (int i = 0; i < m; ++i) P.Qfd[(size_t)i * m + j] = Q[(size_t)i * m + ord[j]];
+    }
+    P.lam = P.lamfd;
+    compute_layout(P);
+    return IFFD_OK;
+  }
+
+  // --- special basis boundary blocks (Section 6) ---------------------------
+  // Left end: Bhat_i = B~_i - B~_{dp - i}, i = 1..half, with B~_k(x) =
+  // B~_p((x - x_k)/h), x_k = k h (p odd) or (k - 1/2) h (p even).  Each lives
+  // on [0, p h], where only the reduced B-splines B_1..B_{p-1} are active; the
+  // coefficients follow from interpolation at their Greville points.
+  const int half = P.half, dp = (p % 2) ? 0 : 1, nbd = p - 1;
+  auto node = [&](int k) { return (p % 2) ? k * h : (k - 0.5) * h; };
+  std::vector<double> C((size_t)nbd * nbd), R((size_t)nbd * half);
+  for (int r = 0; r < nbd; ++r) {
+    int gi = r + 1;  // full index of reduced B_{r+1}
+    double tau = 0;
+    for (int k = 1; k <= p; ++k) tau += U[gi + k];
+    tau /= p;
+    int s = find_span(nb, p, tau, U);
+    basis_and_derivative(s, tau, p, U, val, der);
+    for (int c = 0; c < nbd; ++c) {
+      int gc = c + 1, j = gc - (s - p);
+      C[(size_t)r * nbd + c] = (j >= 0 && j <= p) ? val[j] : 0.0;
+    }
+    for (int c = 0; c < half; ++c) {
+      int i = c + 1;
+      R[(size_t)r * half + c] = cardinal(p, (tau - node(i)) / h) - cardinal(p, (tau - node(dp - i)) / h);
+    }
+  }
+  if (!lu_solve(nbd, C, R, half)) { err = "collocation matrix singular"; return IFFD_E_INVAL; }
+  P.V0 = R;  // (p-1) x half
+  // Right end by reflection x -> 1 - x: the right function paired with left
+  // function i is its mirror image, and B_j(1-x) = B_{m+1-j}(x).
+  P.V1.assign((size_t)nbd * half, 0.0);
+  for (int r = 0; r < nbd; ++r)
+    for (int c = 0; c < half; ++c)
+      P.V1[(size_t)r * half + c] = P.V0[(size_t)(nbd - 1 - r) * half + (half - 1 - c)];
+
+  // --- outlier basis (Section 4): V_out = M^{-1} [W0; 0; W1] ----------------
+  const int nh = nbd - half;  // outliers per end = floor((p-1)/2)
+  std::vector<double> W0((size_t)nbd * nh, 0.0);  // complement of range(V0)
+  if (nh > 0) {
+    // Householder QR of V0 (nbd x half); the trailing columns of Q span
+    // range(V0)'s orthogonal complement.
+    std::vector<double> A = P.V0;
+    std::vector<std::vector<double>> vs;
+    for (int c = 0; c < half; ++c) {
+      std::vector<double> v(nbd, 0.0);
+      double nrm = 0;
+      for (int r = c; r < nbd; ++r) nrm += A[(size_t)r * half + c] * A[(size_t)r * half + c];
+      nrm = std::sqrt(nrm);
+      double alpha = A[(size_t)c * half + c] >= 0 ? -nrm : nrm;
+      for (int r = c; r < nbd; ++r) v[r] = A[(size_t)r * half + c];
+      v[c] -= alpha;
+      double vn = 0;
+      for (int r = c; r < nbd; ++r) vn += v[r] * v[r];
+      if (vn > 0)
+        for (int cc = c; cc < half; ++cc) {
+          double dot = 0;
+          for (int r = c; r < nbd; ++r) dot += v[r] * A[(size_t)r * half + cc];
+          for (int r = c; r < nbd; ++r) A[(size_t)r * half + cc] -= 2 * dot / vn * v[r];
+        }
+      vs.push_back(v);
+    }
+    // columns half..nbd-1 of Q = H_0 H_1 .. e_j
+    for (int j = 0; j < nh; ++j) {
+      std::vector<double> e(nbd, 0.0);
+      e[half + j] = 1.0;
+      for (int c = half - 1; c >= 0; --c) {
+        const std::vector<double>& v = vs[c];
+        double vn = 0, dot = 0;
+        for (int r = 0; r < nbd; ++r) { vn += v[r] * v[r]; dot += v[r] * e[r]; }
+        if (vn > 0)
+          for (int r = 0; r < nbd; ++r) e[r] -= 2 * dot / vn * v[r];
+      }
+      for (int r = 0; r < nbd; ++r) W0[(size_t)r * nh + j] = e[r];
+    }
+  }
+  // banded Cholesky of M (lower band, Lb[i][k] = L(i, i-p+k))
+  std::vector<double> Lb((size_t)m * (p + 1), 0.0);
+  auto Lat = [&](int i, int j) -> double& { return Lb[(size_t)i * (p + 1) + (j - i + p)]; };
+  for (int i = 0; i < m; ++i)
+    for (int j = std::max(0, i - p); j <= i; ++j) {
+      double sum = P.Mb[(size_t)i * bw + (j - i + p)];
+      for (int k = std::max(0, i - p); k < j; ++k) sum -= Lat(i, k) * Lat(j, k);
+      if (i == j) {
+        if (!(sum > 0)) { err = "mass matrix not SPD"; return IFFD_E_INVAL; }
+        Lat(i, i) = std::sqrt(sum);
+      } else {
+        Lat(i, j) = sum / Lat(j, j);
+      }
+    }
+  const int no = P.n_out;
+  P.Vout.assign((size_t)no * m, 0.0);
+  for (int c = 0; c < no; ++c) {
+    std::vector<double> b(m, 0.0);
+    if (c < nh) {
+      for (int r = 0; r < nbd; ++r) b[r] = W0[(size_t)r * nh + c];
+    } else {  // mirrored right-end column
+      int cc = c - nh;
+      for (int r = 0; r < nbd; ++r) b[m - 1 - r] = W0[(size_t)r * nh + cc];
+    }
+    for (int i = 0; i < m; ++i) {  // L y = b
+      double sum = b[i];
+      for (int k = std::max(0, i - p); k < i; ++k) sum -= Lat(i, k) * b[k];
+      b[i] = sum / Lat(i, i);
+    }
+    for (int i = m - 1; i >= 0; --i) {  // L^T x = y
+      double sum = b[i];
+      for (int k = i + 1; k < std::min(m, i + p + 1); ++k) sum -= Lat(k, i) * b[k];
+      b[i] = sum / Lat(i, i);
+    }
+    for (int i = 0; i < m; ++i) P.Vout[(size_t)c * m + i] = b[i];
+  }
+  auto band_mv = [&](const std::vector<double>& Bd, const double* x, double* y) {
+    for (int i = 0; i < m; ++i) {
+      double sum = 0;
+      for (int o = 0; o < bw; ++o) {
+        int j = i + o - p;
+        if (j >= 0 && j < m) sum += Bd[(size_t)i * bw + o] * x[j];
+      }
+      y[i] = sum;
+    }
+  };
+  P.Ao.assign((size_t)no * no, 0.0);
+  P.Bo.assign((size_t)no * no, 0.0);
+  {
+    std::vector<double> kv(m), mv(m);
+    for (int a = 0; a < no; ++a) {
+      band_mv(P.Kb, &P.Vout[(size_t)a * m], kv.data());
+      band_mv(P.Mb, &P.Vout[(size_t)a * m], mv.data());
+      for (int b = 0; b < no; ++b) {
+        double sk = 0, sm = 0;
+        for (int i = 0; i < m; ++i) {
+          sk += P.Vout[(size_t)b * m + i] * kv[i];
+          sm += P.Vout[(size_t)b * m + i] * mv[i];
+        }
+        P.Ao[(size_t)a * no + b] = sk;
+        P.Bo[(size_t)a * no + b] = sm;
+      }
+    }
+    for (int a = 0; a < no; ++a)  // exact symmetry
+      for (int b = a + 1; b < no; ++b) {
+        double k2 = 0.5 * (P.Ao[(size_t)a * no + b] + P.Ao[(size_t)b * no + a]);
+        double m2 = 0.5 * (P.Bo[(size_t)a * no + b] + P.Bo[(size_t)b * no + a]);
+        P.Ao[(size_t)a * no + b] = P.Ao[(size_t)b * no + a] = k2;
+        P.Bo[(size_t)a * no + b] = P.Bo[(size_t)b * no + a] = m2;
+      }
+  }
+
+  // --- regular modes: Dt and Lambda_reg (Section 6, eq:Lambda reg2) -------
+  // U_ij = sin(x_i alpha_j), alpha_j = j pi: p odd sin(pi i j / n),
+  // p even sin(pi (2i-1) j / (2n)); angles are reduced exactly modulo 2 pi.
+  const int nr = P.n_reg;
+  const int period = (p % 2) ? 2 * n : 4 * n;
+  std::vector<double> sintab(period);
+  for (int k = 0; k < period; ++k) sintab[k] = (double)std::sin(2 * kPi * k / period);
+  P.Dt.assign(nr, 0.0);
+  std::vector<double> u(nr), v(m), kv(m), mv(m);
+  for (int j = 1; j <= nr; ++j) {
+    for (int i = 1; i <= nr; ++i) {
+      long long k = (p % 2) ? (long long)i * j : (long long)(2 * i - 1) * j;
+      u[i - 1] = sintab[k % period];
+    }
+    // v = V_reg u
+    std::fill(v.begin(), v.end(), 0.0);
+    for (int r = 0; r < nbd; ++r) {
+      double a = 0, b = 0;
+      for (int c = 0; c < half; ++c) {
+        a += P.V0[(size_t)r * half + c] * u[c];
+        b += P.V1[(size_t)r * half + c] * u[nr - half + c];
+      }
+      v[r] = a;
+      v[m - nbd + r] = b;
+    }
+    for (int i = half; i < nr - half; ++i) v[i + (p - 1 - half)] = u[i];
+    band_mv(P.Kb, v.data(), kv.data());
+    band_mv(P.Mb, v.data(), mv.data());
+    double sk = 0, sm = 0;
+    for (int i = 0; i < m; ++i) { sk += v[i] * kv[i]; sm += v[i] * mv[i]; }
+    P.Dt[j - 1] = std::sqrt(sm);
+    P.lam[j - 1] = sk / sm;
+    P.s[j - 1] = 1.0 / sm;
+  }
+
+  // --- FFT twiddles ------------------------------------------------------------
+  P.twl.assign((size_t)2 * P.L, 0.0);
+  for (int k = 0; k < P.L; ++k) {
+    P.twl[2 * k] = (double)std::cos(2 * kPi * k / P.L);
+    P.twl[2 * k + 1] = (double)-std::sin(2 * kPi * k / P.L);
+  }
+  P.twp.assign((size_t)2 * (n + 1), 0.0);
+  for (int j = 0; j <= n; ++j) {
+    P.twp[2 * j] = (double)std::cos(kPi * j / (2 * n));
+    P.twp[2 * j + 1] = (double)-std::sin(kPi * j / (2 * n));
+  }
+  compute_layout(P);
+  return IFFD_OK;
+}
+
+}  // namespace iffd

@@ -1,0 +1,75 @@
+// Internal plan structure shared by the host setup, the C ABI and the kernel
+// launchers.  Not part of the public interface (include/iffd.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/iffd.h"
+
+namespace iffd {
+
+// Byte offsets of every table inside the caller's device table buffer.  Each
+// array starts on a 256-byte boundary.  Arrays marked "64" are FP64, "32" FP32.
+struct TableLayout {
+  size_t lam64, s64, v0_64, v1_64, vt64, twl64, twp64, kb64, mb64, ao64, bo64, vout64;
+  size_t qfd64, qtfd64, lamfd64;
+  size_t kc64, mc64;  // compact band tables: 2p-1 end rows each side + 1 interior row
+  size_t lam32, s32, v0_32, v1_32, vt32, twl32, twp32;
+  size_t qfd32, qtfd32, lamfd32;
+  size_t total;
+};
+
+// Workspace / state layout of the stepped PCG (all per-slot arrays are
+// [nslots][...]).  Offsets in bytes from the start of the state buffer.
+struct StateLayout {
+  size_t scal;      // [nslots] SlotScalars
+  size_t hist;      // [nslots][kHist] alpha/beta history (2 doubles each)
+  size_t part;      // [3][nslots][npart] FP64 partial sums
+  size_t x, r, p, qz;  // [nslots][N] FP64
+  size_t ws;        // preconditioner workspace [nslots][N] (FP32 apply) or 0
+  size_t fixed, per_slot, total;
+  int npart;
+};
+
+constexpr int kHist = 256;  // alpha/beta history kept per slot for Lanczos
+
+struct Plan {
+  int d = 0, n = 0, p = 0, m = 0, n_reg = 0, n_out = 0, half = 0, L = 0;
+  int method = IFFD_METHOD_FFT, prec = IFFD_PREC_F32, max_rhs = 1;
+  int64_t N = 0;
+
+  // host-side FP64 data
+  std::vector<double> Kb, Mb;       // m x (2p+1) band rows, column i-p..i+p
+  std::vector<double> V0, V1;       // (p-1) x half, row-major
+  std::vector<double> Vout;         // n_out x m (rows = outlier basis vectors)
+  std::vector<double> Ao, Bo;       // outlier pencil, n_out x n_out
+  std::vector<double> lam;          // m: regular eigenvalues, then outliers
+  std::vector<double> Dt;           // n_reg
+  std::vector<double> s;            // m: Dt^{-2} on regular modes, 1 on outliers
+  std::vector<double> Vt;           // n_out x m, Q_out-rotated (after setup)
+  std::vector<double> twl, twp;     // FFT twiddles (interleaved complex)
+  std::vector<double> Qfd, lamfd;   // dense FD: m x m (column j = eigvec j)
+  std::vector<double> Kc, Mc;       // compact band tables (crows x (2p+1))
+  int nbr = 0, crows = 0;
+
+  TableLayout lay{};
+  char* d_tables = nullptr;
+  size_t table_bytes = 0;
+  bool ready = false;
+};
+
+// host setup (plan.cpp)
+int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string& err);
+void compute_layout(Plan& P);
+StateLayout state_layout(const Plan& P, int nslots);
+size_t apply_ws_bytes(const Plan& P, int nrhs);
+int pcg_blocks(const Plan& P);  // number of partial sums per slot
+int matvec_blocks(const Plan& P);  // workgroups of the operator per right-hand side
+
+// whether an FFT length is supported by the built kernels
+bool fft_len_supported(int L);
+
+}  // namespace iffd

@@ -1,0 +1,124 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every symbol the
+header declares, validates arguments, and its host-side plan tables (built by
+its own C++ code) agree with the oracle.  No device work is launched here."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2512_20269_amd as I
+from oracle import bspline
+from oracle import iffd as O
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "iffd.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(iffd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert len(syms) >= 16
+    lib = ctypes.CDLL(I.LIB_PATH)
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(I.SIGNATURES), "binding and header disagree"
+
+
+def host_plan(d, n, p, method=I.METHOD_FFT, prec=I.PREC_F32, max_rhs=1):
+    h = ctypes.c_void_p()
+    opts = I._Opts(method, prec, max_rhs)
+    rc = I.lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts))
+    return rc, h
+
+
+def read(h, what, count):
+    buf = np.zeros(count)
+    rc = I.lib.iffd_plan_read(h, what, buf.ctypes.data_as(ctypes.c_void_p), count, None)
+    assert rc == 0, I.lib.iffd_last_error()
+    return buf
+
+
+@pytest.mark.parametrize("n,p", [(8, 2), (16, 3), (12, 4), (32, 5), (24, 6), (16, 7), (32, 8),
+                                 (96, 4), (128, 3)])
+def test_host_tables_match_oracle(n, p):
+    rc, h = host_plan(3, n, p)
+    assert rc == 0, I.lib.iffd_last_error()
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    m, n_reg, n_out = O.dims(n, p)
+    assert (info.m, info.n_reg, info.n_out, info.N, info.fft_len) == (m, n_reg, n_out, m ** 3, 2 * n)
+    fb = O.factors_route_b(n, p)
+    lam = read(h, I.TABLE_LAM, m)[:n_reg]
+    np.testing.assert_allclose(lam, fb["lam_reg"], rtol=1e-12)
+    np.testing.assert_allclose(read(h, I.TABLE_DT, n_reg), fb["Dt"], rtol=1e-12)
+    K, M = bspline.assemble_dirichlet(n, p)
+    bw = 2 * p + 1
+    for what, ref in ((I.TABLE_KBAND, K), (I.TABLE_MBAND, M)):
+        band = read(h, what, m * bw).reshape(m, bw)
+        dense = np.zeros((m, m))
+        for i in range(m):
+            for o in range(bw):
+                j = i + o - p
+                if 0 <= j < m:
+                    dense[i, j] = band[i, o]
+        np.testing.assert_allclose(dense, ref, atol=1e-13 * np.abs(ref).max())
+    # the special-basis boundary block spans the same space as the oracle's
+    half = p // 2
+    V0 = read(h, I.TABLE_V0, (p - 1) * half).reshape(p - 1, half)
+    np.testing.assert_allclose(V0, fb["V_reg"][:p - 1, :half], atol=1e-12)
+    # Vt needs the device setup
+    buf = np.zeros(max(1, n_out * m))
+    assert I.lib.iffd_plan_read(h, I.TABLE_VT, buf.ctypes.data_as(ctypes.c_void_p), len(buf),
+                                None) == I.E_STATE
+    I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("n,p", [(9, 3), (17, 3)])
+def test_dense_fd_host_eigenvalues(n, p):
+    rc, h = host_plan(2, n, p, method=I.METHOD_DENSE_FD)
+    assert rc == 0
+    m = n + p - 2
+    lam_fd = read(h, I.TABLE_LAM, m)
+    lam_or, *_ = O.factors_fd(n, p)
+    np.testing.assert_allclose(lam_fd, lam_or, rtol=1e-11)
+    I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("d,n,p,code", [
+    (1, 16, 3, I.E_INVAL), (4, 16, 3, I.E_INVAL), (3, 16, 0, I.E_INVAL), (3, 16, 9, I.E_INVAL),
+    (3, 3, 3, I.E_INVAL), (3, 100, 3, I.E_UNSUPPORTED), (3, 16, 1, I.E_UNSUPPORTED),
+    (3, 1024, 3, I.E_UNSUPPORTED)])
+def test_invalid_plans_rejected(d, n, p, code):
+    rc, h = host_plan(d, n, p)
+    assert rc == code
+    assert h.value is None
+    assert len(I.lib.iffd_last_error()) > 0
+
+
+def test_null_and_state_errors():
+    assert I.lib.iffd_plan_create(None, 3, 16, 3, None) == I.E_INVAL
+    rc, h = host_plan(2, 16, 3)
+    assert rc == 0
+    info = I._Info()
+    I.lib.iffd_plan_query(h, ctypes.byref(info))
+    # compute entry points refuse a plan that has not been set up
+    fake = ctypes.c_void_p(256)
+    assert I.lib.iffd_precond_apply(h, fake, ctypes.c_void_p(512), 1, fake, 1 << 20, None) == I.E_STATE
+    assert I.lib.iffd_kron_matvec(h, fake, ctypes.c_void_p(512), 1, None) == I.E_STATE
+    # the default options are FFT / F32 / 1 RHS
+    rc, h2 = host_plan(2, 16, 3)
+    h3 = ctypes.c_void_p()
+    assert I.lib.iffd_plan_create(ctypes.byref(h3), 2, 16, 3, None) == 0
+    i3 = I._Info()
+    I.lib.iffd_plan_query(h3, ctypes.byref(i3))
+    assert (i3.method, i3.apply_prec, i3.max_rhs) == (I.METHOD_FFT, I.PREC_F32, 1)
+    for x in (h, h2, h3):
+        I.lib.iffd_plan_destroy(x)
+    assert I.lib.iffd_status_string(I.E_BREAKDOWN) == b"PCG breakdown"
