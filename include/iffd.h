@@ -81,6 +81,7 @@ typedef struct {
   size_t table_bytes;      /* device buffer for iffd_plan_setup               */
   size_t apply_ws_bytes;   /* workspace for iffd_precond_apply(nrhs=max_rhs)  */
   size_t pcg_ws_bytes;     /* workspace for iffd_pcg_solve(nrhs=max_rhs)      */
+  size_t matvec_ws_bytes;  /* workspace for iffd_kron_matvec(nrhs=max_rhs)    */
   size_t state_bytes_per_slot; /* device state per slot of the stepped PCG    */
   size_t state_bytes_fixed;    /* plus this once per state buffer             */
 } iffd_plan_info;
@@ -150,9 +151,10 @@ int iffd_precond_apply(const iffd_plan* plan, const double* d_r, double* d_z, in
 
 /* y = Ahat x, Ahat = sum_k M x .. x K (slot k) x .. x M (eq:system_matrix and
  * its 3-term analogue), FP64, matrix-free by sum factorization with the
- * banded 1-D matrices.  d_x, d_y: [nrhs][m]^d FP64, must not overlap. */
+ * banded 1-D matrices.  d_x, d_y: [nrhs][m]^d FP64, must not overlap.
+ * d_ws: >= matvec_ws_bytes (for max_rhs), 256-byte aligned (NULL if 0). */
 int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs,
-                     void* stream);
+                     void* d_ws, size_t ws_bytes, void* stream);
 
 /* Solves Ahat u = f for nrhs right-hand sides by PCG with this plan's
  * preconditioner (Section 3), zero initial guess, stopping when
@@ -165,6 +167,30 @@ int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int 
 int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nrhs,
                    double rtol, int maxit, int check_every, iffd_pcg_stats* h_stats,
                    void* d_ws, size_t ws_bytes, void* stream);
+
+/* One pass of iffd_precond_apply (IFFD only), for per-kernel timing: the
+ * apply is the sequence pass = 0 .. iffd_apply_pass_count()-1, where pass k
+ * < d-1 is the forward line transform along direction k+1, pass d-1 the fused
+ * forward transform / Kronecker-sum scaling / backward transform along
+ * direction d, and the remaining passes the backward transforms along
+ * directions d-1 .. 1.  Pass 0 reads d_r, the last pass writes d_z, the
+ * others work in place on the workspace (FP32 apply) or on d_z (FP64 apply).
+ * Same arguments and rules as iffd_precond_apply. */
+int iffd_apply_pass_count(const iffd_plan* plan);
+int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* d_z, int nrhs,
+                    void* d_ws, size_t ws_bytes, void* stream);
+
+/* FFT shape of one pass: variant 0 holds 16 (or 24) transform elements per
+ * thread, variant 1 holds 8 (or 12) with twice the threads.  Both compute the
+ * same result; they differ in speed.  iffd_plan_set_variant forces a choice
+ * (diagnostics, tests); iffd_plan_tune times both variants of every pass on
+ * the device (reps launches each, events on `stream`, which it synchronizes)
+ * and keeps the faster.  d_scratch: >= 16*N bytes + apply_ws_bytes for one
+ * right-hand side, 256-byte aligned; its contents are overwritten.  Tuning
+ * mutates the plan: do not run it while the plan is in use on other streams. */
+int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant);
+int iffd_plan_get_variant(const iffd_plan* plan, int pass);
+int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int reps, void* stream);
 
 /* ---- stepped PCG on resident state (continuous batching) -----------------
  * A state buffer holds `nslots` independent PCG solves of one plan: bytes =

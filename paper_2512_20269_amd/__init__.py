@@ -47,6 +47,7 @@ class _Info(ctypes.Structure):
                 ("method", ctypes.c_int), ("apply_prec", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("N", ctypes.c_int64), ("table_bytes", ctypes.c_size_t),
                 ("apply_ws_bytes", ctypes.c_size_t), ("pcg_ws_bytes", ctypes.c_size_t),
+                ("matvec_ws_bytes", ctypes.c_size_t),
                 ("state_bytes_per_slot", ctypes.c_size_t), ("state_bytes_fixed", ctypes.c_size_t)]
 
 
@@ -66,7 +67,12 @@ SIGNATURES = {
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
     "iffd_precond_apply": (_I, [_P, _P, _P, _I, _P, _Z, _P]),
-    "iffd_kron_matvec": (_I, [_P, _P, _P, _I, _P]),
+    "iffd_kron_matvec": (_I, [_P, _P, _P, _I, _P, _Z, _P]),
+    "iffd_apply_pass_count": (_I, [_P]),
+    "iffd_plan_set_variant": (_I, [_P, _I, _I]),
+    "iffd_plan_get_variant": (_I, [_P, _I]),
+    "iffd_plan_tune": (_I, [_P, _P, _Z, _I, _P]),
+    "iffd_apply_pass": (_I, [_P, _I, _P, _P, _I, _P, _Z, _P]),
     "iffd_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_Stats), _P, _Z, _P]),
     "iffd_pcg_state_init": (_I, [_P, _P, _Z, _I, _P]),
     "iffd_pcg_begin": (_I, [_P, _P, _I, ctypes.POINTER(_I), _I, _P, _D, _I, _P]),
@@ -154,6 +160,8 @@ class Plan:
                    "plan_setup")
             self._ws = torch.empty(max(info.apply_ws_bytes, 256), dtype=torch.uint8,
                                    device=self.device)
+            self._mvws = torch.empty(max(info.matvec_ws_bytes, 256), dtype=torch.uint8,
+                                     device=self.device)
         self._pcg_ws = None
 
     def __del__(self):
@@ -193,14 +201,40 @@ class Plan:
                                       self._ws.numel(), _stream(stream)), "precond_apply")
         return z
 
+    def set_variant(self, k: int, v: int):
+        _check(lib.iffd_plan_set_variant(self._h, k, v), "plan_set_variant")
+
+    def variants(self):
+        return [lib.iffd_plan_get_variant(self._h, k) for k in range(self.n_passes())]
+
+    def tune(self, reps: int = 20, stream=None):
+        """Time both FFT shapes of every pass on the device and keep the faster."""
+        torch = _torch()
+        if self.method != "fft":
+            return []
+        nbytes = 16 * self.N + self.info["apply_ws_bytes"] // max(self.max_rhs, 1) + 4096
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib.iffd_plan_tune(self._h, _ptr(scratch), nbytes, reps, _stream(stream)),
+               "plan_tune")
+        return self.variants()
+
+    def n_passes(self) -> int:
+        return lib.iffd_apply_pass_count(self._h)
+
+    def apply_pass(self, k: int, r, z, stream=None):
+        """One pass of apply() (see iffd_apply_pass); z must be preallocated."""
+        nrhs = self._batch(r, "r")
+        _check(lib.iffd_apply_pass(self._h, k, _ptr(r), _ptr(z), nrhs, _ptr(self._ws),
+                                   self._ws.numel(), _stream(stream)), "apply_pass")
+
     def matvec(self, x, out=None, stream=None):
         """y = Ahat x."""
         torch = _torch()
         nrhs = self._batch(x, "x")
         y = out if out is not None else torch.empty_like(x)
         _need(y, self.shape, torch.float64, "out")
-        _check(lib.iffd_kron_matvec(self._h, _ptr(x), _ptr(y), nrhs, _stream(stream)),
-               "kron_matvec")
+        _check(lib.iffd_kron_matvec(self._h, _ptr(x), _ptr(y), nrhs, _ptr(self._mvws),
+                                    self._mvws.numel(), _stream(stream)), "kron_matvec")
         return y
 
     def solve(self, f, rtol: float = 1e-8, maxit: int = 500, check_every: int = 1, out=None,

@@ -21,7 +21,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiffd.so")
 
-SOURCES = ["plan.cpp", "api.cpp", "apply.hip", "setup.hip", "matvec.hip", "pcg.hip", "dense.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "apply.hip", "apply_la.hip", "apply_lb.hip", "apply_lc.hip",
+           "apply_ld.hip", "apply_le.hip", "apply_lf.hip", "apply_lg.hip", "setup.hip", "matvec.hip",
+           "pcg.hip", "dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -148,6 +148,7 @@ int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info) {
   info->table_bytes = P.lay.total;
   info->apply_ws_bytes = apply_ws_bytes(P, P.max_rhs);
   info->pcg_ws_bytes = state_layout(P, P.max_rhs).total;
+  info->matvec_ws_bytes = matvec_ws_bytes(P, P.max_rhs);
   const StateLayout one = state_layout(P, 1);
   info->state_bytes_per_slot = one.per_slot;
   info->state_bytes_fixed = one.fixed;
@@ -212,6 +213,28 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     for (int k = P.n_reg; k < P.m; ++k) P.lam[k] = lam[k];
     P.Vt = vt;
   }
+  if (P.method == IFFD_METHOD_FFT) {
+    // the line-pass tables as one contiguous blob (one load sweep per block)
+    std::vector<double> blob((size_t)P.blob_len, 0.0);
+    std::copy(P.twl.begin(), P.twl.end(), blob.begin() + P.bo_twl);
+    std::copy(P.twp.begin(), P.twp.end(), blob.begin() + P.bo_twp);
+    std::copy(P.Vt.begin(), P.Vt.end(), blob.begin() + P.bo_vt);
+    std::copy(P.V0.begin(), P.V0.end(), blob.begin() + P.bo_v0);
+    std::copy(P.V1.begin(), P.V1.end(), blob.begin() + P.bo_v1);
+    std::copy(P.lam.begin(), P.lam.end(), blob.begin() + P.bo_lam);
+    std::copy(P.s.begin(), P.s.end(), blob.begin() + P.bo_s);
+    std::vector<char> bb(12 * blob.size() + 16, 0);
+    std::memcpy(bb.data(), blob.data(), 8 * blob.size());
+    for (size_t i = 0; i < blob.size(); ++i) {
+      const float f = (float)blob[i];
+      std::memcpy(bb.data() + 8 * blob.size() + 4 * i, &f, 4);
+    }
+    e = hipMemcpy((char*)d_tables + t.blob64, bb.data(), 8 * blob.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy((char*)d_tables + t.blob32, bb.data() + 8 * blob.size(), 4 * blob.size(),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "blob upload");
+  }
   P.ready = true;
   return IFFD_OK;
 }
@@ -256,13 +279,92 @@ int iffd_precond_apply(const iffd_plan* plan, const double* d_r, double* d_z, in
   return IFFD_OK;
 }
 
-int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs, void* stream) {
+int iffd_apply_pass_count(const iffd_plan* plan) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  return plan->P.method == IFFD_METHOD_FFT ? 2 * plan->P.d - 1 : 0;
+}
+
+int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* d_z, int nrhs,
+                    void* d_ws, size_t ws_bytes, void* stream) {
+  if (!plan || !d_r || !d_z) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (P.method != IFFD_METHOD_FFT) return fail(IFFD_E_STATE, "passes exist for the FFT method only");
+  if (pass < 0 || pass >= 2 * P.d - 1) return fail(IFFD_E_INVAL, "pass out of range");
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(IFFD_E_INVAL, "nrhs out of range");
+  if ((const void*)d_r == (const void*)d_z) return fail(IFFD_E_INVAL, "r and z must not alias");
+  const size_t need = apply_ws_bytes(P, nrhs);
+  if (need && (!d_ws || ws_bytes < need)) return fail(IFFD_E_WORKSPACE, "apply workspace too small");
+  hipError_t e = launch_iffd_pass(P, pass, d_r, d_z, nrhs, d_ws, nullptr, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "apply pass launch");
+  return IFFD_OK;
+}
+
+int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  if (pass < 0 || pass >= 2 * plan->P.d - 1 || (variant != 0 && variant != 1))
+    return fail(IFFD_E_INVAL, "pass or variant out of range");
+  plan->P.variant[pass] = variant;
+  return IFFD_OK;
+}
+
+int iffd_plan_get_variant(const iffd_plan* plan, int pass) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  if (pass < 0 || pass >= 2 * plan->P.d - 1) return fail(IFFD_E_INVAL, "pass out of range");
+  return plan->P.variant[pass];
+}
+
+int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int reps, void* stream) {
+  if (!plan || !d_scratch) return fail(IFFD_E_INVAL, "null argument");
+  Plan& P = plan->P;
+  if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (P.method != IFFD_METHOD_FFT) return IFFD_OK;
+  const size_t need = 16 * (size_t)P.N + apply_ws_bytes(P, 1);
+  if (scratch_bytes < need) return fail(IFFD_E_WORKSPACE, "tuning scratch too small");
+  if (!aligned256(d_scratch)) return fail(IFFD_E_INVAL, "scratch must be 256-byte aligned");
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  double* r = (double*)d_scratch;
+  double* z = r + P.N;
+  void* ws = (char*)d_scratch + 16 * (size_t)P.N;
+  hipError_t e = hipMemsetAsync(d_scratch, 0, need, s);
+  if (e != hipSuccess) return hip_fail(e, "tune memset");
+  hipEvent_t a, b;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "tune event");
+  if ((e = hipEventCreate(&b)) != hipSuccess) { hipEventDestroy(a); return hip_fail(e, "tune event"); }
+  int rc = IFFD_OK;
+  for (int k = 0; k < 2 * P.d - 1 && rc == IFFD_OK; ++k) {
+    float best = 1e30f;
+    int best_v = P.variant[k];
+    for (int v = 0; v < 2 && rc == IFFD_OK; ++v) {
+      P.variant[k] = v;
+      for (int w = 0; w < 2; ++w) launch_iffd_pass(P, k, r, z, 1, ws, nullptr, 0, s);
+      hipEventRecord(a, s);
+      for (int i = 0; i < reps; ++i) e = launch_iffd_pass(P, k, r, z, 1, ws, nullptr, 0, s);
+      hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) { rc = hip_fail(e, "tune launch"); break; }
+      if (ms < best) { best = ms; best_v = v; }
+    }
+    P.variant[k] = best_v;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return rc;
+}
+
+int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs, void* d_ws,
+                     size_t ws_bytes, void* stream) {
   if (!plan || !d_x || !d_y) return fail(IFFD_E_INVAL, "null argument");
   const Plan& P = plan->P;
   if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
   if (nrhs < 1 || nrhs > P.max_rhs) return fail(IFFD_E_INVAL, "nrhs out of range");
   if ((const void*)d_x == (const void*)d_y) return fail(IFFD_E_INVAL, "x and y must not alias");
-  hipError_t e = launch_matvec(P, d_x, d_y, nrhs, nullptr, 0, nullptr, 0, (hipStream_t)stream);
+  const size_t need = matvec_ws_bytes(P, nrhs);
+  if (need && (!d_ws || ws_bytes < need)) return fail(IFFD_E_WORKSPACE, "matvec workspace too small");
+  hipError_t e = launch_matvec(P, d_x, d_y, nrhs, d_ws, nullptr, 0, nullptr, 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "kron_matvec launch");
   return IFFD_OK;
 }
@@ -384,7 +486,7 @@ int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nr
   double* part = (double*)(st + L.part);
   hipError_t e = hipMemcpyAsync(d_u, x, 8 * (size_t)P.N * nrhs, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "copy solution");
-  e = launch_matvec(P, d_u, qz, nrhs, nullptr, 0, nullptr, 0, s);
+  e = launch_matvec(P, d_u, qz, nrhs, L.mvws ? st + L.mvws : nullptr, nullptr, 0, nullptr, 0, s);
   if (e == hipSuccess) e = residual_norms_dev(P, d_f, qz, r, part, nrhs, s);
   if (e != hipSuccess) return hip_fail(e, "true residual");
   const int nb = pcg_blocks(P);

@@ -1,0 +1,505 @@
+#pragma once
+// IFFD line passes on gfx950 (kernel templates; instantiated per FFT length
+// in apply_l*.hip, dispatched in apply.hip).
+//
+// The preconditioner of eq:preconditioner is applied mode-wise: for every
+// direction k, each line of the coefficient tensor along k is transformed by
+// Qt_k^T (forward), the tensor is divided by the Kronecker sum of the
+// eigenvalues, and every line is transformed back by Qt_k (backward).  With
+// Qt = [V_reg U Dt^{-1}, V_out Q_out] (Sections 4 and 6) one line transform is
+//   forward   y_reg = U^T fold(x),          y_out = Vt x
+//   backward  x = unfold(U y_reg) + Vt^T y_out
+// where fold = V_reg^T (the p-1 boundary entries at each end collapse to
+// floor(p/2) values through the special-basis blocks, interior entries pass
+// through), unfold = V_reg, U is the sine matrix of Table 1 (DST-I for odd p,
+// DST-II / DST-III for even p) and Vt = (V_out Q_out)^T is the dense
+// n_out x m outlier block.  The Dt^{-1} factors of both sides are folded into
+// the diagonal scaling: z_hat = y * prod_k s_k / sum_k lam_k with
+// s = Dt^{-2} on regular modes and 1 on outliers.
+//
+// Sine transforms by FFT: two real lines a, b are packed as a + i b into one
+// complex FFT of length L = 2n of an odd extension:
+//   DST-I  (n-1 values g):  z = [0, g, 0, -reverse(g)],  X_a = -Im C / 2,
+//          X_b = Re C / 2 at indices 1..n-1;
+//   DST-II (n values):      z = [g, -reverse(g)], W = e^{-i pi k/(2n)} C,
+//          X_a = -Im W / 2, X_b = Re W / 2 at 1..n;
+//   DST-III (n values c, full weight on c_n): with wbar_j = c_a,j - i c_b,j,
+//          z_j = conj(t_j) wbar_j (0<j<n), z_n = 2i wbar_n,
+//          z_{2n-j} = -t_j wbar_j, t_j = e^{-i pi j/(2n)};
+//          x_a = -Im C / 2, x_b = -Re C / 2 at 1..n.
+//
+// One workgroup owns a tile of TW lines of one right-hand side (pairs never
+// straddle two right-hand sides, so a result does not depend on the batch it
+// is computed in).  The tile is staged through LDS with coalesced loads (lines
+// along direction 1 are contiguous; lines along a strided direction are taken
+// TW at a time from consecutive positions of the faster directions, so each
+// row of the tile is one contiguous run), transformed in registers and LDS,
+// and written back the same way.  Passes along strided directions work in
+// place.
+#include "fft_device.h"
+#include "launch.h"
+
+namespace iffd {
+
+template <typename T>
+struct Tabs {
+  const T* blob;  // twl | twp | Vt | V0 | V1 | lam | s, element offsets below
+  int o_twl, o_twp, o_vt, o_v0, o_v1, o_lam, o_s, len;
+};
+
+struct Geom {
+  int m, n, p, n_reg, n_out, half, nbd, c0;
+  int S;       // element stride along the axis
+  int lpr;     // lines per right-hand side
+  int tpr;     // tiles per right-hand side
+  int N;       // elements per right-hand side
+  int d;
+  const double* active;  // per-RHS flags or null
+  int active_stride;
+};
+
+template <typename T, int L, int V>
+struct Cfg {
+  static constexpr int E = FftPlan<L, V>::E;
+  static constexpr int NT = L / E;
+  static constexpr int CAP = (sizeof(T) == 8 ? 128 : 256) / NT;
+  static constexpr int FPW = CAP >= 32 ? 32 : (CAP < 1 ? 1 : CAP);
+  static constexpr int TW = 2 * FPW;
+  static constexpr int NTH = FPW * NT;
+};
+
+__host__ __device__ inline size_t up16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct LdsMap {
+  size_t x, blob, g, co, lo, so, lb, dm, total;
+};
+
+template <typename T, int L, int V>
+__host__ __device__ inline LdsMap lds_map(int m, int n, int n_out, int half, int p, int blen) {
+  using C = Cfg<T, L, V>;
+  const int MP = m | 1;
+  size_t xs = (size_t)C::TW * MP;
+  size_t fs = (size_t)C::FPW * fft_region<L>() * 2;
+  LdsMap r;
+  size_t off = 0;
+  r.x = off;   off = up16(off + sizeof(T) * (xs > fs ? xs : fs));
+  r.blob = off; off = up16(off + sizeof(T) * blen);
+  r.g = off;   off = up16(off + sizeof(T) * C::TW * 2 * (p > 1 ? p - 1 : 1));
+  r.co = off;  off = up16(off + sizeof(T) * C::TW * (n_out > 0 ? n_out : 1));
+  r.lo = off;  off = up16(off + sizeof(T) * C::TW);
+  r.so = off;  off = up16(off + sizeof(T) * C::TW);
+  r.lb = off;  off = up16(off + sizeof(int) * C::TW);
+  r.dm = off;  off = up16(off + sizeof(T) * 2 * C::NTH);
+  r.total = off;
+  return r;
+}
+
+// copy a small table from global memory to LDS with several loads in flight
+template <typename T>
+__device__ __forceinline__ void to_lds(T* dst, const T* src, int count, int t, int nth) {
+  for (int e0 = t; e0 < count; e0 += 4 * nth) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nth;
+      v[u] = e < count ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nth;
+      if (e < count) dst[e] = v[u];
+    }
+  }
+}
+
+template <int V>
+constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
+
+// Tile layout in LDS: row l of X holds line l (m entries, row stride MP).
+// The folded sequence g = V_reg^T x (n_reg entries) is kept in place at
+// X[l][c0 + idx], c0 = p-1-floor(p/2): interior entries of x already sit
+// there, and the floor(p/2) folded values of each end land inside that end's
+// p-1 boundary slots.  So every FFT input is one branch-free LDS read.  The
+// same holds backwards: U c is written to X[l][c0 + idx] and the p-1 boundary
+// values of each end are then unfolded in place.
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V>
+__global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
+line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
+  using C = Cfg<T, L, V>;
+  constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
+  constexpr int LTW = ilog2<TW>();
+  // contiguous lines (direction 1): RW lanes walk one line, NG lines at once
+  constexpr int RW = NTH < 64 ? NTH : 64;
+  constexpr int NG = NTH / RW;
+  constexpr int UMAX = (264 + RW - 1) / RW;  // m <= 264
+  constexpr int CH = 8;                       // loads in flight per thread
+  extern __shared__ __align__(16) char smem[];
+  const int m = g.m, n = g.n, n_reg = g.n_reg, n_out = g.n_out, half = g.half;
+  const int MP = m | 1;
+  const LdsMap mp = lds_map<T, L, V>(m, n, n_out, half, g.p, tb.len);
+  T* X = reinterpret_cast<T*>(smem + mp.x);
+  cpx<T>* F = reinterpret_cast<cpx<T>*>(smem + mp.x);  // aliases X
+  T* BL = reinterpret_cast<T*>(smem + mp.blob);
+  cpx<T>* twl = reinterpret_cast<cpx<T>*>(BL + tb.o_twl);
+  cpx<T>* twp = reinterpret_cast<cpx<T>*>(BL + tb.o_twp);
+  T* GB = reinterpret_cast<T*>(smem + mp.g);  // per-line boundary values
+  T* CO = reinterpret_cast<T*>(smem + mp.co);
+  T* LO = reinterpret_cast<T*>(smem + mp.lo);
+  T* SO = reinterpret_cast<T*>(smem + mp.so);
+  int* LB = reinterpret_cast<int*>(smem + mp.lb);
+  T* VT = BL + tb.o_vt;
+  T* V0 = BL + tb.o_v0;
+  T* V1 = BL + tb.o_v1;
+  T* LAM = BL + tb.o_lam;
+  T* SS = BL + tb.o_s;
+  const int nbd = g.nbd;
+  T* DM = reinterpret_cast<T*>(smem + mp.dm);  // sink for discarded FFT outputs
+  const int GW = 2 * nbd;
+
+  const int t = threadIdx.x;
+  const int rhs = blockIdx.x / g.tpr;
+  const int tile = blockIdx.x - rhs * g.tpr;
+  if (g.active && g.active[(size_t)rhs * g.active_stride] == 0.0) return;
+  const int q0 = tile * TW;
+  const int nv = min(TW, g.lpr - q0);
+  const int S = g.S;
+  const int c0 = g.c0;
+  const bool odd = (g.p & 1) != 0;
+
+  // ---- tables, twiddles and per-line data into LDS ---------------------------
+  for (int l = t; l < TW; l += NTH) {
+    const int ql = q0 + l;
+    LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
+    if (MODE == PASS_MID) {
+      // spectral indices of the line in the other directions (the middle pass
+      // runs along the last direction, so the inner index holds them all)
+      T lo = T(0), so = T(1);
+      if (l < nv) {
+        const int i = ql % S;
+        const int j1 = i % m, j2 = i / m;
+        lo = tb.blob[tb.o_lam + j1];
+        so = tb.blob[tb.o_s + j1];
+        if (g.d == 3) { lo += tb.blob[tb.o_lam + j2]; so *= tb.blob[tb.o_s + j2]; }
+      }
+      LO[l] = lo;
+      SO[l] = so;
+    }
+  }
+  // issue the table loads now; they land in LDS after the tile loads are issued
+  constexpr int BCH = 16;
+  T bv[BCH];
+#pragma unroll
+  for (int u = 0; u < BCH; ++u) {
+    const int e = t + u * NTH;
+    bv[u] = e < tb.len ? tb.blob[e] : T(0);
+  }
+
+  // ---- load the tile: X[l][j] = in(line l, position j); missing lines = 0 --
+  if (S == 1) {
+    const Tin* src = in + rhs * g.N + q0 * m;  // the tile's lines are contiguous
+    const int lane = t % RW, grp = t / RW;
+    for (int l0 = grp; l0 < TW; l0 += 2 * NG) {
+      Tin v[2][UMAX];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int l = l0 + a * NG;
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u) {
+          const int j = lane + RW * u;
+          v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int l = l0 + a * NG;
+        if (l < TW) {
+#pragma unroll
+          for (int u = 0; u < UMAX; ++u) {
+            const int j = lane + RW * u;
+            if (j < m) X[l * MP + j] = (T)v[a][u];
+          }
+        }
+      }
+    }
+  } else {
+    __syncthreads();  // LB
+    const int cnt = TW * m;
+    for (int e0 = t; e0 < cnt; e0 += NTH * CH) {
+      Tin v[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * NTH;
+        const int l = e & (TW - 1), j = e >> LTW;
+        v[u] = (e < cnt && l < nv) ? in[LB[l] + j * S] : Tin(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * NTH;
+        const int l = e & (TW - 1), j = e >> LTW;
+        if (e < cnt) X[l * MP + j] = (T)v[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < BCH; ++u) {
+    const int e = t + u * NTH;
+    if (e < tb.len) BL[e] = bv[u];
+  }
+  for (int e = t + BCH * NTH; e < tb.len; e += NTH) BL[e] = tb.blob[e];
+  __syncthreads();
+
+  // Kronecker-sum scaling of spectral entry j of line l (middle pass)
+  auto fac = [&](int l, int j) -> T { return SS[j] * SO[l] / (LAM[j] + LO[l]); };
+
+  const int f = t / NT, tid = t - (t / NT) * NT;
+  const int la = 2 * f, lb = 2 * f + 1;
+  cpx<T>* buf = F + f * fft_region<L>();
+  T* Xa = X + la * MP;
+  T* Xb = X + lb * MP;
+  T* Ga = Xa + c0;  // g (or U c) of line a
+  T* Gb = Xb + c0;
+  T* dmy = DM + 2 * t;
+
+  if (MODE == PASS_FWD || MODE == PASS_MID) {
+    // ---- outlier dots; boundary fold into the g slots ----------------------
+    if (n_out > 0) {
+      const int ndots = TW * n_out;
+      int tpd = 1;
+      while (tpd < 64 && ndots * tpd * 2 <= NTH) tpd *= 2;
+      const int sub = t % tpd;
+      for (int di = t / tpd; di < (ndots + (NTH / tpd) - 1) / (NTH / tpd) * (NTH / tpd);
+           di += NTH / tpd) {
+        T acc = T(0);
+        const int l = di % TW, q = di / TW;
+        if (di < ndots) {
+          const T* vr = VT + q * m;
+          const T* xr = X + l * MP;
+          for (int j = sub; j < m; j += tpd) acc += vr[j] * xr[j];
+        }
+        for (int o = 1; o < tpd; o <<= 1) acc += __shfl_xor(acc, o);
+        if (sub == 0 && di < ndots)
+          CO[l * n_out + q] = (MODE == PASS_MID) ? acc * fac(l, n_reg + q) : acc;
+      }
+    }
+    for (int e = t; e < TW * 2 * half; e += NTH) {
+      const int l = e % TW, c = e / TW;
+      T acc = T(0);
+      if (c < half) {
+        for (int r = 0; r < nbd; ++r) acc += V0[r * half + c] * X[l * MP + r];
+      } else {
+        for (int r = 0; r < nbd; ++r) acc += V1[r * half + (c - half)] * X[l * MP + m - nbd + r];
+      }
+      GB[l * GW + c] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < TW * 2 * half; e += NTH) {
+      const int l = e % TW, c = e / TW;
+      const int pos = c < half ? c0 + c : m - nbd + (c - half);
+      X[l * MP + pos] = GB[l * GW + c];
+    }
+    __syncthreads();
+
+    // ---- forward transform: X[l][0..n_reg) = U^T g_l (scaled in the middle) --
+    auto ld = [&](int k) -> cpx<T> {
+      const bool lo = k < n;
+      int idx;
+      if (odd) idx = lo ? k - 1 : 2 * n - k - 1;   // k = 0, n give 0 (below)
+      else idx = lo ? k : 2 * n - 1 - k;
+      idx = idx < 0 ? 0 : idx;
+      T a = Ga[idx], b = Gb[idx];
+      const T sg = lo ? T(1) : T(-1);
+      const bool zero = odd && (k == 0 || k == n);
+      a = zero ? T(0) : sg * a;
+      b = zero ? T(0) : sg * b;
+      return {a, b};
+    };
+    auto st = [&](int k, cpx<T> v) {
+      const bool ok = k >= 1 && k <= n_reg;
+      const int j = ok ? k - 1 : 0;
+      if (!odd) v = c_mul(v, twp[k <= n ? k : n]);
+      T a = T(-0.5) * v.y, b = T(0.5) * v.x;
+      if (MODE == PASS_MID) {  // scaling fused into the transform output
+        a *= fac(la, j);
+        b *= fac(lb, j);
+      }
+      *(ok ? Xa + j : dmy) = a;
+      *(ok ? Xb + j : dmy + 1) = b;
+    };
+    fft_forward<T, L, V>(buf, tid, twl, ld, st);
+    __syncthreads();
+    if (MODE == PASS_FWD) {
+      for (int e = t; e < TW * n_out; e += NTH) {
+        const int l = e / n_out, q = e - (e / n_out) * n_out;
+        X[l * MP + n_reg + q] = CO[e];
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int e = t; e < TW * n_out; e += NTH) {
+      const int l = e / n_out, q = e - (e / n_out) * n_out;
+      CO[e] = X[l * MP + n_reg + q];
+    }
+  }
+
+  if (MODE == PASS_BWD || MODE == PASS_MID) {
+    // ---- backward transform: X[l][c0 + idx] = (U c_l)[idx] -------------------
+    auto ld = [&](int k) -> cpx<T> {
+      if (odd) {
+        const bool lo = k < n;
+        int idx = lo ? k - 1 : 2 * n - k - 1;
+        idx = idx < 0 ? 0 : idx;
+        const T sg = lo ? T(1) : T(-1);
+        const bool zero = (k == 0 || k == n);
+        return {zero ? T(0) : sg * Xa[idx], zero ? T(0) : sg * Xb[idx]};
+      }
+      // DST-III by the anti-Hermitian extension of wbar = c_a - i c_b
+      int j = k <= n ? k : 2 * n - k;
+      const bool zero = j == 0;
+      j = zero ? 1 : j;
+      const cpx<T> wb = {Xa[j - 1], -Xb[j - 1]};
+      const cpx<T> tw = twp[j];
+      cpx<T> z;
+      if (k <= n) {
+        z = c_mul(wb, cpx<T>{tw.x, -tw.y});
+        const T s2 = k == n ? T(2) : T(1);
+        z = {s2 * z.x, s2 * z.y};
+      } else {
+        const cpx<T> u = c_mul(wb, tw);
+        z = {-u.x, -u.y};
+      }
+      return zero ? cpx<T>{T(0), T(0)} : z;
+    };
+    auto st = [&](int k, cpx<T> v) {
+      const bool ok = k >= 1 && k <= n_reg;
+      const int j = ok ? k - 1 : 0;
+      *(ok ? Ga + j : dmy) = T(-0.5) * v.y;
+      *(ok ? Gb + j : dmy + 1) = odd ? T(0.5) * v.x : T(-0.5) * v.x;
+    };
+    fft_forward<T, L, V>(buf, tid, twl, ld, st);
+    __syncthreads();
+    // ---- unfold the ends in place: x = V_reg,0 g_left, V_reg,1 g_right --------
+    for (int e = t; e < TW * 2 * nbd; e += NTH) {
+      const int l = e % TW, r = e / TW;
+      const T* gl = X + l * MP;
+      T acc = T(0);
+      if (r < nbd) {
+        for (int c = 0; c < half; ++c) acc += V0[r * half + c] * gl[c0 + c];
+      } else {
+        const int rr = r - nbd;
+        for (int c = 0; c < half; ++c) acc += V1[rr * half + c] * gl[m - nbd + c];
+      }
+      GB[l * GW + r] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < TW * 2 * nbd; e += NTH) {
+      const int l = e % TW, r = e / TW;
+      const int pos = r < nbd ? r : m - nbd + (r - nbd);
+      X[l * MP + pos] = GB[l * GW + r];
+    }
+    __syncthreads();
+  }
+
+  // ---- store: the tile row, plus the outlier block after the backward pass --
+  auto value = [&](int l, int j) -> T {
+    T v = X[l * MP + j];
+    if (MODE != PASS_FWD)
+      for (int q = 0; q < n_out; ++q) v += VT[q * m + j] * CO[l * n_out + q];
+    return v;
+  };
+  if (S == 1) {
+    Tout* dst = out + rhs * g.N + q0 * m;
+    const int lane = t % RW, grp = t / RW;
+    for (int l = grp; l < nv; l += NG) {
+#pragma unroll
+      for (int u = 0; u < UMAX; ++u) {
+        const int j = lane + RW * u;
+        if (j < m) dst[l * m + j] = (Tout)value(l, j);
+      }
+    }
+  } else {
+    const int cnt = TW * m;
+    for (int e0 = t; e0 < cnt; e0 += NTH * CH) {
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * NTH;
+        const int l = e & (TW - 1), j = e >> LTW;
+        if (e < cnt && l < nv) out[LB[l] + j * S] = (Tout)value(l, j);
+      }
+    }
+  }
+}
+
+template <typename T>
+static Tabs<T> tables_of(const Plan& P) {
+  const char* b = P.d_tables + (sizeof(T) == 8 ? P.lay.blob64 : P.lay.blob32);
+  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s,
+          P.blob_len};
+}
+
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V>
+static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, int nrhs,
+                           const double* active, int astride, hipStream_t s) {
+  using C = Cfg<T, L, V>;
+  Geom g;
+  g.m = P.m; g.n = P.n; g.p = P.p; g.n_reg = P.n_reg; g.n_out = P.n_out; g.half = P.half;
+  g.nbd = P.p - 1; g.c0 = P.p - 1 - P.half;
+  int S = 1;
+  for (int k = 1; k < axis; ++k) S *= P.m;
+  g.S = S;
+  g.N = (int)P.N;
+  g.lpr = (int)(P.N / P.m);
+  g.tpr = (g.lpr + C::TW - 1) / C::TW;
+  g.d = P.d;
+  g.active = active;
+  g.active_stride = astride;
+  const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, P.blob_len);
+  static bool attr_set = false;
+  if (mp.total > 65536 && !attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
+  hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V>), grid, block, mp.total, s,
+                     (const Tin*)in, (Tout*)out, g, tables_of<T>(P));
+  return hipGetLastError();
+}
+
+template <typename Tin, typename Tout, typename T, int MODE, int L>
+static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
+                             const double* a, int as, hipStream_t s) {
+  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0>(P, axis, in, out, nrhs, a, as, s);
+  return launch_t<Tin, Tout, T, MODE, L, 1>(P, axis, in, out, nrhs, a, as, s);
+}
+
+// all modes, element types and variants of the line pass for one FFT length
+template <int L>
+hipError_t line_pass_for_L(const Plan& P, int mode, int var, int axis, int tin, const void* in,
+                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s) {
+  if (P.prec == IFFD_PREC_F64) {
+    if (tin != ELEM_F64 || tout != ELEM_F64) return hipErrorInvalidValue;
+    if (mode == PASS_FWD)
+      return by_variant<double, double, double, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+    if (mode == PASS_BWD)
+      return by_variant<double, double, double, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+    return by_variant<double, double, double, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s);
+  }
+  if (mode == PASS_FWD) {
+    if (tin == ELEM_F64 && tout == ELEM_F32)
+      return by_variant<double, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return by_variant<float, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+  } else if (mode == PASS_BWD) {
+    if (tin == ELEM_F32 && tout == ELEM_F64)
+      return by_variant<float, double, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return by_variant<float, float, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+  } else {
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return by_variant<float, float, float, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace iffd

@@ -1,0 +1,11 @@
+// Instantiations of the IFFD line pass for FFT lengths 256.
+#include "apply_impl.h"
+
+namespace iffd {
+
+hipError_t line_pass_L256(const Plan& P, int mode, int var, int axis, int tin, const void* in,
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s) {
+  return line_pass_for_L<256>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
+}
+
+}  // namespace iffd

@@ -124,25 +124,40 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
   else static_assert(R == 2, "unsupported radix");
 }
 
-// ---- radix plans per FFT length (E elements per thread) ------------------
+// ---- radix plans per FFT length ------------------------------------------
+// Variant V = 0 holds E = 16 (or 24) elements per thread, V = 1 holds 8 (or
+// 12): twice the threads per transform and one more stage, which raises the
+// number of waves in flight for small problems.
 
-template <int L> struct FftPlan;
-template <> struct FftPlan<16>  { static constexpr int E = 16; };
-template <> struct FftPlan<24>  { static constexpr int E = 24; };
-template <> struct FftPlan<32>  { static constexpr int E = 16; };
-template <> struct FftPlan<48>  { static constexpr int E = 12; };
-template <> struct FftPlan<64>  { static constexpr int E = 16; };
-template <> struct FftPlan<96>  { static constexpr int E = 24; };
-template <> struct FftPlan<128> { static constexpr int E = 16; };
-template <> struct FftPlan<192> { static constexpr int E = 24; };
-template <> struct FftPlan<256> { static constexpr int E = 16; };
-template <> struct FftPlan<384> { static constexpr int E = 24; };
-template <> struct FftPlan<512> { static constexpr int E = 16; };
+template <int L, int V> struct FftPlan;
+template <> struct FftPlan<16, 0>  { static constexpr int E = 16; };
+template <> struct FftPlan<24, 0>  { static constexpr int E = 24; };
+template <> struct FftPlan<32, 0>  { static constexpr int E = 16; };
+template <> struct FftPlan<48, 0>  { static constexpr int E = 12; };
+template <> struct FftPlan<64, 0>  { static constexpr int E = 16; };
+template <> struct FftPlan<96, 0>  { static constexpr int E = 24; };
+template <> struct FftPlan<128, 0> { static constexpr int E = 16; };
+template <> struct FftPlan<192, 0> { static constexpr int E = 24; };
+template <> struct FftPlan<256, 0> { static constexpr int E = 16; };
+template <> struct FftPlan<384, 0> { static constexpr int E = 24; };
+template <> struct FftPlan<512, 0> { static constexpr int E = 16; };
+template <> struct FftPlan<16, 1>  { static constexpr int E = 8; };
+template <> struct FftPlan<24, 1>  { static constexpr int E = 12; };
+template <> struct FftPlan<32, 1>  { static constexpr int E = 8; };
+template <> struct FftPlan<48, 1>  { static constexpr int E = 12; };
+template <> struct FftPlan<64, 1>  { static constexpr int E = 8; };
+template <> struct FftPlan<96, 1>  { static constexpr int E = 12; };
+template <> struct FftPlan<128, 1> { static constexpr int E = 8; };
+template <> struct FftPlan<192, 1> { static constexpr int E = 12; };
+template <> struct FftPlan<256, 1> { static constexpr int E = 8; };
+template <> struct FftPlan<384, 1> { static constexpr int E = 12; };
+template <> struct FftPlan<512, 1> { static constexpr int E = 8; };
 
 // padded LDS index of FFT element k: one spare slot every 16 entries keeps
-// the strided Stockham writes off a single bank
+// the strided Stockham writes off a single bank; the regions of consecutive
+// transforms are staggered by 8 elements so they start on different banks
 __device__ __forceinline__ int fpad(int k) { return k + (k >> 4); }
-template <int L> constexpr int fft_region() { return L + L / 16; }
+template <int L> constexpr int fft_region() { return L + L / 16 + 8; }
 
 // One Stockham stage.  FIRST: inputs come from ld(k) instead of LDS;
 // LAST: outputs go to st(k, v) instead of LDS.  Every stage ends its reads
@@ -195,24 +210,38 @@ struct FftRun {
   }
 };
 
-// forward FFT of length L over NT threads; ld(k) supplies input k, st(k, v)
-// receives output k (natural order).  buf: this transform's LDS region of
-// fft_region<L>() elements.  All threads of the block must call it.
-template <typename T, int L, class LD, class ST>
+// forward FFT of length L over NT = L/E threads; ld(k) supplies input k,
+// st(k, v) receives output k (natural order).  buf: this transform's LDS
+// region of fft_region<L>() elements.  All threads of the block must call it.
+template <typename T, int L, int V, class LD, class ST>
 __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* tw, LD& ld,
                                             ST& st) {
-  constexpr int E = FftPlan<L>::E, NT = L / E;
-  if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 16>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 24) FftRun<T, 24, E, NT, 1, 8, 3>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 16, 2>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 48) FftRun<T, 48, E, NT, 1, 4, 4, 3>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 64) FftRun<T, 64, E, NT, 1, 16, 4>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 96) FftRun<T, 96, E, NT, 1, 8, 4, 3>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 8, 8, 2, 3>::run(buf, tid, tw, ld, st);
-  else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 16, 16, 2>::run(buf, tid, tw, ld, st);
+  constexpr int E = FftPlan<L, V>::E, NT = L / E;
+  if constexpr (V == 0) {
+    if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 16>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 24) FftRun<T, 24, E, NT, 1, 8, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 16, 2>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 48) FftRun<T, 48, E, NT, 1, 4, 4, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 64) FftRun<T, 64, E, NT, 1, 16, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 96) FftRun<T, 96, E, NT, 1, 8, 4, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 8, 8, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 16, 16, 2>::run(buf, tid, tw, ld, st);
+  } else {
+    if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 8, 2>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 24) FftRun<T, 24, E, NT, 1, 4, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 8, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 48) FftRun<T, 48, E, NT, 1, 4, 4, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 64) FftRun<T, 64, E, NT, 1, 8, 8>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 96) FftRun<T, 96, E, NT, 1, 4, 4, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 8, 4, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 4, 4, 4, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 8, 8, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 4, 4, 4, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 8, 8, 8>::run(buf, tid, tw, ld, st);
+  }
 }
 
 }  // namespace iffd

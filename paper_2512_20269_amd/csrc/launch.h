@@ -21,6 +21,10 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                              const double* active, int active_stride, hipStream_t s);
 
+// One pass of the IFFD apply (0 .. 2d-2), see iffd_apply_pass.
+hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
+                            void* ws, const double* active, int active_stride, hipStream_t s);
+
 // Dense FD apply (MFMA mode products).
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                            const double* active, int active_stride, hipStream_t s);
@@ -28,8 +32,10 @@ hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, 
 // Outlier pencil eigensolve + table completion (FP64, on device).
 hipError_t launch_setup_outliers(const Plan& P, hipStream_t s);
 
-// y = Ahat x; optional fused partial dot sums part[b][blk] = sum p.y over a block.
-hipError_t launch_matvec(const Plan& P, const double* x, double* y, int nrhs, double* part,
-                         int npart, const double* active, int active_stride, hipStream_t s);
+// y = Ahat x; ws: matvec_ws_bytes(P, nrhs); optional fused partial dot sums
+// part[b][blk] = sum x.y over a workgroup.
+hipError_t launch_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
+                         double* part, int npart, const double* active, int active_stride,
+                         hipStream_t s);
 
 }  // namespace iffd

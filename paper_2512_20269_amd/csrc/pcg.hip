@@ -61,23 +61,40 @@ dot_partials(const double* __restrict__ a, const double* __restrict__ b, int N, 
   if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
 }
 
-// sum of a slot's partials in index order
-__device__ __forceinline__ double psum(const double* part, int nblk, int slot) {
-  const double* p = part + (size_t)slot * nblk;
+// Sum of a slot's partials, computed by one block of VT threads in a fixed
+// order (thread i adds entries i, i+VT, ... in turn; then a fixed butterfly
+// across lanes and waves), so the result does not depend on the batch.  The
+// total is returned in every thread.
+__device__ __forceinline__ double block_psum(const double* __restrict__ p, int n, double* red) {
   double s = 0.0;
-  for (int i = 0; i < nblk; ++i) s += p[i];
-  return s;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * VT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * VT;
+      v[u] = i < n ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < VT / 64; ++w) tot += red[w];
+  __syncthreads();
+  return tot;
 }
 
-// one thread per slot: pq = sum of partials; alpha = rz / pq; breakdown test
-__global__ void pcg_alpha(double* scal, const double* part, int npart_used, int npart, int nslots) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
+// one block per slot: pq = sum of partials; alpha = rz / pq; breakdown test
+__global__ void __launch_bounds__(VT)
+pcg_alpha(double* scal, const double* part, int npart_used, int npart, int nslots) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_ACTIVE] == 0.0) return;
-  const double* pp = part + (size_t)slot * npart;
-  double pq = 0.0;
-  for (int i = 0; i < npart_used; ++i) pq += pp[i];
+  const double pq = block_psum(part + (size_t)slot * npart, npart_used, red);
+  if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT];
   const double rz = sc[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(rz > 0.0) || !isfinite(pq) || !isfinite(rz)) {
@@ -112,13 +129,15 @@ pcg_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __re
   if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
 }
 
-// one thread per slot: iteration count, residual test, history
-__global__ void pcg_check(double* scal, double* hist, const double* part, int nblk, int nslots) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
+// one block per slot: iteration count, residual test, history
+__global__ void __launch_bounds__(VT)
+pcg_check(double* scal, double* hist, const double* part, int nblk, int nslots) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_ACTIVE] == 0.0) return;
-  const double rr = psum(part, nblk, slot);
+  const double rr = block_psum(part + (size_t)slot * nblk, nblk, red);
+  if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT] + 1;
   sc[S_IT] = it;
   if (it - 1 < kHist) hist[((size_t)slot * kHist + it - 1) * 2] = sc[S_ALPHA];
@@ -137,13 +156,15 @@ __global__ void pcg_check(double* scal, double* hist, const double* part, int nb
   }
 }
 
-// one thread per slot: rz' = sum of partials, beta = rz'/rz
-__global__ void pcg_beta(double* scal, double* hist, const double* part, int nblk, int nslots) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
+// one block per slot: rz' = sum of partials, beta = rz'/rz
+__global__ void __launch_bounds__(VT)
+pcg_beta(double* scal, double* hist, const double* part, int nblk, int nslots) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_ACTIVE] == 0.0) return;
-  const double rzn = psum(part, nblk, slot);
+  const double rzn = block_psum(part + (size_t)slot * nblk, nblk, red);
+  if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT];  // already counts this iteration
   const double rzo = sc[S_RZ0 + ((it - 1) & 1)];
   if (!(rzn > 0.0) || !isfinite(rzn)) {
@@ -193,15 +214,16 @@ pcg_begin_copy(double* __restrict__ x, double* __restrict__ r, const double* __r
   if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
 }
 
-// begin scalars (one thread per started slot)
-__global__ void pcg_begin_scal(double* scal, const double* part, int nblk, BeginSlots slots,
-                               double rtol, int maxit) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= slots.count) return;
-  const int slot = slots.slot[k];
+// begin scalars (one block per started slot)
+__global__ void __launch_bounds__(VT)
+pcg_begin_scal(double* scal, const double* part, int nblk, BeginSlots slots, double rtol,
+               int maxit) {
+  __shared__ double red[VT / 64];
+  const int slot = slots.slot[blockIdx.x];
   double* sc = scal + (size_t)slot * kScal;
+  const double ff = block_psum(part + (size_t)slot * nblk, nblk, red);
+  if (threadIdx.x != 0) return;
   for (int i = 0; i < kScal; ++i) sc[i] = 0.0;
-  const double ff = psum(part, nblk, slot);
   sc[S_FF] = ff;
   sc[S_TOL] = rtol;
   sc[S_MAXIT] = maxit;
@@ -230,12 +252,14 @@ pcg_begin_p(double* __restrict__ p, const double* __restrict__ z, int N, int nbl
   for (int i = lo + threadIdx.x; i < hi; i += VT) p[o + i] = z[o + i];
 }
 
-__global__ void pcg_begin_finish(double* scal, const double* part, int nblk, int nslots) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
+__global__ void __launch_bounds__(VT)
+pcg_begin_finish(double* scal, const double* part, int nblk, int nslots) {
+  __shared__ double red[VT / 64];
+  const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_NEW] == 0.0) return;
-  const double rz = psum(part, nblk, slot);
+  const double rz = block_psum(part + (size_t)slot * nblk, nblk, red);
+  if (threadIdx.x != 0) return;
   sc[S_NEW] = 0.0;
   if (!(rz > 0.0) || !isfinite(rz)) {
     sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
@@ -308,7 +332,7 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   double* p = (double*)(st + L.p);
   double* qz = (double*)(st + L.qz);
   hipLaunchKernelGGL(pcg_begin_copy, dim3(count * nb), dim3(VT), 0, s, x, r, f, bs, N, nb, part);
-  hipLaunchKernelGGL(pcg_begin_scal, dim3(1), dim3(64), 0, s, scal, part, nb, bs, rtol, maxit);
+  hipLaunchKernelGGL(pcg_begin_scal, dim3(count), dim3(VT), 0, s, scal, part, nb, bs, rtol, maxit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // z = P^{-1} r for the new slots only
@@ -319,8 +343,7 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
                      (int)S_NEW);
   hipLaunchKernelGGL(pcg_begin_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
-  hipLaunchKernelGGL(pcg_begin_finish, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, part, nb,
-                     nslots);
+  hipLaunchKernelGGL(pcg_begin_finish, dim3(nslots), dim3(VT), 0, s, scal, part, nb, nslots);
   return hipGetLastError();
 }
 
@@ -336,20 +359,21 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
   double* p = (double*)(st + L.p);
   double* qz = (double*)(st + L.qz);
   void* ws = L.ws ? st + L.ws : nullptr;
+  void* mvws = L.mvws ? st + L.mvws : nullptr;
   const int nmv = matvec_blocks(P);
   for (int it = 0; it < k; ++it) {
-    hipError_t e = launch_matvec(P, p, qz, nslots, part2, nb, scal + S_ACTIVE, kScal, s);
+    hipError_t e = launch_matvec(P, p, qz, nslots, mvws, part2, nb, scal + S_ACTIVE, kScal, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pcg_alpha, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, part2, nmv, nb, nslots);
+    hipLaunchKernelGGL(pcg_alpha, dim3(nslots), dim3(VT), 0, s, scal, part2, nmv, nb, nslots);
     hipLaunchKernelGGL(pcg_update_xr, dim3(nslots * nb), dim3(VT), 0, s, x, r, p, qz, N, nb, scal, part);
-    hipLaunchKernelGGL(pcg_check, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, hist, part, nb, nslots);
+    hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nslots);
     e = (P.method == IFFD_METHOD_FFT)
             ? launch_iffd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s)
             : launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
                        (int)S_ACTIVE);
-    hipLaunchKernelGGL(pcg_beta, dim3(cdiv(nslots, 64)), dim3(64), 0, s, scal, hist, part, nb, nslots);
+    hipLaunchKernelGGL(pcg_beta, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nslots);
     hipLaunchKernelGGL(pcg_update_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

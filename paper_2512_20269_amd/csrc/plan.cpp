@@ -214,6 +214,19 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 void compute_layout(Plan& P) {
   TableLayout& t = P.lay;
+  {
+    const int nbh = (P.p - 1) * P.half;
+    int o = 0;
+    P.bo_twl = o; o += 2 * std::max(P.L, 1);
+    P.bo_twp = o; o += 2 * (P.n + 1);
+    P.bo_vt = o;  o += P.n_out * P.m;
+    P.bo_v0 = o;  o += nbh;
+    P.bo_v1 = o;  o += nbh;
+    o += o & 1;
+    P.bo_lam = o; o += P.m;
+    P.bo_s = o;   o += P.m;
+    P.blob_len = o + (o & 1);
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -250,6 +263,8 @@ void compute_layout(Plan& P) {
   t.qfd32 = take(4 * mm);
   t.qtfd32 = take(4 * mm);
   t.lamfd32 = take(4 * m);
+  t.blob64 = take(8 * (size_t)P.blob_len);
+  t.blob32 = take(4 * (size_t)P.blob_len);
   t.total = off;
 }
 
@@ -283,10 +298,13 @@ StateLayout state_layout(const Plan& P, int nslots) {
   s.qz = take((size_t)nslots * P.N * 8);
   size_t ws = apply_ws_bytes(P, nslots);
   s.ws = ws ? take(ws) : 0;
+  size_t mw = matvec_ws_bytes(P, nslots);
+  s.mvws = mw ? take(mw) : 0;
   s.total = off;
   // linear in nslots up to alignment: report a safe per-slot bound
   s.per_slot = align256(16 * 8) + align256(kHist * 16) + align256((size_t)3 * s.npart * 8) +
-               4 * align256((size_t)P.N * 8) + apply_ws_bytes(P, 1) + 8 * 256;
+               4 * align256((size_t)P.N * 8) + apply_ws_bytes(P, 1) + matvec_ws_bytes(P, 1) +
+               8 * 256;
   s.fixed = 4096;
   return s;
 }

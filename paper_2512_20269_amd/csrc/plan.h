@@ -17,6 +17,7 @@ struct TableLayout {
   size_t lam64, s64, v0_64, v1_64, vt64, twl64, twp64, kb64, mb64, ao64, bo64, vout64;
   size_t qfd64, qtfd64, lamfd64;
   size_t kc64, mc64;  // compact band tables: 2p-1 end rows each side + 1 interior row
+  size_t blob64, blob32;  // line-pass tables back to back (see Plan::bo_*)
   size_t lam32, s32, v0_32, v1_32, vt32, twl32, twp32;
   size_t qfd32, qtfd32, lamfd32;
   size_t total;
@@ -30,6 +31,7 @@ struct StateLayout {
   size_t part;      // [3][nslots][npart] FP64 partial sums
   size_t x, r, p, qz;  // [nslots][N] FP64
   size_t ws;        // preconditioner workspace [nslots][N] (FP32 apply) or 0
+  size_t mvws;      // operator workspace (3D: 2 [nslots][N] FP64) or 0
   size_t fixed, per_slot, total;
   int npart;
 };
@@ -54,6 +56,11 @@ struct Plan {
   std::vector<double> Qfd, lamfd;   // dense FD: m x m (column j = eigvec j)
   std::vector<double> Kc, Mc;       // compact band tables (crows x (2p+1))
   int nbr = 0, crows = 0;
+  // element offsets of the line-pass tables inside one contiguous blob:
+  // twl (2L) | twp (2(n+1)) | Vt (n_out m) | V0 | V1 ((p-1) floor(p/2) each) | lam (m) | s (m)
+  int bo_twl = 0, bo_twp = 0, bo_vt = 0, bo_v0 = 0, bo_v1 = 0, bo_lam = 0, bo_s = 0, blob_len = 0;
+
+  int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
 
   TableLayout lay{};
   char* d_tables = nullptr;
@@ -68,6 +75,7 @@ StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);
 int pcg_blocks(const Plan& P);  // number of partial sums per slot
 int matvec_blocks(const Plan& P);  // workgroups of the operator per right-hand side
+size_t matvec_ws_bytes(const Plan& P, int nrhs);
 
 // whether an FFT length is supported by the built kernels
 bool fft_len_supported(int L);

@@ -111,7 +111,7 @@ def test_null_and_state_errors():
     # compute entry points refuse a plan that has not been set up
     fake = ctypes.c_void_p(256)
     assert I.lib.iffd_precond_apply(h, fake, ctypes.c_void_p(512), 1, fake, 1 << 20, None) == I.E_STATE
-    assert I.lib.iffd_kron_matvec(h, fake, ctypes.c_void_p(512), 1, None) == I.E_STATE
+    assert I.lib.iffd_kron_matvec(h, fake, ctypes.c_void_p(512), 1, fake, 1 << 20, None) == I.E_STATE
     # the default options are FFT / F32 / 1 RHS
     rc, h2 = host_plan(2, 16, 3)
     h3 = ctypes.c_void_p()
