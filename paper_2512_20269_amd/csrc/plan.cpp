@@ -275,8 +275,10 @@ int pcg_blocks(const Plan& P) {
 }
 
 size_t apply_ws_bytes(const Plan& P, int nrhs) {
-  if (P.prec == IFFD_PREC_F32) return align256((size_t)4 * P.N * nrhs);
+  // FD: two FP32 buffers, or one FP64 buffer used in turn with the output;
+  // IFFD: one FP32 buffer (the FP64 apply works in place on the output)
   if (P.method == IFFD_METHOD_DENSE_FD) return align256((size_t)8 * P.N * nrhs);
+  if (P.prec == IFFD_PREC_F32) return align256((size_t)4 * P.N * nrhs);
   return 0;
 }
 

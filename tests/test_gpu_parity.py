@@ -242,3 +242,24 @@ def test_fft_variants_and_tuner(d, n, p):
         chosen = pl.tune(reps=3)
         assert len(chosen) == 2 * d - 1 and set(chosen) <= {0, 1}
         assert rel(host(pl.apply(dev(r))), zo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("d,n,p", [(2, 16, 3), (2, 33, 4), (2, 64, 1), (3, 12, 3), (3, 17, 5),
+                                   (3, 24, 2)])
+def test_dense_fd_is_direct_solver(d, n, p):
+    """Dense FD on the matrix cores: z = Ahat^{-1} r (Section 3)."""
+    r = workloads.uniform_rhs(d, n, p, seed=9)
+    zo = oracle(d, n, p, "fd").apply(r)
+    for prec, tol in (("f64", 1e-11), ("f32", 1e-4)):
+        pl = plan(d, n, p, prec, "dense")
+        z = host(pl.apply(dev(r)))
+        assert rel(z, zo) <= tol
+        back = host(pl.matvec(dev(z)))
+        assert rel(back, r) <= (1e-10 if prec == "f64" else 1e-4)
+
+
+def test_dense_fd_pcg_one_iteration():
+    d, n, p = 3, 16, 3
+    f = workloads.uniform_rhs(d, n, p, seed=3)
+    u, st = plan(d, n, p, "f64", "dense").solve(dev(f), rtol=1e-8)
+    assert st[0]["converged"] and st[0]["iterations"] == 1
