@@ -1,25 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the IFFD preconditioner apply on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision f32|f64]
 
 A step is one application z = P^{-1} r of the FFT-based Fast Diagonalization
 preconditioner (forward line transforms along every direction, Kronecker-sum
-scaling, backward transforms) to one right-hand side already resident in
-HBM, in the default workload: 3D unit cube, n = 128 elements per direction,
-degree p = 3 (2,146,689 DoFs), FP32 transform arithmetic with FP64 input and
-output.  The K timed steps are replays of a HIP graph holding one apply.
+scaling, backward transforms) to the workload's right-hand sides, already
+resident in HBM.  Default workload: 3D unit cube, n = 128 elements per
+direction, degree p = 3 (2,146,689 DoFs), FP32 transform arithmetic with FP64
+input and output.
 
-Printed as one JSON line: the apply throughput (GDoF/s) with the roofline of
-its dominant kernel (HIP events around each pass inside the timed loop), PCG
-solve latency to 1e-8 (FP64 PCG, FP32 apply), the dense-FD baseline apply, and
-the FP64 CPU oracle timed on the host cores on a bounded sample.
+The K timed steps are enqueued back to back behind a device-side spin (so the
+host never starves the GPU) with a HIP event after every pass; the events give
+both the step time and each pass kernel's average duration.  The same apply
+replayed from a HIP graph is timed as well.
+
+Printed as one JSON line: apply throughput (GDoF/s) with the roofline of its
+dominant kernel, PCG solve latency to 1e-8 (FP64 PCG, this apply), the
+dense-FD baseline (apply on the matrix cores and PCG), and the FP64 CPU oracle
+timed on the host cores on a bounded sample.
 """
 
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -30,18 +34,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 METRIC = "FFT-FD apply GDoF/s vs dense FD; PCG solves/s + p99 latency to 1e-8 rel res"
 
+# name: (d, n, p, right-hand sides, RHS recipe)
 WORKLOADS = {
-    "cube_n128_p3": (3, 128, 3),
-    "square_n64_p3": (2, 64, 3),
-    "cube_n256_p3": (3, 256, 3),
-    "cube_n96_p4": (3, 96, 4),
+    "cube_n128_p3": (3, 128, 3, 1, "uniform[-1,1] seed 2"),
+    "square_n64_p3": (2, 64, 3, 1, "uniform[-1,1] seed 1"),
+    "cube_n256_p3": (3, 256, 3, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
+    "cube_n96_p4_b64": (3, 96, 4, 64, "uniform[-1,1], seeds 4000+b"),
 }
 
 
+def make_rhs(workload):
+    import workloads
+    if workload == "cube_n256_p3":
+        return workloads.workload_rhs("cube_n256", p=3)
+    return workloads.workload_rhs(workload)
+
+
 def pass_bytes(d, N, prec):
-    """Algorithmic HBM bytes of each pass (read + write of the tensor once)."""
+    """Algorithmic HBM bytes of each pass over one right-hand side: the
+    tensor is read once and written once (FP64 at the ends of the apply,
+    the transform precision in between)."""
     w = 8 if prec == "f64" else 4
     out = []
     for k in range(2 * d - 1):
@@ -57,14 +72,6 @@ def pass_names(d):
     return names
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for f in ("apply_impl.h", "fft_device.h"):
-        with open(os.path.join(ROOT, "paper_2512_20269_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload, prec):
     """HBM bytes per dispatch measured with rocprofv3 counters, if they were
     taken on the current kernel sources (else None)."""
@@ -73,26 +80,30 @@ def load_traffic(workload, prec):
         return None
     with open(path) as fh:
         t = json.load(fh)
+    from paper_2512_20269_amd.profiling import source_hash
     if t.get("source_hash") != source_hash():
         return None
     return t
 
 
-def sleep_cycles_for(torch, ms):
-    """Cycles for torch.cuda._sleep to keep the GPU busy ~ms (lets the host
-    enqueue a timed loop ahead of the device)."""
+def sleep_cycles_per_ms(torch):
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record()
     torch.cuda._sleep(1_000_000)
     b.record()
     torch.cuda.synchronize()
-    per = max(a.elapsed_time(b), 1e-3) / 1_000_000
-    return int(ms / per)
+    return 1_000_000 / max(a.elapsed_time(b), 1e-3)
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(q * len(xs)))]
 
 
 def cpu_baseline(d, n, p, r_np, budget_s=12.0):
-    """The FP64 oracle (dense mode products) on the host cores."""
+    """The FP64 oracle (dense O(m^2)-per-line mode products) on the host cores,
+    applied to the first right-hand side."""
     from threadpoolctl import threadpool_info
     from oracle import iffd as O
     pre = O.Preconditioner(d, n, p, "iffd_b")
@@ -108,9 +119,21 @@ def cpu_baseline(d, n, p, r_np, budget_s=12.0):
     N = r_np.size
     return {"value": round(N / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} FP64 oracle applies (dense O(m^2)-per-line mode products, "
-                      f"structured route) of the same {d}D n={n} p={p} right-hand side; "
-                      f"{dt * 1e3:.1f} ms per apply"}
+            "sample": f"{reps} FP64 oracle applies (structured route, dense mode products) "
+                      f"of one {d}D n={n} p={p} right-hand side; {dt * 1e3:.1f} ms per apply; "
+                      f"host nproc={os.cpu_count()}"}
+
+
+def time_solves(torch, plan, f, count, rtol=1e-8):
+    u, st = plan.solve(f, rtol=rtol)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(count):
+        t0 = time.perf_counter()
+        u, st = plan.solve(f, rtol=rtol, out=u)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    return lat, st
 
 
 def main():
@@ -124,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed apply loop (for profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB with a plain elementwise kernel "
+                         "(reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, no collectives); "
@@ -134,27 +160,41 @@ def main():
     import torch
 
     import paper_2512_20269_amd as iffd
-    import workloads
 
-    d, n, p = WORKLOADS[args.workload]
+    d, n, p, B, recipe = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    if args.workload == "cube_n96_p4":
-        r_np = workloads.uniform_rhs(d, n, p, seed=4000)
-    elif args.workload in workloads.WORKLOADS:
-        r_np = workloads.workload_rhs(args.workload)
-    else:
-        r_np = workloads.uniform_rhs(d, n, p, seed=2)
+    r_np = make_rhs(args.workload)
     r = torch.from_numpy(r_np).cuda()
     z = torch.empty_like(r)
-    plan = iffd.Plan(d, n, p, method="fft", precision=args.precision)
+    plan = iffd.Plan(d, n, p, method="fft", precision=args.precision, max_rhs=B)
     N = plan.N
     npass = plan.n_passes()
     variants = plan.tune(reps=20)   # FFT shape per pass, timed on the device
 
-    # ---- warmup, then capture one apply in a HIP graph ----------------------
     for _ in range(max(args.warmup, 1)):
         plan.apply(r, out=z)
     torch.cuda.synchronize()
+
+    # ---- timed region: K applies, an event after every pass -------------------
+    cpm = sleep_cycles_per_ms(torch)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps * npass + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    torch.cuda._sleep(int(cpm * (5.0 + 0.03 * args.steps * npass)))
+    evs[0].record()
+    for s in range(args.steps):
+        for k in range(npass):
+            plan.apply_pass(k, r, z)
+            evs[s * npass + k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = evs[0].elapsed_time(evs[-1])
+    ms_per_step = total_ms / args.steps
+    value = B * N / (ms_per_step * 1e-3) / 1e9
+    per_pass = [statistics.mean(evs[s * npass + k].elapsed_time(evs[s * npass + k + 1])
+                                for s in range(args.steps)) for k in range(npass)]
+
+    # ---- the same apply replayed from a HIP graph ------------------------------
     cap = torch.cuda.Stream()
     cap.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -167,99 +207,106 @@ def main():
     for _ in range(args.warmup):
         g.replay()
     torch.cuda.synchronize()
-
-    # ---- timed region: K graph replays -----------------------------------------
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(int(cpm * 5.0))
+    g0.record()
     for _ in range(args.steps):
         g.replay()
-    e1.record()
+    g1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    value = N / (ms_per_step * 1e-3) / 1e9
+    graph_ms = g0.elapsed_time(g1) / args.steps
 
-    # ---- per-kernel durations: HIP events between the passes ------------------
-    cyc = sleep_cycles_for(torch, 30.0)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(npass + 1)]
-           for _ in range(args.steps)]
-    torch.cuda._sleep(cyc)  # the host enqueues the loop while the GPU is busy
-    for s in range(args.steps):
-        evs[s][0].record()
-        for k in range(npass):
-            plan.apply_pass(k, r, z)
-            evs[s][k + 1].record()
-    torch.cuda.synchronize()
-    per_pass = [statistics.mean(evs[s][k].elapsed_time(evs[s][k + 1]) for s in range(args.steps))
-                for k in range(npass)]
-    pb = pass_bytes(d, N, args.precision)
+    pb = [B * x for x in pass_bytes(d, N, args.precision)]
     names = pass_names(d)
     dom = max(range(npass), key=lambda k: per_pass[k])
     achieved = pb[dom] / (per_pass[dom] * 1e-3) / 1e9
     traffic = load_traffic(args.workload, args.precision)
-    roofline = {"bound": "hbm", "kernel": f"line_pass {names[dom]}",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic["passes"][dom] if traffic else None,
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (traffic["passes"][dom][str(variants[dom])]["bytes"]
+                            if traffic and str(variants[dom]) in traffic["passes"][dom]
+                            else None),
+                "kernel": f"line_pass {names[dom]}",
+                "alg_bytes_per_launch": pb[dom],
                 "per_pass_us": {names[k]: round(per_pass[k] * 1e3, 2) for k in range(npass)},
                 "per_pass_alg_GBs": {names[k]: round(pb[k] / (per_pass[k] * 1e-3) / 1e9, 1)
                                      for k in range(npass)},
                 "apply_alg_bytes": sum(pb),
                 "apply_alg_GBs": round(sum(pb) / (ms_per_step * 1e-3) / 1e9, 1),
-                "fft_variant_per_pass": variants}
+                "fft_len": plan.info["fft_len"], "fft_variant_per_pass": variants}
+    if traffic:
+        roofline["traffic_source"] = traffic["source"]
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": args.precision, "data": "synthetic",
-           "config": {"workload": args.workload, "d": d, "n": n, "p": p, "dofs": N,
-                      "rhs": "uniform[-1,1] seed 2", "apply_io": "f64",
-                      "step": "one preconditioner apply (HIP graph replay)"},
+           "config": {"workload": args.workload, "d": d, "n": n, "p": p, "dofs_per_rhs": N,
+                      "rhs": B, "rhs_recipe": recipe, "apply_io": "f64",
+                      "step": f"one preconditioner apply to {B} right-hand side(s)"},
+           "graph_ms_per_step": round(graph_ms, 5),
+           "graph_gdof_s": round(B * N / (graph_ms * 1e-3) / 1e9, 3),
            "wall_s_timed": round(wall, 4), "roofline": roofline}
 
     if not args.no_extras:
+        # ---- accuracy of this apply against the FP64 apply -----------------------
+        ref = iffd.Plan(d, n, p, method="fft", precision="f64", max_rhs=B)
+        z64 = ref.apply(r)
+        plan.apply(r, out=z)
+        out["apply_relerr_vs_f64"] = float((z - z64).norm() / z64.norm())
+        del ref, z64
+        f = r[0] if B > 1 else r
         # ---- PCG solves to 1e-8 (FP64 PCG, this apply) ---------------------------
-        lat, its = [], []
-        u, st = plan.solve(r, rtol=1e-8)
-        torch.cuda.synchronize()
-        for _ in range(args.solves):
-            t0 = time.perf_counter()
-            u, st = plan.solve(r, rtol=1e-8, out=u)
-            torch.cuda.synchronize()
-            lat.append((time.perf_counter() - t0) * 1e3)
-            its.append(st[0]["iterations"])
-        lat.sort()
+        lat, st = time_solves(torch, plan, f, args.solves)
         out["pcg"] = {"solves_per_s": round(1e3 / statistics.mean(lat), 2),
-                      "p50_ms": round(lat[len(lat) // 2], 3),
-                      "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
-                      "iterations": its[0], "relres_true": st[0]["relres_true"],
-                      "kappa_est": round(st[0]["kappa_est"], 4), "solves": args.solves}
-        # ---- dense FD baseline apply ---------------------------------------------
+                      "p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
+                      "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"],
+                      "kappa_est": round(st[0]["kappa_est"], 4), "solves": args.solves,
+                      "rhs": "first right-hand side of the workload"}
+        # ---- dense FD baseline: apply on the matrix cores, and PCG ---------------
         try:
-            fd = iffd.Plan(d, n, p, method="dense", precision=args.precision)
+            fd = iffd.Plan(d, n, p, method="dense", precision=args.precision, max_rhs=B)
             zf = torch.empty_like(r)
             for _ in range(5):
                 fd.apply(r, out=zf)
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            torch.cuda._sleep(int(cpm * 5.0))
             a.record()
-            for _ in range(50):
+            for _ in range(reps):
                 fd.apply(r, out=zf)
             b.record()
             torch.cuda.synchronize()
-            fms = a.elapsed_time(b) / 50
-            flops = 4 * d * fd.m ** (d + 1)
-            out["dense_fd"] = {"gdof_s": round(N / (fms * 1e-3) / 1e9, 3), "ms": round(fms, 5),
-                               "tflops": round(flops / (fms * 1e-3) / 1e12, 2),
-                               "iffd_speedup": round(fms / ms_per_step, 3)}
+            fms = a.elapsed_time(b) / reps
+            flops = B * 4 * d * fd.m ** (d + 1)
+            tf = flops / (fms * 1e-3) / 1e12
+            flat, fst = time_solves(torch, fd, f, max(5, args.solves // 3))
+            out["dense_fd"] = {
+                "gdof_s": round(B * N / (fms * 1e-3) / 1e9, 3), "ms_per_apply": round(fms, 5),
+                "roofline": {"bound": "mfma", "achieved": round(tf, 2),
+                             "peak": MFMA_PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
+                             "frac": round(tf / MFMA_PEAK_TFLOPS[args.precision], 4),
+                             "flops_per_apply": flops},
+                "iffd_apply_speedup": round(fms / ms_per_step, 3),
+                "pcg": {"solves_per_s": round(1e3 / statistics.mean(flat), 2),
+                        "p50_ms": round(pct(flat, 0.5), 3), "p99_ms": round(pct(flat, 0.99), 3),
+                        "iterations": fst[0]["iterations"]},
+                "iffd_solve_speedup": round(statistics.mean(flat) / statistics.mean(lat), 3)}
+            del fd, zf
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": nel * 8, "write": nel * 8}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, n, p, r_np)
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(d, n, p, r_np[0] if B > 1 else r_np)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
