@@ -263,6 +263,28 @@ def main():
                       "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"],
                       "kappa_est": round(st[0]["kappa_est"], 4), "solves": args.solves,
                       "rhs": "first right-hand side of the workload"}
+        if B > 1:
+            # ---- the whole batch: PCG with the iteration loop in a HIP graph ------
+            gs = iffd.GraphSolver(plan, B, k=2)
+            U, gst = gs.solve(r, rtol=1e-8)
+            torch.cuda.synchronize()
+            glat = []
+            for _ in range(max(3, args.solves // 5)):
+                t0 = time.perf_counter()
+                U, gst = gs.solve(r, rtol=1e-8, out=U)
+                torch.cuda.synchronize()
+                glat.append((time.perf_counter() - t0) * 1e3)
+            elat, est = time_solves(torch, plan, r, max(3, args.solves // 5))
+            its = [s_["iterations"] for s_ in gst]
+            out["batched_pcg"] = {
+                "rhs": B, "graph_batch_ms_p50": round(pct(glat, 0.5), 3),
+                "graph_batch_ms_p99": round(pct(glat, 0.99), 3),
+                "graph_solves_per_s": round(B * 1e3 / statistics.mean(glat), 2),
+                "eager_batch_ms_p50": round(pct(elat, 0.5), 3),
+                "eager_solves_per_s": round(B * 1e3 / statistics.mean(elat), 2),
+                "iterations_min_max": [min(its), max(its)],
+                "all_converged": all(s_["converged"] for s_ in gst)}
+            del gs, U
         # ---- dense FD baseline: apply on the matrix cores, and PCG ---------------
         try:
             fd = iffd.Plan(d, n, p, method="dense", precision=args.precision, max_rhs=B)
@@ -282,6 +304,8 @@ def main():
             flops = B * 4 * d * fd.m ** (d + 1)
             tf = flops / (fms * 1e-3) / 1e12
             flat, fst = time_solves(torch, fd, f, max(5, args.solves // 3))
+            if B > 1:
+                fblat, fbst = time_solves(torch, fd, r, max(3, args.solves // 5))
             out["dense_fd"] = {
                 "gdof_s": round(B * N / (fms * 1e-3) / 1e9, 3), "ms_per_apply": round(fms, 5),
                 "roofline": {"bound": "mfma", "achieved": round(tf, 2),
@@ -293,6 +317,11 @@ def main():
                         "p50_ms": round(pct(flat, 0.5), 3), "p99_ms": round(pct(flat, 0.99), 3),
                         "iterations": fst[0]["iterations"]},
                 "iffd_solve_speedup": round(statistics.mean(flat) / statistics.mean(lat), 3)}
+            if B > 1:
+                out["dense_fd"]["batched_pcg"] = {
+                    "rhs": B, "batch_ms_p50": round(pct(fblat, 0.5), 3),
+                    "solves_per_s": round(B * 1e3 / statistics.mean(fblat), 2),
+                    "iterations": fbst[0]["iterations"]}
             del fd, zf
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}

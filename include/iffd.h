@@ -221,7 +221,8 @@ int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double
                   void* stream);
 
 /* Copies the current iterate of slot `slot` into d_u ([m]^d FP64) and frees
- * the slot.  Asynchronous. */
+ * the slot; slot = -1 copies every slot (d_u holds nslots vectors,
+ * [nslots][m]^d) and frees them all.  Asynchronous. */
 int iffd_pcg_take(const iffd_plan* plan, void* d_state, int nslots, int slot, double* d_u,
                   void* stream);
 

@@ -292,12 +292,70 @@ class PcgState:
         return out
 
     def take(self, slot: int, out=None, stream=None):
+        """Copy slot `slot`'s iterate out and free the slot; slot = -1 copies
+        every slot into a (nslots, m, ..) tensor and frees them all."""
         torch = _torch()
-        u = out if out is not None else torch.empty(self.plan.shape, dtype=torch.float64,
+        shape = self.plan.shape if slot >= 0 else (self.nslots,) + self.plan.shape
+        u = out if out is not None else torch.empty(shape, dtype=torch.float64,
                                                     device=self.plan.device)
+        _need(u, self.plan.shape, torch.float64, "out")
+        if u.numel() != int(np.prod(shape)):
+            raise ValueError(f"out must hold {shape}")
         _check(lib.iffd_pcg_take(self.plan._h, _ptr(self.buf), self.nslots, slot, _ptr(u),
                                  _stream(stream)), "pcg_take")
         return u
+
+
+class GraphSolver:
+    """PCG for a batch of right-hand sides of one plan, with the iteration
+    loop replayed from a HIP graph.
+
+    The graph holds `k` PCG iterations over every slot of a resident state
+    (iffd_pcg_iterate is asynchronous and allocation-free, and converged
+    slots are skipped on the device), captured once per solver.  A solve
+    starts the slots eagerly, replays the graph until poll() reports no
+    active slot, and copies the solutions out."""
+
+    def __init__(self, plan: Plan, nrhs: int, k: int = 2):
+        torch = _torch()
+        self.plan, self.nrhs, self.k = plan, nrhs, k
+        self.state = PcgState(plan, nrhs)
+        self.graph = None
+        self._cap = torch.cuda.Stream(device=plan.device)
+
+    def _capture(self):
+        torch = _torch()
+        g = torch.cuda.CUDAGraph()
+        self._cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self._cap):
+            with torch.cuda.graph(g, stream=self._cap):
+                self.state.iterate(self.k)
+        torch.cuda.current_stream().wait_stream(self._cap)
+        self.graph = g
+
+    def solve(self, f, rtol: float = 1e-8, maxit: int = 500, out=None):
+        """f: (nrhs, m, ..) FP64.  Returns (u, [per-RHS dict: iterations,
+        converged, status, relres])."""
+        torch = _torch()
+        _need(f, self.plan.shape, torch.float64, "f")
+        if f.numel() != self.nrhs * self.plan.N:
+            raise ValueError(f"f must hold {self.nrhs} right-hand sides")
+        self.state.begin(range(self.nrhs), f, rtol, maxit)
+        if self.graph is None:
+            # capture with every slot inactive would record the same launches;
+            # the slots just begun stay untouched until the first replay
+            self._capture()
+        done = 0
+        while True:
+            st = self.state.poll()
+            if not st[:, 0].any() or done >= maxit:
+                break
+            self.graph.replay()
+            done += self.k
+        u = self.state.take(-1, out=out)
+        stats = [{"iterations": int(r[2]), "converged": int(r[1]) == 0 and r[0] == 0,
+                  "status": int(r[1]), "relres": float(r[3])} for r in st]
+        return u, stats
 
 
 def device_ok() -> bool:

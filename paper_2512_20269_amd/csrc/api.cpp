@@ -440,7 +440,7 @@ int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double
 int iffd_pcg_take(const iffd_plan* plan, void* d_state, int nslots, int slot, double* d_u,
                   void* stream) {
   if (!plan || !d_state || !d_u) return fail(IFFD_E_INVAL, "null argument");
-  if (slot < 0 || slot >= nslots) return fail(IFFD_E_INVAL, "slot out of range");
+  if (slot < -1 || slot >= nslots || nslots < 1) return fail(IFFD_E_INVAL, "slot out of range");
   hipError_t e = pcg_take_dev(plan->P, (char*)d_state, nslots, slot, d_u, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pcg take");
   return IFFD_OK;

@@ -277,15 +277,21 @@ __global__ void fill_zero(double* p, size_t n) {
 }
 
 // u = x[slot]; mark the slot free
+// copy slot `slot`'s iterate to u and free the slot; slot < 0: every slot
+// (u holds nslots vectors back to back)
 __global__ void pcg_take_kernel(const double* __restrict__ x, double* __restrict__ u, int N,
-                                int slot, double* scal) {
-  const size_t o = (size_t)slot * N;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+                                int slot, int nslots, double* scal) {
+  const size_t o = slot < 0 ? 0 : (size_t)slot * N;
+  const size_t cnt = slot < 0 ? (size_t)nslots * N : (size_t)N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (size_t)gridDim.x * blockDim.x)
     u[i] = x[o + i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double* sc = scal + (size_t)slot * kScal;
-    sc[S_USED] = 0.0;
-    sc[S_ACTIVE] = 0.0;
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < (slot < 0 ? nslots : 1); k += blockDim.x) {
+      double* sc = scal + (size_t)(slot < 0 ? k : slot) * kScal;
+      sc[S_USED] = 0.0;
+      sc[S_ACTIVE] = 0.0;
+    }
   }
 }
 
@@ -383,8 +389,8 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
 
 hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u, hipStream_t s) {
   const StateLayout L = state_layout(P, nslots);
-  hipLaunchKernelGGL(pcg_take_kernel, dim3(256), dim3(256), 0, s, (const double*)(st + L.x), u,
-                     (int)P.N, slot, (double*)(st + L.scal));
+  hipLaunchKernelGGL(pcg_take_kernel, dim3(slot < 0 ? 2048 : 256), dim3(256), 0, s,
+                     (const double*)(st + L.x), u, (int)P.N, slot, nslots, (double*)(st + L.scal));
   return hipGetLastError();
 }
 
