@@ -136,6 +136,67 @@ def time_solves(torch, plan, f, count, rtol=1e-8):
     return lat, st
 
 
+def serving(torch, count, warm, fracs, budget_gb=96.0, slots=8, iters=2, check=4):
+    """Continuous-batching solve server on a Poisson stream of mixed (d, n, p)
+    requests: a saturation run (every request present at t = 0) and one run
+    per QPS = frac x saturation throughput.  Latency = arrival -> result."""
+    import workloads
+    import paper_2512_20269_amd as iffd
+    from paper_2512_20269_amd.serve import Request, SolveServer
+    spec = workloads.serving_requests(warm + count, qps=1.0)
+    fs = [torch.from_numpy(workloads.uniform_rhs(d, n, p, rs)).cuda()
+          for (_, d, n, p, rs) in spec]
+    srv = SolveServer(int(budget_gb * 2**30), slots=slots, iters_per_round=iters)
+
+    def reqs(ids, qps):
+        t_first = spec[ids[0]][0]
+        return [Request(k, 0.0 if qps is None else (spec[k][0] - t_first) / qps,
+                        *spec[k][1:4], fs[k]) for k in ids]
+
+    srv.run(reqs(list(range(warm)), None))          # warm the resident plans
+    ids = list(range(warm, warm + count))
+
+    def measure(qps):
+        r0 = (srv.launches, srv.busy_slots_at_launch, srv.inflight_at_launch)
+        done = [r for r in srv.run(reqs(ids, qps)) if r.status != "rejected"]
+        lat = [(r.t_done - r.arrival) * 1e3 for r in done]
+        span = max(r.t_done for r in done) - min(r.arrival for r in done)
+        launches = srv.launches - r0[0]
+        res = {"qps_offered": None if qps is None else round(qps, 2),
+               "solves_per_s": round(len(done) / span, 2), "completed": len(done),
+               "p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
+               "mean_slots_per_launch":
+                   round((srv.busy_slots_at_launch - r0[1]) / max(launches, 1), 2),
+               "mean_shapes_in_flight":
+                   round((srv.inflight_at_launch - r0[2]) / max(launches, 1), 2),
+               "all_converged": all(r.status == 0 for r in done)}
+        buckets = {}
+        for r in done:
+            b = f"d{r.d}_n{'<=64' if r.n <= 64 else ('96-128' if r.n <= 128 else '192-256')}"
+            buckets.setdefault(b, []).append((r.t_done - r.arrival) * 1e3)
+        res["by_bucket"] = {b: {"count": len(v), "p50_ms": round(pct(v, 0.5), 3),
+                                "p99_ms": round(pct(v, 0.99), 3)}
+                            for b, v in sorted(buckets.items())}
+        return res, done
+
+    sat, done = measure(None)
+    runs = []
+    for frac in fracs:
+        res, done = measure(frac * sat["solves_per_s"])
+        res["frac_of_saturation"] = frac
+        runs.append(res)
+    # a request's solution is the same bits alone (its own single-slot plan)
+    same = True
+    for r in done[:: max(1, len(done) // check)][:check]:
+        solo = iffd.Plan(r.d, r.n, r.p, method="fft", precision="f32", max_rhs=1)
+        u1, _ = solo.solve(r.f, rtol=1e-8, maxit=200)
+        same = same and bool(torch.equal(u1, r.u))
+    return {"requests": count, "warmup_requests": warm, "slots_per_shape": slots,
+            "iters_per_round": iters, "hbm_budget_gb": budget_gb,
+            "peak_footprint_gb": round(srv.peak / 2**30, 2), "saturation": sat,
+            "runs": runs, "sampled_same_bits_as_alone": same, "sampled": check}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +211,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB with a plain elementwise kernel "
                          "(reference dispatch for HBM byte counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="only the serving benchmark (Poisson stream of mixed solves)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, no collectives); "
@@ -161,8 +227,18 @@ def main():
 
     import paper_2512_20269_amd as iffd
 
-    d, n, p, B, recipe = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.serve:
+        res = serving(torch, args.serve_requests, args.serve_warmup,
+                      [float(x) for x in args.serve_fracs.split(",")])
+        print(json.dumps({"metric": "PCG solves/s and p50/p99 latency, serving stream",
+                          "unit": "solves/s", "value": res["saturation"]["solves_per_s"],
+                          "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+                          "data": "synthetic",
+                          "config": {"workload": "serving_mixed_d2_3_n32_256_p2_6"},
+                          "serving": res}), flush=True)
+        return
+    d, n, p, B, recipe = WORKLOADS[args.workload]
     r_np = make_rhs(args.workload)
     r = torch.from_numpy(r_np).cuda()
     z = torch.empty_like(r)
@@ -325,6 +401,8 @@ def main():
             del fd, zf
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}
+        if B == 1:
+            out["serving"] = serving(torch, 200, 60, [0.5, 0.9])
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")

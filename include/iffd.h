@@ -220,6 +220,13 @@ int iffd_pcg_iterate(const iffd_plan* plan, void* d_state, int nslots, int k, vo
 int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double* h_out,
                   void* stream);
 
+/* Asynchronous form of iffd_pcg_poll: enqueues on `stream` a kernel that
+ * writes the same nslots records of 4 doubles into device memory d_out
+ * (the caller copies them out and waits on an event of its own).  Lets a
+ * scheduler watch many states without blocking on any one of them. */
+int iffd_pcg_status(const iffd_plan* plan, const void* d_state, int nslots, double* d_out,
+                    void* stream);
+
 /* Copies the current iterate of slot `slot` into d_u ([m]^d FP64) and frees
  * the slot; slot = -1 copies every slot (d_u holds nslots vectors,
  * [nslots][m]^d) and frees them all.  Asynchronous. */

@@ -78,6 +78,7 @@ SIGNATURES = {
     "iffd_pcg_begin": (_I, [_P, _P, _I, ctypes.POINTER(_I), _I, _P, _D, _I, _P]),
     "iffd_pcg_iterate": (_I, [_P, _P, _I, _I, _P]),
     "iffd_pcg_poll": (_I, [_P, _P, _I, _P, _P]),
+    "iffd_pcg_status": (_I, [_P, _P, _I, _P, _P]),
     "iffd_pcg_take": (_I, [_P, _P, _I, _I, _P, _P]),
     "iffd_status_string": (ctypes.c_char_p, [_I]),
     "iffd_last_error": (ctypes.c_char_p, []),
@@ -158,11 +159,22 @@ class Plan:
             assert self.tables.data_ptr() % 256 == 0
             _check(lib.iffd_plan_setup(h, _ptr(self.tables), info.table_bytes, _stream()),
                    "plan_setup")
-            self._ws = torch.empty(max(info.apply_ws_bytes, 256), dtype=torch.uint8,
-                                   device=self.device)
-            self._mvws = torch.empty(max(info.matvec_ws_bytes, 256), dtype=torch.uint8,
-                                     device=self.device)
-        self._pcg_ws = None
+        # workspaces of apply() / matvec() / solve(), allocated on first use
+        self._ws_t = self._mvws_t = self._pcg_ws = None
+
+    @property
+    def _ws(self):
+        if self._ws_t is None:
+            self._ws_t = _torch().empty(max(self.info["apply_ws_bytes"], 256),
+                                        dtype=_torch().uint8, device=self.device)
+        return self._ws_t
+
+    @property
+    def _mvws(self):
+        if self._mvws_t is None:
+            self._mvws_t = _torch().empty(max(self.info["matvec_ws_bytes"], 256),
+                                          dtype=_torch().uint8, device=self.device)
+        return self._mvws_t
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -290,6 +302,12 @@ class PcgState:
         _check(lib.iffd_pcg_poll(self.plan._h, _ptr(self.buf), self.nslots,
                                  out.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "pcg_poll")
         return out
+
+    def status_async(self, out, stream=None):
+        """Enqueue the poll() records into the device tensor `out`
+        (nslots x 4 FP64) without waiting."""
+        _check(lib.iffd_pcg_status(self.plan._h, _ptr(self.buf), self.nslots, _ptr(out),
+                                   _stream(stream)), "pcg_status")
 
     def take(self, slot: int, out=None, stream=None):
         """Copy slot `slot`'s iterate out and free the slot; slot = -1 copies

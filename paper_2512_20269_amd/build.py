@@ -1,6 +1,8 @@
 """Build the HIP library libiffd.so in-tree for gfx950.
 
-    python -m paper_2512_20269_amd.build          # or: python paper_2512_20269_amd/build.py
+    python paper_2512_20269_amd/build.py
+
+(run as a script: importing the package would load the library being built)
 
 Every source is compiled with hipcc (device code for gfx950 only) with
 packed FP32 instructions disabled, then linked into one shared library next

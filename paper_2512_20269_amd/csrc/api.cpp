@@ -18,6 +18,7 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
                          const double* f, double rtol, int maxit, hipStream_t s);
 hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream_t s);
 hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u, hipStream_t s);
+hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out, hipStream_t s);
 hipError_t residual_norms_dev(const Plan& P, const double* f, const double* y, double* tmp,
                               double* part, int nrhs, hipStream_t s);
 }  // namespace iffd
@@ -434,6 +435,16 @@ int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double
     h_out[4 * i + 2] = r[S_IT];
     h_out[4 * i + 3] = r[S_RELRES];
   }
+  return IFFD_OK;
+}
+
+int iffd_pcg_status(const iffd_plan* plan, const void* d_state, int nslots, double* d_out,
+                    void* stream) {
+  if (!plan || !d_state || !d_out) return fail(IFFD_E_INVAL, "null argument");
+  if (nslots < 1) return fail(IFFD_E_INVAL, "nslots must be >= 1");
+  if (!plan->P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  hipError_t e = pcg_status_dev(plan->P, (const char*)d_state, nslots, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pcg status");
   return IFFD_OK;
 }
 

@@ -295,6 +295,26 @@ __global__ void pcg_take_kernel(const double* __restrict__ x, double* __restrict
   }
 }
 
+// per-slot summary for asynchronous polling: out[4 k ..] = active, status
+// (-100 for a free slot), iterations, relres
+__global__ void pcg_status_kernel(const double* __restrict__ scal, double* __restrict__ out,
+                                  int nslots) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nslots) return;
+  const double* r = scal + (size_t)k * kScal;
+  out[4 * k + 0] = r[S_ACTIVE];
+  out[4 * k + 1] = r[S_USED] != 0.0 ? r[S_STATUS] : -100.0;
+  out[4 * k + 2] = r[S_IT];
+  out[4 * k + 3] = r[S_RELRES];
+}
+
+hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out, hipStream_t s) {
+  const StateLayout L = state_layout(P, nslots);
+  hipLaunchKernelGGL(pcg_status_kernel, dim3((nslots + 63) / 64), dim3(64), 0, s,
+                     (const double*)(st + L.scal), out, nslots);
+  return hipGetLastError();
+}
+
 // r = f - y (for the true residual), per slot
 __global__ void __launch_bounds__(VT)
 axpby_res(double* __restrict__ out, const double* __restrict__ f, const double* __restrict__ y,
