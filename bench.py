@@ -41,15 +41,19 @@ METRIC = "FFT-FD apply GDoF/s vs dense FD; PCG solves/s + p99 latency to 1e-8 re
 WORKLOADS = {
     "cube_n128_p3": (3, 128, 3, 1, "uniform[-1,1] seed 2"),
     "square_n64_p3": (2, 64, 3, 1, "uniform[-1,1] seed 1"),
+    "cube_n256_p2": (3, 256, 2, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
     "cube_n256_p3": (3, 256, 3, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
+    "cube_n256_p4": (3, 256, 4, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
+    "cube_n256_p6": (3, 256, 6, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
+    "cube_n256_p8": (3, 256, 8, 1, "smooth 8-mode sine + 1e-3 noise, seed 3"),
     "cube_n96_p4_b64": (3, 96, 4, 64, "uniform[-1,1], seeds 4000+b"),
 }
 
 
 def make_rhs(workload):
     import workloads
-    if workload == "cube_n256_p3":
-        return workloads.workload_rhs("cube_n256", p=3)
+    if workload.startswith("cube_n256_p"):
+        return workloads.workload_rhs("cube_n256", p=int(workload[len("cube_n256_p"):]))
     return workloads.workload_rhs(workload)
 
 

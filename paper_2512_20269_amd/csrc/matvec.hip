@@ -12,11 +12,9 @@
 //
 // Pass 1: one thread per (i1, i2) column and chunk of C3 planes; the thread
 // loads its window of C3 + 2p values at once, so every load is in flight
-// together, and writes C3 values of t and s.  Pass 2: one workgroup per
-// TY x TX tile of a plane; the tile of t and s with a p-wide halo goes
-// through LDS, the direction-2 products are formed for the tile rows over the
-// halo columns, then the direction-1 products for the tile.  Pass 2 also
-// forms the per-workgroup partial of x . y that PCG needs for p . Ap.
+// together, and writes C3 values of t and s.  Pass 2 (below) forms both
+// in-plane directions and the per-workgroup partial of x . y that PCG needs
+// for p . Ap.
 // The 1-D matrices are Toeplitz away from the ends, so they are held
 // compactly: the 2p-1 special rows at each end plus one interior row.
 #include "launch.h"
@@ -79,125 +77,146 @@ mv_axis3(const double* __restrict__ x, double* __restrict__ t3, double* __restri
   }
 }
 
+// Pass 2: one wave per (plane, strip of 64 - 2p columns, chunk of 8 rows).
+// Lane c owns column i1 = strip start - p + c and walks down its rows with a
+// register window of C2 + 2p values of t (and s): direction 2 is formed in
+// registers (the band row is the same for every lane), direction 1 takes the
+// neighbouring columns' u, v from the other lanes by shuffles, so the pass
+// needs no LDS tile and no barrier.  The outer p lanes on each side only feed
+// their neighbours.  Each workgroup of four waves writes one partial of x . y.
 constexpr int MV2_THREADS = 256;
-constexpr int MV2_TX = 64;  // tile columns (direction 1)
+
+// whole-wave lane shifts of a double by one lane (DPP wave_shr:1 / wave_shl:1;
+// the lane that has no source receives 0)
+__device__ __forceinline__ double wave_from_lower(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, true),
+                          __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double wave_from_upper(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x130, 0xF, 0xF, true),
+                          __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xF, 0xF, true));
+}
+
 template <int P>
-constexpr int mv2_ty() { return P <= 4 ? 16 : 8; }  // tile rows (direction 2)
+constexpr int mv2_rows() { return 8; }
+
+__host__ __device__ inline void mv2_geom(int m, int planes, int P, int& ncs, int& nch, int& bpr) {
+  const int out = 64 - 2 * P;
+  const int c2 = 8;
+  ncs = (m + out - 1) / out;
+  nch = (m + c2 - 1) / c2;
+  const long long items = (long long)planes * ncs * nch;
+  bpr = (int)((items + MV2_THREADS / 64 - 1) / (MV2_THREADS / 64));
+}
 
 template <int P, bool HAS_S>
 __global__ void __launch_bounds__(MV2_THREADS)
-mv_plane(const double* __restrict__ xin, const double* __restrict__ t3,
-         const double* __restrict__ s3, double* __restrict__ y, int m, int N, int ntx, int nty,
-         const double* __restrict__ kc, const double* __restrict__ mc, int nbr, int crows,
-         double* __restrict__ part, int npart, const double* __restrict__ active, int astride) {
+mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
+        const double* __restrict__ s3, double* __restrict__ y, int m, int N, int ncs, int nch,
+        int bpr, const double* __restrict__ kc, const double* __restrict__ mc, int nbr, int crows,
+        double* __restrict__ part, int npart, const double* __restrict__ active, int astride) {
   constexpr int BW = 2 * P + 1;
-  constexpr int MV2_TY = mv2_ty<P>();
-  constexpr int XW = MV2_TX + 2 * P;   // tile width with the column halo
-  constexpr int RH = MV2_TY + 2 * P;   // tile height with the row halo
-  __shared__ double ts[RH * XW];
-  __shared__ double ss[HAS_S ? RH * XW : 1];
-  __shared__ double us[MV2_TY * XW];
-  __shared__ double vs[MV2_TY * XW];
-  __shared__ double kcs[(4 * P - 1) * BW];
-  __shared__ double mcs[(4 * P - 1) * BW];
+  constexpr int C2 = mv2_rows<P>();
+  constexpr int WIN = C2 + 2 * P;
+  constexpr int OUT = 64 - 2 * P;
   __shared__ double red[MV2_THREADS / 64];
-
-  const int t = threadIdx.x;
-  const int tiles = ntx * nty;
-  const int planes = N / (m * m);
-  int bid = blockIdx.x;
-  const int per_rhs = tiles * planes;
-  const int rhs = bid / per_rhs;
-  bid -= rhs * per_rhs;
-  const int pl = bid / tiles;
-  const int tl = bid - pl * tiles;
-  const int by = tl / ntx, bx = tl - by * ntx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rhs = blockIdx.x / bpr;
+  const int blk = blockIdx.x - rhs * bpr;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
-  const size_t base = (size_t)rhs * N + (size_t)pl * m * m;
-  const int r0 = by * MV2_TY, q0 = bx * MV2_TX;
-
-  for (int e = t; e < crows * BW; e += MV2_THREADS) {
-    kcs[e] = kc[e];
-    mcs[e] = mc[e];
-  }
-  // tile of t (and s) with halo, zero outside the domain
-  for (int e0 = t; e0 < RH * XW; e0 += MV2_THREADS * 4) {
-    double a[4], b[4];
+  const int plane = m * m;
+  const int planes = N / plane;
+  const int ipp = ncs * nch;
+  const int item = blk * (MV2_THREADS / 64) + w;
+  double dot = 0.0;
+  if (item < planes * ipp) {
+    // row chunks vary fastest, so the waves of a workgroup take consecutive
+    // chunks of one strip and share their p-row halos through the cache
+    const int pl = item / ipp;
+    const int rem = item - pl * ipp;
+    const int cs = rem / nch;
+    const int ch = rem - cs * nch;
+    const int i1 = cs * OUT - P + lane;
+    const bool col = i1 >= 0 && i1 < m;
+    const int r0 = ch * C2;
+    const size_t base = (size_t)rhs * N + (size_t)pl * plane;
+    double wt[WIN], wsv[WIN];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * MV2_THREADS;
-      const int r = e / XW, c = e - (e / XW) * XW;
-      const int i2 = r0 + r - P, i1 = q0 + c - P;
-      const bool in = e < RH * XW && i2 >= 0 && i2 < m && i1 >= 0 && i1 < m;
-      const size_t gi = base + (size_t)i2 * m + i1;
-      a[u] = in ? t3[gi] : 0.0;
-      b[u] = (HAS_S && in) ? s3[gi] : 0.0;
+    for (int k = 0; k < WIN; ++k) {
+      const int i2 = r0 - P + k;
+      const bool in = col && i2 >= 0 && i2 < m;
+      const size_t gi = base + (size_t)(in ? i2 : 0) * m + (in ? i1 : 0);
+      wt[k] = in ? t3[gi] : 0.0;
+      wsv[k] = (HAS_S && in) ? s3[gi] : 0.0;
+    }
+    // x at the output points, for the partial x . y (loaded with the window so
+    // that no load waits inside the row loop)
+    const bool out = lane >= P && lane < 64 - P && col;
+    double xv[C2];
+#pragma unroll
+    for (int r = 0; r < C2; ++r) {
+      const bool in = part && out && r0 + r < m;
+      xv[r] = in ? xin[base + (size_t)(r0 + r) * m + i1] : 0.0;
+    }
+    // row by row: direction 2 from the register window, direction 1 from the
+    // neighbouring lanes through DPP whole-wave shifts (VALU moves, no LDS)
+    const int cr1 = crow(col ? i1 : 0, m, nbr, crows);
+    double k1[BW], m1[BW];
+#pragma unroll
+    for (int o = 0; o < BW; ++o) {
+      k1[o] = kc[cr1 * BW + o];
+      m1[o] = mc[cr1 * BW + o];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * MV2_THREADS;
-      if (e < RH * XW) {
-        ts[e] = a[u];
-        if (HAS_S) ss[e] = b[u];
-      }
-    }
-  }
-  __syncthreads();
-  // direction 2 on the tile rows, over the halo columns: u = M2 t, v = K2 t + M2 s
-  for (int e = t; e < MV2_TY * XW; e += MV2_THREADS) {
-    const int r = e / XW, c = e - (e / XW) * XW;
-    const int i2 = r0 + r;
-    double uv = 0.0, vv = 0.0;
-    if (i2 < m) {
-      const int cr = crow(i2, m, nbr, crows);
-      const double* krow = kcs + cr * BW;
-      const double* mrow = mcs + cr * BW;
+    for (int r = 0; r < C2; ++r) {
+      // the band row is the same for the whole wave: scalar loads
+      const int cr2 = __builtin_amdgcn_readfirstlane(crow(min(r0 + r, m - 1), m, nbr, crows));
+      const double* k2 = kc + cr2 * BW;
+      const double* m2 = mc + cr2 * BW;
+      double u = 0.0, v = 0.0;
 #pragma unroll
       for (int o = 0; o < BW; ++o) {
-        const double tv = ts[(r + o) * XW + c];
-        uv += mrow[o] * tv;
-        vv += krow[o] * tv;
-        if (HAS_S) vv += mrow[o] * ss[(r + o) * XW + c];
+        u += m2[o] * wt[r + o];
+        v += k2[o] * wt[r + o];
+        if (HAS_S) v += m2[o] * wsv[r + o];
+      }
+      // tap o needs column i1 - P + o, held by lane - P + o
+      double yv = k1[P] * u + m1[P] * v;
+      double ul = u, vl = v, ur = u, vr = v;
+#pragma unroll
+      for (int d = 1; d <= P; ++d) {
+        ul = wave_from_lower(ul);   // value of lane - d
+        vl = wave_from_lower(vl);
+        ur = wave_from_upper(ur);   // value of lane + d
+        vr = wave_from_upper(vr);
+        yv += k1[P - d] * ul + m1[P - d] * vl;
+        yv += k1[P + d] * ur + m1[P + d] * vr;
+      }
+      if (out && r0 + r < m) {
+        y[base + (size_t)(r0 + r) * m + i1] = yv;
+        dot += xv[r] * yv;
       }
     }
-    us[e] = uv;
-    vs[e] = vv;
-  }
-  __syncthreads();
-  // direction 1: y = K1 u + M1 v
-  double dot = 0.0;
-  for (int e = t; e < MV2_TY * MV2_TX; e += MV2_THREADS) {
-    const int r = e / MV2_TX, c = e - (e / MV2_TX) * MV2_TX;
-    const int i2 = r0 + r, i1 = q0 + c;
-    if (i2 >= m || i1 >= m) continue;
-    const int cr = crow(i1, m, nbr, crows);
-    const double* krow = kcs + cr * BW;
-    const double* mrow = mcs + cr * BW;
-    double yv = 0.0;
-#pragma unroll
-    for (int o = 0; o < BW; ++o) yv += krow[o] * us[r * XW + c + o] + mrow[o] * vs[r * XW + c + o];
-    const size_t gi = base + (size_t)i2 * m + i1;
-    y[gi] = yv;
-    if (part) dot += xin[gi] * yv;
   }
   if (part) {
     for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
-    if ((t & 63) == 0) red[t >> 6] = dot;
+    if (lane == 0) red[w] = dot;
     __syncthreads();
-    if (t == 0) {
+    if (threadIdx.x == 0) {
       double s = 0.0;
-      for (int w = 0; w < MV2_THREADS / 64; ++w) s += red[w];
-      part[(size_t)rhs * npart + (blockIdx.x - rhs * per_rhs)] = s;
+      for (int k = 0; k < MV2_THREADS / 64; ++k) s += red[k];
+      part[(size_t)rhs * npart + blk] = s;
     }
   }
 }
 
 // workgroups of the operator per right-hand side (pass 2 produces the partials)
 int matvec_blocks(const Plan& P_) {
-  const int m = P_.m;
-  const int ty = P_.p <= 4 ? 16 : 8;
-  const int ntx = (m + MV2_TX - 1) / MV2_TX, nty = (m + ty - 1) / ty;
-  return ntx * nty * (P_.d == 3 ? m : 1);
+  int ncs, nch, bpr;
+  mv2_geom(P_.m, P_.d == 3 ? P_.m : 1, P_.p, ncs, nch, bpr);
+  return bpr;
 }
 
 size_t matvec_ws_bytes(const Plan& P_, int nrhs) {
@@ -212,23 +231,23 @@ static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs
   const double* kc = (const double*)(b + P_.lay.kc64);
   const double* mc = (const double*)(b + P_.lay.mc64);
   const int nbr = 2 * P - 1, crows = P_.crows;
-  const int ntx = (m + MV2_TX - 1) / MV2_TX, nty = (m + mv2_ty<P>() - 1) / mv2_ty<P>();
-  const int per_rhs = matvec_blocks(P_);
-  if (part && per_rhs > npart) return hipErrorInvalidValue;
+  int ncs, nch, bpr;
+  mv2_geom(m, P_.d == 3 ? m : 1, P, ncs, nch, bpr);
+  if (part && bpr > npart) return hipErrorInvalidValue;
   if (P_.d == 3) {
     if (!ws) return hipErrorInvalidValue;
     double* t3 = (double*)ws;
     double* s3 = t3 + (size_t)N * nrhs;
-    const int nch = (m + MV1_C3 - 1) / MV1_C3;
+    const int n3 = (m + MV1_C3 - 1) / MV1_C3;
     const int cb = (m * m + MV1_THREADS - 1) / MV1_THREADS;
-    hipLaunchKernelGGL(mv_axis3<P>, dim3(cb * nch * nrhs), dim3(MV1_THREADS), 0, s, x, t3, s3, m,
-                       N, nch, kc, mc, nbr, crows, a, as);
-    hipLaunchKernelGGL((mv_plane<P, true>), dim3(per_rhs * nrhs), dim3(MV2_THREADS), 0, s, x, t3,
-                       s3, y, m, N, ntx, nty, kc, mc, nbr, crows, part, npart, a, as);
+    hipLaunchKernelGGL(mv_axis3<P>, dim3(cb * n3 * nrhs), dim3(MV1_THREADS), 0, s, x, t3, s3, m,
+                       N, n3, kc, mc, nbr, crows, a, as);
+    hipLaunchKernelGGL((mv_rows<P, true>), dim3(bpr * nrhs), dim3(MV2_THREADS), 0, s, x, t3, s3,
+                       y, m, N, ncs, nch, bpr, kc, mc, nbr, crows, part, npart, a, as);
   } else {
-    hipLaunchKernelGGL((mv_plane<P, false>), dim3(per_rhs * nrhs), dim3(MV2_THREADS), 0, s, x, x,
-                       (const double*)nullptr, y, m, N, ntx, nty, kc, mc, nbr, crows, part, npart,
-                       a, as);
+    hipLaunchKernelGGL((mv_rows<P, false>), dim3(bpr * nrhs), dim3(MV2_THREADS), 0, s, x, x,
+                       (const double*)nullptr, y, m, N, ncs, nch, bpr, kc, mc, nbr, crows, part,
+                       npart, a, as);
   }
   return hipGetLastError();
 }
