@@ -221,6 +221,29 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
         }
       }
     }
+  } else if constexpr (NTH % TW == 0) {
+    // every thread keeps one line l = t mod TW and takes its rows j0, j0 + JS, ..
+    // (rows of the tile are runs of TW consecutive entries of the tensor)
+    constexpr int JS = NTH / TW;
+    const int l = t & (TW - 1), j0 = t >> LTW;
+    const int q = q0 + l;
+    const bool lv = l < nv;
+    const Tin* src = in + ((size_t)rhs * g.N + (size_t)(q / S) * m * S + (q % S) +
+                           (size_t)j0 * S) * (lv ? 1 : 0);
+    T* dst = X + l * MP + j0;
+    const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
+    const size_t step = (size_t)JS * S;
+    for (int k0 = 0; k0 < cnt; k0 += CH) {
+      Tin v[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int k = k0 + u;
+        v[u] = (k < cnt && lv) ? src[k * step] : Tin(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (k0 + u < cnt) dst[(k0 + u) * JS] = (T)v[u];
+    }
   } else {
     __syncthreads();  // LB
     const int cnt = TW * m;
@@ -249,7 +272,12 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   __syncthreads();
 
   // Kronecker-sum scaling of spectral entry j of line l (middle pass)
-  auto fac = [&](int l, int j) -> T { return SS[j] * SO[l] / (LAM[j] + LO[l]); };
+  auto fac = [&](int l, int j) -> T {
+    if constexpr (sizeof(T) == 4)   // hardware reciprocal (1 ulp) for the FP32 apply
+      return SS[j] * SO[l] * __builtin_amdgcn_rcpf(LAM[j] + LO[l]);
+    else
+      return SS[j] * SO[l] / (LAM[j] + LO[l]);
+  };
 
   const int f = t / NT, tid = t - (t / NT) * NT;
   const int la = 2 * f, lb = 2 * f + 1;
@@ -300,17 +328,15 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     __syncthreads();
 
     // ---- forward transform: X[l][0..n_reg) = U^T g_l (scaled in the middle) --
-    auto ld = [&](int k) -> cpx<T> {
-      const bool lo = k < n;
+    auto ld = [&](int k, bool lo, bool k0, bool kh) -> cpx<T> {
       int idx;
       if (odd) idx = lo ? k - 1 : 2 * n - k - 1;   // k = 0, n give 0 (below)
       else idx = lo ? k : 2 * n - 1 - k;
       idx = idx < 0 ? 0 : idx;
       T a = Ga[idx], b = Gb[idx];
-      const T sg = lo ? T(1) : T(-1);
-      const bool zero = odd && (k == 0 || k == n);
-      a = zero ? T(0) : sg * a;
-      b = zero ? T(0) : sg * b;
+      const bool zero = odd && (k0 || kh);
+      a = zero ? T(0) : (lo ? a : -a);
+      b = zero ? T(0) : (lo ? b : -b);
       return {a, b};
     };
     auto st = [&](int k, cpx<T> v) {
@@ -343,31 +369,30 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 
   if (MODE == PASS_BWD || MODE == PASS_MID) {
     // ---- backward transform: X[l][c0 + idx] = (U c_l)[idx] -------------------
-    auto ld = [&](int k) -> cpx<T> {
+    auto ld = [&](int k, bool lo, bool k0, bool kh) -> cpx<T> {
       if (odd) {
-        const bool lo = k < n;
         int idx = lo ? k - 1 : 2 * n - k - 1;
         idx = idx < 0 ? 0 : idx;
-        const T sg = lo ? T(1) : T(-1);
-        const bool zero = (k == 0 || k == n);
-        return {zero ? T(0) : sg * Xa[idx], zero ? T(0) : sg * Xb[idx]};
+        const bool zero = k0 || kh;
+        const T a = Xa[idx], b = Xb[idx];
+        return {zero ? T(0) : (lo ? a : -a), zero ? T(0) : (lo ? b : -b)};
       }
       // DST-III by the anti-Hermitian extension of wbar = c_a - i c_b
-      int j = k <= n ? k : 2 * n - k;
-      const bool zero = j == 0;
-      j = zero ? 1 : j;
+      const bool le = lo || kh;   // k <= n
+      int j = le ? k : 2 * n - k;
+      j = k0 ? 1 : j;
       const cpx<T> wb = {Xa[j - 1], -Xb[j - 1]};
       const cpx<T> tw = twp[j];
       cpx<T> z;
-      if (k <= n) {
+      if (le) {
         z = c_mul(wb, cpx<T>{tw.x, -tw.y});
-        const T s2 = k == n ? T(2) : T(1);
+        const T s2 = kh ? T(2) : T(1);
         z = {s2 * z.x, s2 * z.y};
       } else {
         const cpx<T> u = c_mul(wb, tw);
         z = {-u.x, -u.y};
       }
-      return zero ? cpx<T>{T(0), T(0)} : z;
+      return k0 ? cpx<T>{T(0), T(0)} : z;
     };
     auto st = [&](int k, cpx<T> v) {
       const bool ok = k >= 1 && k <= n_reg;
@@ -415,6 +440,16 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
         const int j = lane + RW * u;
         if (j < m) dst[l * m + j] = (Tout)value(l, j);
       }
+    }
+  } else if constexpr (NTH % TW == 0) {
+    constexpr int JS = NTH / TW;
+    const int l = t & (TW - 1), j0 = t >> LTW;
+    const int q = q0 + l;
+    if (l < nv && j0 < m) {
+      Tout* dst = out + (size_t)rhs * g.N + (size_t)(q / S) * m * S + (q % S) + (size_t)j0 * S;
+      const int cnt = (m - j0 + JS - 1) / JS;
+      const size_t step = (size_t)JS * S;
+      for (int k = 0; k < cnt; ++k) dst[k * step] = (Tout)value(l, j0 + k * JS);
     }
   } else {
     const int cnt = TW * m;

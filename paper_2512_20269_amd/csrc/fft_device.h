@@ -17,7 +17,7 @@
 namespace iffd {
 
 template <typename T>
-struct cpx {
+struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 
@@ -159,9 +159,11 @@ template <> struct FftPlan<512, 1> { static constexpr int E = 8; };
 __device__ __forceinline__ int fpad(int k) { return k + (k >> 4); }
 template <int L> constexpr int fft_region() { return L + L / 16 + 8; }
 
-// One Stockham stage.  FIRST: inputs come from ld(k) instead of LDS;
-// LAST: outputs go to st(k, v) instead of LDS.  Every stage ends its reads
-// with a barrier before it writes, so `buf` may alias whatever ld reads.
+// One Stockham stage: reads, butterflies, barrier, writes.  FIRST: inputs
+// come from ld(k, lo, k0, kh) instead of LDS, with lo = (k < L/2),
+// k0 = (k == 0) and kh = (k == L/2) known per unrolled slot; LAST: outputs go
+// to st(k, v) instead of LDS.  The barrier between a stage's reads and its
+// writes lets `buf` alias whatever ld reads.
 template <typename T, int L, int E, int NT, int NS, int R, bool FIRST, bool LAST, class LD,
           class ST>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, int tid, const cpx<T>* tw, LD& ld,
@@ -174,11 +176,12 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int tid, const cpx<T>* tw
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int k = j + r * (L / R);
-      if constexpr (FIRST) v[b][r] = ld(k);
+      // first stage: j < L/R, so k < L/2 exactly when r < R/2 (R is even for
+      // every first radix), and k is 0 or L/2 only for j = 0
+      if constexpr (FIRST) v[b][r] = ld(k, r < R / 2, j == 0 && r == 0, j == 0 && 2 * r == R);
       else v[b][r] = buf[fpad(k)];
     }
   }
-  __syncthreads();
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = tid + NT * b;
@@ -188,7 +191,14 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int tid, const cpx<T>* tw
       for (int r = 1; r < R; ++r) v[b][r] = c_mul(v[b][r], tw[k * r * (L / (NS * R))]);
     }
     dft<T, R>(v[b]);
-    const int o = (j / NS) * NS * R + k;
+  }
+  // every read of this stage precedes every write (the stages work in place);
+  // the butterflies above overlap the other waves' reads
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = tid + NT * b;
+    const int o = (j / NS) * NS * R + j % NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (LAST) st(o + r * NS, v[b][r]);
@@ -210,7 +220,7 @@ struct FftRun {
   }
 };
 
-// forward FFT of length L over NT = L/E threads; ld(k) supplies input k,
+// forward FFT of length L over NT = L/E threads; ld(k, lo, k0, kh) supplies input k,
 // st(k, v) receives output k (natural order).  buf: this transform's LDS
 // region of fft_region<L>() elements.  All threads of the block must call it.
 template <typename T, int L, int V, class LD, class ST>
