@@ -178,7 +178,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:   # lib is None at interpreter exit
             lib.iffd_plan_destroy(h)
             self._h = None
 

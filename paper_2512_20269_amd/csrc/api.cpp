@@ -476,20 +476,55 @@ int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nr
   for (int k = 0; k < nrhs; ++k) slots[k] = k;
   rc = iffd_pcg_begin(plan, d_ws, nrhs, slots.data(), nrhs, d_f, rtol, maxit, stream);
   if (rc != IFFD_OK) return rc;
+  // Pipelined polling: the next batch of iterations is enqueued before the
+  // host waits for the previous batch's slot records (copied to pinned host
+  // memory), so the device never idles on the host.  Converged slots make the
+  // extra batch a no-op.
   const int step = check_every > 0 ? check_every : 1;
-  std::vector<double> poll((size_t)4 * nrhs);
-  int done_it = 0;
-  while (true) {
-    rc = iffd_pcg_poll(plan, d_ws, nrhs, poll.data(), stream);
-    if (rc != IFFD_OK) return rc;
-    bool any = false;
-    for (int k = 0; k < nrhs; ++k) any = any || poll[4 * k] != 0.0;
-    if (!any || done_it >= maxit) break;
-    const int kk = std::min(step, maxit - done_it);
-    hipError_t e = pcg_iterate_dev(P, st, nrhs, kk, s);
-    if (e != hipSuccess) return hip_fail(e, "pcg iterate");
-    done_it += kk;
+  const size_t rec = (size_t)4 * nrhs;
+  static thread_local double* hbuf = nullptr;
+  static thread_local size_t hcap = 0;
+  if (hcap < 2 * rec) {
+    if (hbuf) (void)hipHostFree(hbuf);
+    hbuf = nullptr;
+    hcap = 0;
+    hipError_t e = hipHostMalloc((void**)&hbuf, 2 * rec * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned status buffer");
+    hcap = 2 * rec;
   }
+  double* dstat = (double*)(st + L.stat);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "event");
+  }
+  auto post_status = [&](int b) -> hipError_t {
+    hipError_t e = pcg_status_dev(P, st, nrhs, dstat + b * rec, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hbuf + b * rec, dstat + b * rec, rec * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[b], s);
+    return e;
+  };
+  hipError_t pe = post_status(0);   // the slots right after begin
+  int done_it = 0, cur = 0;
+  while (pe == hipSuccess) {
+    const int kk = std::min(step, maxit - done_it);
+    if (kk > 0) {
+      pe = pcg_iterate_dev(P, st, nrhs, kk, s);
+      if (pe == hipSuccess) pe = post_status(cur ^ 1);
+      if (pe != hipSuccess) break;
+      done_it += kk;
+    }
+    pe = hipEventSynchronize(ev[cur]);
+    if (pe != hipSuccess) break;
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) any = any || hbuf[cur * rec + 4 * k] != 0.0;
+    if (!any || kk == 0) break;
+    cur ^= 1;
+  }
+  for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
+  if (pe != hipSuccess) return hip_fail(pe, "pcg iterate");
   // solution out, true residual
   double* x = (double*)(st + L.x);
   double* qz = (double*)(st + L.qz);

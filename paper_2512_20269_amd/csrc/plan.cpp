@@ -302,11 +302,12 @@ StateLayout state_layout(const Plan& P, int nslots) {
   s.ws = ws ? take(ws) : 0;
   size_t mw = matvec_ws_bytes(P, nslots);
   s.mvws = mw ? take(mw) : 0;
+  s.stat = take((size_t)2 * nslots * 4 * 8);
   s.total = off;
   // linear in nslots up to alignment: report a safe per-slot bound
   s.per_slot = align256(16 * 8) + align256(kHist * 16) + align256((size_t)3 * s.npart * 8) +
                4 * align256((size_t)P.N * 8) + apply_ws_bytes(P, 1) + matvec_ws_bytes(P, 1) +
-               8 * 256;
+               align256(2 * 4 * 8) + 8 * 256;
   s.fixed = 4096;
   return s;
 }

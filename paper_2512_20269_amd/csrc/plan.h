@@ -32,6 +32,7 @@ struct StateLayout {
   size_t x, r, p, qz;  // [nslots][N] FP64
   size_t ws;        // preconditioner workspace [nslots][N] (FP32 apply) or 0
   size_t mvws;      // operator workspace (3D: 2 [nslots][N] FP64) or 0
+  size_t stat;      // [2][nslots][4] per-slot records for pipelined polling
   size_t fixed, per_slot, total;
   int npart;
 };
