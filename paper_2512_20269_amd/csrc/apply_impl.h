@@ -132,7 +132,10 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   constexpr int RW = NTH < 64 ? NTH : 64;
   constexpr int NG = NTH / RW;
   constexpr int UMAX = (264 + RW - 1) / RW;  // m <= 264
-  constexpr int CH = 8;                       // loads in flight per thread
+  constexpr int CH = 8;                       // loads in flight per thread (generic path)
+  constexpr int MMAX = L / 2 + 6;             // m = n + p - 2 <= n + 6 = L/2 + 6
+  constexpr int UMX = (MMAX + RW - 1) / RW;   // row chunks of a contiguous line
+  constexpr int LPT = (TW + NG - 1) / NG;     // contiguous lines per thread
   extern __shared__ __align__(16) char smem[];
   const int m = g.m, n = g.n, n_reg = g.n_reg, n_out = g.n_out, half = g.half;
   const int MP = m | 1;
@@ -167,22 +170,10 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   const bool odd = (g.p & 1) != 0;
 
   // ---- tables, twiddles and per-line data into LDS ---------------------------
-  for (int l = t; l < TW; l += NTH) {
-    const int ql = q0 + l;
-    LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
-    if (MODE == PASS_MID) {
-      // spectral indices of the line in the other directions (the middle pass
-      // runs along the last direction, so the inner index holds them all)
-      T lo = T(0), so = T(1);
-      if (l < nv) {
-        const int i = ql % S;
-        const int j1 = i % m, j2 = i / m;
-        lo = tb.blob[tb.o_lam + j1];
-        so = tb.blob[tb.o_s + j1];
-        if (g.d == 3) { lo += tb.blob[tb.o_lam + j2]; so *= tb.blob[tb.o_s + j2]; }
-      }
-      LO[l] = lo;
-      SO[l] = so;
+  if (!(NTH % TW == 0 && S > 1)) {   // line bases for the generic tile paths
+    for (int l = t; l < TW; l += NTH) {
+      const int ql = q0 + l;
+      LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
     }
   }
   // issue the table loads now; they land in LDS after the tile loads are issued
@@ -196,28 +187,27 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 
   // ---- load the tile: X[l][j] = in(line l, position j); missing lines = 0 --
   if (S == 1) {
+    // every load of the thread is issued before the first LDS write
     const Tin* src = in + rhs * g.N + q0 * m;  // the tile's lines are contiguous
     const int lane = t % RW, grp = t / RW;
-    for (int l0 = grp; l0 < TW; l0 += 2 * NG) {
-      Tin v[2][UMAX];
+    Tin v[LPT][UMX];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int l = l0 + a * NG;
+    for (int a = 0; a < LPT; ++a) {
+      const int l = grp + a * NG;
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u) {
-          const int j = lane + RW * u;
-          v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
-        }
+      for (int u = 0; u < UMX; ++u) {
+        const int j = lane + RW * u;
+        v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
       }
+    }
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int l = l0 + a * NG;
-        if (l < TW) {
+    for (int a = 0; a < LPT; ++a) {
+      const int l = grp + a * NG;
+      if (l < TW) {
 #pragma unroll
-          for (int u = 0; u < UMAX; ++u) {
-            const int j = lane + RW * u;
-            if (j < m) X[l * MP + j] = (T)v[a][u];
-          }
+        for (int u = 0; u < UMX; ++u) {
+          const int j = lane + RW * u;
+          if (j < m) X[l * MP + j] = (T)v[a][u];
         }
       }
     }
@@ -233,17 +223,13 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     T* dst = X + l * MP + j0;
     const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
     const size_t step = (size_t)JS * S;
-    for (int k0 = 0; k0 < cnt; k0 += CH) {
-      Tin v[CH];
+    constexpr int KMAX = (MMAX + JS - 1) / JS;   // rows per thread, all in flight
+    Tin v[KMAX];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int k = k0 + u;
-        v[u] = (k < cnt && lv) ? src[k * step] : Tin(0);
-      }
+    for (int k = 0; k < KMAX; ++k) v[k] = (k < cnt && lv) ? src[k * step] : Tin(0);
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
-        if (k0 + u < cnt) dst[(k0 + u) * JS] = (T)v[u];
-    }
+    for (int k = 0; k < KMAX; ++k)
+      if (k < cnt) dst[k * JS] = (T)v[k];
   } else {
     __syncthreads();  // LB
     const int cnt = TW * m;
@@ -270,6 +256,23 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   }
   for (int e = t + BCH * NTH; e < tb.len; e += NTH) BL[e] = tb.blob[e];
   __syncthreads();
+  if (MODE == PASS_MID) {
+    // spectral indices of each line in the other directions (the middle pass
+    // runs along the last direction, so the inner index holds them all);
+    // read after the next barrier, by the forward transform's output stage
+    for (int l = t; l < TW; l += NTH) {
+      T lo = T(0), so = T(1);
+      if (l < nv) {
+        const int i = (q0 + l) % S;
+        const int j1 = i % m, j2 = i / m;
+        lo = LAM[j1];
+        so = SS[j1];
+        if (g.d == 3) { lo += LAM[j2]; so *= SS[j2]; }
+      }
+      LO[l] = lo;
+      SO[l] = so;
+    }
+  }
 
   // Kronecker-sum scaling of spectral entry j of line l (middle pass)
   auto fac = [&](int l, int j) -> T {
@@ -305,8 +308,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
           for (int j = sub; j < m; j += tpd) acc += vr[j] * xr[j];
         }
         for (int o = 1; o < tpd; o <<= 1) acc += __shfl_xor(acc, o);
-        if (sub == 0 && di < ndots)
-          CO[l * n_out + q] = (MODE == PASS_MID) ? acc * fac(l, n_reg + q) : acc;
+        if (sub == 0 && di < ndots) CO[l * n_out + q] = acc;
       }
     }
     for (int e = t; e < TW * 2 * half; e += NTH) {
@@ -325,6 +327,11 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       const int pos = c < half ? c0 + c : m - nbd + (c - half);
       X[l * MP + pos] = GB[l * GW + c];
     }
+    if (MODE == PASS_MID)   // the outlier coefficients take the same scaling
+      for (int e = t; e < TW * n_out; e += NTH) {
+        const int l = e / n_out, q = e - (e / n_out) * n_out;
+        CO[e] *= fac(l, n_reg + q);
+      }
     __syncthreads();
 
     // ---- forward transform: X[l][0..n_reg) = U^T g_l (scaled in the middle) --
