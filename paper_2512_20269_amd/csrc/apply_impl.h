@@ -295,8 +295,9 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     // ---- outlier dots; boundary fold into the g slots ----------------------
     if (n_out > 0) {
       const int ndots = TW * n_out;
-      int tpd = 1;
+      int tpd = 1;   // threads per dot: as many as the workgroup allows
       while (tpd < 64 && ndots * tpd * 2 <= NTH) tpd *= 2;
+      if (ndots * tpd < NTH && tpd < 64) tpd *= 2;
       const int sub = t % tpd;
       for (int di = t / tpd; di < (ndots + (NTH / tpd) - 1) / (NTH / tpd) * (NTH / tpd);
            di += NTH / tpd) {
@@ -305,7 +306,17 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
         if (di < ndots) {
           const T* vr = VT + q * m;
           const T* xr = X + l * MP;
-          for (int j = sub; j < m; j += tpd) acc += vr[j] * xr[j];
+          // four independent partial sums keep several LDS reads in flight
+          T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+          int j = sub;
+          for (; j + 3 * tpd < m; j += 4 * tpd) {
+            a0 += vr[j] * xr[j];
+            a1 += vr[j + tpd] * xr[j + tpd];
+            a2 += vr[j + 2 * tpd] * xr[j + 2 * tpd];
+            a3 += vr[j + 3 * tpd] * xr[j + 3 * tpd];
+          }
+          for (; j < m; j += tpd) a0 += vr[j] * xr[j];
+          acc = (a0 + a1) + (a2 + a3);
         }
         for (int o = 1; o < tpd; o <<= 1) acc += __shfl_xor(acc, o);
         if (sub == 0 && di < ndots) CO[l * n_out + q] = acc;
