@@ -301,3 +301,21 @@ def test_graph_solver_batch_of_64_full_size():
         assert np.array_equal(host(u1), U[b])
         assert s1[0]["iterations"] == st[b]["iterations"]
         assert s1[0]["relres_true"] <= 1.01e-8
+
+
+@pytest.mark.parametrize("p", [3, 8])
+def test_cube_n256_smooth_full_size_vs_oracle(p):
+    """The largest workload (3D n = 256, smooth right-hand side) against the
+    oracle at full size.  FP64: the 1e-12 gate.  FP32: at high degree the
+    operator amplifies the FP32 rounding of the input itself, so the bound is
+    the oracle's own error on the FP32-rounded input (plus the 1e-5 gate)."""
+    d, n = 3, 256
+    r = workloads.workload_rhs("cube_n256", p=p)
+    pre = oracle(d, n, p)
+    zo = pre.apply(r)
+    z64 = host(plan(d, n, p, "f64").apply(dev(r)))
+    assert rel(z64, zo) <= TOL["f64"]
+    e_in = rel(pre.apply(r.astype(np.float32).astype(np.float64)), zo)
+    z32 = host(plan(d, n, p, "f32").apply(dev(r)))
+    print(p, rel(z64, zo), rel(z32, zo), e_in, flush=True)
+    assert rel(z32, zo) <= TOL["f32"] + 20 * e_in
