@@ -488,11 +488,13 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   }
 }
 
+// the tables a pass stages in LDS: a prefix of the blob (odd p needs no twp,
+// only the middle pass needs lam and s)
 template <typename T>
-static Tabs<T> tables_of(const Plan& P) {
+static Tabs<T> tables_of(const Plan& P, int mode) {
   const char* b = P.d_tables + (sizeof(T) == 8 ? P.lay.blob64 : P.lay.blob32);
-  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s,
-          P.blob_len};
+  const int len = mode == PASS_MID ? P.blob_len : ((P.p & 1) ? P.bo_twp : P.bo_lam);
+  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len};
 }
 
 template <typename Tin, typename Tout, typename T, int MODE, int L, int V>
@@ -511,7 +513,8 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.d = P.d;
   g.active = active;
   g.active_stride = astride;
-  const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, P.blob_len);
+  const Tabs<T> tb = tables_of<T>(P, MODE);
+  const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, tb.len);
   static bool attr_set = false;
   if (mp.total > 65536 && !attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V>,
@@ -521,7 +524,7 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   }
   dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
   hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V>), grid, block, mp.total, s,
-                     (const Tin*)in, (Tout*)out, g, tables_of<T>(P));
+                     (const Tin*)in, (Tout*)out, g, tb);
   return hipGetLastError();
 }
 

@@ -217,12 +217,14 @@ void compute_layout(Plan& P) {
   {
     const int nbh = (P.p - 1) * P.half;
     int o = 0;
+    // ordered by use: every pass reads twl, Vt, V0, V1; even p also twp; only
+    // the middle pass reads lam and s (a pass stages just its prefix in LDS)
     P.bo_twl = o; o += 2 * std::max(P.L, 1);
-    P.bo_twp = o; o += 2 * (P.n + 1);
     P.bo_vt = o;  o += P.n_out * P.m;
     P.bo_v0 = o;  o += nbh;
     P.bo_v1 = o;  o += nbh;
     o += o & 1;
+    P.bo_twp = o; o += 2 * (P.n + 1);
     P.bo_lam = o; o += P.m;
     P.bo_s = o;   o += P.m;
     P.blob_len = o + (o & 1);

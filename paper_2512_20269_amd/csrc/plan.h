@@ -58,7 +58,7 @@ struct Plan {
   std::vector<double> Kc, Mc;       // compact band tables (crows x (2p+1))
   int nbr = 0, crows = 0;
   // element offsets of the line-pass tables inside one contiguous blob:
-  // twl (2L) | twp (2(n+1)) | Vt (n_out m) | V0 | V1 ((p-1) floor(p/2) each) | lam (m) | s (m)
+  // twl (2L) | Vt (n_out m) | V0 | V1 ((p-1) floor(p/2) each) | twp (2(n+1)) | lam (m) | s (m)
   int bo_twl = 0, bo_twp = 0, bo_vt = 0, bo_v0 = 0, bo_v1 = 0, bo_lam = 0, bo_s = 0, blob_len = 0;
 
   int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
