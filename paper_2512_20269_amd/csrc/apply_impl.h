@@ -160,12 +160,9 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   const int GW = 2 * nbd;
 
   const int t = threadIdx.x;
-  // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8), each XCD
-  // with its own L2.  Give every XCD one contiguous run of tiles, so tiles that
-  // share cache lines (neighbouring lines of a strided pass) meet in one L2.
-  const int nb = gridDim.x, q8 = nb >> 3, r8 = nb & 7;
-  const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
-  const int lin = xcd * q8 + (xcd < r8 ? xcd : r8) + kx;
+  // XCD-aware order: tiles that share cache lines (neighbouring lines of a
+  // strided pass) meet in one L2
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
   const int rhs = lin / g.tpr;
   const int tile = lin - rhs * g.tpr;
   if (g.active && g.active[(size_t)rhs * g.active_stride] == 0.0) return;

@@ -8,6 +8,16 @@
 namespace iffd {
 
 enum PassMode { PASS_FWD = 0, PASS_BWD = 1, PASS_MID = 2 };
+
+// Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8), each XCD
+// with its own L2.  This bijection of [0, nblocks) gives every XCD one
+// contiguous run of work items, so neighbouring items (which share cache
+// lines or halos) meet in one L2.
+__device__ __forceinline__ int xcd_linear(int b, int nblocks) {
+  const int q8 = nblocks >> 3, r8 = nblocks & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q8 + (x < r8 ? x : r8) + k;
+}
 enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
 
 // One IFFD line pass along `axis` (1-based; direction 1 = fastest) of the

@@ -40,7 +40,7 @@ mv_axis3(const double* __restrict__ x, double* __restrict__ t3, double* __restri
   constexpr int WIN = MV1_C3 + 2 * P;
   const int plane = m * m;
   const int cols_blocks = (plane + MV1_THREADS - 1) / MV1_THREADS;
-  int bid = blockIdx.x;
+  int bid = xcd_linear(blockIdx.x, gridDim.x);   // chunks of a column meet in one L2
   const int per_rhs = cols_blocks * nch;
   const int rhs = bid / per_rhs;
   bid -= rhs * per_rhs;
@@ -123,8 +123,9 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
   constexpr int OUT = 64 - 2 * P;
   __shared__ double red[MV2_THREADS / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int rhs = blockIdx.x / bpr;
-  const int blk = blockIdx.x - rhs * bpr;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);   // halo rows meet in one L2
+  const int rhs = lin / bpr;
+  const int blk = lin - rhs * bpr;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
   const int plane = m * m;
   const int planes = N / plane;
