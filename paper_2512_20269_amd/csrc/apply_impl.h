@@ -122,7 +122,7 @@ constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
 // p-1 boundary slots.  So every FFT input is one branch-free LDS read.  The
 // same holds backwards: U c is written to X[l][c0 + idx] and the p-1 boundary
 // values of each end are then unfolded in place.
-template <typename Tin, typename Tout, typename T, int MODE, int L, int V>
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, bool HALF>
 __global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
 line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
   using C = Cfg<T, L, V>;
@@ -133,8 +133,10 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   constexpr int NG = NTH / RW;
   constexpr int UMAX = (264 + RW - 1) / RW;  // m <= 264
   constexpr int CH = 8;                       // loads in flight per thread (generic path)
-  constexpr int MMAX = L / 2 + 6;             // m = n + p - 2 <= n + 6 = L/2 + 6
-  constexpr int UMX = (MMAX + RW - 1) / RW;   // row chunks of a contiguous line
+  // m = n + p - 2 <= n + 6; the loads of a tile row go in batches of MB entries,
+  // one batch when L = 2n, two when L = n (even p, length-n transforms)
+  constexpr int MB = L / 2 + 6;
+  constexpr int UMX = (MB + RW - 1) / RW;     // row chunks of a contiguous line per batch
   constexpr int LPT = (TW + NG - 1) / NG;     // contiguous lines per thread
   extern __shared__ __align__(16) char smem[];
   const int m = g.m, n = g.n, n_reg = g.n_reg, n_out = g.n_out, half = g.half;
@@ -193,24 +195,26 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     // every load of the thread is issued before the first LDS write
     const Tin* src = in + rhs * g.N + q0 * m;  // the tile's lines are contiguous
     const int lane = t % RW, grp = t / RW;
-    Tin v[LPT][UMX];
+    for (int jb = 0; jb < m; jb += UMX * RW) {
+      Tin v[LPT][UMX];
 #pragma unroll
-    for (int a = 0; a < LPT; ++a) {
-      const int l = grp + a * NG;
-#pragma unroll
-      for (int u = 0; u < UMX; ++u) {
-        const int j = lane + RW * u;
-        v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < LPT; ++a) {
-      const int l = grp + a * NG;
-      if (l < TW) {
+      for (int a = 0; a < LPT; ++a) {
+        const int l = grp + a * NG;
 #pragma unroll
         for (int u = 0; u < UMX; ++u) {
-          const int j = lane + RW * u;
-          if (j < m) X[l * MP + j] = (T)v[a][u];
+          const int j = jb + lane + RW * u;
+          v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < LPT; ++a) {
+        const int l = grp + a * NG;
+        if (l < TW) {
+#pragma unroll
+          for (int u = 0; u < UMX; ++u) {
+            const int j = jb + lane + RW * u;
+            if (j < m) X[l * MP + j] = (T)v[a][u];
+          }
         }
       }
     }
@@ -226,13 +230,16 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     T* dst = X + l * MP + j0;
     const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
     const size_t step = (size_t)JS * S;
-    constexpr int KMAX = (MMAX + JS - 1) / JS;   // rows per thread, all in flight
-    Tin v[KMAX];
+    constexpr int KMAX = (MB + JS - 1) / JS;   // rows per thread and batch, all in flight
+    for (int kb = 0; kb < cnt; kb += KMAX) {
+      Tin v[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) v[k] = (k < cnt && lv) ? src[k * step] : Tin(0);
+      for (int k = 0; k < KMAX; ++k)
+        v[k] = (kb + k < cnt && lv) ? src[(kb + k) * step] : Tin(0);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < cnt) dst[k * JS] = (T)v[k];
+      for (int k = 0; k < KMAX; ++k)
+        if (kb + k < cnt) dst[(kb + k) * JS] = (T)v[k];
+    }
   } else {
     __syncthreads();  // LB
     const int cnt = TW * m;
@@ -372,8 +379,62 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Xa + j : dmy) = a;
       *(ok ? Xb + j : dmy + 1) = b;
     };
-    fft_forward<T, L, V>(buf, tid, twl, ld, st);
-    __syncthreads();
+    if constexpr (!HALF) {
+      fft_forward<T, L, V>(buf, tid, twl, ld, st);
+      __syncthreads();
+    } else {
+      // even p with L = n: the length-n transform of the reordered sequence
+      // v_i = g_2i, v_{n-1-i} = -g_{2i+1} (two lines packed as real and
+      // imaginary parts) stays in this transform's LDS region in natural order;
+      // the pair (W_k, W_{n-k}) then gives the coefficients n-k and k of both
+      // lines: V = (W_k + conj W_{n-k})/2 for line a, -i (W_k - conj W_{n-k})/2
+      // for line b, C(k) = Re(t_k V), C(n-k) = Re(t_{n-k} conj V), t = twp.
+      constexpr int N = L;
+      auto ldh = [&](int k, bool lo, bool, bool) -> cpx<T> {
+        const int idx = lo ? 2 * k : 2 * N - 1 - 2 * k;
+        const T a = Ga[idx], b = Gb[idx];
+        return {lo ? a : -a, lo ? b : -b};
+      };
+      auto sth = [&](int k, cpx<T> v) { buf[fpad(k)] = v; };
+      fft_forward<T, L, V>(buf, tid, twl, ldh, sth);
+      __syncthreads();
+      constexpr int NP = (N / 2 + 1 + NT - 1) / NT;   // pairs per thread
+      T ra[NP][2], rb[NP][2];
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int k = tid + NT * u;
+        const int kk = k <= N / 2 ? k : 0;
+        const cpx<T> wk = buf[fpad(kk)], wm = buf[fpad(kk == 0 ? 0 : N - kk)];
+        const cpx<T> va = {T(0.5) * (wk.x + wm.x), T(0.5) * (wk.y - wm.y)};
+        const cpx<T> vb = {T(0.5) * (wk.y + wm.y), T(-0.5) * (wk.x - wm.x)};
+        const cpx<T> tk = twp[kk], tm = twp[N - kk];
+        ra[u][0] = tk.x * va.x - tk.y * va.y;   // C_a(k)
+        rb[u][0] = tk.x * vb.x - tk.y * vb.y;
+        ra[u][1] = tm.x * va.x + tm.y * va.y;   // C_a(n-k)
+        rb[u][1] = tm.x * vb.x + tm.y * vb.y;
+      }
+      __syncthreads();   // every W is read before the rows (aliasing the regions) are written
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int k = tid + NT * u;
+        if (k <= N / 2) {
+          // coefficient j = n - k at position n-k-1, coefficient k at position k-1
+          const int p0 = N - k - 1;
+          T a0 = ra[u][0], b0 = rb[u][0];
+          if (MODE == PASS_MID) { a0 *= fac(la, p0); b0 *= fac(lb, p0); }
+          Xa[p0] = a0;
+          Xb[p0] = b0;
+          if (k >= 1 && 2 * k < N) {
+            const int p1 = k - 1;
+            T a1 = ra[u][1], b1 = rb[u][1];
+            if (MODE == PASS_MID) { a1 *= fac(la, p1); b1 *= fac(lb, p1); }
+            Xa[p1] = a1;
+            Xb[p1] = b1;
+          }
+        }
+      }
+      __syncthreads();
+    }
     if (MODE == PASS_FWD) {
       for (int e = t; e < TW * n_out; e += NTH) {
         const int l = e / n_out, q = e - (e / n_out) * n_out;
@@ -421,7 +482,31 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Ga + j : dmy) = T(-0.5) * v.y;
       *(ok ? Gb + j : dmy + 1) = odd ? T(0.5) * v.x : T(-0.5) * v.x;
     };
-    fft_forward<T, L, V>(buf, tid, twl, ld, st);
+    if constexpr (!HALF) {
+      fft_forward<T, L, V>(buf, tid, twl, ld, st);
+    } else {
+      // even p with L = n: with d_k = c_{n-k} (d_n = 0), the Hermitian sequence
+      // Z_0 = d_0, Z_k = t_k (d_k + i d_{n-k}) / 2 has a real transform v; two
+      // lines packed as Z_a + i Z_b, and x_2i = v_i, x_{2i+1} = -v_{n-1-i}
+      constexpr int N = L;
+      auto ldh = [&](int k, bool, bool k0, bool) -> cpx<T> {
+        const T ak = Xa[N - k - 1], bk = Xb[N - k - 1];
+        const int km = k0 ? 0 : k - 1;
+        const T am = k0 ? T(0) : Xa[km], bm = k0 ? T(0) : Xb[km];
+        const cpx<T> tk = twp[k];
+        const cpx<T> za = c_mul(tk, cpx<T>{ak, am}), zb = c_mul(tk, cpx<T>{bk, bm});
+        const cpx<T> ya = k0 ? cpx<T>{ak, T(0)} : cpx<T>{T(0.5) * za.x, T(0.5) * za.y};
+        const cpx<T> yb = k0 ? cpx<T>{bk, T(0)} : cpx<T>{T(0.5) * zb.x, T(0.5) * zb.y};
+        return {ya.x - yb.y, ya.y + yb.x};
+      };
+      auto sth = [&](int k, cpx<T> v) {
+        const bool lo = k < N / 2;
+        const int idx = lo ? 2 * k : 2 * (N - 1 - k) + 1;
+        Ga[idx] = lo ? v.x : -v.x;
+        Gb[idx] = lo ? v.y : -v.y;
+      };
+      fft_forward<T, L, V>(buf, tid, twl, ldh, sth);
+    }
     __syncthreads();
     // ---- unfold the ends in place: x = V_reg,0 g_left, V_reg,1 g_right --------
     for (int e = t; e < TW * 2 * nbd; e += NTH) {
@@ -494,7 +579,7 @@ static Tabs<T> tables_of(const Plan& P, int mode) {
   return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len};
 }
 
-template <typename Tin, typename Tout, typename T, int MODE, int L, int V>
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, bool HALF>
 static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, int nrhs,
                            const double* active, int astride, hipStream_t s) {
   using C = Cfg<T, L, V>;
@@ -514,13 +599,13 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, tb.len);
   static bool attr_set = false;
   if (mp.total > 65536 && !attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V, HALF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
-  hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V>), grid, block, mp.total, s,
+  hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V, HALF>), grid, block, mp.total, s,
                      (const Tin*)in, (Tout*)out, g, tb);
   return hipGetLastError();
 }
@@ -528,8 +613,13 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
                              const double* a, int as, hipStream_t s) {
-  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0>(P, axis, in, out, nrhs, a, as, s);
-  return launch_t<Tin, Tout, T, MODE, L, 1>(P, axis, in, out, nrhs, a, as, s);
+  // even p with length-n transforms: a kernel of its own (L = n)
+  if (P.half_len) {
+    if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, true>(P, axis, in, out, nrhs, a, as, s);
+    return launch_t<Tin, Tout, T, MODE, L, 1, true>(P, axis, in, out, nrhs, a, as, s);
+  }
+  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, false>(P, axis, in, out, nrhs, a, as, s);
+  return launch_t<Tin, Tout, T, MODE, L, 1, false>(P, axis, in, out, nrhs, a, as, s);
 }
 
 // all modes, element types and variants of the line pass for one FFT length

@@ -337,8 +337,12 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   if (P.N * (int64_t)P.max_rhs >= (int64_t(1) << 31)) { err = "problem too large for 32-bit indexing"; return IFFD_E_UNSUPPORTED; }
   if (P.method == IFFD_METHOD_FFT) {
     if (p < 2) { err = "IFFD needs p >= 2 (p = 1 has no outlier split; use DENSE_FD)"; return IFFD_E_UNSUPPORTED; }
-    P.L = 2 * n;
-    if (!fft_len_supported(P.L)) { err = "n must be 2^a or 3*2^a with 8 <= n <= 256 for the FFT kernels"; return IFFD_E_UNSUPPORTED; }
+    // odd p: DST-I through a length-2n FFT of the odd extension; even p:
+    // DST-II / DST-III through a length-n FFT of a reordered sequence where
+    // the kernels have that length, else through the length-2n extension
+    P.half_len = (p % 2 == 0) && fft_len_supported(n);
+    P.L = P.half_len ? n : 2 * n;
+    if (n > 256 || !fft_len_supported(P.L)) { err = "n must be 2^a or 3*2^a with 8 <= n <= 256 for the FFT kernels"; return IFFD_E_UNSUPPORTED; }
   }
   const int m = P.m, bw = 2 * p + 1, nb = n + p;  // nb: full basis size
   const double h = 1.0 / n;
