@@ -41,10 +41,13 @@
 
 namespace iffd {
 
+enum { PK_ODD = 0, PK_EVEN_2N = 1, PK_EVEN_N = 2 };
+
 template <typename T>
 struct Tabs {
   const T* blob;  // twl | twp | Vt | V0 | V1 | lam | s, element offsets below
   int o_twl, o_twp, o_vt, o_v0, o_v1, o_lam, o_s, len;
+  int nch;  // 16-byte chunks covering the staged prefix (the blob is padded)
 };
 
 struct Geom {
@@ -54,6 +57,7 @@ struct Geom {
   int tpr;     // tiles per right-hand side
   int N;       // elements per right-hand side
   int d;
+  int tpd_log;  // log2 of the threads per outlier dot
   const double* active;  // per-RHS flags or null
   int active_stride;
 };
@@ -122,7 +126,9 @@ constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
 // p-1 boundary slots.  So every FFT input is one branch-free LDS read.  The
 // same holds backwards: U c is written to X[l][c0 + idx] and the p-1 boundary
 // values of each end are then unfolded in place.
-template <typename Tin, typename Tout, typename T, int MODE, int L, int V, bool HALF>
+// PK: the sine transform route, fixed per kernel: PK_ODD (DST-I, L = 2n),
+// PK_EVEN_2N (DST-II / DST-III, L = 2n), PK_EVEN_N (DST-II / DST-III, L = n).
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
 __global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
 line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
   using C = Cfg<T, L, V>;
@@ -172,49 +178,46 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   const int nv = min(TW, g.lpr - q0);
   const int S = g.S;
   const int c0 = g.c0;
-  const bool odd = (g.p & 1) != 0;
+  constexpr bool odd = PK == PK_ODD;
 
   // ---- tables, twiddles and per-line data into LDS ---------------------------
-  if (!(NTH % TW == 0 && S > 1)) {   // line bases for the generic tile paths
-    for (int l = t; l < TW; l += NTH) {
-      const int ql = q0 + l;
-      LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
-    }
+  if constexpr (NTH % TW != 0) {   // line bases for the generic strided path
+    if (S > 1)
+      for (int l = t; l < TW; l += NTH) {
+        const int ql = q0 + l;
+        LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
+      }
   }
-  // issue the table loads now; they land in LDS after the tile loads are issued
-  constexpr int BCH = 16;
-  T bv[BCH];
+  // issue the table loads (16-byte chunks) now; they land in LDS after the
+  // tile loads are issued
+  constexpr int BCH = 4;
+  const auto trs = buf_rsrc(tb.blob, (unsigned)tb.nch * 16u);
+  u32x4 bv[BCH];
 #pragma unroll
-  for (int u = 0; u < BCH; ++u) {
-    const int e = t + u * NTH;
-    bv[u] = e < tb.len ? tb.blob[e] : T(0);
-  }
+  for (int u = 0; u < BCH; ++u) bv[u] = buf_ld16(trs, (unsigned)(t + u * NTH) * 16u);
 
   // ---- load the tile: X[l][j] = in(line l, position j); missing lines = 0 --
+  // (buffer loads: entries past the tile or the tensor read as 0)
   if (S == 1) {
-    // every load of the thread is issued before the first LDS write
-    const Tin* src = in + rhs * g.N + q0 * m;  // the tile's lines are contiguous
+    // every load of a batch is issued before its first LDS write
+    const auto rs = buf_rsrc(in + (size_t)rhs * g.N + (size_t)q0 * m,
+                             (unsigned)(nv * m * (int)sizeof(Tin)));
     const int lane = t % RW, grp = t / RW;
+    const unsigned vo = (unsigned)(grp * m + lane) * sizeof(Tin);
     for (int jb = 0; jb < m; jb += UMX * RW) {
       Tin v[LPT][UMX];
 #pragma unroll
-      for (int a = 0; a < LPT; ++a) {
-        const int l = grp + a * NG;
+      for (int a = 0; a < LPT; ++a)
 #pragma unroll
-        for (int u = 0; u < UMX; ++u) {
-          const int j = jb + lane + RW * u;
-          v[a][u] = (l < nv && j < m) ? src[l * m + j] : Tin(0);
-        }
-      }
+        for (int u = 0; u < UMX; ++u)
+          v[a][u] = buf_ld<Tin>(rs, vo + (unsigned)((a * NG * m + jb + RW * u) * (int)sizeof(Tin)));
 #pragma unroll
-      for (int a = 0; a < LPT; ++a) {
-        const int l = grp + a * NG;
-        if (l < TW) {
+      for (int u = 0; u < UMX; ++u) {
+        const int j = jb + lane + RW * u;
+        if (j < m) {
 #pragma unroll
-          for (int u = 0; u < UMX; ++u) {
-            const int j = jb + lane + RW * u;
-            if (j < m) X[l * MP + j] = (T)v[a][u];
-          }
+          for (int a = 0; a < LPT; ++a)
+            if (grp + a * NG < TW) X[(grp + a * NG) * MP + j] = (T)v[a][u];
         }
       }
     }
@@ -224,18 +227,18 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     constexpr int JS = NTH / TW;
     const int l = t & (TW - 1), j0 = t >> LTW;
     const int q = q0 + l;
-    const bool lv = l < nv;
-    const Tin* src = in + ((size_t)rhs * g.N + (size_t)(q / S) * m * S + (q % S) +
-                           (size_t)j0 * S) * (lv ? 1 : 0);
+    const auto rs = buf_rsrc(in + (size_t)rhs * g.N, (unsigned)(g.N * (int)sizeof(Tin)));
+    const unsigned vo = l < nv ? (unsigned)((q / S) * m * S + (q % S) + j0 * S) * sizeof(Tin)
+                               : BUF_OOB;
     T* dst = X + l * MP + j0;
     const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
-    const size_t step = (size_t)JS * S;
+    const int step = JS * S * (int)sizeof(Tin);
     constexpr int KMAX = (MB + JS - 1) / JS;   // rows per thread and batch, all in flight
-    for (int kb = 0; kb < cnt; kb += KMAX) {
+    const int kend = (m + JS - 1) / JS;        // the most rows any thread has
+    for (int kb = 0; kb < kend; kb += KMAX) {
       Tin v[KMAX];
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        v[k] = (kb + k < cnt && lv) ? src[(kb + k) * step] : Tin(0);
+      for (int k = 0; k < KMAX; ++k) v[k] = buf_ld<Tin>(rs, vo + (unsigned)((kb + k) * step));
 #pragma unroll
       for (int k = 0; k < KMAX; ++k)
         if (kb + k < cnt) dst[(kb + k) * JS] = (T)v[k];
@@ -259,12 +262,13 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       }
     }
   }
+  {
+    u32x4* B4 = reinterpret_cast<u32x4*>(BL);
 #pragma unroll
-  for (int u = 0; u < BCH; ++u) {
-    const int e = t + u * NTH;
-    if (e < tb.len) BL[e] = bv[u];
+    for (int u = 0; u < BCH; ++u)
+      if (t + u * NTH < tb.nch) B4[t + u * NTH] = bv[u];
+    for (int c = t + BCH * NTH; c < tb.nch; c += NTH) B4[c] = buf_ld16(trs, (unsigned)c * 16u);
   }
-  for (int e = t + BCH * NTH; e < tb.len; e += NTH) BL[e] = tb.blob[e];
   __syncthreads();
   if (MODE == PASS_MID) {
     // spectral indices of each line in the other directions (the middle pass
@@ -304,15 +308,17 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   if (MODE == PASS_FWD || MODE == PASS_MID) {
     // ---- outlier dots; boundary fold into the g slots ----------------------
     if (n_out > 0) {
+      // 1 << tl threads per dot (chosen on the host), every thread runs the
+      // same number of rounds so the shuffles see all lanes
+      const int tl = g.tpd_log, tpd = 1 << tl;
       const int ndots = TW * n_out;
-      int tpd = 1;   // threads per dot: as many as the workgroup allows
-      while (tpd < 64 && ndots * tpd * 2 <= NTH) tpd *= 2;
-      if (ndots * tpd < NTH && tpd < 64) tpd *= 2;
-      const int sub = t % tpd;
-      for (int di = t / tpd; di < (ndots + (NTH / tpd) - 1) / (NTH / tpd) * (NTH / tpd);
-           di += NTH / tpd) {
+      const int per = NTH >> tl;
+      const int rounds = (ndots + per - 1) / per;
+      const int sub = t & (tpd - 1);
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int di = (t >> tl) + rd * per;
         T acc = T(0);
-        const int l = di % TW, q = di / TW;
+        const int l = di & (TW - 1), q = di >> LTW;
         if (di < ndots) {
           const T* vr = VT + q * m;
           const T* xr = X + l * MP;
@@ -350,8 +356,8 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     }
     if (MODE == PASS_MID)   // the outlier coefficients take the same scaling
       for (int e = t; e < TW * n_out; e += NTH) {
-        const int l = e / n_out, q = e - (e / n_out) * n_out;
-        CO[e] *= fac(l, n_reg + q);
+        const int l = e & (TW - 1), q = e >> LTW;
+        CO[l * n_out + q] *= fac(l, n_reg + q);
       }
     __syncthreads();
 
@@ -379,7 +385,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Xa + j : dmy) = a;
       *(ok ? Xb + j : dmy + 1) = b;
     };
-    if constexpr (!HALF) {
+    if constexpr (PK != PK_EVEN_N) {
       fft_forward<T, L, V>(buf, tid, twl, ld, st);
       __syncthreads();
     } else {
@@ -437,15 +443,15 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     }
     if (MODE == PASS_FWD) {
       for (int e = t; e < TW * n_out; e += NTH) {
-        const int l = e / n_out, q = e - (e / n_out) * n_out;
-        X[l * MP + n_reg + q] = CO[e];
+        const int l = e & (TW - 1), q = e >> LTW;
+        X[l * MP + n_reg + q] = CO[l * n_out + q];
       }
       __syncthreads();
     }
   } else {
     for (int e = t; e < TW * n_out; e += NTH) {
-      const int l = e / n_out, q = e - (e / n_out) * n_out;
-      CO[e] = X[l * MP + n_reg + q];
+      const int l = e & (TW - 1), q = e >> LTW;
+      CO[l * n_out + q] = X[l * MP + n_reg + q];
     }
   }
 
@@ -482,7 +488,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Ga + j : dmy) = T(-0.5) * v.y;
       *(ok ? Gb + j : dmy + 1) = odd ? T(0.5) * v.x : T(-0.5) * v.x;
     };
-    if constexpr (!HALF) {
+    if constexpr (PK != PK_EVEN_N) {
       fft_forward<T, L, V>(buf, tid, twl, ld, st);
     } else {
       // even p with L = n: with d_k = c_{n-k} (d_n = 0), the Hermitian sequence
@@ -531,20 +537,32 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   }
 
   // ---- store: the tile row, plus the outlier block after the backward pass --
-  auto value = [&](int l, int j) -> T {
+  // n_out <= 6 (p <= 8); a line's outlier coefficients are held in registers
+  constexpr int MAXO = 6;
+  auto load_co = [&](int l, T* co) {
+#pragma unroll
+    for (int q = 0; q < MAXO; ++q) co[q] = (MODE != PASS_FWD && q < n_out) ? CO[l * n_out + q] : T(0);
+  };
+  auto value = [&](int l, int j, const T* co) -> T {
     T v = X[l * MP + j];
-    if (MODE != PASS_FWD)
-      for (int q = 0; q < n_out; ++q) v += VT[q * m + j] * CO[l * n_out + q];
+    if (MODE != PASS_FWD) {
+#pragma unroll
+      for (int q = 0; q < MAXO; ++q)
+        if (q < n_out) v += VT[q * m + j] * co[q];
+    }
     return v;
   };
   if (S == 1) {
-    Tout* dst = out + rhs * g.N + q0 * m;
+    const auto rs = buf_rsrc(out + (size_t)rhs * g.N + (size_t)q0 * m,
+                             (unsigned)(nv * m * (int)sizeof(Tout)));
     const int lane = t % RW, grp = t / RW;
     for (int l = grp; l < nv; l += NG) {
+      T co[MAXO];
+      load_co(l, co);
 #pragma unroll
       for (int u = 0; u < UMAX; ++u) {
         const int j = lane + RW * u;
-        if (j < m) dst[l * m + j] = (Tout)value(l, j);
+        if (j < m) buf_st<Tout>((Tout)value(l, j, co), rs, (unsigned)(l * m + j) * sizeof(Tout));
       }
     }
   } else if constexpr (NTH % TW == 0) {
@@ -552,10 +570,14 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     const int l = t & (TW - 1), j0 = t >> LTW;
     const int q = q0 + l;
     if (l < nv && j0 < m) {
-      Tout* dst = out + (size_t)rhs * g.N + (size_t)(q / S) * m * S + (q % S) + (size_t)j0 * S;
+      T co[MAXO];
+      load_co(l, co);
+      const auto rs = buf_rsrc(out + (size_t)rhs * g.N, (unsigned)(g.N * (int)sizeof(Tout)));
+      const unsigned vo = (unsigned)((q / S) * m * S + (q % S) + j0 * S) * sizeof(Tout);
       const int cnt = (m - j0 + JS - 1) / JS;
-      const size_t step = (size_t)JS * S;
-      for (int k = 0; k < cnt; ++k) dst[k * step] = (Tout)value(l, j0 + k * JS);
+      const int step = JS * S * (int)sizeof(Tout);
+      for (int k = 0; k < cnt; ++k)
+        buf_st<Tout>((Tout)value(l, j0 + k * JS, co), rs, vo + (unsigned)(k * step));
     }
   } else {
     const int cnt = TW * m;
@@ -564,7 +586,11 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       for (int u = 0; u < CH; ++u) {
         const int e = e0 + u * NTH;
         const int l = e & (TW - 1), j = e >> LTW;
-        if (e < cnt && l < nv) out[LB[l] + j * S] = (Tout)value(l, j);
+        if (e < cnt && l < nv) {
+          T co[MAXO];
+          load_co(l, co);
+          out[LB[l] + j * S] = (Tout)value(l, j, co);
+        }
       }
     }
   }
@@ -576,10 +602,11 @@ template <typename T>
 static Tabs<T> tables_of(const Plan& P, int mode) {
   const char* b = P.d_tables + (sizeof(T) == 8 ? P.lay.blob64 : P.lay.blob32);
   const int len = mode == PASS_MID ? P.blob_len : ((P.p & 1) ? P.bo_twp : P.bo_lam);
-  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len};
+  const int nch = (int)((len * sizeof(T) + 15) / 16);
+  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len, nch};
 }
 
-template <typename Tin, typename Tout, typename T, int MODE, int L, int V, bool HALF>
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
 static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, int nrhs,
                            const double* active, int astride, hipStream_t s) {
   using C = Cfg<T, L, V>;
@@ -595,17 +622,27 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.d = P.d;
   g.active = active;
   g.active_stride = astride;
+  {
+    // threads per outlier dot: as many as the workgroup allows, up to a wave
+    const int ndots = C::TW * P.n_out;
+    int tpd = 1;
+    while (tpd < 64 && ndots * tpd * 2 <= C::NTH) tpd *= 2;
+    if (ndots * tpd < C::NTH && tpd < 64) tpd *= 2;
+    int tl = 0;
+    while ((1 << tl) < tpd) ++tl;
+    g.tpd_log = tl;
+  }
   const Tabs<T> tb = tables_of<T>(P, MODE);
   const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, tb.len);
   static bool attr_set = false;
   if (mp.total > 65536 && !attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V, HALF>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V, PK>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
-  hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V, HALF>), grid, block, mp.total, s,
+  hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V, PK>), grid, block, mp.total, s,
                      (const Tin*)in, (Tout*)out, g, tb);
   return hipGetLastError();
 }
@@ -613,13 +650,25 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
                              const double* a, int as, hipStream_t s) {
-  // even p with length-n transforms: a kernel of its own (L = n)
-  if (P.half_len) {
-    if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, true>(P, axis, in, out, nrhs, a, as, s);
-    return launch_t<Tin, Tout, T, MODE, L, 1, true>(P, axis, in, out, nrhs, a, as, s);
+  // one kernel per transform route; L = 2n for even p only where n is not a
+  // supported length (n = 8, 12), L = n only up to 256
+  if (P.p & 1) {
+    if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_ODD>(P, axis, in, out, nrhs, a, as, s);
+    return launch_t<Tin, Tout, T, MODE, L, 1, PK_ODD>(P, axis, in, out, nrhs, a, as, s);
   }
-  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, false>(P, axis, in, out, nrhs, a, as, s);
-  return launch_t<Tin, Tout, T, MODE, L, 1, false>(P, axis, in, out, nrhs, a, as, s);
+  if constexpr (L <= 24) {
+    if (!P.half_len) {
+      if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_EVEN_2N>(P, axis, in, out, nrhs, a, as, s);
+      return launch_t<Tin, Tout, T, MODE, L, 1, PK_EVEN_2N>(P, axis, in, out, nrhs, a, as, s);
+    }
+  }
+  if constexpr (L <= 256) {
+    if (P.half_len) {
+      if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_EVEN_N>(P, axis, in, out, nrhs, a, as, s);
+      return launch_t<Tin, Tout, T, MODE, L, 1, PK_EVEN_N>(P, axis, in, out, nrhs, a, as, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // all modes, element types and variants of the line pass for one FFT length

@@ -18,6 +18,39 @@ __device__ __forceinline__ int xcd_linear(int b, int nblocks) {
   const int x = b & 7, k = b >> 3;
   return x * q8 + (x < r8 ? x : r8) + k;
 }
+// Raw buffer access (gfx9 buffer resource, 32-bit data format): the hardware
+// checks each lane's offset (`voff` plus the instruction's immediate offset)
+// against `bytes`; a load beyond returns 0 and a store beyond is dropped, so
+// tails and missing lines need no branches.  The whole offset goes in `voff`
+// (the scalar offset field, not range-checked, stays 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+// an offset no resource reaches (resources cover under 2 GiB)
+constexpr unsigned BUF_OOB = 0x80000000u;
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, unsigned voff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)voff, 0, 0);
+}
+// 16 bytes
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+__device__ __forceinline__ u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0);
+}
+
 enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
 
 // One IFFD line pass along `axis` (1-based; direction 1 = fastest) of the
