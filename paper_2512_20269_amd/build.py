@@ -24,7 +24,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiffd.so")
 
 SOURCES = ["plan.cpp", "api.cpp", "apply.hip", "apply_la.hip", "apply_lb.hip", "apply_lc.hip",
-           "apply_ld.hip", "apply_le.hip", "apply_lf.hip", "apply_lg.hip", "setup.hip", "matvec.hip",
+           "apply_ld.hip", "apply_le.hip", "setup.hip", "matvec.hip",
            "pcg.hip", "dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,10 +22,6 @@ hipError_t line_pass_L192(const Plan& P, int mode, int var, int axis, int tin, c
                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
 hipError_t line_pass_L256(const Plan& P, int mode, int var, int axis, int tin, const void* in,
                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
-hipError_t line_pass_L384(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
-hipError_t line_pass_L512(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
 
 hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
                             void* out, int nrhs, const double* a, int as, hipStream_t s) {
@@ -43,8 +39,6 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
     case 128: return line_pass_L128(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
     case 192: return line_pass_L192(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
     case 256: return line_pass_L256(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 384: return line_pass_L384(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 512: return line_pass_L512(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
     default: return hipErrorInvalidValue;
   }
 }

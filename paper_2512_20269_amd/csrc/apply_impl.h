@@ -41,7 +41,7 @@
 
 namespace iffd {
 
-enum { PK_ODD = 0, PK_EVEN_2N = 1, PK_EVEN_N = 2 };
+enum { PK_ODD = 0, PK_EVEN_2N = 1, PK_EVEN_N = 2, PK_ODD_N = 3 };
 
 template <typename T>
 struct Tabs {
@@ -62,11 +62,14 @@ struct Geom {
   int active_stride;
 };
 
+// Tile shape of variant V: E transform elements per thread (variant 2 takes
+// variant 1's FFT shape), FPW line pairs per workgroup (variant 2 half as many,
+// for problems too small to fill the chip with full tiles).
 template <typename T, int L, int V>
 struct Cfg {
   static constexpr int E = FftPlan<L, V>::E;
   static constexpr int NT = L / E;
-  static constexpr int CAP = (sizeof(T) == 8 ? 128 : 256) / NT;
+  static constexpr int CAP = (sizeof(T) == 8 ? 128 : 256) / (V == 2 ? 2 * NT : NT);
   static constexpr int FPW = CAP >= 32 ? 32 : (CAP < 1 ? 1 : CAP);
   static constexpr int TW = 2 * FPW;
   static constexpr int NTH = FPW * NT;
@@ -127,7 +130,8 @@ constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
 // same holds backwards: U c is written to X[l][c0 + idx] and the p-1 boundary
 // values of each end are then unfolded in place.
 // PK: the sine transform route, fixed per kernel: PK_ODD (DST-I, L = 2n),
-// PK_EVEN_2N (DST-II / DST-III, L = 2n), PK_EVEN_N (DST-II / DST-III, L = n).
+// PK_EVEN_2N (DST-II / DST-III, L = 2n), PK_EVEN_N (DST-II / DST-III, L = n),
+// PK_ODD_N (DST-I, L = n).
 template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
 __global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
 line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
@@ -170,6 +174,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   const int t = threadIdx.x;
   // XCD-aware order: tiles that share cache lines (neighbouring lines of a
   // strided pass) meet in one L2
+  T* sink = DM + 2 * t;  // per-thread slot for discarded values
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
   const int rhs = lin / g.tpr;
   const int tile = lin - rhs * g.tpr;
@@ -178,7 +183,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   const int nv = min(TW, g.lpr - q0);
   const int S = g.S;
   const int c0 = g.c0;
-  constexpr bool odd = PK == PK_ODD;
+  constexpr bool odd = PK == PK_ODD || PK == PK_ODD_N;
 
   // ---- tables, twiddles and per-line data into LDS ---------------------------
   if constexpr (NTH % TW != 0) {   // line bases for the generic strided path
@@ -211,13 +216,15 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 #pragma unroll
         for (int u = 0; u < UMX; ++u)
           v[a][u] = buf_ld<Tin>(rs, vo + (unsigned)((a * NG * m + jb + RW * u) * (int)sizeof(Tin)));
+      // entries past the row go to a sink (a select, not a branch, so the
+      // compiler keeps every load of the batch ahead of the first write)
 #pragma unroll
       for (int u = 0; u < UMX; ++u) {
         const int j = jb + lane + RW * u;
-        if (j < m) {
 #pragma unroll
-          for (int a = 0; a < LPT; ++a)
-            if (grp + a * NG < TW) X[(grp + a * NG) * MP + j] = (T)v[a][u];
+        for (int a = 0; a < LPT; ++a) {
+          const int l = grp + a * NG;
+          *((j < m && l < TW) ? X + l * MP + j : sink) = (T)v[a][u];
         }
       }
     }
@@ -240,8 +247,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) v[k] = buf_ld<Tin>(rs, vo + (unsigned)((kb + k) * step));
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (kb + k < cnt) dst[(kb + k) * JS] = (T)v[k];
+      for (int k = 0; k < KMAX; ++k) *(kb + k < cnt ? dst + (kb + k) * JS : sink) = (T)v[k];
     }
   } else {
     __syncthreads();  // LB
@@ -304,6 +310,78 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   T* Ga = Xa + c0;  // g (or U c) of line a
   T* Gb = Xb + c0;
   T* dmy = DM + 2 * t;
+
+  // DST-I of the two lines of this pair by one length-n FFT (odd p, L = n).
+  // With v_0 = v_n = 0, S_j = sin(pi j / n) and
+  //   y_j = S_j (v_j + v_{n-j}) + (v_j - v_{n-j}) / 2,
+  // the transform Y_k = sum_j y_j e^{-2 pi i jk/n} = A_k - i B_k gives the sine
+  // coefficients F_k = sum_j v_j sin(pi jk/n) as F_2k = B_k and
+  // F_2k+1 = F_2k-1 + A_k with F_-1 = -F_1, i.e. F_2k+1 = A_0 + .. + A_k - A_0/2
+  // (the sine part of y is odd about n/2 and the difference part even, and
+  // 2 sin(pi j/n) cos(2 pi jk/n) = sin(pi j(2k+1)/n) - sin(pi j(2k-1)/n)).
+  // The two lines go in as y_a + i y_b; each thread then takes E/2
+  // consecutive k, the prefix sums of A run through the pair's NT lanes.
+  // Input v_j at sa/sb[j-1], output F_k at da/db[k-1] (times the Kronecker-sum
+  // factor when SCALE).
+  auto dst1n = [&](const T* sa, const T* sb, T* da, T* db, auto scale_tag) {
+    constexpr bool SCALE = decltype(scale_tag)::value;
+    constexpr int N = L;
+    auto ldo = [&](int j, bool, bool j0, bool) -> cpx<T> {
+      const int jj = j0 ? 1 : j;   // y_0 = 0; keeps the reads in range
+      const T va = sa[jj - 1], vb = sb[jj - 1];
+      const T wa = sa[N - jj - 1], wb = sb[N - jj - 1];
+      const int h = jj <= N / 2 ? jj : N - jj;
+      const T sj = -twp[2 * h].y;
+      const T ya = sj * (va + wa) + T(0.5) * (va - wa);
+      const T yb = sj * (vb + wb) + T(0.5) * (vb - wb);
+      return j0 ? cpx<T>{T(0), T(0)} : cpx<T>{ya, yb};
+    };
+    auto sto = [&](int k, cpx<T> v) { buf[fpad(k)] = v; };
+    fft_forward<T, L, V>(buf, tid, twl, ldo, sto);
+    __syncthreads();
+    constexpr int CK = N / (2 * NT);   // k values per thread (E / 2)
+    const int k0 = tid * CK;
+    T ea[CK], eb[CK], oa[CK], ob[CK];  // F_2k and running sums of A
+    T pa = T(0), pb = T(0), a0a = T(0), a0b = T(0);
+#pragma unroll
+    for (int c = 0; c < CK; ++c) {
+      const int k = k0 + c;
+      const cpx<T> wk = buf[fpad(k)], wm = buf[fpad(k == 0 ? 0 : N - k)];
+      // line a: (W_k + conj W_{n-k}) / 2, line b: -i (W_k - conj W_{n-k}) / 2
+      const T aa = T(0.5) * (wk.x + wm.x), ab = T(0.5) * (wk.y + wm.y);
+      ea[c] = T(0.5) * (wm.y - wk.y);
+      eb[c] = T(0.5) * (wk.x - wm.x);
+      pa += aa;
+      pb += ab;
+      oa[c] = pa;
+      ob[c] = pb;
+      if (c == 0) { a0a = aa; a0b = ab; }
+    }
+    // exclusive prefix of the block sums over the pair's lanes, and A_0
+    T ta = pa, tb = pb;
+#pragma unroll
+    for (int dd = 1; dd < NT; dd <<= 1) {
+      const T ua = __shfl_up(ta, dd, NT), ub = __shfl_up(tb, dd, NT);
+      if (tid >= dd) { ta += ua; tb += ub; }
+    }
+    const T offa = (ta - pa) - T(0.5) * __shfl(a0a, 0, NT);
+    const T offb = (tb - pb) - T(0.5) * __shfl(a0b, 0, NT);
+    __syncthreads();   // every W is read before the rows (aliasing the regions) are written
+#pragma unroll
+    for (int c = 0; c < CK; ++c) {
+      const int k = k0 + c;
+      T fa = oa[c] + offa, fb = ob[c] + offb;   // F_2k+1 at position 2k
+      if constexpr (SCALE) { fa *= fac(la, 2 * k); fb *= fac(lb, 2 * k); }
+      da[2 * k] = fa;
+      db[2 * k] = fb;
+      if (k >= 1) {                              // F_2k at position 2k-1
+        T ga = ea[c], gb = eb[c];
+        if constexpr (SCALE) { ga *= fac(la, 2 * k - 1); gb *= fac(lb, 2 * k - 1); }
+        da[2 * k - 1] = ga;
+        db[2 * k - 1] = gb;
+      }
+    }
+  };
 
   if (MODE == PASS_FWD || MODE == PASS_MID) {
     // ---- outlier dots; boundary fold into the g slots ----------------------
@@ -385,7 +463,10 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Xa + j : dmy) = a;
       *(ok ? Xb + j : dmy + 1) = b;
     };
-    if constexpr (PK != PK_EVEN_N) {
+    if constexpr (PK == PK_ODD_N) {
+      dst1n(Ga, Gb, Xa, Xb, std::integral_constant<bool, MODE == PASS_MID>{});
+      __syncthreads();
+    } else if constexpr (PK != PK_EVEN_N) {
       fft_forward<T, L, V>(buf, tid, twl, ld, st);
       __syncthreads();
     } else {
@@ -488,7 +569,9 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       *(ok ? Ga + j : dmy) = T(-0.5) * v.y;
       *(ok ? Gb + j : dmy + 1) = odd ? T(0.5) * v.x : T(-0.5) * v.x;
     };
-    if constexpr (PK != PK_EVEN_N) {
+    if constexpr (PK == PK_ODD_N) {
+      dst1n(Xa, Xb, Ga, Gb, std::integral_constant<bool, false>{});
+    } else if constexpr (PK != PK_EVEN_N) {
       fft_forward<T, L, V>(buf, tid, twl, ld, st);
     } else {
       // even p with L = n: with d_k = c_{n-k} (d_n = 0), the Hermitian sequence
@@ -562,7 +645,11 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 #pragma unroll
       for (int u = 0; u < UMAX; ++u) {
         const int j = lane + RW * u;
-        if (j < m) buf_st<Tout>((Tout)value(l, j, co), rs, (unsigned)(l * m + j) * sizeof(Tout));
+        if (RW * u < m) {   // uniform: skip chunks past every row
+          const int jj = j < m ? j : 0;
+          buf_st<Tout>((Tout)value(l, jj, co), rs,
+                       j < m ? (unsigned)(l * m + j) * sizeof(Tout) : BUF_OOB);
+        }
       }
     }
   } else if constexpr (NTH % TW == 0) {
@@ -601,7 +688,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 template <typename T>
 static Tabs<T> tables_of(const Plan& P, int mode) {
   const char* b = P.d_tables + (sizeof(T) == 8 ? P.lay.blob64 : P.lay.blob32);
-  const int len = mode == PASS_MID ? P.blob_len : ((P.p & 1) ? P.bo_twp : P.bo_lam);
+  const int len = mode == PASS_MID ? P.blob_len : (((P.p & 1) && !P.half_len) ? P.bo_twp : P.bo_lam);
   const int nch = (int)((len * sizeof(T) + 15) / 16);
   return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len, nch};
 }
@@ -647,25 +734,34 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   return hipGetLastError();
 }
 
+template <typename Tin, typename Tout, typename T, int MODE, int L, int PK>
+static hipError_t by_shape(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
+                           const double* a, int as, hipStream_t s) {
+  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK>(P, axis, in, out, nrhs, a, as, s);
+  if (var == 1) return launch_t<Tin, Tout, T, MODE, L, 1, PK>(P, axis, in, out, nrhs, a, as, s);
+  return launch_t<Tin, Tout, T, MODE, L, 2, PK>(P, axis, in, out, nrhs, a, as, s);
+}
+
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
                              const double* a, int as, hipStream_t s) {
-  // one kernel per transform route; L = 2n for even p only where n is not a
-  // supported length (n = 8, 12), L = n only up to 256
-  if (P.p & 1) {
-    if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_ODD>(P, axis, in, out, nrhs, a, as, s);
-    return launch_t<Tin, Tout, T, MODE, L, 1, PK_ODD>(P, axis, in, out, nrhs, a, as, s);
-  }
+  // one kernel per transform route: L = n where n is a supported length
+  // (n >= 16), L = 2n for n = 8 and 12
+  const bool odd = (P.p & 1) != 0;
   if constexpr (L <= 24) {
     if (!P.half_len) {
-      if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_EVEN_2N>(P, axis, in, out, nrhs, a, as, s);
-      return launch_t<Tin, Tout, T, MODE, L, 1, PK_EVEN_2N>(P, axis, in, out, nrhs, a, as, s);
+      if (odd) {
+        return by_shape<Tin, Tout, T, MODE, L, PK_ODD>(P, var, axis, in, out, nrhs, a, as, s);
+      }
+      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_2N>(P, var, axis, in, out, nrhs, a, as, s);
     }
   }
   if constexpr (L <= 256) {
     if (P.half_len) {
-      if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK_EVEN_N>(P, axis, in, out, nrhs, a, as, s);
-      return launch_t<Tin, Tout, T, MODE, L, 1, PK_EVEN_N>(P, axis, in, out, nrhs, a, as, s);
+      if (odd) {
+        return by_shape<Tin, Tout, T, MODE, L, PK_ODD_N>(P, var, axis, in, out, nrhs, a, as, s);
+      }
+      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_N>(P, var, axis, in, out, nrhs, a, as, s);
     }
   }
   return hipErrorInvalidValue;

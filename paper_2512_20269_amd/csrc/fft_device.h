@@ -139,8 +139,6 @@ template <> struct FftPlan<96, 0>  { static constexpr int E = 24; };
 template <> struct FftPlan<128, 0> { static constexpr int E = 16; };
 template <> struct FftPlan<192, 0> { static constexpr int E = 24; };
 template <> struct FftPlan<256, 0> { static constexpr int E = 16; };
-template <> struct FftPlan<384, 0> { static constexpr int E = 24; };
-template <> struct FftPlan<512, 0> { static constexpr int E = 16; };
 template <> struct FftPlan<16, 1>  { static constexpr int E = 8; };
 template <> struct FftPlan<24, 1>  { static constexpr int E = 12; };
 template <> struct FftPlan<32, 1>  { static constexpr int E = 8; };
@@ -150,8 +148,8 @@ template <> struct FftPlan<96, 1>  { static constexpr int E = 12; };
 template <> struct FftPlan<128, 1> { static constexpr int E = 8; };
 template <> struct FftPlan<192, 1> { static constexpr int E = 12; };
 template <> struct FftPlan<256, 1> { static constexpr int E = 8; };
-template <> struct FftPlan<384, 1> { static constexpr int E = 12; };
-template <> struct FftPlan<512, 1> { static constexpr int E = 8; };
+// variant 2: variant 1's transform shape (it differs only in lines per workgroup)
+template <int L> struct FftPlan<L, 2> : FftPlan<L, 1> {};
 
 // padded LDS index of FFT element k: one spare slot every 16 entries keeps
 // the strided Stockham writes off a single bank; the regions of consecutive
@@ -237,8 +235,6 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
-    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 8, 8, 2, 3>::run(buf, tid, tw, ld, st);
-    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 16, 16, 2>::run(buf, tid, tw, ld, st);
   } else {
     if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 8, 2>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 24) FftRun<T, 24, E, NT, 1, 4, 2, 3>::run(buf, tid, tw, ld, st);
@@ -249,8 +245,6 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 8, 4, 4>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 4, 4, 4, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 8, 8, 4>::run(buf, tid, tw, ld, st);
-    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 4, 4, 4, 2, 3>::run(buf, tid, tw, ld, st);
-    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 8, 8, 8>::run(buf, tid, tw, ld, st);
   }
 }
 

@@ -62,7 +62,7 @@ struct Plan {
   int bo_twl = 0, bo_twp = 0, bo_vt = 0, bo_v0 = 0, bo_v1 = 0, bo_lam = 0, bo_s = 0, blob_len = 0;
 
   int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
-  bool half_len = false;  // even p: sine transforms through length-n FFTs (L = n)
+  bool half_len = false;  // sine transforms through length-n FFTs (L = n), else L = 2n
 
   TableLayout lay{};
   char* d_tables = nullptr;

@@ -227,20 +227,21 @@ def test_stepped_pcg_alone_equals_in_mix():
 
 
 @pytest.mark.parametrize("d,n,p", [(3, 16, 3), (3, 24, 4), (2, 48, 5), (3, 32, 8), (2, 96, 6),
-                                   (3, 12, 2)])
+                                   (3, 12, 2), (2, 8, 3), (2, 12, 5), (2, 192, 7), (2, 256, 3)])
 def test_fft_variants_and_tuner(d, n, p):
-    """Both FFT shapes of every pass give the oracle's result; the tuner keeps
-    a valid choice."""
+    """Every FFT shape of every pass gives the oracle's result (length-n
+    transforms for n >= 16, length-2n ones for n = 8, 12, both parities); the
+    tuner keeps a valid choice."""
     r = workloads.uniform_rhs(d, n, p, seed=77)
     zo = oracle(d, n, p).apply(r)
     for prec in ("f64", "f32"):
         pl = I.Plan(d, n, p, precision=prec)
-        for v in (0, 1):
+        for v in (0, 1, 2):
             for k in range(pl.n_passes()):
                 pl.set_variant(k, v)
             assert rel(host(pl.apply(dev(r))), zo) <= TOL[prec]
         chosen = pl.tune(reps=3)
-        assert len(chosen) == 2 * d - 1 and set(chosen) <= {0, 1}
+        assert len(chosen) == 2 * d - 1 and set(chosen) <= {0, 1, 2}
         assert rel(host(pl.apply(dev(r))), zo) <= TOL[prec]
 
 
