@@ -213,15 +213,179 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
   }
 }
 
-// workgroups of the operator per right-hand side (pass 2 produces the partials)
+// ---------------------------------------------------------------------------
+// 3D, p <= 4: one fused pass.  A workgroup of 8 waves owns a tile of 32
+// columns (direction 1) x 16 rows (direction 2) x MVF_C3 planes (direction 3);
+// each wave holds two rows, one per half-wave, a lane per column.  The outer
+// p columns and rows of the tile only feed their neighbours.  Every thread
+// loads its column of x over the tile's planes plus a p-plane halo at once
+// (all loads in flight), forms t = M3 x and s = K3 x for one plane at a time
+// in registers and passes them through LDS (double-buffered by plane parity,
+// one barrier per plane); the waves holding output rows form u = M2 t and
+// v = K2 t + M2 s down the rows and y = K1 u + M1 v across the lanes with DPP
+// whole-wave shifts (a shift never crosses from one half into the other's
+// output lanes).  x is read once per tile plus halos (largely from L2) and y
+// written once, against 48 bytes per point for the two passes above.  Small
+// workgroups let several share a compute unit, so one's barrier waits are
+// covered by another's work.  The partial x . y of a workgroup uses the x
+// value at the window centre.
+constexpr int MVF_C3 = 8;
+constexpr int MVF_RT = 16;   // tile rows
+constexpr int MVF_CW = 32;   // tile columns (half a wave)
+constexpr int MVF_THREADS = MVF_RT * MVF_CW;
+
+__host__ __device__ inline void mvf_geom(int m, int P, int& ncs, int& nrb, int& n3c) {
+  ncs = (m + (MVF_CW - 2 * P) - 1) / (MVF_CW - 2 * P);
+  nrb = (m + (MVF_RT - 2 * P) - 1) / (MVF_RT - 2 * P);
+  n3c = (m + MVF_C3 - 1) / MVF_C3;
+}
+
+static bool mv_fused(const Plan& P_) { return P_.d == 3 && P_.p <= 4; }
+
+template <int P>
+__global__ void __launch_bounds__(MVF_THREADS)
+mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, int ncs, int nrb,
+          int n3c, const double* __restrict__ kc, const double* __restrict__ mc, int nbr,
+          int crows, double* __restrict__ part, int npart, const double* __restrict__ active,
+          int astride) {
+  constexpr int BW = 2 * P + 1;
+  constexpr int WIN = MVF_C3 + 2 * P;
+  constexpr int OUT = MVF_CW - 2 * P, R2 = MVF_RT - 2 * P;
+  __shared__ double ts[2][2][MVF_RT][MVF_CW];   // [plane parity][t, s][row][column]
+  __shared__ double b1[2][BW][MVF_CW];           // direction-1 band rows of the columns
+  __shared__ double b2[2][MVF_RT][BW];           // direction-2 band rows of the rows
+  __shared__ double red[MVF_THREADS / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cl = lane & (MVF_CW - 1);
+  const int ty = 2 * wv + (lane >> 5);
+  const int bpr = ncs * nrb * n3c;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);   // neighbouring tiles share halos in one L2
+  const int rhs = lin / bpr;
+  const int blk = lin - rhs * bpr;
+  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  // plane chunks vary fastest, then row blocks, then column strips
+  const int ch = blk % n3c;
+  const int rb = (blk / n3c) % nrb;
+  const int cs = blk / (n3c * nrb);
+  const int i1 = cs * OUT - P + cl;
+  const int i2 = rb * R2 - P + ty;
+  const int c0 = ch * MVF_C3;
+  const bool colrow = i1 >= 0 && i1 < m && i2 >= 0 && i2 < m;
+  const int plane = m * m;
+  // x column window, planes c0 - P .. c0 + C3 + P - 1 (0 outside the tensor)
+  const auto rs = buf_rsrc(x + (size_t)rhs * N, (unsigned)N * 8u);
+  const unsigned vo = colrow ? (unsigned)(i2 * m + i1) * 8u : BUF_OOB;
+  double w[WIN];
+#pragma unroll
+  for (int k = 0; k < WIN; ++k) {
+    const int c = c0 - P + k;
+    w[k] = (c >= 0 && c < m) ? buf_ld<double>(rs, vo + (unsigned)(c * plane) * 8u) : 0.0;
+  }
+  // band rows of the tile's columns and rows (read after the first barrier)
+  for (int e = threadIdx.x; e < BW * MVF_CW; e += MVF_THREADS) {
+    const int o = e / MVF_CW, c = e - o * MVF_CW;
+    const int j1 = cs * OUT - P + c;
+    const int cr = crow(j1 >= 0 && j1 < m ? j1 : 0, m, nbr, crows);
+    b1[0][o][c] = kc[cr * BW + o];
+    b1[1][o][c] = mc[cr * BW + o];
+  }
+  for (int e = threadIdx.x; e < BW * MVF_RT; e += MVF_THREADS) {
+    const int r = e / BW, o = e - r * BW;
+    const int j2 = rb * R2 - P + r;
+    const int cr = crow(j2 >= 0 && j2 < m ? j2 : 0, m, nbr, crows);
+    b2[0][r][o] = kc[cr * BW + o];
+    b2[1][r][o] = mc[cr * BW + o];
+  }
+  // waves with an output row in either half do the in-plane work
+  const bool owave = 2 * wv + 1 >= P && 2 * wv < P + R2;
+  const bool out = ty >= P && ty < P + R2 && i2 < m && cl >= P && cl < MVF_CW - P && i1 < m;
+  const int ta = ty >= P && ty < P + R2 ? ty : P;   // rows the halo half-wave reads (discarded)
+  const auto ws = buf_rsrc(y + (size_t)rhs * N, (unsigned)N * 8u);
+  // a tile whose columns and rows all take the interior (Toeplitz) band row
+  // reads its coefficients from scalar registers instead of LDS
+  const bool inter = crows < m && cs * OUT - P >= nbr && cs * OUT - P + MVF_CW <= m - nbr &&
+                     rb * R2 - P >= nbr && rb * R2 - P + MVF_RT <= m - nbr;
+  double dot = 0.0;
+  auto run = [&](auto tag) {
+    constexpr bool INTER = decltype(tag)::value;
+    const double* ki = kc + nbr * BW;   // the interior row
+    const double* mi = mc + nbr * BW;
+    auto K1 = [&](int o) { return INTER ? ki[o] : b1[0][o][cl]; };
+    auto M1 = [&](int o) { return INTER ? mi[o] : b1[1][o][cl]; };
+    auto K2 = [&](int o) { return INTER ? ki[o] : b2[0][ta][o]; };
+    auto M2 = [&](int o) { return INTER ? mi[o] : b2[1][ta][o]; };
+#pragma unroll
+    for (int k = 0; k < MVF_C3; ++k) {
+      const int i3 = c0 + k;
+      if (i3 >= m) break;   // uniform
+      const int cr3 = __builtin_amdgcn_readfirstlane(crow(i3, m, nbr, crows));
+      const double* k3 = kc + cr3 * BW;
+      const double* m3 = mc + cr3 * BW;
+      double t = 0.0, sv = 0.0;
+#pragma unroll
+      for (int o = 0; o < BW; ++o) {
+        t += m3[o] * w[k + o];
+        sv += k3[o] * w[k + o];
+      }
+      ts[k & 1][0][ty][cl] = t;
+      ts[k & 1][1][ty][cl] = sv;
+      __syncthreads();
+      if (owave) {
+        double u = 0.0, v = 0.0;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          const double tt = ts[k & 1][0][ta - P + o][cl];
+          const double ss = ts[k & 1][1][ta - P + o][cl];
+          u += M2(o) * tt;
+          v += K2(o) * tt + M2(o) * ss;
+        }
+        double yv = K1(P) * u + M1(P) * v;
+        double ul = u, vl = v, ur = u, vr = v;
+#pragma unroll
+        for (int d = 1; d <= P; ++d) {
+          ul = wave_from_lower(ul);   // value of column cl - d
+          vl = wave_from_lower(vl);
+          ur = wave_from_upper(ur);   // value of column cl + d
+          vr = wave_from_upper(vr);
+          yv += K1(P - d) * ul + M1(P - d) * vl;
+          yv += K1(P + d) * ur + M1(P + d) * vr;
+        }
+        if (out) {
+          buf_st<double>(yv, ws, (unsigned)(i3 * plane + i2 * m + i1) * 8u);
+          dot += w[k + P] * yv;
+        }
+      }
+    }
+  };
+  if (inter) run(std::integral_constant<bool, true>{});
+  else run(std::integral_constant<bool, false>{});
+  if (part) {
+    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+    if (lane == 0) red[wv] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s2 = 0.0;
+      for (int k = 0; k < MVF_THREADS / 64; ++k) s2 += red[k];
+      part[(size_t)rhs * npart + blk] = s2;
+    }
+  }
+}
+
+// workgroups of the operator per right-hand side (the pass that produces the
+// partials)
 int matvec_blocks(const Plan& P_) {
+  if (mv_fused(P_)) {
+    int ncs, nrb, n3c;
+    mvf_geom(P_.m, P_.p, ncs, nrb, n3c);
+    return ncs * nrb * n3c;
+  }
   int ncs, nch, bpr;
   mv2_geom(P_.m, P_.d == 3 ? P_.m : 1, P_.p, ncs, nch, bpr);
   return bpr;
 }
 
 size_t matvec_ws_bytes(const Plan& P_, int nrhs) {
-  return P_.d == 3 ? (size_t)2 * 8 * P_.N * nrhs : 0;
+  return (P_.d == 3 && !mv_fused(P_)) ? (size_t)2 * 8 * P_.N * nrhs : 0;
 }
 
 template <int P>
@@ -232,6 +396,17 @@ static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs
   const double* kc = (const double*)(b + P_.lay.kc64);
   const double* mc = (const double*)(b + P_.lay.mc64);
   const int nbr = 2 * P - 1, crows = P_.crows;
+  if constexpr (P <= 4) {
+    if (mv_fused(P_)) {
+      int ncs, nrb, n3c;
+      mvf_geom(m, P, ncs, nrb, n3c);
+      const int bpr = ncs * nrb * n3c;
+      if (part && bpr > npart) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(mv_fused3<P>, dim3(bpr * nrhs), dim3(MVF_THREADS), 0, s, x, y, m, N, ncs,
+                         nrb, n3c, kc, mc, nbr, crows, part, npart, a, as);
+      return hipGetLastError();
+    }
+  }
   int ncs, nch, bpr;
   mv2_geom(m, P_.d == 3 ? m : 1, P, ncs, nch, bpr);
   if (part && bpr > npart) return hipErrorInvalidValue;
