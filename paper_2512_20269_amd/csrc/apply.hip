@@ -1,50 +1,61 @@
 // IFFD apply: dispatch of the line passes (apply_impl.h) over FFT lengths and
 // the sequence of passes that forms z = P^{-1} r.
-#include "launch.h"
+#include "apply_impl.h"
 
 namespace iffd {
 
 hipError_t line_pass_L16(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L24(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L32(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L48(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L64(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L96(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L128(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L192(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 hipError_t line_pass_L256(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk);
 
 hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
-                            void* out, int nrhs, const double* a, int as, hipStream_t s) {
+                            void* out, int nrhs, const double* a, int as, hipStream_t s,
+                            const PassHook* hk) {
   // pass index of (mode, axis) for the per-pass variant choice
   const int d = P.d;
   const int pass = mode == PASS_FWD ? axis - 1 : (mode == PASS_MID ? d - 1 : 2 * d - 1 - axis);
   const int var = P.variant[pass];
   switch (P.L) {
-    case 16: return line_pass_L16(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 24: return line_pass_L24(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 32: return line_pass_L32(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 48: return line_pass_L48(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 64: return line_pass_L64(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 96: return line_pass_L96(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 128: return line_pass_L128(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 192: return line_pass_L192(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
-    case 256: return line_pass_L256(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
+    case 16: return line_pass_L16(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 24: return line_pass_L24(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 32: return line_pass_L32(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 48: return line_pass_L48(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 64: return line_pass_L64(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 96: return line_pass_L96(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 128: return line_pass_L128(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 192: return line_pass_L192(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 256: return line_pass_L256(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
-                            void* ws, const double* a, int as, hipStream_t s) {
+                            void* ws, const double* a, int as, hipStream_t s,
+                            const PassHook* last) {
   const int d = P.d;
   const bool f64 = P.prec == IFFD_PREC_F64;
   const int et = f64 ? ELEM_F64 : ELEM_F32;
@@ -57,20 +68,49 @@ hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z,
   if (pass == d - 1) return launch_line_pass(P, PASS_MID, d, et, w, et, w, nrhs, a, as, s);
   if (pass < 2 * d - 1) {
     const int axis = 2 * d - 1 - pass;  // d-1 .. 1
-    const bool last = axis == 1;
-    return launch_line_pass(P, PASS_BWD, axis, et, w, last ? ELEM_F64 : et, last ? (void*)z : w,
-                            nrhs, a, as, s);
+    return launch_line_pass(P, PASS_BWD, axis, et, w, axis == 1 ? ELEM_F64 : et,
+                            axis == 1 ? (void*)z : w, nrhs, a, as, s, axis == 1 ? last : nullptr);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
-                             const double* a, int as, hipStream_t s) {
+                             const double* a, int as, hipStream_t s, const PassHook* last) {
   for (int k = 0; k < 2 * P.d - 1; ++k) {
-    hipError_t e = launch_iffd_pass(P, k, r, z, nrhs, ws, a, as, s);
+    hipError_t e = launch_iffd_pass(P, k, r, z, nrhs, ws, a, as, s, last);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// tiles per right-hand side of the direction-1 pass with the smallest tile
+// of any variant (bounds the partials a PassHook receives)
+template <typename T, int L>
+static int tw_min() {
+  int a = Cfg<T, L, 0>::TW, b = Cfg<T, L, 1>::TW, c = Cfg<T, L, 2>::TW;
+  return a < b ? (a < c ? a : c) : (b < c ? b : c);
+}
+template <int L>
+static int tw_min_p(bool f64) { return f64 ? tw_min<double, L>() : tw_min<float, L>(); }
+
+int apply_last_tiles_max(const Plan& P) {
+  if (P.method != IFFD_METHOD_FFT) return 1;
+  const bool f64 = P.prec == IFFD_PREC_F64;
+  int tw = 1;
+  switch (P.L) {
+    case 16: tw = tw_min_p<16>(f64); break;
+    case 24: tw = tw_min_p<24>(f64); break;
+    case 32: tw = tw_min_p<32>(f64); break;
+    case 48: tw = tw_min_p<48>(f64); break;
+    case 64: tw = tw_min_p<64>(f64); break;
+    case 96: tw = tw_min_p<96>(f64); break;
+    case 128: tw = tw_min_p<128>(f64); break;
+    case 192: tw = tw_min_p<192>(f64); break;
+    case 256: tw = tw_min_p<256>(f64); break;
+    default: return 1;
+  }
+  const long long lpr = P.N / P.m;
+  return (int)((lpr + tw - 1) / tw);
 }
 
 }  // namespace iffd

@@ -58,6 +58,9 @@ struct Geom {
   int N;       // elements per right-hand side
   int d;
   int tpd_log;  // log2 of the threads per outlier dot
+  const double* dr;  // fused dr . out partials (backward pass along direction 1), or null
+  double* dpart;
+  int dnpart;
   const double* active;  // per-RHS flags or null
   int active_stride;
 };
@@ -639,6 +642,11 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     const auto rs = buf_rsrc(out + (size_t)rhs * g.N + (size_t)q0 * m,
                              (unsigned)(nv * m * (int)sizeof(Tout)));
     const int lane = t % RW, grp = t / RW;
+    // fused partial dr . out of the tile (the values as stored, FP64)
+    const bool fdot = MODE == PASS_BWD && sizeof(Tout) == 8 && g.dr != nullptr;
+    const auto rd = buf_rsrc(fdot ? g.dr + (size_t)rhs * g.N + (size_t)q0 * m : (const double*)out,
+                             fdot ? (unsigned)(nv * m * 8) : 0u);
+    double dacc = 0.0;
     for (int l = grp; l < nv; l += NG) {
       T co[MAXO];
       load_co(l, co);
@@ -647,9 +655,27 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
         const int j = lane + RW * u;
         if (RW * u < m) {   // uniform: skip chunks past every row
           const int jj = j < m ? j : 0;
-          buf_st<Tout>((Tout)value(l, jj, co), rs,
-                       j < m ? (unsigned)(l * m + j) * sizeof(Tout) : BUF_OOB);
+          const unsigned off = j < m ? (unsigned)(l * m + j) : BUF_OOB / 8u;
+          const Tout v = (Tout)value(l, jj, co);
+          buf_st<Tout>(v, rs, off * (unsigned)sizeof(Tout));
+          if (fdot) dacc += (double)v * buf_ld<double>(rd, off * 8u);
         }
+      }
+    }
+    if (fdot) {   // uniform; fixed-order sum over the workgroup
+      double* red = reinterpret_cast<double*>(DM);   // NTH doubles fit in DM
+      if constexpr (NTH % 64 == 0) {
+        for (int o = 32; o > 0; o >>= 1) dacc += __shfl_xor(dacc, o);
+        if ((t & 63) == 0) red[t >> 6] = dacc;
+      } else {
+        red[t] = dacc;   // a partial wave: no shuffles
+      }
+      __syncthreads();
+      if (t == 0) {
+        constexpr int NR = NTH % 64 == 0 ? NTH / 64 : NTH;
+        double sum = 0.0;
+        for (int k = 0; k < NR; ++k) sum += red[k];
+        g.dpart[(size_t)rhs * g.dnpart + tile] = sum;
       }
     }
   } else if constexpr (NTH % TW == 0) {
@@ -695,7 +721,7 @@ static Tabs<T> tables_of(const Plan& P, int mode) {
 
 template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
 static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, int nrhs,
-                           const double* active, int astride, hipStream_t s) {
+                           const double* active, int astride, hipStream_t s, const PassHook* hk) {
   using C = Cfg<T, L, V>;
   Geom g;
   g.m = P.m; g.n = P.n; g.p = P.p; g.n_reg = P.n_reg; g.n_out = P.n_out; g.half = P.half;
@@ -709,6 +735,14 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.d = P.d;
   g.active = active;
   g.active_stride = astride;
+  g.dr = hk ? hk->dr : nullptr;
+  g.dpart = hk ? hk->part : nullptr;
+  g.dnpart = hk ? hk->npart : 0;
+  if (hk) {
+    if (axis != 1 || MODE != PASS_BWD || sizeof(Tout) != 8 || g.tpr > hk->npart)
+      return hipErrorInvalidValue;
+    hk->tiles = g.tpr;
+  }
   {
     // threads per outlier dot: as many as the workgroup allows, up to a wave
     const int ndots = C::TW * P.n_out;
@@ -736,32 +770,32 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
 
 template <typename Tin, typename Tout, typename T, int MODE, int L, int PK>
 static hipError_t by_shape(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
-                           const double* a, int as, hipStream_t s) {
-  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK>(P, axis, in, out, nrhs, a, as, s);
-  if (var == 1) return launch_t<Tin, Tout, T, MODE, L, 1, PK>(P, axis, in, out, nrhs, a, as, s);
-  return launch_t<Tin, Tout, T, MODE, L, 2, PK>(P, axis, in, out, nrhs, a, as, s);
+                           const double* a, int as, hipStream_t s, const PassHook* hk) {
+  if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK>(P, axis, in, out, nrhs, a, as, s, hk);
+  if (var == 1) return launch_t<Tin, Tout, T, MODE, L, 1, PK>(P, axis, in, out, nrhs, a, as, s, hk);
+  return launch_t<Tin, Tout, T, MODE, L, 2, PK>(P, axis, in, out, nrhs, a, as, s, hk);
 }
 
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, void* out, int nrhs,
-                             const double* a, int as, hipStream_t s) {
+                             const double* a, int as, hipStream_t s, const PassHook* hk) {
   // one kernel per transform route: L = n where n is a supported length
   // (n >= 16), L = 2n for n = 8 and 12
   const bool odd = (P.p & 1) != 0;
   if constexpr (L <= 24) {
     if (!P.half_len) {
       if (odd) {
-        return by_shape<Tin, Tout, T, MODE, L, PK_ODD>(P, var, axis, in, out, nrhs, a, as, s);
+        return by_shape<Tin, Tout, T, MODE, L, PK_ODD>(P, var, axis, in, out, nrhs, a, as, s, hk);
       }
-      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_2N>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_2N>(P, var, axis, in, out, nrhs, a, as, s, hk);
     }
   }
   if constexpr (L <= 256) {
     if (P.half_len) {
       if (odd) {
-        return by_shape<Tin, Tout, T, MODE, L, PK_ODD_N>(P, var, axis, in, out, nrhs, a, as, s);
+        return by_shape<Tin, Tout, T, MODE, L, PK_ODD_N>(P, var, axis, in, out, nrhs, a, as, s, hk);
       }
-      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_N>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_N>(P, var, axis, in, out, nrhs, a, as, s, hk);
     }
   }
   return hipErrorInvalidValue;
@@ -770,28 +804,29 @@ static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, v
 // all modes, element types and variants of the line pass for one FFT length
 template <int L>
 hipError_t line_pass_for_L(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s) {
+                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                           const PassHook* hk) {
   if (P.prec == IFFD_PREC_F64) {
     if (tin != ELEM_F64 || tout != ELEM_F64) return hipErrorInvalidValue;
     if (mode == PASS_FWD)
-      return by_variant<double, double, double, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<double, double, double, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (mode == PASS_BWD)
-      return by_variant<double, double, double, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
-    return by_variant<double, double, double, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<double, double, double, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
+    return by_variant<double, double, double, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   }
   if (mode == PASS_FWD) {
     if (tin == ELEM_F64 && tout == ELEM_F32)
-      return by_variant<double, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<double, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F32 && tout == ELEM_F32)
-      return by_variant<float, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<float, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   } else if (mode == PASS_BWD) {
     if (tin == ELEM_F32 && tout == ELEM_F64)
-      return by_variant<float, double, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<float, double, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F32 && tout == ELEM_F32)
-      return by_variant<float, float, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<float, float, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   } else {
     if (tin == ELEM_F32 && tout == ELEM_F32)
-      return by_variant<float, float, float, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s);
+      return by_variant<float, float, float, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   }
   return hipErrorInvalidValue;
 }

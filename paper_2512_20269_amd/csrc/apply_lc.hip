@@ -4,8 +4,9 @@
 namespace iffd {
 
 hipError_t line_pass_L128(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s) {
-  return line_pass_for_L<128>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s);
+                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk) {
+  return line_pass_for_L<128>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
 }
 
 }  // namespace iffd

@@ -53,20 +53,33 @@ __device__ __forceinline__ u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, unsigned vof
 
 enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
 
+// Optional work fused into the last (direction-1, backward) line pass of the
+// IFFD apply: per-tile partials part[rhs][tile] = sum over the tile of
+// dr . z (z as stored, FP64); `tiles` receives the tile count per right-hand
+// side of the launch (at most apply_last_tiles_max).
+struct PassHook {
+  const double* dr;
+  double* part;
+  int npart;
+  mutable int tiles;
+};
+
 // One IFFD line pass along `axis` (1-based; direction 1 = fastest) of the
 // [nrhs][m]^d tensor.  Tin/Tout: ELEM_*; compute precision = plan.prec.
 // active: optional per-RHS flags (stride `active_stride` doubles; 0 = skip).
 hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
                             void* out, int nrhs, const double* active, int active_stride,
-                            hipStream_t s);
+                            hipStream_t s, const PassHook* hk = nullptr);
 
 // Full IFFD apply z = P^{-1} r (FP64 in/out), ws = apply workspace.
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
-                             const double* active, int active_stride, hipStream_t s);
+                             const double* active, int active_stride, hipStream_t s,
+                             const PassHook* last = nullptr);
 
 // One pass of the IFFD apply (0 .. 2d-2), see iffd_apply_pass.
 hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
-                            void* ws, const double* active, int active_stride, hipStream_t s);
+                            void* ws, const double* active, int active_stride, hipStream_t s,
+                            const PassHook* last = nullptr);
 
 // Dense FD apply (MFMA mode products).
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,

@@ -9,9 +9,12 @@
 //
 // One iteration, per active slot:
 //   q = A p, pq = p.q (fused in the operator)      -> reduce pq
-//   alpha = rz / pq; x += alpha p; r -= alpha q; rr -> reduce rr, test
-//   z = P^{-1} r; rz' = r.z                        -> reduce rz'
-//   beta = rz'/rz; p = z + beta p
+//   alpha = rz / pq; r -= alpha q; rr              -> reduce rr, test
+//   z = P^{-1} r; rz' = r.z (fused in the IFFD apply's last pass)
+//                                                  -> reduce rz'
+//   beta = rz'/rz; x += alpha p; p = z + beta p
+// x takes its update in the same sweep as p (it reads the old p anyway); a
+// slot that stops in this iteration still gets it (flag S_RUN).
 // rz alternates between two record entries by iteration parity so that no
 // kernel reads a value another block of the same kernel overwrites.
 #include "launch.h"
@@ -92,24 +95,28 @@ pcg_alpha(double* scal, const double* part, int npart_used, int npart, int nslot
   __shared__ double red[VT / 64];
   const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
-  if (sc[S_ACTIVE] == 0.0) return;
+  if (sc[S_ACTIVE] == 0.0) {
+    if (threadIdx.x == 0) sc[S_RUN] = 0.0;
+    return;
+  }
   const double pq = block_psum(part + (size_t)slot * npart, npart_used, red);
   if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT];
   const double rz = sc[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(rz > 0.0) || !isfinite(pq) || !isfinite(rz)) {
     sc[S_ACTIVE] = 0.0;
+    sc[S_RUN] = 0.0;
     sc[S_STATUS] = (double)IFFD_E_BREAKDOWN;
     return;
   }
   sc[S_ALPHA] = rz / pq;
+  sc[S_RUN] = 1.0;
 }
 
-// x += alpha p; r -= alpha q; partial r.r
+// r -= alpha q; partial r.r
 __global__ void __launch_bounds__(VT)
-pcg_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-              const double* __restrict__ q, int N, int nblk, const double* __restrict__ scal,
-              double* __restrict__ part) {
+pcg_update_r(double* __restrict__ r, const double* __restrict__ q, int N, int nblk,
+             const double* __restrict__ scal, double* __restrict__ part) {
   __shared__ double red[VT / 64];
   const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
   const double* sc = scal + (size_t)slot * kScal;
@@ -120,7 +127,6 @@ pcg_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __re
   const size_t o = (size_t)slot * N;
   double s = 0.0;
   for (int i = lo + threadIdx.x; i < hi; i += VT) {
-    x[o + i] += alpha * p[o + i];
     const double rv = r[o + i] - alpha * q[o + i];
     r[o + i] = rv;
     s += rv * rv;
@@ -156,14 +162,14 @@ pcg_check(double* scal, double* hist, const double* part, int nblk, int nslots) 
   }
 }
 
-// one block per slot: rz' = sum of partials, beta = rz'/rz
+// one block per slot: rz' = sum of the nused partials, beta = rz'/rz
 __global__ void __launch_bounds__(VT)
-pcg_beta(double* scal, double* hist, const double* part, int nblk, int nslots) {
+pcg_beta(double* scal, double* hist, const double* part, int nused, int stride, int nslots) {
   __shared__ double red[VT / 64];
   const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_ACTIVE] == 0.0) return;
-  const double rzn = block_psum(part + (size_t)slot * nblk, nblk, red);
+  const double rzn = block_psum(part + (size_t)slot * stride, nused, red);
   if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT];  // already counts this iteration
   const double rzo = sc[S_RZ0 + ((it - 1) & 1)];
@@ -178,18 +184,28 @@ pcg_beta(double* scal, double* hist, const double* part, int nblk, int nslots) {
   if (it - 1 < kHist) hist[((size_t)slot * kHist + it - 1) * 2 + 1] = beta;
 }
 
-// p = z + beta p
+// x += alpha p (every slot whose alpha is valid); p = z + beta p (slots still
+// iterating)
 __global__ void __launch_bounds__(VT)
-pcg_update_p(double* __restrict__ p, const double* __restrict__ z, int N, int nblk,
-             const double* __restrict__ scal) {
+pcg_update_p(double* __restrict__ x, double* __restrict__ p, const double* __restrict__ z, int N,
+             int nblk, const double* __restrict__ scal) {
   const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
   const double* sc = scal + (size_t)slot * kScal;
-  if (sc[S_ACTIVE] == 0.0) return;
-  const double beta = sc[S_BETA];
+  if (sc[S_RUN] == 0.0) return;
+  const double alpha = sc[S_ALPHA], beta = sc[S_BETA];
+  const bool act = sc[S_ACTIVE] != 0.0;
   int lo, hi;
   chunk(N, nblk, blk, lo, hi);
   const size_t o = (size_t)slot * N;
-  for (int i = lo + threadIdx.x; i < hi; i += VT) p[o + i] = z[o + i] + beta * p[o + i];
+  if (act) {
+    for (int i = lo + threadIdx.x; i < hi; i += VT) {
+      const double pv = p[o + i];
+      x[o + i] += alpha * pv;
+      p[o + i] = z[o + i] + beta * pv;
+    }
+  } else {
+    for (int i = lo + threadIdx.x; i < hi; i += VT) x[o + i] += alpha * p[o + i];
+  }
 }
 
 // begin: x = 0, r = f (f packed [count][N], slot list), partial f.f
@@ -391,16 +407,23 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
     hipError_t e = launch_matvec(P, p, qz, nslots, mvws, part2, nb, scal + S_ACTIVE, kScal, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pcg_alpha, dim3(nslots), dim3(VT), 0, s, scal, part2, nmv, nb, nslots);
-    hipLaunchKernelGGL(pcg_update_xr, dim3(nslots * nb), dim3(VT), 0, s, x, r, p, qz, N, nb, scal, part);
+    hipLaunchKernelGGL(pcg_update_r, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, scal, part);
     hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nslots);
-    e = (P.method == IFFD_METHOD_FFT)
-            ? launch_iffd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s)
-            : launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
-                       (int)S_ACTIVE);
-    hipLaunchKernelGGL(pcg_beta, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nslots);
-    hipLaunchKernelGGL(pcg_update_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
+    int nrz = nb;
+    if (P.method == IFFD_METHOD_FFT) {
+      // r.z partials come from the apply's last pass
+      const PassHook hk{r, part, nb, 0};
+      e = launch_iffd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s, &hk);
+      if (e != hipSuccess) return e;
+      nrz = hk.tiles;
+    } else {
+      e = launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
+                         (int)S_ACTIVE);
+    }
+    hipLaunchKernelGGL(pcg_beta, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nrz, nb, nslots);
+    hipLaunchKernelGGL(pcg_update_p, dim3(nslots * nb), dim3(VT), 0, s, x, p, qz, N, nb, scal);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -18,7 +18,8 @@ enum ScalIndex {
   S_ALPHA = 10,
   S_BETA = 11,
   S_NEW = 12,    // 1 while being started by iffd_pcg_begin
-  S_USED = 13    // slot holds a solve (until taken)
+  S_USED = 13,   // slot holds a solve (until taken)
+  S_RUN = 14     // 1 if this iteration's alpha is valid (x += alpha p is due)
 };
 
 }  // namespace iffd

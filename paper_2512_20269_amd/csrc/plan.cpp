@@ -286,7 +286,7 @@ size_t apply_ws_bytes(const Plan& P, int nrhs) {
 
 StateLayout state_layout(const Plan& P, int nslots) {
   StateLayout s{};
-  s.npart = std::max(pcg_blocks(P), matvec_blocks(P));
+  s.npart = std::max(std::max(pcg_blocks(P), matvec_blocks(P)), apply_last_tiles_max(P));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;

@@ -77,6 +77,7 @@ StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);
 int pcg_blocks(const Plan& P);  // number of partial sums per slot
 int matvec_blocks(const Plan& P);  // workgroups of the operator per right-hand side
+int apply_last_tiles_max(const Plan& P);  // partials of the apply's fused r.z
 size_t matvec_ws_bytes(const Plan& P, int nrhs);
 
 // whether an FFT length is supported by the built kernels
