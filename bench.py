@@ -11,9 +11,10 @@ direction, degree p = 3 (2,146,689 DoFs), FP32 transform arithmetic with FP64
 input and output.
 
 The K timed steps are enqueued back to back behind a device-side spin (so the
-host never starves the GPU) with a HIP event after every pass; the events give
-both the step time and each pass kernel's average duration.  The same apply
-replayed from a HIP graph is timed as well.
+host never starves the GPU) with a HIP event after every step; then every pass
+kernel is launched K times back to back between two events, which gives its
+average duration (the roofline figure).  The same apply replayed from a HIP
+graph is timed as well.
 
 Printed as one JSON line: apply throughput (GDoF/s) with the roofline of its
 dominant kernel, PCG solve latency to 1e-8 (FP64 PCG, this apply), the
@@ -252,6 +253,9 @@ def main():
                     help="only the 3D n=256 degree sweep (smooth right-hand side)")
     ap.add_argument("--serve", action="store_true",
                     help="only the serving benchmark (Poisson stream of mixed solves)")
+    ap.add_argument("--pcg-only", choices=["fft", "dense"],
+                    help="only PCG solves of the workload's first right-hand side with this "
+                         "preconditioner (3 warm-up + --solves timed; for kernel traces)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
@@ -285,6 +289,22 @@ def main():
                           "serving": res}), flush=True)
         return
     d, n, p, B, recipe = WORKLOADS[args.workload]
+    if args.pcg_only:
+        f_np = make_rhs(args.workload)
+        f = torch.from_numpy(f_np[0] if B > 1 else f_np).cuda()
+        pl = iffd.Plan(d, n, p, method=args.pcg_only, precision=args.precision)
+        if args.pcg_only == "fft":
+            pl.tune(reps=20)
+        for _ in range(2):
+            pl.solve(f, rtol=1e-8)
+        lat, st = time_solves(torch, pl, f, args.solves)
+        print(json.dumps({"metric": "PCG solve to 1e-8 relative residual", "unit": "ms",
+                          "value": round(statistics.mean(lat), 4), "higher_is_better": False,
+                          "p50_ms": round(pct(lat, 0.5), 4), "p99_ms": round(pct(lat, 0.99), 4),
+                          "iterations": st[0]["iterations"], "method": args.pcg_only,
+                          "dtype": args.precision, "solves": args.solves,
+                          "config": {"workload": args.workload}}), flush=True)
+        return
     r_np = make_rhs(args.workload)
     r = torch.from_numpy(r_np).cuda()
     z = torch.empty_like(r)
@@ -297,9 +317,9 @@ def main():
         plan.apply(r, out=z)
     torch.cuda.synchronize()
 
-    # ---- timed region: K applies, an event after every pass -------------------
+    # ---- timed region: K applies back to back, an event after every step -----
     cpm = sleep_cycles_per_ms(torch)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps * npass + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     torch.cuda._sleep(int(cpm * (5.0 + 0.03 * args.steps * npass)))
@@ -307,14 +327,26 @@ def main():
     for s in range(args.steps):
         for k in range(npass):
             plan.apply_pass(k, r, z)
-            evs[s * npass + k + 1].record()
+        evs[s + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     total_ms = evs[0].elapsed_time(evs[-1])
     ms_per_step = total_ms / args.steps
     value = B * N / (ms_per_step * 1e-3) / 1e9
-    per_pass = [statistics.mean(evs[s * npass + k].elapsed_time(evs[s * npass + k + 1])
-                                for s in range(args.steps)) for k in range(npass)]
+    # ---- each pass kernel's average duration: K launches of that pass back to
+    # back between two events (no event between launches, so the span is the
+    # kernels plus the dispatch gaps of a full queue) -------------------------
+    per_pass = []
+    for k in range(npass):
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(int(cpm * (2.0 + 0.03 * args.steps)))
+        a_.record()
+        for s in range(args.steps):
+            plan.apply_pass(k, r, z)
+        b_.record()
+        torch.cuda.synchronize()
+        per_pass.append(a_.elapsed_time(b_) / args.steps)
+    plan.apply(r, out=z)   # the passes above leave intermediate data in z and the workspace
 
     # ---- the same apply replayed from a HIP graph ------------------------------
     cap = torch.cuda.Stream()

@@ -18,7 +18,11 @@
 // s = Dt^{-2} on regular modes and 1 on outliers.
 //
 // Sine transforms by FFT: two real lines a, b are packed as a + i b into one
-// complex FFT of length L = 2n of an odd extension:
+// complex FFT.  Where n is a supported FFT length (n >= 16) the FFT has length
+// L = n (PK_ODD_N: DST-I by a pre-twist, the sine part of the spectrum and
+// prefix sums of its cosine part, see dst1n; PK_EVEN_N: DST-II / DST-III by a
+// reordering and a quarter-wave twiddle).  For n = 8, 12 it has length L = 2n
+// and runs on an odd extension:
 //   DST-I  (n-1 values g):  z = [0, g, 0, -reverse(g)],  X_a = -Im C / 2,
 //          X_b = Re C / 2 at indices 1..n-1;
 //   DST-II (n values):      z = [g, -reverse(g)], W = e^{-i pi k/(2n)} C,

@@ -18,19 +18,27 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and whitespace (what the compiler sees)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
 def source_hash() -> str:
-    """Hash of the line-pass kernel sources; traffic measured on other
-    sources is stale."""
+    """Hash of the line-pass kernel sources (code only; comments do not count);
+    traffic measured on other code is stale."""
     h = hashlib.sha256()
-    for f in ("apply_impl.h", "fft_device.h"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("apply_impl.h", "fft_device.h", "launch.h"):
+        with open(os.path.join(HERE, "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -69,13 +77,15 @@ def stats_text(db: str, cmd: str, top: int = 25) -> str:
     return "\n".join(out) + "\n"
 
 
-def line_pass_name(d: int, prec: str, k: int, L: int, variant: int) -> str:
-    """Demangled name of pass k's kernel (see launch_iffd_pass)."""
+def line_pass_name(d: int, prec: str, k: int, L: int, variant: int, n: int, p: int) -> str:
+    """Demangled name of pass k's kernel (see launch_iffd_pass); the last
+    template argument is the sine-transform route (length n or 2n, parity)."""
     t = "double" if prec == "f64" else "float"
     tin = "double" if k == 0 else t
     tout = "double" if k == 2 * d - 2 else t
     mode = 0 if k < d - 1 else (2 if k == d - 1 else 1)
-    return f"void iffd::line_pass<{tin}, {tout}, {t}, {mode}, {L}, {variant}>"
+    route = (3 if p % 2 else 2) if L == n else (0 if p % 2 else 1)
+    return f"void iffd::line_pass<{tin}, {tout}, {t}, {mode}, {L}, {variant}, {route}>"
 
 
 def copy_entry(table):
@@ -94,15 +104,15 @@ def traffic(fetch_db: str, write_db: str, bench: dict, cmd_fetch: str, cmd_write
     fs = cb["read"] / (f_copy * 1024.0)
     ws = cb["write"] / (w_copy * 1024.0)
     cfg, roof = bench["config"], bench["roofline"]
-    d, N, B = cfg["d"], cfg["dofs_per_rhs"], cfg["rhs"]
+    d, N, B, n, p = cfg["d"], cfg["dofs_per_rhs"], cfg["rhs"], cfg["n"], cfg["p"]
     prec = bench["dtype"]
     passes = []
     w = 8 if prec == "f64" else 4
     for k in range(len(roof["fft_variant_per_pass"])):
         alg = B * N * ((8 if k == 0 else w) + (8 if k == 2 * d - 2 else w))
         entry = {}
-        for v in (0, 1):    # the tuner dispatches both FFT shapes of every pass
-            name = line_pass_name(d, prec, k, roof["fft_len"], v)
+        for v in (0, 1, 2):    # the tuner dispatches every FFT shape of every pass
+            name = line_pass_name(d, prec, k, roof["fft_len"], v, n, p)
             fk = [val for key, val in fe.items() if key.startswith(name + "(")]
             wk = [val for key, val in wr.items() if key.startswith(name + "(")]
             if not fk or not wk:
