@@ -88,7 +88,9 @@ hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs
 template <typename T, int L>
 static int tw_min() {
   int a = Cfg<T, L, 0>::TW, b = Cfg<T, L, 1>::TW, c = Cfg<T, L, 2>::TW;
-  return a < b ? (a < c ? a : c) : (b < c ? b : c);
+  int w = a < b ? (a < c ? a : c) : (b < c ? b : c);
+  if constexpr (fft_has_v3<L>()) w = w < Cfg<T, L, 3>::TW ? w : Cfg<T, L, 3>::TW;
+  return w;
 }
 template <int L>
 static int tw_min_p(bool f64) { return f64 ? tw_min<double, L>() : tw_min<float, L>(); }

@@ -70,8 +70,9 @@ struct Geom {
 };
 
 // Tile shape of variant V: E transform elements per thread (variant 2 takes
-// variant 1's FFT shape), FPW line pairs per workgroup (variant 2 half as many,
-// for problems too small to fill the chip with full tiles).
+// variant 1's FFT shape, variant 3 has 4), FPW line pairs per workgroup
+// (variant 2 half as many, for problems too small to fill the chip with full
+// tiles).
 template <typename T, int L, int V>
 struct Cfg {
   static constexpr int E = FftPlan<L, V>::E;
@@ -777,6 +778,9 @@ static hipError_t by_shape(const Plan& P, int var, int axis, const void* in, voi
                            const double* a, int as, hipStream_t s, const PassHook* hk) {
   if (var == 0) return launch_t<Tin, Tout, T, MODE, L, 0, PK>(P, axis, in, out, nrhs, a, as, s, hk);
   if (var == 1) return launch_t<Tin, Tout, T, MODE, L, 1, PK>(P, axis, in, out, nrhs, a, as, s, hk);
+  if constexpr (fft_has_v3<L>()) {
+    if (var == 3) return launch_t<Tin, Tout, T, MODE, L, 3, PK>(P, axis, in, out, nrhs, a, as, s, hk);
+  }
   return launch_t<Tin, Tout, T, MODE, L, 2, PK>(P, axis, in, out, nrhs, a, as, s, hk);
 }
 

@@ -150,6 +150,11 @@ template <> struct FftPlan<192, 1> { static constexpr int E = 12; };
 template <> struct FftPlan<256, 1> { static constexpr int E = 8; };
 // variant 2: variant 1's transform shape (it differs only in lines per workgroup)
 template <int L> struct FftPlan<L, 2> : FftPlan<L, 1> {};
+// variant 3: 4 elements per thread (radix 4 and 2 only, so lengths 2^a):
+// twice variant 1's threads per transform, for problems too small to keep
+// enough waves in flight
+template <int L> struct FftPlan<L, 3> { static constexpr int E = 4; };
+template <int L> constexpr bool fft_has_v3() { return (L & (L - 1)) == 0 && L >= 16; }
 
 // padded LDS index of FFT element k: one spare slot every 16 entries keeps
 // the strided Stockham writes off a single bank; the regions of consecutive
@@ -235,6 +240,13 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
+  } else if constexpr (V == 3) {
+    if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 4, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 4, 4, 2>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 64) FftRun<T, 64, E, NT, 1, 4, 4, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 4, 4, 4, 2>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 4, 4, 4, 4>::run(buf, tid, tw, ld, st);
+    else static_assert(L == 16, "variant 3 needs a power-of-two length");
   } else {
     if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 8, 2>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 24) FftRun<T, 24, E, NT, 1, 4, 2, 3>::run(buf, tid, tw, ld, st);
