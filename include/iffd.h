@@ -183,10 +183,11 @@ int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* 
 /* FFT shape of one pass: variant 0 holds 16 (or 24) transform elements per
  * thread, variant 1 holds 8 (or 12) with twice the threads, variant 2 has
  * variant 1's shape with half the lines per workgroup (more workgroups for
- * small problems), variant 3 holds 4 elements per thread (power-of-two
- * transform lengths; elsewhere it runs variant 2).  All compute the same
- * result; they differ in speed.
- * iffd_plan_set_variant forces a choice (variant 0..3; diagnostics, tests);
+ * small problems), variant 3 holds 4 elements per thread and variant 4 has
+ * variant 3's shape with half the lines per workgroup (power-of-two transform
+ * lengths; elsewhere both run variant 2).  All compute the same result; they
+ * differ in speed.
+ * iffd_plan_set_variant forces a choice (variant 0..4; diagnostics, tests);
  * iffd_plan_tune times every variant of every pass on
  * the device (reps launches each, events on `stream`, which it synchronizes)
  * and keeps the faster.  d_scratch: >= 16*N bytes + apply_ws_bytes for one

@@ -23,9 +23,13 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiffd.so")
 
-SOURCES = ["plan.cpp", "api.cpp", "apply.hip", "apply_la.hip", "apply_lb.hip", "apply_lc.hip",
-           "apply_ld.hip", "apply_le.hip", "setup.hip", "matvec.hip",
-           "pcg.hip", "dense.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "apply.hip",
+           "apply_la_fwd.hip", "apply_la_bwd.hip", "apply_la_mid.hip",
+           "apply_lb_fwd.hip", "apply_lb_bwd.hip", "apply_lb_mid.hip",
+           "apply_lc_fwd.hip", "apply_lc_bwd.hip", "apply_lc_mid.hip",
+           "apply_ld_fwd.hip", "apply_ld_bwd.hip", "apply_ld_mid.hip",
+           "apply_le_fwd.hip", "apply_le_bwd.hip", "apply_le_mid.hip",
+           "setup.hip", "matvec.hip", "pcg.hip", "dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -46,7 +50,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    jobs = min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -303,7 +303,7 @@ int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* 
 
 int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant) {
   if (!plan) return fail(IFFD_E_INVAL, "null argument");
-  if (pass < 0 || pass >= 2 * plan->P.d - 1 || variant < 0 || variant > 3)
+  if (pass < 0 || pass >= 2 * plan->P.d - 1 || variant < 0 || variant > 4)
     return fail(IFFD_E_INVAL, "pass or variant out of range");
   plan->P.variant[pass] = variant;
   return IFFD_OK;
@@ -337,8 +337,8 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
   for (int k = 0; k < 2 * P.d - 1 && rc == IFFD_OK; ++k) {
     float best = 1e30f;
     int best_v = P.variant[k];
-    // variant 3 exists for power-of-two transform lengths only
-    const int nvar = (P.L & (P.L - 1)) == 0 ? 4 : 3;
+    // variants 3 and 4 exist for power-of-two transform lengths only
+    const int nvar = (P.L & (P.L - 1)) == 0 ? 5 : 3;
     for (int v = 0; v < nvar && rc == IFFD_OK; ++v) {
       P.variant[k] = v;
       for (int w = 0; w < 2; ++w) launch_iffd_pass(P, k, r, z, 1, ws, nullptr, 0, s);

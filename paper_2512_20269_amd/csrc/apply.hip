@@ -4,33 +4,45 @@
 
 namespace iffd {
 
-hipError_t line_pass_L16(const Plan& P, int mode, int var, int axis, int tin, const void* in,
+// each (L, mode) pair is compiled in its own translation unit (apply_l*_*.hip)
+extern template IFFD_LINE_PASS_MODE(16, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(16, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(16, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(24, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(24, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(24, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(32, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(32, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(32, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(48, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(48, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(48, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(64, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(64, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(64, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(96, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(96, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(96, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(128, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(128, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(128, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(192, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(192, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(192, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(256, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(256, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(256, PASS_MID);
+
+template <int L>
+static hipError_t by_mode(const Plan& P, int mode, int var, int axis, int tin, const void* in,
                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L24(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L32(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L48(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L64(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L96(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L128(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L192(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
-hipError_t line_pass_L256(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                          int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                          const PassHook* hk);
+                          const PassHook* hk) {
+  if (mode == PASS_FWD)
+    return line_pass_mode<L, PASS_FWD>(P, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+  if (mode == PASS_BWD)
+    return line_pass_mode<L, PASS_BWD>(P, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+  return line_pass_mode<L, PASS_MID>(P, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+}
 
 hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
                             void* out, int nrhs, const double* a, int as, hipStream_t s,
@@ -40,15 +52,15 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
   const int pass = mode == PASS_FWD ? axis - 1 : (mode == PASS_MID ? d - 1 : 2 * d - 1 - axis);
   const int var = P.variant[pass];
   switch (P.L) {
-    case 16: return line_pass_L16(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 24: return line_pass_L24(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 32: return line_pass_L32(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 48: return line_pass_L48(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 64: return line_pass_L64(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 96: return line_pass_L96(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 128: return line_pass_L128(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 192: return line_pass_L192(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
-    case 256: return line_pass_L256(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 16: return by_mode<16>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 24: return by_mode<24>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 32: return by_mode<32>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 48: return by_mode<48>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 64: return by_mode<64>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 96: return by_mode<96>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 128: return by_mode<128>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 192: return by_mode<192>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 256: return by_mode<256>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
     default: return hipErrorInvalidValue;
   }
 }
@@ -89,7 +101,10 @@ template <typename T, int L>
 static int tw_min() {
   int a = Cfg<T, L, 0>::TW, b = Cfg<T, L, 1>::TW, c = Cfg<T, L, 2>::TW;
   int w = a < b ? (a < c ? a : c) : (b < c ? b : c);
-  if constexpr (fft_has_v3<L>()) w = w < Cfg<T, L, 3>::TW ? w : Cfg<T, L, 3>::TW;
+  if constexpr (fft_has_v3<L>()) {
+    w = w < Cfg<T, L, 3>::TW ? w : Cfg<T, L, 3>::TW;
+    w = w < Cfg<T, L, 4>::TW ? w : Cfg<T, L, 4>::TW;
+  }
   return w;
 }
 template <int L>

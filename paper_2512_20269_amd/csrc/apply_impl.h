@@ -70,14 +70,14 @@ struct Geom {
 };
 
 // Tile shape of variant V: E transform elements per thread (variant 2 takes
-// variant 1's FFT shape, variant 3 has 4), FPW line pairs per workgroup
-// (variant 2 half as many, for problems too small to fill the chip with full
-// tiles).
+// variant 1's FFT shape, variant 3 has 4, variant 4 takes variant 3's), FPW
+// line pairs per workgroup (variants 2 and 4 half as many, for problems too
+// small to fill the chip with full tiles).
 template <typename T, int L, int V>
 struct Cfg {
   static constexpr int E = FftPlan<L, V>::E;
   static constexpr int NT = L / E;
-  static constexpr int CAP = (sizeof(T) == 8 ? 128 : 256) / (V == 2 ? 2 * NT : NT);
+  static constexpr int CAP = (sizeof(T) == 8 ? 128 : 256) / ((V == 2 || V == 4) ? 2 * NT : NT);
   static constexpr int FPW = CAP >= 32 ? 32 : (CAP < 1 ? 1 : CAP);
   static constexpr int TW = 2 * FPW;
   static constexpr int NTH = FPW * NT;
@@ -344,7 +344,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       const T yb = sj * (vb + wb) + T(0.5) * (vb - wb);
       return j0 ? cpx<T>{T(0), T(0)} : cpx<T>{ya, yb};
     };
-    auto sto = [&](int k, cpx<T> v) { buf[fpad(k)] = v; };
+    auto sto = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
     fft_forward<T, L, V>(buf, tid, twl, ldo, sto);
     __syncthreads();
     constexpr int CK = N / (2 * NT);   // k values per thread (E / 2)
@@ -354,7 +354,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 #pragma unroll
     for (int c = 0; c < CK; ++c) {
       const int k = k0 + c;
-      const cpx<T> wk = buf[fpad(k)], wm = buf[fpad(k == 0 ? 0 : N - k)];
+      const cpx<T> wk = buf[fpad<L>(k)], wm = buf[fpad<L>(k == 0 ? 0 : N - k)];
       // line a: (W_k + conj W_{n-k}) / 2, line b: -i (W_k - conj W_{n-k}) / 2
       const T aa = T(0.5) * (wk.x + wm.x), ab = T(0.5) * (wk.y + wm.y);
       ea[c] = T(0.5) * (wm.y - wk.y);
@@ -490,7 +490,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
         const T a = Ga[idx], b = Gb[idx];
         return {lo ? a : -a, lo ? b : -b};
       };
-      auto sth = [&](int k, cpx<T> v) { buf[fpad(k)] = v; };
+      auto sth = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
       fft_forward<T, L, V>(buf, tid, twl, ldh, sth);
       __syncthreads();
       constexpr int NP = (N / 2 + 1 + NT - 1) / NT;   // pairs per thread
@@ -499,7 +499,7 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
       for (int u = 0; u < NP; ++u) {
         const int k = tid + NT * u;
         const int kk = k <= N / 2 ? k : 0;
-        const cpx<T> wk = buf[fpad(kk)], wm = buf[fpad(kk == 0 ? 0 : N - kk)];
+        const cpx<T> wk = buf[fpad<L>(kk)], wm = buf[fpad<L>(kk == 0 ? 0 : N - kk)];
         const cpx<T> va = {T(0.5) * (wk.x + wm.x), T(0.5) * (wk.y - wm.y)};
         const cpx<T> vb = {T(0.5) * (wk.y + wm.y), T(-0.5) * (wk.x - wm.x)};
         const cpx<T> tk = twp[kk], tm = twp[N - kk];
@@ -780,6 +780,7 @@ static hipError_t by_shape(const Plan& P, int var, int axis, const void* in, voi
   if (var == 1) return launch_t<Tin, Tout, T, MODE, L, 1, PK>(P, axis, in, out, nrhs, a, as, s, hk);
   if constexpr (fft_has_v3<L>()) {
     if (var == 3) return launch_t<Tin, Tout, T, MODE, L, 3, PK>(P, axis, in, out, nrhs, a, as, s, hk);
+    if (var == 4) return launch_t<Tin, Tout, T, MODE, L, 4, PK>(P, axis, in, out, nrhs, a, as, s, hk);
   }
   return launch_t<Tin, Tout, T, MODE, L, 2, PK>(P, axis, in, out, nrhs, a, as, s, hk);
 }
@@ -809,25 +810,22 @@ static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, v
   return hipErrorInvalidValue;
 }
 
-// all modes, element types and variants of the line pass for one FFT length
-template <int L>
-hipError_t line_pass_for_L(const Plan& P, int mode, int var, int axis, int tin, const void* in,
-                           int tout, void* out, int nrhs, const double* a, int as, hipStream_t s,
-                           const PassHook* hk) {
+// the element types and variants of the line pass for one FFT length and mode
+// (each (L, MODE) pair is instantiated in its own translation unit)
+template <int L, int MODE>
+hipError_t line_pass_mode(const Plan& P, int var, int axis, int tin, const void* in, int tout,
+                          void* out, int nrhs, const double* a, int as, hipStream_t s,
+                          const PassHook* hk) {
   if (P.prec == IFFD_PREC_F64) {
     if (tin != ELEM_F64 || tout != ELEM_F64) return hipErrorInvalidValue;
-    if (mode == PASS_FWD)
-      return by_variant<double, double, double, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
-    if (mode == PASS_BWD)
-      return by_variant<double, double, double, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
-    return by_variant<double, double, double, PASS_MID, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
+    return by_variant<double, double, double, MODE, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   }
-  if (mode == PASS_FWD) {
+  if constexpr (MODE == PASS_FWD) {
     if (tin == ELEM_F64 && tout == ELEM_F32)
       return by_variant<double, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F32 && tout == ELEM_F32)
       return by_variant<float, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
-  } else if (mode == PASS_BWD) {
+  } else if constexpr (MODE == PASS_BWD) {
     if (tin == ELEM_F32 && tout == ELEM_F64)
       return by_variant<float, double, float, PASS_BWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F32 && tout == ELEM_F32)
@@ -838,5 +836,9 @@ hipError_t line_pass_for_L(const Plan& P, int mode, int var, int axis, int tin, 
   }
   return hipErrorInvalidValue;
 }
+
+#define IFFD_LINE_PASS_MODE(L, MODE)                                                         \
+  hipError_t line_pass_mode<L, MODE>(const Plan&, int, int, int, const void*, int, void*, int, \
+                                     const double*, int, hipStream_t, const PassHook*)
 
 }  // namespace iffd

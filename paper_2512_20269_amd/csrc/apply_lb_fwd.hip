@@ -1,0 +1,9 @@
+// Instantiations of the IFFD line pass: FFT lengths 64, 96, forward passes.
+#include "apply_impl.h"
+
+namespace iffd {
+
+template IFFD_LINE_PASS_MODE(64, PASS_FWD);
+template IFFD_LINE_PASS_MODE(96, PASS_FWD);
+
+}  // namespace iffd

@@ -154,13 +154,19 @@ template <int L> struct FftPlan<L, 2> : FftPlan<L, 1> {};
 // twice variant 1's threads per transform, for problems too small to keep
 // enough waves in flight
 template <int L> struct FftPlan<L, 3> { static constexpr int E = 4; };
+// variant 4: variant 3's transform shape (it differs only in lines per workgroup)
+template <int L> struct FftPlan<L, 4> : FftPlan<L, 3> {};
 template <int L> constexpr bool fft_has_v3() { return (L & (L - 1)) == 0 && L >= 16; }
 
-// padded LDS index of FFT element k: one spare slot every 16 entries keeps
-// the strided Stockham writes off a single bank; the regions of consecutive
-// transforms are staggered by 8 elements so they start on different banks
-__device__ __forceinline__ int fpad(int k) { return k + (k >> 4); }
-template <int L> constexpr int fft_region() { return L + L / 16 + 8; }
+// padded LDS index of FFT element k of a length-L transform: for power-of-two
+// lengths one spare slot every 16 entries keeps the strided Stockham writes
+// off a single bank; lengths with a factor 3 (radix-3 last stage) measured
+// fastest unpadded.  The regions of consecutive transforms are staggered by 8
+// elements so they start on different banks.
+template <int L> constexpr bool fft_padded() { return L % 3 != 0; }
+template <int L>
+__device__ __forceinline__ int fpad(int k) { return fft_padded<L>() ? k + (k >> 4) : k; }
+template <int L> constexpr int fft_region() { return L + (fft_padded<L>() ? L / 16 : 0) + 8; }
 
 // One Stockham stage: reads, butterflies, barrier, writes.  FIRST: inputs
 // come from ld(k, lo, k0, kh) instead of LDS, with lo = (k < L/2),
@@ -182,7 +188,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int tid, const cpx<T>* tw
       // first stage: j < L/R, so k < L/2 exactly when r < R/2 (R is even for
       // every first radix), and k is 0 or L/2 only for j = 0
       if constexpr (FIRST) v[b][r] = ld(k, r < R / 2, j == 0 && r == 0, j == 0 && 2 * r == R);
-      else v[b][r] = buf[fpad(k)];
+      else v[b][r] = buf[fpad<L>(k)];
     }
   }
 #pragma unroll
@@ -205,7 +211,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int tid, const cpx<T>* tw
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (LAST) st(o + r * NS, v[b][r]);
-      else buf[fpad(o + r * NS)] = v[b][r];
+      else buf[fpad<L>(o + r * NS)] = v[b][r];
     }
   }
   if constexpr (!LAST) __syncthreads();
@@ -240,7 +246,7 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
-  } else if constexpr (V == 3) {
+  } else if constexpr (V == 3 || V == 4) {
     if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 4, 4>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 4, 4, 2>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 64) FftRun<T, 64, E, NT, 1, 4, 4, 4>::run(buf, tid, tw, ld, st);

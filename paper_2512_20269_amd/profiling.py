@@ -111,7 +111,7 @@ def traffic(fetch_db: str, write_db: str, bench: dict, cmd_fetch: str, cmd_write
     for k in range(len(roof["fft_variant_per_pass"])):
         alg = B * N * ((8 if k == 0 else w) + (8 if k == 2 * d - 2 else w))
         entry = {}
-        for v in (0, 1, 2, 3):    # the tuner dispatches every FFT shape of every pass
+        for v in (0, 1, 2, 3, 4):    # the tuner dispatches every FFT shape of every pass
             name = line_pass_name(d, prec, k, roof["fft_len"], v, n, p)
             fk = [val for key, val in fe.items() if key.startswith(name + "(")]
             wk = [val for key, val in wr.items() if key.startswith(name + "(")]

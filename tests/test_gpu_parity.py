@@ -240,12 +240,12 @@ def test_fft_variants_and_tuner(d, n, p):
     zo = oracle(d, n, p).apply(r)
     for prec in ("f64", "f32"):
         pl = I.Plan(d, n, p, precision=prec)
-        for v in (0, 1, 2, 3):
+        for v in (0, 1, 2, 3, 4):
             for k in range(pl.n_passes()):
                 pl.set_variant(k, v)
             assert rel(host(pl.apply(dev(r))), zo) <= TOL[prec]
         chosen = pl.tune(reps=3)
-        assert len(chosen) == 2 * d - 1 and set(chosen) <= {0, 1, 2, 3}
+        assert len(chosen) == 2 * d - 1 and set(chosen) <= {0, 1, 2, 3, 4}
         assert rel(host(pl.apply(dev(r))), zo) <= TOL[prec]
 
 
