@@ -19,8 +19,6 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
 hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream_t s);
 hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u, hipStream_t s);
 hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out, hipStream_t s);
-hipError_t residual_norms_dev(const Plan& P, const double* f, const double* y, double* tmp,
-                              double* part, int nrhs, hipStream_t s);
 }  // namespace iffd
 
 using namespace iffd;
@@ -530,15 +528,15 @@ int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nr
   // solution out, true residual
   double* x = (double*)(st + L.x);
   double* qz = (double*)(st + L.qz);
-  double* r = (double*)(st + L.r);
   double* part = (double*)(st + L.part);
   hipError_t e = hipMemcpyAsync(d_u, x, 8 * (size_t)P.N * nrhs, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "copy solution");
-  e = launch_matvec(P, d_u, qz, nrhs, L.mvws ? st + L.mvws : nullptr, nullptr, 0, nullptr, 0, s);
-  if (e == hipSuccess) e = residual_norms_dev(P, d_f, qz, r, part, nrhs, s);
+  // true residual: ||f - A u||^2 partials straight from the operator
+  e = launch_matvec(P, d_u, qz, nrhs, L.mvws ? st + L.mvws : nullptr, part, L.npart, nullptr, 0,
+                    s, d_f);
   if (e != hipSuccess) return hip_fail(e, "true residual");
-  const int nb = pcg_blocks(P);
-  std::vector<double> parts((size_t)nrhs * nb), sc((size_t)nrhs * kScal),
+  const int nb = matvec_blocks(P), stride = L.npart;
+  std::vector<double> parts((size_t)nrhs * stride), sc((size_t)nrhs * kScal),
       hist((size_t)nrhs * kHist * 2);
   e = hipMemcpyAsync(parts.data(), part, 8 * parts.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
@@ -551,7 +549,7 @@ int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nr
   for (int k = 0; k < nrhs; ++k) {
     const double* rec = &sc[(size_t)k * kScal];
     double rr = 0.0;
-    for (int i = 0; i < nb; ++i) rr += parts[(size_t)k * nb + i];
+    for (int i = 0; i < nb; ++i) rr += parts[(size_t)k * stride + i];
     const int status = (int)rec[S_STATUS];
     if (status < 0) worst = std::min(worst, status);
     else if (worst >= 0) worst = std::max(worst, status);

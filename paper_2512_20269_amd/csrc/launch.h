@@ -88,10 +88,11 @@ hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, 
 // Outlier pencil eigensolve + table completion (FP64, on device).
 hipError_t launch_setup_outliers(const Plan& P, hipStream_t s);
 
-// y = Ahat x; ws: matvec_ws_bytes(P, nrhs); optional fused partial dot sums
-// part[b][blk] = sum x.y over a workgroup.
+// y = Ahat x; ws: matvec_ws_bytes(P, nrhs); optional fused partial sums per
+// workgroup: part[b][blk] = sum x.y, or sum (f - y)^2 when fres (the true
+// residual of a solution x for the right-hand side f) is given.
 hipError_t launch_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
                          double* part, int npart, const double* active, int active_stride,
-                         hipStream_t s);
+                         hipStream_t s, const double* fres = nullptr);
 
 }  // namespace iffd

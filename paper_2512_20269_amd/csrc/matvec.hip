@@ -116,7 +116,8 @@ __global__ void __launch_bounds__(MV2_THREADS)
 mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
         const double* __restrict__ s3, double* __restrict__ y, int m, int N, int ncs, int nch,
         int bpr, const double* __restrict__ kc, const double* __restrict__ mc, int nbr, int crows,
-        double* __restrict__ part, int npart, const double* __restrict__ active, int astride) {
+        double* __restrict__ part, int npart, const double* __restrict__ active, int astride,
+        const double* __restrict__ fres) {
   constexpr int BW = 2 * P + 1;
   constexpr int C2 = mv2_rows<P>();
   constexpr int WIN = C2 + 2 * P;
@@ -152,14 +153,15 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
       wt[k] = in ? t3[gi] : 0.0;
       wsv[k] = (HAS_S && in) ? s3[gi] : 0.0;
     }
-    // x at the output points, for the partial x . y (loaded with the window so
-    // that no load waits inside the row loop)
+    // x (or f for the residual) at the output points, for the partial sums
+    // (loaded with the window so that no load waits inside the row loop)
     const bool out = lane >= P && lane < 64 - P && col;
+    const double* xsrc = fres ? fres : xin;
     double xv[C2];
 #pragma unroll
     for (int r = 0; r < C2; ++r) {
       const bool in = part && out && r0 + r < m;
-      xv[r] = in ? xin[base + (size_t)(r0 + r) * m + i1] : 0.0;
+      xv[r] = in ? xsrc[base + (size_t)(r0 + r) * m + i1] : 0.0;
     }
     // row by row: direction 2 from the register window, direction 1 from the
     // neighbouring lanes through DPP whole-wave shifts (VALU moves, no LDS)
@@ -197,7 +199,8 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
       }
       if (out && r0 + r < m) {
         y[base + (size_t)(r0 + r) * m + i1] = yv;
-        dot += xv[r] * yv;
+        const double dv = xv[r] - yv;
+        dot += fres ? dv * dv : xv[r] * yv;
       }
     }
   }
@@ -247,7 +250,7 @@ __global__ void __launch_bounds__(MVF_THREADS)
 mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, int ncs, int nrb,
           int n3c, const double* __restrict__ kc, const double* __restrict__ mc, int nbr,
           int crows, double* __restrict__ part, int npart, const double* __restrict__ active,
-          int astride) {
+          int astride, const double* __restrict__ fres) {
   constexpr int BW = 2 * P + 1;
   constexpr int WIN = MVF_C3 + 2 * P;
   constexpr int OUT = MVF_CW - 2 * P, R2 = MVF_RT - 2 * P;
@@ -301,6 +304,7 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
   const bool out = ty >= P && ty < P + R2 && i2 < m && cl >= P && cl < MVF_CW - P && i1 < m;
   const int ta = ty >= P && ty < P + R2 ? ty : P;   // rows the halo half-wave reads (discarded)
   const auto ws = buf_rsrc(y + (size_t)rhs * N, (unsigned)N * 8u);
+  const auto fr = buf_rsrc(fres ? fres + (size_t)rhs * N : y, fres ? (unsigned)N * 8u : 0u);
   // a tile whose columns and rows all take the interior (Toeplitz) band row
   // reads its coefficients from scalar registers instead of LDS
   const bool inter = crows < m && cs * OUT - P >= nbr && cs * OUT - P + MVF_CW <= m - nbr &&
@@ -351,8 +355,14 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
           yv += K1(P + d) * ur + M1(P + d) * vr;
         }
         if (out) {
-          buf_st<double>(yv, ws, (unsigned)(i3 * plane + i2 * m + i1) * 8u);
-          dot += w[k + P] * yv;
+          const unsigned oo = (unsigned)(i3 * plane + i2 * m + i1) * 8u;
+          buf_st<double>(yv, ws, oo);
+          if (fres) {   // uniform
+            const double dv = buf_ld<double>(fr, oo) - yv;
+            dot += dv * dv;
+          } else {
+            dot += w[k + P] * yv;
+          }
         }
       }
     }
@@ -390,7 +400,8 @@ size_t matvec_ws_bytes(const Plan& P_, int nrhs) {
 
 template <int P>
 static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs, void* ws,
-                            double* part, int npart, const double* a, int as, hipStream_t s) {
+                            double* part, int npart, const double* a, int as, hipStream_t s,
+                            const double* fres) {
   const int m = P_.m, N = (int)P_.N;
   const char* b = P_.d_tables;
   const double* kc = (const double*)(b + P_.lay.kc64);
@@ -403,7 +414,7 @@ static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs
       const int bpr = ncs * nrb * n3c;
       if (part && bpr > npart) return hipErrorInvalidValue;
       hipLaunchKernelGGL(mv_fused3<P>, dim3(bpr * nrhs), dim3(MVF_THREADS), 0, s, x, y, m, N, ncs,
-                         nrb, n3c, kc, mc, nbr, crows, part, npart, a, as);
+                         nrb, n3c, kc, mc, nbr, crows, part, npart, a, as, fres);
       return hipGetLastError();
     }
   }
@@ -419,26 +430,27 @@ static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs
     hipLaunchKernelGGL(mv_axis3<P>, dim3(cb * n3 * nrhs), dim3(MV1_THREADS), 0, s, x, t3, s3, m,
                        N, n3, kc, mc, nbr, crows, a, as);
     hipLaunchKernelGGL((mv_rows<P, true>), dim3(bpr * nrhs), dim3(MV2_THREADS), 0, s, x, t3, s3,
-                       y, m, N, ncs, nch, bpr, kc, mc, nbr, crows, part, npart, a, as);
+                       y, m, N, ncs, nch, bpr, kc, mc, nbr, crows, part, npart, a, as, fres);
   } else {
     hipLaunchKernelGGL((mv_rows<P, false>), dim3(bpr * nrhs), dim3(MV2_THREADS), 0, s, x, x,
                        (const double*)nullptr, y, m, N, ncs, nch, bpr, kc, mc, nbr, crows, part,
-                       npart, a, as);
+                       npart, a, as, fres);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_matvec(const Plan& P_, const double* x, double* y, int nrhs, void* ws,
-                         double* part, int npart, const double* a, int as, hipStream_t s) {
+                         double* part, int npart, const double* a, int as, hipStream_t s,
+                         const double* fres) {
   switch (P_.p) {
-    case 1: return mv_launch<1>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 2: return mv_launch<2>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 3: return mv_launch<3>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 4: return mv_launch<4>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 5: return mv_launch<5>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 6: return mv_launch<6>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 7: return mv_launch<7>(P_, x, y, nrhs, ws, part, npart, a, as, s);
-    case 8: return mv_launch<8>(P_, x, y, nrhs, ws, part, npart, a, as, s);
+    case 1: return mv_launch<1>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 2: return mv_launch<2>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 3: return mv_launch<3>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 4: return mv_launch<4>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 5: return mv_launch<5>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 6: return mv_launch<6>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 7: return mv_launch<7>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
+    case 8: return mv_launch<8>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
     default: return hipErrorInvalidValue;
   }
 }

@@ -269,12 +269,12 @@ pcg_begin_p(double* __restrict__ p, const double* __restrict__ z, int N, int nbl
 }
 
 __global__ void __launch_bounds__(VT)
-pcg_begin_finish(double* scal, const double* part, int nblk, int nslots) {
+pcg_begin_finish(double* scal, const double* part, int nused, int stride, int nslots) {
   __shared__ double red[VT / 64];
   const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_NEW] == 0.0) return;
-  const double rz = block_psum(part + (size_t)slot * nblk, nblk, red);
+  const double rz = block_psum(part + (size_t)slot * stride, nused, red);
   if (threadIdx.x != 0) return;
   sc[S_NEW] = 0.0;
   if (!(rz > 0.0) || !isfinite(rz)) {
@@ -331,14 +331,6 @@ hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out
   return hipGetLastError();
 }
 
-// r = f - y (for the true residual), per slot
-__global__ void __launch_bounds__(VT)
-axpby_res(double* __restrict__ out, const double* __restrict__ f, const double* __restrict__ y,
-          size_t n) {
-  for (size_t i = (size_t)blockIdx.x * VT + threadIdx.x; i < n; i += (size_t)gridDim.x * VT)
-    out[i] = f[i] - y[i];
-}
-
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
@@ -377,15 +369,22 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   hipLaunchKernelGGL(pcg_begin_scal, dim3(count), dim3(VT), 0, s, scal, part, nb, bs, rtol, maxit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // z = P^{-1} r for the new slots only
-  e = (P.method == IFFD_METHOD_FFT)
-          ? launch_iffd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s)
-          : launch_fd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
-                     (int)S_NEW);
+  // z = P^{-1} r for the new slots only (IFFD: r . z partials from its last pass)
+  int nrz = nb;
+  if (P.method == IFFD_METHOD_FFT) {
+    const PassHook hk{r, part, nb, 0};
+    e = launch_iffd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s,
+                          &hk);
+    if (e != hipSuccess) return e;
+    nrz = hk.tiles;
+  } else {
+    e = launch_fd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
+                       (int)S_NEW);
+  }
   hipLaunchKernelGGL(pcg_begin_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
-  hipLaunchKernelGGL(pcg_begin_finish, dim3(nslots), dim3(VT), 0, s, scal, part, nb, nslots);
+  hipLaunchKernelGGL(pcg_begin_finish, dim3(nslots), dim3(VT), 0, s, scal, part, nrz, nb, nslots);
   return hipGetLastError();
 }
 
@@ -434,16 +433,6 @@ hipError_t pcg_take_dev(const Plan& P, char* st, int nslots, int slot, double* u
   const StateLayout L = state_layout(P, nslots);
   hipLaunchKernelGGL(pcg_take_kernel, dim3(slot < 0 ? 2048 : 256), dim3(256), 0, s,
                      (const double*)(st + L.x), u, (int)P.N, slot, nslots, (double*)(st + L.scal));
-  return hipGetLastError();
-}
-
-// norms of f - y for nrhs vectors (true residual): out[k] = ||f_k - y_k||^2
-hipError_t residual_norms_dev(const Plan& P, const double* f, const double* y, double* tmp,
-                              double* part, int nrhs, hipStream_t s) {
-  const int N = (int)P.N, nb = pcg_blocks(P);
-  hipLaunchKernelGGL(axpby_res, dim3(1024), dim3(VT), 0, s, tmp, f, y, (size_t)N * nrhs);
-  hipLaunchKernelGGL(dot_partials, dim3(nrhs * nb), dim3(VT), 0, s, tmp, tmp, N, nb, part,
-                     (const double*)nullptr, 0);
   return hipGetLastError();
 }
 
