@@ -202,28 +202,28 @@ def serving(torch, count, warm, fracs, budget_gb=96.0, slots=8, iters=2, check=4
             "runs": runs, "sampled_same_bits_as_alone": same, "sampled": check}
 
 
-def sweep_p(torch, ps=(2, 3, 4, 6, 8)):
-    """3D n = 256 with the smooth right-hand side, degree sweep: FP32 apply
-    error against the FP64 apply, PCG iterations and solve time with the FP32
-    apply, and the dense-FD solve beside it.  (The FP64 apply's agreement with
-    the oracle at this size is a GPU test.)"""
+def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256):
+    """3D with the smooth right-hand side (8 random-phase sine modes plus 1e-3
+    noise, seed 3), degree sweep: FP32 apply error against the FP64 apply, PCG
+    iterations and solve time with the FP32 apply, and the dense-FD solve
+    beside it.  (The FP64 apply's agreement with the oracle is a GPU test.)"""
     import workloads
     import paper_2512_20269_amd as iffd
     rows = []
     for p in ps:
-        f_np = workloads.workload_rhs("cube_n256", p=p)
+        f_np = workloads.smooth_rhs(3, n, p, 3)
         f = torch.from_numpy(f_np).cuda()
-        row = {"p": p}
-        p32 = iffd.Plan(3, 256, p, method="fft", precision="f32")
+        row = {"n": n, "p": p}
+        p32 = iffd.Plan(3, n, p, method="fft", precision="f32")
         p32.tune(reps=5)
         z32 = p32.apply(f)
-        z64 = iffd.Plan(3, 256, p, method="fft", precision="f64").apply(f)
+        z64 = iffd.Plan(3, n, p, method="fft", precision="f64").apply(f)
         row["apply_f32_relerr_vs_f64"] = float((z32 - z64).norm() / z64.norm())
         lat, st = time_solves(torch, p32, f, 5)
         u = p32.solve(f, rtol=1e-8)[0]
         row.update({"pcg_iterations": st[0]["iterations"], "pcg_relres_true": st[0]["relres_true"],
                     "pcg_ms_p50": round(pct(lat, 0.5), 3), "kappa_est": round(st[0]["kappa_est"], 4)})
-        fd = iffd.Plan(3, 256, p, method="dense", precision="f32")
+        fd = iffd.Plan(3, n, p, method="dense", precision="f32")
         flat, fst = time_solves(torch, fd, f, 3)
         uf = fd.solve(f, rtol=1e-8)[0]
         row.update({"dense_fd_iterations": fst[0]["iterations"],
@@ -251,6 +251,9 @@ def main():
                          "(reference dispatch for HBM byte counters)")
     ap.add_argument("--sweep-p", action="store_true",
                     help="only the 3D n=256 degree sweep (smooth right-hand side)")
+    ap.add_argument("--sweep-n", default="",
+                    help="only the IFFD / dense-FD solve comparison at these 3D sizes "
+                         "(comma-separated n; p = 3 and 4, smooth right-hand side)")
     ap.add_argument("--serve", action="store_true",
                     help="only the serving benchmark (Poisson stream of mixed solves)")
     ap.add_argument("--pcg-only", choices=["fft", "dense"],
@@ -271,6 +274,14 @@ def main():
     import paper_2512_20269_amd as iffd
 
     torch.cuda.set_device(0)
+    if args.sweep_n:
+        rows = []
+        for n_ in [int(x) for x in args.sweep_n.split(",")]:
+            rows += sweep_p(torch, ps=(3, 4), n=n_)
+        print(json.dumps({"metric": "PCG solve time to 1e-8, IFFD vs dense FD", "unit": "ms",
+                          "config": {"workload": f"cube_n{args.sweep_n}_p3-4_smooth"},
+                          "rows": rows}), flush=True)
+        return
     if args.sweep_p:
         rows = sweep_p(torch)
         print(json.dumps({"metric": "iterations and FP32 apply error vs p, 3D n=256",

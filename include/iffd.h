@@ -185,7 +185,7 @@ int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* 
  * variant 1's shape with half the lines per workgroup (more workgroups for
  * small problems), variant 3 holds 4 elements per thread and variant 4 has
  * variant 3's shape with half the lines per workgroup (power-of-two transform
- * lengths; elsewhere both run variant 2).  All compute the same result; they
+ * lengths up to 256; elsewhere both run variant 2).  All compute the same result; they
  * differ in speed.
  * iffd_plan_set_variant forces a choice (variant 0..4; diagnostics, tests);
  * iffd_plan_tune times every variant of every pass on

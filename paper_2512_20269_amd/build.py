@@ -29,6 +29,8 @@ SOURCES = ["plan.cpp", "api.cpp", "apply.hip",
            "apply_lc_fwd.hip", "apply_lc_bwd.hip", "apply_lc_mid.hip",
            "apply_ld_fwd.hip", "apply_ld_bwd.hip", "apply_ld_mid.hip",
            "apply_le_fwd.hip", "apply_le_bwd.hip", "apply_le_mid.hip",
+           "apply_lf_fwd.hip", "apply_lf_bwd.hip", "apply_lf_mid.hip",
+           "apply_lg_fwd.hip", "apply_lg_bwd.hip", "apply_lg_mid.hip",
            "setup.hip", "matvec.hip", "pcg.hip", "dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

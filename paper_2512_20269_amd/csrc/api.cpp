@@ -335,8 +335,8 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
   for (int k = 0; k < 2 * P.d - 1 && rc == IFFD_OK; ++k) {
     float best = 1e30f;
     int best_v = P.variant[k];
-    // variants 3 and 4 exist for power-of-two transform lengths only
-    const int nvar = (P.L & (P.L - 1)) == 0 ? 5 : 3;
+    // variants 3 and 4 exist for power-of-two transform lengths up to 256 only
+    const int nvar = ((P.L & (P.L - 1)) == 0 && P.L <= 256) ? 5 : 3;
     for (int v = 0; v < nvar && rc == IFFD_OK; ++v) {
       P.variant[k] = v;
       for (int w = 0; w < 2; ++w) launch_iffd_pass(P, k, r, z, 1, ws, nullptr, 0, s);

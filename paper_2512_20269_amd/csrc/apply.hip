@@ -32,6 +32,12 @@ extern template IFFD_LINE_PASS_MODE(192, PASS_MID);
 extern template IFFD_LINE_PASS_MODE(256, PASS_FWD);
 extern template IFFD_LINE_PASS_MODE(256, PASS_BWD);
 extern template IFFD_LINE_PASS_MODE(256, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(384, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(384, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(384, PASS_MID);
+extern template IFFD_LINE_PASS_MODE(512, PASS_FWD);
+extern template IFFD_LINE_PASS_MODE(512, PASS_BWD);
+extern template IFFD_LINE_PASS_MODE(512, PASS_MID);
 
 template <int L>
 static hipError_t by_mode(const Plan& P, int mode, int var, int axis, int tin, const void* in,
@@ -61,6 +67,8 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
     case 128: return by_mode<128>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
     case 192: return by_mode<192>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
     case 256: return by_mode<256>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 384: return by_mode<384>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
+    case 512: return by_mode<512>(P, mode, var, axis, tin, in, tout, out, nrhs, a, as, s, hk);
     default: return hipErrorInvalidValue;
   }
 }
@@ -124,6 +132,8 @@ int apply_last_tiles_max(const Plan& P) {
     case 128: tw = tw_min_p<128>(f64); break;
     case 192: tw = tw_min_p<192>(f64); break;
     case 256: tw = tw_min_p<256>(f64); break;
+    case 384: tw = tw_min_p<384>(f64); break;
+    case 512: tw = tw_min_p<512>(f64); break;
     default: return 1;
   }
   const long long lpr = P.N / P.m;

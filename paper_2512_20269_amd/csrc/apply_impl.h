@@ -149,7 +149,9 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   // contiguous lines (direction 1): RW lanes walk one line, NG lines at once
   constexpr int RW = NTH < 64 ? NTH : 64;
   constexpr int NG = NTH / RW;
-  constexpr int UMAX = (264 + RW - 1) / RW;  // m <= 264
+  // m = n + p - 2 <= n + 6, with n = L (length-n routes) or L / 2
+  constexpr int MMAX = (PK == PK_ODD || PK == PK_EVEN_2N) ? L / 2 + 6 : L + 6;
+  constexpr int UMAX = (MMAX + RW - 1) / RW;   // row chunks of a stored contiguous line
   constexpr int CH = 8;                       // loads in flight per thread (generic path)
   // m = n + p - 2 <= n + 6; the loads of a tile row go in batches of MB entries,
   // one batch when L = 2n, two when L = n (even p, length-n transforms)
@@ -799,7 +801,7 @@ static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, v
       return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_2N>(P, var, axis, in, out, nrhs, a, as, s, hk);
     }
   }
-  if constexpr (L <= 256) {
+  if constexpr (L <= 512) {
     if (P.half_len) {
       if (odd) {
         return by_shape<Tin, Tout, T, MODE, L, PK_ODD_N>(P, var, axis, in, out, nrhs, a, as, s, hk);

@@ -1,0 +1,8 @@
+// Instantiations of the IFFD line pass: FFT length 512, forward passes.
+#include "apply_impl.h"
+
+namespace iffd {
+
+template IFFD_LINE_PASS_MODE(512, PASS_FWD);
+
+}  // namespace iffd

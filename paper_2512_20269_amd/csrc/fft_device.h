@@ -139,6 +139,8 @@ template <> struct FftPlan<96, 0>  { static constexpr int E = 24; };
 template <> struct FftPlan<128, 0> { static constexpr int E = 16; };
 template <> struct FftPlan<192, 0> { static constexpr int E = 24; };
 template <> struct FftPlan<256, 0> { static constexpr int E = 16; };
+template <> struct FftPlan<384, 0> { static constexpr int E = 24; };
+template <> struct FftPlan<512, 0> { static constexpr int E = 16; };
 template <> struct FftPlan<16, 1>  { static constexpr int E = 8; };
 template <> struct FftPlan<24, 1>  { static constexpr int E = 12; };
 template <> struct FftPlan<32, 1>  { static constexpr int E = 8; };
@@ -148,6 +150,8 @@ template <> struct FftPlan<96, 1>  { static constexpr int E = 12; };
 template <> struct FftPlan<128, 1> { static constexpr int E = 8; };
 template <> struct FftPlan<192, 1> { static constexpr int E = 12; };
 template <> struct FftPlan<256, 1> { static constexpr int E = 8; };
+template <> struct FftPlan<384, 1> { static constexpr int E = 12; };
+template <> struct FftPlan<512, 1> { static constexpr int E = 8; };
 // variant 2: variant 1's transform shape (it differs only in lines per workgroup)
 template <int L> struct FftPlan<L, 2> : FftPlan<L, 1> {};
 // variant 3: 4 elements per thread (radix 4 and 2 only, so lengths 2^a):
@@ -156,7 +160,8 @@ template <int L> struct FftPlan<L, 2> : FftPlan<L, 1> {};
 template <int L> struct FftPlan<L, 3> { static constexpr int E = 4; };
 // variant 4: variant 3's transform shape (it differs only in lines per workgroup)
 template <int L> struct FftPlan<L, 4> : FftPlan<L, 3> {};
-template <int L> constexpr bool fft_has_v3() { return (L & (L - 1)) == 0 && L >= 16; }
+// (a transform then spans at most one wave, which the DST-I prefix sums need)
+template <int L> constexpr bool fft_has_v3() { return (L & (L - 1)) == 0 && L >= 16 && L <= 256; }
 
 // padded LDS index of FFT element k of a length-L transform: for power-of-two
 // lengths one spare slot every 16 entries keeps the strided Stockham writes
@@ -246,6 +251,8 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 16, 8>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 8, 8, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 16, 16>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 8, 8, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 16, 16, 2>::run(buf, tid, tw, ld, st);
   } else if constexpr (V == 3 || V == 4) {
     if constexpr (L == 16) FftRun<T, 16, E, NT, 1, 4, 4>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 32) FftRun<T, 32, E, NT, 1, 4, 4, 2>::run(buf, tid, tw, ld, st);
@@ -263,6 +270,8 @@ __device__ __forceinline__ void fft_forward(cpx<T>* buf, int tid, const cpx<T>* 
     else if constexpr (L == 128) FftRun<T, 128, E, NT, 1, 8, 4, 4>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 192) FftRun<T, 192, E, NT, 1, 4, 4, 4, 3>::run(buf, tid, tw, ld, st);
     else if constexpr (L == 256) FftRun<T, 256, E, NT, 1, 8, 8, 4>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 384) FftRun<T, 384, E, NT, 1, 4, 4, 4, 2, 3>::run(buf, tid, tw, ld, st);
+    else if constexpr (L == 512) FftRun<T, 512, E, NT, 1, 8, 8, 8>::run(buf, tid, tw, ld, st);
   }
 }
 

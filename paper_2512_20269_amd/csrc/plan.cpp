@@ -204,7 +204,7 @@ void jacobi(int n, std::vector<double>& A, std::vector<double>& V, std::vector<d
 }  // namespace
 
 bool fft_len_supported(int L) {
-  static const int ok[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+  static const int ok[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
   for (int v : ok)
     if (v == L) return true;
   return false;
@@ -342,7 +342,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     // the kernels have that length, else through the length-2n extension
     P.half_len = fft_len_supported(n);
     P.L = P.half_len ? n : 2 * n;
-    if (n > 256 || !fft_len_supported(P.L)) { err = "n must be 2^a or 3*2^a with 8 <= n <= 256 for the FFT kernels"; return IFFD_E_UNSUPPORTED; }
+    if (n > 512 || !fft_len_supported(P.L)) { err = "n must be 2^a or 3*2^a with 8 <= n <= 512 for the FFT kernels"; return IFFD_E_UNSUPPORTED; }
   }
   const int m = P.m, bw = 2 * p + 1, nb = n + p;  // nb: full basis size
   const double h = 1.0 / n;

@@ -53,7 +53,19 @@ def host(x):
 APPLY_CASES = [(2, 8, 3), (2, 16, 2), (2, 16, 3), (2, 24, 4), (2, 12, 5), (2, 32, 5), (2, 48, 6),
                (2, 64, 3), (2, 64, 7), (2, 96, 8), (2, 128, 4), (2, 192, 3), (2, 256, 6),
                (3, 8, 2), (3, 16, 3), (3, 12, 4), (3, 16, 5), (3, 24, 6), (3, 16, 7), (3, 16, 8),
-               (3, 32, 3), (3, 48, 4)]
+               (3, 32, 3), (3, 48, 4), (2, 384, 4), (2, 512, 3)]
+
+
+def tol_apply(prec, n):
+    """FP64: 1e-12 up to n = 256.  Above, the plan and the oracle assemble the
+    1-D K and M independently in FP64, and the Rayleigh quotient of the
+    smoothest sine mode (which dominates P^{-1} r) cancels like eps times
+    lambda_max / lambda_min, i.e. like n^2: the two eigenvalue tables already
+    differ by 2.2e-13 at n = 256 and 1.5e-12 at n = 512 (test_lib_host), so the
+    gate grows as (n / 256)^2 there."""
+    if prec == "f32" or n <= 256:
+        return TOL[prec]
+    return TOL[prec] * (n / 256) ** 2
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -63,7 +75,7 @@ def test_apply_matches_oracle(d, n, p, prec):
     r = workloads.uniform_rhs(d, n, p, seed=100 * d + n + p)
     z = host(plan(d, n, p, prec).apply(dev(r)))
     zo = oracle(d, n, p).apply(r)
-    assert rel(z, zo) <= TOL[prec]
+    assert rel(z, zo) <= tol_apply(prec, n)
 
 
 @pytest.mark.parametrize("d,n,p", [(2, 16, 3), (2, 64, 3), (3, 16, 3), (3, 12, 4), (3, 24, 8),
