@@ -61,6 +61,11 @@ extern "C" {
 #define IFFD_PREC_F64         0   /* preconditioner arithmetic in FP64          */
 #define IFFD_PREC_F32         1   /* preconditioner arithmetic in FP32; inputs,
                                      outputs and all Krylov work stay FP64      */
+#define IFFD_PREC_F16S        2   /* dense FD only: mode products on FP16 matrix
+                                     cores (FP32 accumulation), every line along
+                                     the transformed direction scaled by its own
+                                     max |value| before rounding to FP16, Q by
+                                     its max |entry|; FP32 in between          */
 
 typedef struct iffd_plan iffd_plan;
 

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libiffd.so")
 OK, W_NOT_CONVERGED = 0, 1
 E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_F16S = 0, 1, 2
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
 
@@ -136,14 +136,15 @@ class Plan:
     """One (d, n, p) problem with its device tables, workspace and PCG state.
 
     method: "fft" (IFFD) or "dense" (classical FD); precision: "f32" or "f64"
-    for the preconditioner arithmetic (vectors and Krylov work are FP64)."""
+    for the preconditioner arithmetic (vectors and Krylov work are FP64), or
+    "f16s" (dense FD only: FP16 matrix cores with per-line scaling)."""
 
     def __init__(self, d: int, n: int, p: int, method: str = "fft", precision: str = "f32",
                  max_rhs: int = 1, device=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
-                     PREC_F32 if precision == "f32" else PREC_F64, max_rhs)
+                     {"f32": PREC_F32, "f64": PREC_F64, "f16s": PREC_F16S}[precision], max_rhs)
         h = ctypes.c_void_p()
         _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h

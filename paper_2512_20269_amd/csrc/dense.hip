@@ -10,8 +10,12 @@
 //                              (S = m^{k-1})
 // The division by sum_k lambda_{j_k} is fused into the epilogue of the last
 // forward product.  FP32 uses v_mfma_f32_32x32x2f32 (a wave owns a 32 x 32
-// tile), FP64 v_mfma_f64_16x16x4f64 (16 x 16 per wave); four waves per
-// workgroup, K staged through LDS in chunks.
+// tile), FP64 v_mfma_f64_16x16x4f64 (16 x 16 per wave), FP16 (IFFD_PREC_F16S)
+// v_mfma_f32_32x32x8f16 with FP32 accumulation; four waves per workgroup, K
+// staged through LDS in chunks.  In FP16 every line along the transformed
+// direction is first divided by its largest |value| and rounded (quant_lines),
+// Q carries one scale s_Q, and the epilogue multiplies both back.
+#include <type_traits>
 #include <utility>
 
 #include "launch.h"
@@ -20,6 +24,7 @@ namespace iffd {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
   int M, N, K;
@@ -32,11 +37,17 @@ struct GemmArgs {
   const void* lam;
   int scale_mode;          // 0 none, 2: 2D (lam[i] + lam[j]), 3: 3D (lam[i] + lam[j%m] + lam[j/m])
   int m;
+  // FP16 operands: C[i][j] *= qs * ls[line], line = row i (ls_mode 1) or
+  // batch entry * N + column j (ls_mode 2)
+  const float* ls;
+  int ls_mode;
+  const float* qs;
 };
 
 template <typename T> struct MfmaCfg;
 template <> struct MfmaCfg<float> { static constexpr int WT = 32, BK = 16; };   // wave tile
 template <> struct MfmaCfg<double> { static constexpr int WT = 16, BK = 16; };
+template <> struct MfmaCfg<_Float16> { static constexpr int WT = 32, BK = 16; };
 
 // C = A * B (all row-major), one workgroup of 4 waves per (2 WT) x (2 WT) tile
 template <typename TA, typename TB, typename TC, typename T>
@@ -58,6 +69,8 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
 
   f32x16 accf = {};
   f64x4 accd = {};
+  // T is the operand type; the accumulator is FP64 for FP64, else FP32
+  using TE = std::conditional_t<sizeof(T) == 8, double, float>;
 
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     // stage A (BM x BK) and B (BK x BN) tiles, zero outside the matrices
@@ -72,7 +85,19 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
       Bs[k][j] = (gk < g.K && gj < g.N) ? (T)Bb[(long long)gk * g.ldb + gj] : T(0);
     }
     __syncthreads();
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 2) {
+      // 32x32x8 f16: lane l supplies row (column) l%32, k = 4(l/32) .. +3
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        f16x4 a, b;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = As[kk + 4 * (lane >> 5) + u][wm + (lane & 31)];
+          b[u] = Bs[kk + 4 * (lane >> 5) + u][wn + (lane & 31)];
+        }
+        accf = __builtin_amdgcn_mfma_f32_32x32x8f16(a, b, accf, 0, 0, 0);
+      }
+    } else if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
         const float a = As[kk + (lane >> 5)][wm + (lane & 31)];
@@ -90,14 +115,19 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
     __syncthreads();
   }
   // epilogue
-  const T* lam = (const T*)g.lam;
-  auto put = [&](int i, int j, T v) {
+  const TE* lam = (const TE*)g.lam;
+  auto put = [&](int i, int j, TE v) {
     if (i >= g.M || j >= g.N) return;
+    if constexpr (sizeof(T) == 2) {
+      const float ls = g.ls_mode == 1 ? g.ls[(long long)bat * g.M + i]
+                                      : g.ls[(long long)bat * g.N + j];
+      v *= g.qs[0] * ls;
+    }
     if (g.scale_mode == 2) v /= lam[i] + lam[j];
     else if (g.scale_mode == 3) v /= lam[i] + lam[j % g.m] + lam[j / g.m];
     Cb[(long long)i * g.ldc + j] = (TC)v;
   };
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) != 8) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       // 32x32x2 f32: accumulator v of lane l holds row 8(v/4) + 4(l/32) + v%4, column l%32
@@ -114,6 +144,53 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
       put(i, j, accd[v]);
     }
   }
+}
+
+// FP16 operand of a mode product along a direction with stride S: line q of
+// a right-hand side (q = o S + j, entries o m S + i S + j, i < m) is divided
+// by its largest |value| and rounded to FP16; scale[rhs][q] keeps that value
+// (1 for an all-zero line).  One thread per line: for S > 1 consecutive
+// threads read consecutive addresses.
+template <typename TI>
+__global__ void __launch_bounds__(256)
+quant_lines(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restrict__ scale,
+            int m, int S, int lines, long long N, int nrhs, const double* __restrict__ active,
+            int astride) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (long long)lines * nrhs) return;
+  const int rhs = (int)(q / lines);
+  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  const int ql = (int)(q - (long long)rhs * lines);
+  const long long base = (long long)rhs * N + (long long)(ql / S) * m * S + (ql % S);
+  float mx = 0.0f;
+  for (int i = 0; i < m; ++i) mx = fmaxf(mx, fabsf((float)in[base + (long long)i * S]));
+  const float sc = mx > 0.0f ? mx : 1.0f;
+  const float inv = 1.0f / sc;
+  for (int i = 0; i < m; ++i)
+    out[base + (long long)i * S] = (_Float16)((float)in[base + (long long)i * S] * inv);
+  scale[q] = sc;
+}
+
+// direction 1 (lines contiguous): one wave per line, lanes stride the line
+template <typename TI>
+__global__ void __launch_bounds__(256)
+quant_rows(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restrict__ scale,
+           int m, int lines, long long N, int nrhs, const double* __restrict__ active,
+           int astride) {
+  const long long q = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= (long long)lines * nrhs) return;   // uniform per wave
+  const int rhs = (int)(q / lines);
+  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  const int ql = (int)(q - (long long)rhs * lines);
+  const long long base = (long long)rhs * N + (long long)ql * m;
+  float mx = 0.0f;
+  for (int i = lane; i < m; i += 64) mx = fmaxf(mx, fabsf((float)in[base + i]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  const float sc = mx > 0.0f ? mx : 1.0f;
+  const float inv = 1.0f / sc;
+  for (int i = lane; i < m; i += 64) out[base + i] = (_Float16)((float)in[base + i] * inv);
+  if (lane == 0) scale[q] = sc;
 }
 
 template <typename TA, typename TB, typename TC, typename T>
@@ -186,9 +263,85 @@ static hipError_t fd_apply_t(const Plan& P, const double* r, double* z, int nrhs
   return mode_product<T, double, T>(P, 1, false, cur, z, nrhs, 0, a, as, s);
 }
 
+// FP16 mode product along `axis`: in (TI) -> quantized lines -> FP16 GEMM ->
+// out (TO), line scales and s_Q restored in the epilogue
+template <typename TI, typename TO>
+static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in, TO* out,
+                                 _Float16* x16, float* ls, int nrhs, int scale, const double* act,
+                                 int as, hipStream_t s) {
+  const char* tb = P.d_tables;
+  const _Float16* Q = (const _Float16*)(tb + P.lay.qfd16);
+  const _Float16* QT = (const _Float16*)(tb + P.lay.qtfd16);
+  const float* qs = (const float*)(tb + P.lay.qs16);
+  const float* lam = (const float*)(tb + P.lay.lamfd32);
+  const int m = P.m;
+  const long long N = P.N;
+  int S = 1;
+  for (int k = 1; k < axis; ++k) S *= m;
+  const int lines = (int)(N / m);
+  const long long nq = (long long)lines * nrhs;
+  if (S == 1)
+    hipLaunchKernelGGL(quant_rows<TI>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, in, x16,
+                       ls, m, lines, N, nrhs, act, as);
+  else
+    hipLaunchKernelGGL(quant_lines<TI>, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, in,
+                       x16, ls, m, S, lines, N, nrhs, act, as);
+  GemmArgs g{};
+  g.active = act;
+  g.astride = as;
+  g.lam = lam;
+  g.scale_mode = scale;
+  g.m = m;
+  g.ls = ls;
+  g.qs = qs;
+  if (axis == 1) {
+    g.M = lines; g.N = m; g.K = m;
+    g.lda = m; g.ldb = m; g.ldc = m;
+    g.sA = N; g.sB = 0; g.sC = N;
+    g.batch_per_rhs = 1;
+    g.ls_mode = 1;
+    return gemm<_Float16, _Float16, TO, _Float16>(x16, fwd ? Q : QT, out, g, nrhs, s);
+  }
+  const int outer = (int)(N / ((long long)S * m));
+  g.M = m; g.N = S; g.K = m;
+  g.lda = m; g.ldb = S; g.ldc = S;
+  g.sA = 0; g.sB = (long long)S * m; g.sC = (long long)S * m;
+  g.batch_per_rhs = outer;
+  g.ls_mode = 2;
+  return gemm<_Float16, _Float16, TO, _Float16>(fwd ? QT : Q, x16, out, g, outer * nrhs, s);
+}
+
+static hipError_t fd_apply_f16(const Plan& P, const double* r, double* z, int nrhs, void* ws,
+                               const double* a, int as, hipStream_t s) {
+  const int d = P.d;
+  const size_t N = (size_t)P.N * nrhs;
+  const size_t b32 = (8 * N + 255) & ~(size_t)255, b16 = (2 * N + 255) & ~(size_t)255;
+  float* t1 = (float*)ws;
+  float* t2 = t1 + N;
+  _Float16* x16 = (_Float16*)((char*)ws + b32);
+  float* ls = (float*)((char*)ws + b32 + b16);
+  hipError_t e = mode_product16<double, float>(P, 1, true, r, t1, x16, ls, nrhs, d == 1 ? d : 0,
+                                               a, as, s);
+  if (e != hipSuccess) return e;
+  float* cur = t1;
+  float* nxt = t2;
+  for (int k = 2; k <= d; ++k) {
+    e = mode_product16<float, float>(P, k, true, cur, nxt, x16, ls, nrhs, k == d ? d : 0, a, as, s);
+    if (e != hipSuccess) return e;
+    std::swap(cur, nxt);
+  }
+  for (int k = d; k >= 2; --k) {
+    e = mode_product16<float, float>(P, k, false, cur, nxt, x16, ls, nrhs, 0, a, as, s);
+    if (e != hipSuccess) return e;
+    std::swap(cur, nxt);
+  }
+  return mode_product16<float, double>(P, 1, false, cur, z, x16, ls, nrhs, 0, a, as, s);
+}
+
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                            const double* active, int astride, hipStream_t s) {
   if (P.method != IFFD_METHOD_DENSE_FD) return hipErrorInvalidValue;
+  if (P.prec == IFFD_PREC_F16S) return fd_apply_f16(P, r, z, nrhs, ws, active, astride, s);
   if (P.prec == IFFD_PREC_F64) return fd_apply_t<double>(P, r, z, nrhs, ws, active, astride, s);
   return fd_apply_t<float>(P, r, z, nrhs, ws, active, astride, s);
 }

@@ -20,6 +20,7 @@ struct TableLayout {
   size_t blob64, blob32;  // line-pass tables back to back (see Plan::bo_*)
   size_t lam32, s32, v0_32, v1_32, vt32, twl32, twp32;
   size_t qfd32, qtfd32, lamfd32;
+  size_t qfd16, qtfd16, qs16;  // dense FD in FP16: Q / s_Q, Q^T / s_Q, s_Q (FP32)
   size_t total;
 };
 

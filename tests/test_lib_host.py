@@ -45,6 +45,20 @@ def read(h, what, count):
     return buf
 
 
+def test_fp16_scaled_option_is_dense_fd_only():
+    opts = I._Opts(I.METHOD_FFT, I.PREC_F16S, 1)
+    h = ctypes.c_void_p()
+    assert I.lib.iffd_plan_create(ctypes.byref(h), 3, 16, 3, ctypes.byref(opts)) == I.E_INVAL
+    rc, h = host_plan(3, 16, 3, I.METHOD_DENSE_FD, I.PREC_F16S)
+    assert rc == 0, I.lib.iffd_last_error()
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    m = O.dims(16, 3)[0]
+    # workspace: two FP32 tensors, an FP16 copy and one FP32 scale per line
+    assert info.apply_ws_bytes >= 8 * m ** 3 + 2 * m ** 3 + 4 * m ** 2
+    I.lib.iffd_plan_destroy(h)
+
+
 @pytest.mark.parametrize("n", [256, 512])
 def test_eigenvalue_tables_agree_within_conditioning(n):
     """The regular eigenvalues are Rayleigh quotients of sine modes with the
