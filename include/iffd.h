@@ -80,7 +80,8 @@ typedef struct {
   int m;            /* n + p - 2                                               */
   int n_reg;        /* dim of the regular subspace: n-1 (p odd), n (p even)    */
   int n_out;        /* dim of the outlier subspace: p-1 (p odd), p-2 (p even)  */
-  int fft_len;      /* complex FFT length used per pair of lines (2n); 0 for FD*/
+  int fft_len;      /* complex FFT length per pair of lines: n, or 2n for
+                       n = 8, 12; 0 for FD                                    */
   int method, apply_prec, max_rhs;
   int64_t N;        /* m^d                                                     */
   size_t table_bytes;      /* device buffer for iffd_plan_setup               */
@@ -112,7 +113,7 @@ typedef struct {
  * (eq:Lambda reg2); for DENSE_FD, the full FP64 eigendecomposition of the
  * pencil (K, M) (eq:eigendecomposition).  Valid range: d in {2,3},
  * 1 <= p <= 8, n > p (the paper's standing assumption), m^d*max_rhs < 2^31
- * per pass; IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 256
+ * per pass; IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 512
  * (IFFD_E_UNSUPPORTED otherwise).  *out receives the plan (NULL on error). */
 int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
 
