@@ -6,7 +6,8 @@ a resident PCG state of several slots (iffd_pcg_state_*), admits a request
 into a free slot of its shape as soon as the HBM budget allows, advances every
 shape's active slots by a few PCG iterations per round on that shape's own
 stream (so different shapes overlap on the device and same-shape solves share
-one launch per kernel), and hands a solution back as soon as its slot
+one launch per kernel; a round is one replay of a HIP graph captured when the
+shape's entry is created), and hands a solution back as soon as its slot
 converges.  A slot's arithmetic does not depend on the other slots, so a
 request gives the same bits alone and in the mix.
 
@@ -30,7 +31,7 @@ from . import PcgState, Plan
 
 
 class _Entry:
-    def __init__(self, key, slots, tune, device):
+    def __init__(self, key, slots, tune, device, k, graphs):
         import torch
         d, n, p = key
         self.key = key
@@ -50,6 +51,28 @@ class _Entry:
         self.inflight = False
         self.watch = ()                     # slots that were busy at the last launch
         self.bytes = self.plan.tables.numel() + self.state.buf.numel()
+        # k PCG iterations over every slot, captured once as a HIP graph (the
+        # kernels read the per-slot active flags on the device, so the same
+        # graph serves any mix of busy and free slots); one launch per round
+        self.k = k
+        self.graph = None
+        if graphs:
+            g = torch.cuda.CUDAGraph()
+            cap = torch.cuda.Stream(device=self.plan.device)
+            cap.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cap):
+                with torch.cuda.graph(g, stream=cap):
+                    self.state.iterate(k)
+            torch.cuda.current_stream().wait_stream(cap)
+            self.graph = g
+
+    def iterate(self):
+        import torch
+        if self.graph is not None:
+            with torch.cuda.stream(self.stream):
+                self.graph.replay()
+        else:
+            self.state.iterate(self.k, stream=self.stream)
 
 
 class Request:
@@ -69,16 +92,19 @@ class Request:
 class SolveServer:
     """hbm_budget: bytes the server may hold (plans, states, result buffers).
     slots: PCG slots per shape.  iters_per_round: PCG iterations enqueued per
-    shape between two polls."""
+    shape between two polls.  graphs: replay each shape's round from a HIP
+    graph (else launch its kernels one by one)."""
 
     def __init__(self, hbm_budget: int, slots: int = 8, iters_per_round: int = 2,
-                 rtol: float = 1e-8, maxit: int = 200, tune: bool = False, device="cuda"):
+                 rtol: float = 1e-8, maxit: int = 200, tune: bool = False, device="cuda",
+                 graphs: bool = True):
         self.budget = int(hbm_budget)
         self.slots = slots
         self.k = iters_per_round
         self.rtol, self.maxit = rtol, maxit
         self.tune = tune
         self.device = device
+        self.graphs = graphs
         self.entries = collections.OrderedDict()   # key -> _Entry (LRU order)
         self.used = 0
         self.peak = 0
@@ -129,7 +155,7 @@ class SolveServer:
                 del self.entries[k]
         if self.used + need > self.budget:
             return None
-        e = _Entry(key, self.slots, self.tune, self.device)
+        e = _Entry(key, self.slots, self.tune, self.device, self.k, self.graphs)
         self.entries[key] = e
         self.used += e.bytes
         self.peak = max(self.peak, self.used)
@@ -163,7 +189,7 @@ class SolveServer:
         """Enqueue k iterations of every busy slot of a shape and an
         asynchronous copy of its slot records; never waits."""
         import torch
-        e.state.iterate(self.k, stream=e.stream)
+        e.iterate()
         e.state.status_async(e.dstat, stream=e.stream)
         with torch.cuda.stream(e.stream):
             e.hstat.copy_(e.dstat, non_blocking=True)
