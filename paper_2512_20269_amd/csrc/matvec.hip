@@ -80,8 +80,8 @@ mv_axis3(const double* __restrict__ x, double* __restrict__ t3, double* __restri
 // Pass 2: one wave per (plane, strip of 64 - 2p columns, chunk of 8 rows).
 // Lane c owns column i1 = strip start - p + c and walks down its rows with a
 // register window of C2 + 2p values of t (and s): direction 2 is formed in
-// registers (the band row is the same for every lane), direction 1 takes the
-// neighbouring columns' u, v from the other lanes by shuffles, so the pass
+// registers (the band row is the same for every lane), direction 1 moves the
+// neighbouring columns' terms across the lanes by DPP shifts, so the pass
 // needs no LDS tile and no barrier.  The outer p lanes on each side only feed
 // their neighbours.  Each workgroup of four waves writes one partial of x . y.
 constexpr int MV2_THREADS = 256;
@@ -165,12 +165,20 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
     }
     // row by row: direction 2 from the register window, direction 1 from the
     // neighbouring lanes through DPP whole-wave shifts (VALU moves, no LDS)
+    // direction-1 coefficients: the centre of this column's band row, and
+    // what columns i1 + d (kl, ml) and i1 - d (kh, mh) apply to column i1
     const int cr1 = crow(col ? i1 : 0, m, nbr, crows);
-    double k1[BW], m1[BW];
+    const double k1c = kc[cr1 * BW + P], m1c = mc[cr1 * BW + P];
+    double kl[P + 1], ml[P + 1], kh[P + 1], mh[P + 1];
 #pragma unroll
-    for (int o = 0; o < BW; ++o) {
-      k1[o] = kc[cr1 * BW + o];
-      m1[o] = mc[cr1 * BW + o];
+    for (int d = 1; d <= P; ++d) {
+      const int jl = i1 + d, jh = i1 - d;
+      const int crl = crow(jl >= 0 && jl < m ? jl : 0, m, nbr, crows);
+      const int crh = crow(jh >= 0 && jh < m ? jh : 0, m, nbr, crows);
+      kl[d] = kc[crl * BW + P - d];
+      ml[d] = mc[crl * BW + P - d];
+      kh[d] = kc[crh * BW + P + d];
+      mh[d] = mc[crh * BW + P + d];
     }
 #pragma unroll
     for (int r = 0; r < C2; ++r) {
@@ -185,18 +193,21 @@ mv_rows(const double* __restrict__ xin, const double* __restrict__ t3,
         v += k2[o] * wt[r + o];
         if (HAS_S) v += m2[o] * wsv[r + o];
       }
-      // tap o needs column i1 - P + o, held by lane - P + o
-      double yv = k1[P] * u + m1[P] * v;
-      double ul = u, vl = v, ur = u, vr = v;
+      // column i1 takes the terms of columns i1 -+ d, formed on their lanes
+      // with column i1's coefficients and accumulated along single-lane
+      // shifts (Horner's scheme): P shifts per direction
+      double lo = kl[P] * u + ml[P] * v;
+      double hi = kh[P] * u + mh[P] * v;
 #pragma unroll
-      for (int d = 1; d <= P; ++d) {
-        ul = wave_from_lower(ul);   // value of lane - d
-        vl = wave_from_lower(vl);
-        ur = wave_from_upper(ur);   // value of lane + d
-        vr = wave_from_upper(vr);
-        yv += k1[P - d] * ul + m1[P - d] * vl;
-        yv += k1[P + d] * ur + m1[P + d] * vr;
+      for (int d = P - 1; d >= 1; --d) {
+        lo = wave_from_lower(lo);
+        hi = wave_from_upper(hi);
+        lo = fma(kl[d], u, fma(ml[d], v, lo));
+        hi = fma(kh[d], u, fma(mh[d], v, hi));
       }
+      lo = wave_from_lower(lo);
+      hi = wave_from_upper(hi);
+      const double yv = fma(k1c, u, fma(m1c, v, lo + hi));
       if (out && r0 + r < m) {
         y[base + (size_t)(r0 + r) * m + i1] = yv;
         const double dv = xv[r] - yv;
@@ -316,6 +327,12 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
     const double* mi = mc + nbr * BW;
     auto K1 = [&](int o) { return INTER ? ki[o] : b1[0][o][cl]; };
     auto M1 = [&](int o) { return INTER ? mi[o] : b1[1][o][cl]; };
+    // coefficient that column cl + d (L) or cl - d (H) applies to this
+    // column's u and v; a column outside the half-wave is no output column
+    auto K1L = [&](int d) { return INTER ? ki[P - d] : b1[0][P - d][(cl + d) & (MVF_CW - 1)]; };
+    auto M1L = [&](int d) { return INTER ? mi[P - d] : b1[1][P - d][(cl + d) & (MVF_CW - 1)]; };
+    auto K1H = [&](int d) { return INTER ? ki[P + d] : b1[0][P + d][(cl - d) & (MVF_CW - 1)]; };
+    auto M1H = [&](int d) { return INTER ? mi[P + d] : b1[1][P + d][(cl - d) & (MVF_CW - 1)]; };
     auto K2 = [&](int o) { return INTER ? ki[o] : b2[0][ta][o]; };
     auto M2 = [&](int o) { return INTER ? mi[o] : b2[1][ta][o]; };
 #pragma unroll
@@ -343,17 +360,23 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
           u += M2(o) * tt;
           v += K2(o) * tt + M2(o) * ss;
         }
-        double yv = K1(P) * u + M1(P) * v;
-        double ul = u, vl = v, ur = u, vr = v;
+        // direction 1: column j takes K1[j][j-d] u + M1[j][j-d] v of column
+        // j - d and the same of column j + d (d = 1..P).  The lane of column
+        // j - d forms that term with column j's coefficients and the terms
+        // ride one lane per step towards their column, each step adding the
+        // next nearer one (Horner's scheme): P shifts per direction in all.
+        double lo = K1L(P) * u + M1L(P) * v;
+        double hi = K1H(P) * u + M1H(P) * v;
 #pragma unroll
-        for (int d = 1; d <= P; ++d) {
-          ul = wave_from_lower(ul);   // value of column cl - d
-          vl = wave_from_lower(vl);
-          ur = wave_from_upper(ur);   // value of column cl + d
-          vr = wave_from_upper(vr);
-          yv += K1(P - d) * ul + M1(P - d) * vl;
-          yv += K1(P + d) * ur + M1(P + d) * vr;
+        for (int d = P - 1; d >= 1; --d) {
+          lo = wave_from_lower(lo);
+          hi = wave_from_upper(hi);
+          lo = fma(K1L(d), u, fma(M1L(d), v, lo));
+          hi = fma(K1H(d), u, fma(M1H(d), v, hi));
         }
+        lo = wave_from_lower(lo);   // sum over d of the terms of columns j - d
+        hi = wave_from_upper(hi);   // and of columns j + d
+        const double yv = fma(K1(P), u, fma(M1(P), v, lo + hi));
         if (out) {
           const unsigned oo = (unsigned)(i3 * plane + i2 * m + i1) * 8u;
           buf_st<double>(yv, ws, oo);
