@@ -75,15 +75,15 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
 
 hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
                             void* ws, const double* a, int as, hipStream_t s,
-                            const PassHook* last) {
+                            const PassHook* last, const PassHook* first) {
   const int d = P.d;
   const bool f64 = P.prec == IFFD_PREC_F64;
   const int et = f64 ? ELEM_F64 : ELEM_F32;
   void* w = f64 ? (void*)z : ws;
   if (pass < d - 1) {
-    const bool first = pass == 0;
-    return launch_line_pass(P, PASS_FWD, pass + 1, first ? ELEM_F64 : et, first ? (const void*)r : w,
-                            et, w, nrhs, a, as, s);
+    const bool p0 = pass == 0;
+    return launch_line_pass(P, PASS_FWD, pass + 1, p0 ? ELEM_F64 : et, p0 ? (const void*)r : w,
+                            et, w, nrhs, a, as, s, p0 ? first : nullptr);
   }
   if (pass == d - 1) return launch_line_pass(P, PASS_MID, d, et, w, et, w, nrhs, a, as, s);
   if (pass < 2 * d - 1) {
@@ -95,9 +95,10 @@ hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z,
 }
 
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
-                             const double* a, int as, hipStream_t s, const PassHook* last) {
+                             const double* a, int as, hipStream_t s, const PassHook* last,
+                             const PassHook* first) {
   for (int k = 0; k < 2 * P.d - 1; ++k) {
-    hipError_t e = launch_iffd_pass(P, k, r, z, nrhs, ws, a, as, s, last);
+    hipError_t e = launch_iffd_pass(P, k, r, z, nrhs, ws, a, as, s, last, first);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -63,7 +63,10 @@ struct Geom {
   int d;
   int tpd_log;  // log2 of the threads per outlier dot
   const double* dr;  // fused dr . out partials (backward pass along direction 1), or null
-  double* dpart;
+  const double* fq;  // fused in <- in - alpha q (forward pass along direction 1), or null
+  const double* falpha;
+  double* fr;        // = in, written back
+  double* dpart;     // per-tile partials of either fused step
   int dnpart;
   const double* active;  // per-RHS flags or null
   int active_stride;
@@ -140,9 +143,13 @@ constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
 // PK: the sine transform route, fixed per kernel: PK_ODD (DST-I, L = 2n),
 // PK_EVEN_2N (DST-II / DST-III, L = 2n), PK_EVEN_N (DST-II / DST-III, L = n),
 // PK_ODD_N (DST-I, L = n).
-template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
-__global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
-line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
+// UPD: the forward pass of FP64 input along direction 1 also applies the PCG
+// residual update r <- r - alpha q to its input (g.fq, g.falpha, g.fr, partial
+// sums of the updated r^2 in g.dpart); a kernel of its own (line_pass_upd), so
+// that the plain pass keeps its registers.
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK, bool UPD>
+__device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                               const Geom& g, const Tabs<T>& tb) {
   using C = Cfg<T, L, V>;
   constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
   constexpr int LTW = ilog2<TW>();
@@ -213,12 +220,20 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 
   // ---- load the tile: X[l][j] = in(line l, position j); missing lines = 0 --
   // (buffer loads: entries past the tile or the tensor read as 0)
+  // the fused residual update (forward pass of FP64 input along direction 1)
+  constexpr bool FU = UPD && MODE == PASS_FWD && sizeof(Tin) == 8;
+  double racc = 0.0;   // this thread's share of the updated r^2
   if (S == 1) {
     // every load of a batch is issued before its first LDS write
     const auto rs = buf_rsrc(in + (size_t)rhs * g.N + (size_t)q0 * m,
                              (unsigned)(nv * m * (int)sizeof(Tin)));
     const int lane = t % RW, grp = t / RW;
     const unsigned vo = (unsigned)(grp * m + lane) * sizeof(Tin);
+    const unsigned frec = FU ? (unsigned)(nv * m * 8) : 0u;
+    const size_t fo = (size_t)rhs * g.N + (size_t)q0 * m;
+    const auto qs = buf_rsrc(FU ? g.fq + fo : (const double*)in, frec);
+    const auto rw = buf_rsrc(FU ? g.fr + fo : (const double*)in, frec);
+    const double alpha = FU ? g.falpha[(size_t)rhs * g.active_stride] : 0.0;
     for (int jb = 0; jb < m; jb += UMX * RW) {
       Tin v[LPT][UMX];
 #pragma unroll
@@ -226,6 +241,28 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
 #pragma unroll
         for (int u = 0; u < UMX; ++u)
           v[a][u] = buf_ld<Tin>(rs, vo + (unsigned)((a * NG * m + jb + RW * u) * (int)sizeof(Tin)));
+      if constexpr (FU) {
+        {
+          // r <- r - alpha q, written back once per entry (line l < nv, j < m)
+          double qv[LPT][UMX];
+#pragma unroll
+          for (int a = 0; a < LPT; ++a)
+#pragma unroll
+            for (int u = 0; u < UMX; ++u)
+              qv[a][u] = buf_ld<double>(qs, vo + (unsigned)((a * NG * m + jb + RW * u) * 8));
+#pragma unroll
+          for (int a = 0; a < LPT; ++a)
+#pragma unroll
+            for (int u = 0; u < UMX; ++u) {
+              const int j = jb + lane + RW * u, l = grp + a * NG;
+              const bool own = j < m && l < nv;
+              const double rv = (double)v[a][u] - alpha * qv[a][u];
+              v[a][u] = (Tin)rv;
+              buf_st<double>(rv, rw, own ? vo + (unsigned)((a * NG * m + jb + RW * u) * 8) : BUF_OOB);
+              racc += own ? rv * rv : 0.0;
+            }
+        }
+      }
       // entries past the row go to a sink (a select, not a branch, so the
       // compiler keeps every load of the batch ahead of the first write)
 #pragma unroll
@@ -286,6 +323,25 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
     for (int c = t + BCH * NTH; c < tb.nch; c += NTH) B4[c] = buf_ld16(trs, (unsigned)c * 16u);
   }
   __syncthreads();
+  if constexpr (FU) {
+    {   // fixed-order sum of the updated r^2 over the workgroup
+      double* red = reinterpret_cast<double*>(DM);   // NTH doubles fit in DM
+      if constexpr (NTH % 64 == 0) {
+        for (int o = 32; o > 0; o >>= 1) racc += __shfl_xor(racc, o);
+        if ((t & 63) == 0) red[t >> 6] = racc;
+      } else {
+        red[t] = racc;   // a partial wave: no shuffles
+      }
+      __syncthreads();
+      if (t == 0) {
+        constexpr int NR = NTH % 64 == 0 ? NTH / 64 : NTH;
+        double sum = 0.0;
+        for (int k = 0; k < NR; ++k) sum += red[k];
+        g.dpart[(size_t)rhs * g.dnpart + tile] = sum;
+      }
+      __syncthreads();   // DM takes discarded values again below
+    }
+  }
   if (MODE == PASS_MID) {
     // spectral indices of each line in the other directions (the middle pass
     // runs along the last direction, so the inner index holds them all);
@@ -716,6 +772,18 @@ line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb
   }
 }
 
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
+__global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
+line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
+  line_pass_body<Tin, Tout, T, MODE, L, V, PK, false>(in, out, g, tb);
+}
+
+template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
+__global__ void __launch_bounds__((Cfg<T, L, V>::NTH))
+line_pass_upd(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T> tb) {
+  line_pass_body<Tin, Tout, T, MODE, L, V, PK, true>(in, out, g, tb);
+}
+
 // the tables a pass stages in LDS: a prefix of the blob (odd p needs no twp,
 // only the middle pass needs lam and s)
 template <typename T>
@@ -742,12 +810,23 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.d = P.d;
   g.active = active;
   g.active_stride = astride;
-  g.dr = hk ? hk->dr : nullptr;
-  g.dpart = hk ? hk->part : nullptr;
-  g.dnpart = hk ? hk->npart : 0;
+  g.dr = nullptr;
+  g.fq = nullptr;
+  g.falpha = nullptr;
+  g.fr = nullptr;
+  g.dpart = nullptr;
+  g.dnpart = 0;
   if (hk) {
-    if (axis != 1 || MODE != PASS_BWD || sizeof(Tout) != 8 || g.tpr > hk->npart)
-      return hipErrorInvalidValue;
+    const bool dot = MODE == PASS_BWD && sizeof(Tout) == 8 && hk->dr && !hk->q;
+    const bool upd = MODE == PASS_FWD && sizeof(Tin) == 8 && hk->q && hk->alpha &&
+                     hk->r_out == in && !hk->dr;
+    if (axis != 1 || !(dot || upd) || !hk->part || g.tpr > hk->npart) return hipErrorInvalidValue;
+    g.dr = hk->dr;
+    g.fq = hk->q;
+    g.falpha = hk->alpha;
+    g.fr = hk->r_out;
+    g.dpart = hk->part;
+    g.dnpart = hk->npart;
     hk->tiles = g.tpr;
   }
   {
@@ -762,6 +841,21 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   }
   const Tabs<T> tb = tables_of<T>(P, MODE);
   const LdsMap mp = lds_map<T, L, V>(P.m, P.n, P.n_out, P.half, P.p, tb.len);
+  dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
+  if constexpr (MODE == PASS_FWD && sizeof(Tin) == 8) {
+    if (g.fq) {
+      static bool attr_upd = false;
+      if (mp.total > 65536 && !attr_upd) {
+        hipError_t e = hipFuncSetAttribute((const void*)line_pass_upd<Tin, Tout, T, MODE, L, V, PK>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_upd = true;
+      }
+      hipLaunchKernelGGL((line_pass_upd<Tin, Tout, T, MODE, L, V, PK>), grid, block, mp.total, s,
+                         (const Tin*)in, (Tout*)out, g, tb);
+      return hipGetLastError();
+    }
+  }
   static bool attr_set = false;
   if (mp.total > 65536 && !attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)line_pass<Tin, Tout, T, MODE, L, V, PK>,
@@ -769,7 +863,6 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  dim3 grid((unsigned)(g.tpr * nrhs)), block(C::NTH);
   hipLaunchKernelGGL((line_pass<Tin, Tout, T, MODE, L, V, PK>), grid, block, mp.total, s,
                      (const Tin*)in, (Tout*)out, g, tb);
   return hipGetLastError();

@@ -54,14 +54,23 @@ __device__ __forceinline__ u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, unsigned vof
 enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
 
 // Optional work fused into the last (direction-1, backward) line pass of the
-// IFFD apply: per-tile partials part[rhs][tile] = sum over the tile of
-// dr . z (z as stored, FP64); `tiles` receives the tile count per right-hand
-// side of the launch (at most apply_last_tiles_max).
+// Work fused into an IFFD line pass along direction 1, reported as per-tile
+// partial sums part[rhs][tile]; `tiles` receives the tile count per
+// right-hand side of the launch (at most apply_last_tiles_max).
+//  - backward pass with FP64 output z (dr set): part = sum over the tile of
+//    dr . z, z as stored;
+//  - forward pass with FP64 input r (q set, r_out = r): the PCG residual
+//    update r <- r - alpha_b q (alpha_b = alpha[b * active_stride]) is applied
+//    to each entry as it is loaded and written back to r, the transform takes
+//    the updated r, and part = sum over the tile of the updated r^2.
 struct PassHook {
   const double* dr;
   double* part;
   int npart;
   mutable int tiles;
+  const double* q = nullptr;
+  const double* alpha = nullptr;
+  double* r_out = nullptr;
 };
 
 // One IFFD line pass along `axis` (1-based; direction 1 = fastest) of the
@@ -71,15 +80,16 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
                             void* out, int nrhs, const double* active, int active_stride,
                             hipStream_t s, const PassHook* hk = nullptr);
 
-// Full IFFD apply z = P^{-1} r (FP64 in/out), ws = apply workspace.
+// Full IFFD apply z = P^{-1} r (FP64 in/out), ws = apply workspace; `first`
+// and `last` are fused into its first and last pass.
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                              const double* active, int active_stride, hipStream_t s,
-                             const PassHook* last = nullptr);
+                             const PassHook* last = nullptr, const PassHook* first = nullptr);
 
 // One pass of the IFFD apply (0 .. 2d-2), see iffd_apply_pass.
 hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
                             void* ws, const double* active, int active_stride, hipStream_t s,
-                            const PassHook* last = nullptr);
+                            const PassHook* last = nullptr, const PassHook* first = nullptr);
 
 // Dense FD apply (MFMA mode products).
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,

@@ -12,6 +12,8 @@
 //   alpha = rz / pq; r -= alpha q; rr              -> reduce rr, test
 //   z = P^{-1} r; rz' = r.z (fused in the IFFD apply's last pass)
 //                                                  -> reduce rz'
+// With IFFD the update of r and its rr are fused into the apply's first pass
+// and the test runs between that pass and the rest.
 //   beta = rz'/rz; x += alpha p; p = z + beta p
 // x takes its update in the same sweep as p (it reads the old p anyway); a
 // slot that stops in this iteration still gets it (flag S_RUN).
@@ -135,14 +137,15 @@ pcg_update_r(double* __restrict__ r, const double* __restrict__ q, int N, int nb
   if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
 }
 
-// one block per slot: iteration count, residual test, history
+// one block per slot: iteration count, residual test, history (r.r = the
+// first nused of the slot's partials, stride apart per slot)
 __global__ void __launch_bounds__(VT)
-pcg_check(double* scal, double* hist, const double* part, int nblk, int nslots) {
+pcg_check(double* scal, double* hist, const double* part, int nused, int stride, int nslots) {
   __shared__ double red[VT / 64];
   const int slot = blockIdx.x;
   double* sc = scal + (size_t)slot * kScal;
   if (sc[S_ACTIVE] == 0.0) return;
-  const double rr = block_psum(part + (size_t)slot * nblk, nblk, red);
+  const double rr = block_psum(part + (size_t)slot * stride, nused, red);
   if (threadIdx.x != 0) return;
   const int it = (int)sc[S_IT] + 1;
   sc[S_IT] = it;
@@ -406,16 +409,29 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
     hipError_t e = launch_matvec(P, p, qz, nslots, mvws, part2, nb, scal + S_ACTIVE, kScal, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pcg_alpha, dim3(nslots), dim3(VT), 0, s, scal, part2, nmv, nb, nslots);
-    hipLaunchKernelGGL(pcg_update_r, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, scal, part);
-    hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nslots);
     int nrz = nb;
     if (P.method == IFFD_METHOD_FFT) {
-      // r.z partials come from the apply's last pass
-      const PassHook hk{r, part, nb, 0};
-      e = launch_iffd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s, &hk);
+      // the apply's first pass takes r <- r - alpha q on its way in (r.r
+      // partials), the residual test follows it, so the other passes skip the
+      // slots that converged; r.z partials come from the last pass
+      PassHook up{nullptr, part, nb, 0};
+      up.q = qz;
+      up.alpha = scal + S_ALPHA;
+      up.r_out = r;
+      e = launch_iffd_pass(P, 0, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s, nullptr, &up);
       if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, up.tiles, nb,
+                         nslots);
+      const PassHook hk{r, part, nb, 0};
+      for (int k = 1; k < 2 * P.d - 1; ++k) {
+        e = launch_iffd_pass(P, k, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s, &hk);
+        if (e != hipSuccess) return e;
+      }
       nrz = hk.tiles;
     } else {
+      hipLaunchKernelGGL(pcg_update_r, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, scal,
+                         part);
+      hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nb, nslots);
       e = launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
