@@ -72,19 +72,49 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
   // T is the operand type; the accumulator is FP64 for FP64, else FP32
   using TE = std::conditional_t<sizeof(T) == 8, double, float>;
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // stage A (BM x BK) and B (BK x BN) tiles, zero outside the matrices
-    for (int e = t; e < BM * BK; e += 256) {
+  // K chunks of the A (BM x BK) and B (BK x BN) tiles: the next chunk's loads
+  // are issued into registers before the current chunk's products, so their
+  // latency hides behind the matrix cores; entries outside the matrices read
+  // 0 (buffer loads with a range check, no branches)
+  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  const auto ra_ = buf_rsrc(Ab, (unsigned)(((long long)(g.M - 1) * g.lda + g.K) * sizeof(TA)));
+  const auto rb_ = buf_rsrc(Bb, (unsigned)(((long long)(g.K - 1) * g.ldb + g.N) * sizeof(TB)));
+  TA va[NA];
+  TB vb[NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
       const int i = e / BK, k = e - (e / BK) * BK;
       const int gi = m0 + i, gk = k0 + k;
-      As[k][i] = (gi < g.M && gk < g.K) ? (T)Ab[(long long)gi * g.lda + gk] : T(0);
+      const unsigned off = (gi < g.M && gk < g.K)
+                               ? (unsigned)(((long long)gi * g.lda + gk) * sizeof(TA)) : BUF_OOB;
+      va[u] = buf_ld<TA>(ra_, off);
     }
-    for (int e = t; e < BK * BN; e += 256) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
       const int k = e / BN, j = e - (e / BN) * BN;
       const int gk = k0 + k, gj = n0 + j;
-      Bs[k][j] = (gk < g.K && gj < g.N) ? (T)Bb[(long long)gk * g.ldb + gj] : T(0);
+      const unsigned off = (gk < g.K && gj < g.N)
+                               ? (unsigned)(((long long)gk * g.ldb + gj) * sizeof(TB)) : BUF_OOB;
+      vb[u] = buf_ld<TB>(rb_, off);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
+      As[e - (e / BK) * BK][e / BK] = (T)va[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
+      Bs[e / BN][e - (e / BN) * BN] = (T)vb[u];
     }
     __syncthreads();
+    if (k0 + BK < g.K) fetch(k0 + BK);
     if constexpr (sizeof(T) == 2) {
       // 32x32x8 f16: lane l supplies row (column) l%32, k = 4(l/32) .. +3
 #pragma unroll

@@ -32,7 +32,9 @@ constexpr unsigned BUF_OOB = 0x80000000u;
 
 template <typename T>
 __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff) {
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, 0, 0));
+  else if constexpr (sizeof(T) == 4)
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 0));
@@ -53,7 +55,6 @@ __device__ __forceinline__ u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, unsigned vof
 
 enum ElemType { ELEM_F32 = 0, ELEM_F64 = 1 };
 
-// Optional work fused into the last (direction-1, backward) line pass of the
 // Work fused into an IFFD line pass along direction 1, reported as per-tile
 // partial sums part[rhs][tile]; `tiles` receives the tile count per
 // right-hand side of the launch (at most apply_last_tiles_max).
