@@ -113,7 +113,8 @@ typedef struct {
  * (eq:Lambda reg2); for DENSE_FD, the full FP64 eigendecomposition of the
  * pencil (K, M) (eq:eigendecomposition).  Valid range: d in {2,3},
  * 1 <= p <= 8, n > p (the paper's standing assumption), m^d*max_rhs < 2^31
- * per pass; IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 512
+ * per pass and m^d < 2^28 (one right-hand side below 2 GiB in FP64, the
+ * reach of the kernels' 32-bit buffer offsets); IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 512
  * (IFFD_E_UNSUPPORTED otherwise).  *out receives the plan (NULL on error). */
 int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
 

@@ -345,6 +345,9 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   P.N = 1;
   for (int k = 0; k < d; ++k) P.N *= P.m;
   if (P.N * (int64_t)P.max_rhs >= (int64_t(1) << 31)) { err = "problem too large for 32-bit indexing"; return IFFD_E_UNSUPPORTED; }
+  // the kernels reach one right-hand side's FP64 tensor through buffer
+  // resources, whose byte offsets stay below 2^31
+  if (P.N * 8 >= (int64_t(1) << 31)) { err = "one right-hand side above 2 GiB in FP64 (m^d >= 2^28)"; return IFFD_E_UNSUPPORTED; }
   if (P.method == IFFD_METHOD_FFT) {
     if (p < 2) { err = "IFFD needs p >= 2 (p = 1 has no outlier split; use DENSE_FD)"; return IFFD_E_UNSUPPORTED; }
     // odd p: DST-I through a length-2n FFT of the odd extension; even p:

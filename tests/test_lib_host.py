@@ -138,6 +138,15 @@ def test_invalid_plans_rejected(d, n, p, code):
     assert len(I.lib.iffd_last_error()) > 0
 
 
+def test_dense_plan_above_two_gib_per_rhs_rejected():
+    """3D dense FD at n = 700 (m^3 = 344M, 2.75 GB in FP64) passes the 2^31
+    element bound but not the 2 GiB per right-hand side of buffer addressing;
+    n = 512 (the largest IFFD size) stays inside it."""
+    rc, h = host_plan(3, 700, 3, method=I.METHOD_DENSE_FD)
+    assert rc == I.E_UNSUPPORTED and h.value is None
+    assert "2 GiB" in I.lib.iffd_last_error().decode()
+
+
 def test_null_and_state_errors():
     assert I.lib.iffd_plan_create(None, 3, 16, 3, None) == I.E_INVAL
     rc, h = host_plan(2, 16, 3)
