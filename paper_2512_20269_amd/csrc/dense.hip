@@ -176,29 +176,39 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
   }
 }
 
-// FP16 operand of a mode product along a direction with stride S: line q of
-// a right-hand side (q = o S + j, entries o m S + i S + j, i < m) is divided
-// by its largest |value| and rounded to FP16; scale[rhs][q] keeps that value
-// (1 for an all-zero line).  One thread per line: for S > 1 consecutive
-// threads read consecutive addresses.
+// FP16 operand of a mode product along a direction with stride S > 1: line q
+// of a right-hand side (q = o S + j, entries o m S + i S + j, i < m) is
+// divided by its largest |value| and rounded to FP16; scale[rhs][q] keeps
+// that value (1 for an all-zero line).  A workgroup takes QL consecutive lines
+// (neighbouring addresses) with QG threads per line, each on every QG-th
+// entry; the partial maxima meet in LDS.
+constexpr int QL = 32, QG = 256 / QL;
 template <typename TI>
 __global__ void __launch_bounds__(256)
 quant_lines(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restrict__ scale,
             int m, int S, int lines, long long N, int nrhs, const double* __restrict__ active,
             int astride) {
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (long long)lines * nrhs) return;
-  const int rhs = (int)(q / lines);
-  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  __shared__ float red[QG][QL];
+  const int l = threadIdx.x % QL, gq = threadIdx.x / QL;
+  const long long q = (long long)blockIdx.x * QL + l;
+  bool ok = q < (long long)lines * nrhs;
+  const int rhs = ok ? (int)(q / lines) : 0;
+  if (ok && active && active[(size_t)rhs * astride] == 0.0) ok = false;
   const int ql = (int)(q - (long long)rhs * lines);
   const long long base = (long long)rhs * N + (long long)(ql / S) * m * S + (ql % S);
   float mx = 0.0f;
-  for (int i = 0; i < m; ++i) mx = fmaxf(mx, fabsf((float)in[base + (long long)i * S]));
+  if (ok)
+    for (int i = gq; i < m; i += QG) mx = fmaxf(mx, fabsf((float)in[base + (long long)i * S]));
+  red[gq][l] = mx;
+  __syncthreads();   // every thread arrives (no early exit above)
+  mx = red[0][l];
+  for (int k = 1; k < QG; ++k) mx = fmaxf(mx, red[k][l]);
+  if (!ok) return;
   const float sc = mx > 0.0f ? mx : 1.0f;
   const float inv = 1.0f / sc;
-  for (int i = 0; i < m; ++i)
+  for (int i = gq; i < m; i += QG)
     out[base + (long long)i * S] = (_Float16)((float)in[base + (long long)i * S] * inv);
-  scale[q] = sc;
+  if (gq == 0) scale[q] = sc;
 }
 
 // direction 1 (lines contiguous): one wave per line, lanes stride the line
@@ -314,7 +324,7 @@ static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in
     hipLaunchKernelGGL(quant_rows<TI>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, in, x16,
                        ls, m, lines, N, nrhs, act, as);
   else
-    hipLaunchKernelGGL(quant_lines<TI>, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, in,
+    hipLaunchKernelGGL(quant_lines<TI>, dim3((unsigned)((nq + QL - 1) / QL)), dim3(256), 0, s, in,
                        x16, ls, m, S, lines, N, nrhs, act, as);
   GemmArgs g{};
   g.active = act;
