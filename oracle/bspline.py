@@ -81,10 +81,12 @@ def derivative(knots: np.ndarray, p: int, x, k: int) -> np.ndarray:
     return out
 
 
-def assemble_full(n: int, p: int):
+def assemble_full(n: int, p: int, coef=None):
     """Mass and stiffness matrices of the full space S_{p,h} (size n+p),
     by Gauss-Legendre quadrature with p+1 points per element, which is exact
-    for the degree-2p integrands (Section 3, eq:system_matrix's factors)."""
+    for the degree-2p integrands (Section 3, eq:system_matrix's factors).
+    coef: optional stiffness coefficient c(x), [K]_{ij} = int c B_j' B_i'
+    (still exact for c of degree <= 3: the integrand has degree 2p - 2 + 3)."""
     knots = open_knots(n, p)
     nb = n + p
     gx, gw = np.polynomial.legendre.leggauss(p + 1)
@@ -97,14 +99,15 @@ def assemble_full(n: int, p: int):
         B = basis(knots, p, xq)
         dB = derivative(knots, p, xq, 1)
         M += (B * wq[:, None]).T @ B
-        K += (dB * wq[:, None]).T @ dB
+        wk = wq if coef is None else wq * coef(xq)
+        K += (dB * wk[:, None]).T @ dB
     return K, M
 
 
-def assemble_dirichlet(n: int, p: int):
+def assemble_dirichlet(n: int, p: int, coef=None):
     """K and M on S_{p,h,{0,1}}: the two B-splines that do not vanish at the
     ends are removed (Section 2), leaving m = n+p-2 functions B_1..B_{n+p-2}."""
-    K, M = assemble_full(n, p)
+    K, M = assemble_full(n, p, coef)
     return K[1:-1, 1:-1].copy(), M[1:-1, 1:-1].copy()
 
 
