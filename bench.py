@@ -202,19 +202,21 @@ def serving(torch, count, warm, fracs, budget_gb=96.0, slots=8, iters=2, check=4
             "runs": runs, "sampled_same_bits_as_alone": same, "sampled": check}
 
 
-def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256):
+def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256, coef=0.0):
     """3D with the smooth right-hand side (8 random-phase sine modes plus 1e-3
     noise, seed 3), degree sweep: FP32 apply error against the FP64 apply, PCG
     iterations and solve time with the FP32 apply, and the dense-FD solve
-    beside it.  (The FP64 apply's agreement with the oracle is a GPU test.)"""
+    beside it.  (The FP64 apply's agreement with the oracle is a GPU test.)
+    coef != 0: the system matrix is A_c with c(x) = 1 + coef x per direction
+    (both preconditioners stay those of A-hat, so neither is exact)."""
     import workloads
     import paper_2512_20269_amd as iffd
     rows = []
     for p in ps:
         f_np = workloads.smooth_rhs(3, n, p, 3)
         f = torch.from_numpy(f_np).cuda()
-        row = {"n": n, "p": p}
-        p32 = iffd.Plan(3, n, p, method="fft", precision="f32")
+        row = {"n": n, "p": p, "coef_a": coef}
+        p32 = iffd.Plan(3, n, p, method="fft", precision="f32", coef_a=coef)
         p32.tune(reps=5)
         z32 = p32.apply(f)
         z64 = iffd.Plan(3, n, p, method="fft", precision="f64").apply(f)
@@ -223,7 +225,7 @@ def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256):
         u = p32.solve(f, rtol=1e-8)[0]
         row.update({"pcg_iterations": st[0]["iterations"], "pcg_relres_true": st[0]["relres_true"],
                     "pcg_ms_p50": round(pct(lat, 0.5), 3), "kappa_est": round(st[0]["kappa_est"], 4)})
-        fd = iffd.Plan(3, n, p, method="dense", precision="f32")
+        fd = iffd.Plan(3, n, p, method="dense", precision="f32", coef_a=coef)
         flat, fst = time_solves(torch, fd, f, 3)
         uf = fd.solve(f, rtol=1e-8)[0]
         row.update({"dense_fd_iterations": fst[0]["iterations"],
@@ -254,6 +256,10 @@ def main():
     ap.add_argument("--sweep-n", default="",
                     help="only the IFFD / dense-FD solve comparison at these 3D sizes "
                          "(comma-separated n; p = 3 and 4, smooth right-hand side)")
+    ap.add_argument("--coef", type=float, default=0.0,
+                    help="with --sweep-p / --sweep-n: solve with the variable-coefficient "
+                         "system matrix A_c, c(x) = 1 + COEF x per direction (preconditioners "
+                         "of A-hat)")
     ap.add_argument("--serve", action="store_true",
                     help="only the serving benchmark (Poisson stream of mixed solves)")
     ap.add_argument("--pcg-only", choices=["fft", "dense"],
@@ -277,16 +283,18 @@ def main():
     if args.sweep_n:
         rows = []
         for n_ in [int(x) for x in args.sweep_n.split(",")]:
-            rows += sweep_p(torch, ps=(3, 4), n=n_)
+            rows += sweep_p(torch, ps=(3, 4), n=n_, coef=args.coef)
+        cs = f"_coef{args.coef:g}" if args.coef else ""
         print(json.dumps({"metric": "PCG solve time to 1e-8, IFFD vs dense FD", "unit": "ms",
-                          "config": {"workload": f"cube_n{args.sweep_n}_p3-4_smooth"},
+                          "config": {"workload": f"cube_n{args.sweep_n}_p3-4_smooth{cs}"},
                           "rows": rows}), flush=True)
         return
     if args.sweep_p:
-        rows = sweep_p(torch)
+        rows = sweep_p(torch, coef=args.coef)
+        cs = f"_coef{args.coef:g}" if args.coef else ""
         print(json.dumps({"metric": "iterations and FP32 apply error vs p, 3D n=256",
                           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
-                          "config": {"workload": "cube_n256_p2-8_smooth"}, "rows": rows}),
+                          "config": {"workload": f"cube_n256_p2-8_smooth{cs}"}, "rows": rows}),
               flush=True)
         return
     if args.serve:

@@ -73,7 +73,17 @@ typedef struct {
   int method;       /* IFFD_METHOD_*                                           */
   int apply_prec;   /* IFFD_PREC_*                                             */
   int max_rhs;      /* largest batch (nrhs) the workspaces are sized for, >= 1 */
-} iffd_opts;        /* NULL opts = {IFFD_METHOD_FFT, IFFD_PREC_F32, 1}         */
+  double coef_a;    /* system matrix of iffd_kron_matvec and iffd_pcg_*: 0 gives
+                       A-hat (the Laplacian's Galerkin matrix, Section 3); a != 0
+                       gives A_c = sum_k M x .. x K_c (slot k) x .. x M with
+                       [K_c]_ij = int (1 + a x) B_j' B_i', the matrix of the
+                       weighted form int grad u . D grad v with the diagonal
+                       coefficient D = diag(1 + a x_k) (a reading of Section 1's
+                       coefficient-weighted form), -1 < a <= 1000.  The
+                       preconditioners (IFFD and FD) are always built from
+                       A-hat, so for a != 0 neither is exact and
+                       kappa(A-hat^{-1} A_c) <= max c / min c (Section 3).   */
+} iffd_opts;        /* NULL opts = {IFFD_METHOD_FFT, IFFD_PREC_F32, 1, 0.0}    */
 
 typedef struct {
   int d, n, p;
@@ -134,7 +144,9 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
  *   2 K band, 3 M band (m*(2p+1) doubles, row i holds columns i-p..i+p),
  *   4 V_reg,0 ((p-1)*floor(p/2) doubles, row-major), 5 V_reg,1 (same),
  *   6 Vt_out (n_out*m doubles: rows = Q_out-rotated outlier basis vectors,
- *            available after iffd_plan_setup; syncs `stream`).
+ *            available after iffd_plan_setup; syncs `stream`),
+ *   7 the system matrix's 1-D stiffness band (K_c of iffd_opts.coef_a, the
+ *            same as 2 for coef_a = 0; m*(2p+1) doubles).
  * `count` is the capacity of h_out in doubles; returns IFFD_E_WORKSPACE if
  * too small. */
 int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream);

@@ -38,7 +38,8 @@ class IffdError(RuntimeError):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("method", ctypes.c_int), ("apply_prec", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+    _fields_ = [("method", ctypes.c_int), ("apply_prec", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("coef_a", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -137,14 +138,19 @@ class Plan:
 
     method: "fft" (IFFD) or "dense" (classical FD); precision: "f32" or "f64"
     for the preconditioner arithmetic (vectors and Krylov work are FP64), or
-    "f16s" (dense FD only: FP16 matrix cores with per-line scaling)."""
+    "f16s" (dense FD only: FP16 matrix cores with per-line scaling).
+    coef_a: the system matrix of matvec() and solve() (iffd_opts.coef_a): 0
+    for A-hat, else the variable-coefficient A_c with c(x) = 1 + coef_a x in
+    every direction; the preconditioner is built from A-hat either way."""
 
     def __init__(self, d: int, n: int, p: int, method: str = "fft", precision: str = "f32",
-                 max_rhs: int = 1, device=None):
+                 max_rhs: int = 1, device=None, coef_a: float = 0.0):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
-                     {"f32": PREC_F32, "f64": PREC_F64, "f16s": PREC_F16S}[precision], max_rhs)
+                     {"f32": PREC_F32, "f64": PREC_F64, "f16s": PREC_F16S}[precision], max_rhs,
+                     float(coef_a))
+        self.coef_a = float(coef_a)
         h = ctypes.c_void_p()
         _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h

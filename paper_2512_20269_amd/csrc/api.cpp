@@ -267,6 +267,7 @@ int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count,
       if (!P.ready) return fail(IFFD_E_STATE, "Vt is available after iffd_plan_setup");
       v = &P.Vt;
       break;
+    case 7: v = &P.Kop; break;
     default: return fail(IFFD_E_INVAL, "unknown table id");
   }
   if (count < v->size()) return fail(IFFD_E_WORKSPACE, "output array too small");

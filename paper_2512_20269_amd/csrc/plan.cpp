@@ -337,7 +337,9 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     P.method = opts->method;
     P.prec = opts->apply_prec;
     P.max_rhs = opts->max_rhs;
+    P.coef_a = opts->coef_a;
   }
+  if (!(P.coef_a > -1.0 && P.coef_a <= 1000.0)) { err = "coef_a must lie in (-1, 1000]"; return IFFD_E_INVAL; }
   if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
   if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64 && P.prec != IFFD_PREC_F16S) { err = "bad apply_prec"; return IFFD_E_INVAL; }
   if (P.prec == IFFD_PREC_F16S && P.method != IFFD_METHOD_DENSE_FD) { err = "IFFD_PREC_F16S is for dense FD only"; return IFFD_E_INVAL; }
@@ -367,6 +369,10 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   std::vector<double> gx, gw;
   gauss_legendre(p + 1, gx, gw);
   std::vector<double> Kf((size_t)nb * bw, 0.0), Mf((size_t)nb * bw, 0.0);  // full, banded
+  // the system matrix's stiffness K_c (coefficient 1 + a x; exact quadrature:
+  // the integrand has degree 2p - 1)
+  const bool coef = P.coef_a != 0.0;
+  std::vector<double> Kcf(coef ? (size_t)nb * bw : 0, 0.0);
   std::vector<double> val, der;
   for (int e = 0; e < n; ++e) {
     const int s = p + e;  // knot span of element e
@@ -379,6 +385,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
           int gi = s - p + i, gj = s - p + j;
           Mf[(size_t)gi * bw + (gj - gi + p)] += wq * val[i] * val[j];
           Kf[(size_t)gi * bw + (gj - gi + p)] += wq * der[i] * der[j];
+          if (coef) Kcf[(size_t)gi * bw + (gj - gi + p)] += wq * (1.0 + P.coef_a * x) * der[i] * der[j];
         }
     }
   }
@@ -392,11 +399,20 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
       P.Kb[(size_t)i * bw + o] = Kf[(size_t)(i + 1) * bw + o];
       P.Mb[(size_t)i * bw + o] = Mf[(size_t)(i + 1) * bw + o];
     }
+  P.Kop = P.Kb;
+  if (coef)
+    for (int i = 0; i < m; ++i)
+      for (int o = 0; o < bw; ++o) {
+        int j = i + o - p;
+        if (j < 0 || j >= m) continue;
+        P.Kop[(size_t)i * bw + o] = Kcf[(size_t)(i + 1) * bw + o];
+      }
 
   // compact band tables: rows 0..nbr-1 and m-nbr..m-1 are special, the rows
   // in between equal the interior (Toeplitz) stencil
+  // (the system matrix's band rows: with a coefficient every row differs)
   P.nbr = 2 * p - 1;
-  P.crows = (m > 2 * P.nbr + 1) ? 2 * P.nbr + 1 : m;
+  P.crows = (!coef && m > 2 * P.nbr + 1) ? 2 * P.nbr + 1 : m;
   P.Kc.assign((size_t)P.crows * bw, 0.0);
   P.Mc.assign((size_t)P.crows * bw, 0.0);
   for (int cr = 0; cr < P.crows; ++cr) {
@@ -406,7 +422,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     else if (cr == P.nbr) i = m / 2;
     else i = m - P.nbr + (cr - P.nbr - 1);
     for (int o = 0; o < bw; ++o) {
-      P.Kc[(size_t)cr * bw + o] = P.Kb[(size_t)i * bw + o];
+      P.Kc[(size_t)cr * bw + o] = P.Kop[(size_t)i * bw + o];
       P.Mc[(size_t)cr * bw + o] = P.Mb[(size_t)i * bw + o];
     }
   }

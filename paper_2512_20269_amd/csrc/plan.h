@@ -47,6 +47,8 @@ struct Plan {
 
   // host-side FP64 data
   std::vector<double> Kb, Mb;       // m x (2p+1) band rows, column i-p..i+p
+  double coef_a = 0.0;              // system matrix: K_c = int (1 + a x) B' B' (0: A-hat)
+  std::vector<double> Kop;          // K_c band rows (= Kb for coef_a = 0)
   std::vector<double> V0, V1;       // (p-1) x half, row-major
   std::vector<double> Vout;         // n_out x m (rows = outlier basis vectors)
   std::vector<double> Ao, Bo;       // outlier pencil, n_out x n_out

@@ -31,9 +31,9 @@ def test_exports_every_declared_symbol():
     assert set(syms) == set(I.SIGNATURES), "binding and header disagree"
 
 
-def host_plan(d, n, p, method=I.METHOD_FFT, prec=I.PREC_F32, max_rhs=1):
+def host_plan(d, n, p, method=I.METHOD_FFT, prec=I.PREC_F32, max_rhs=1, coef_a=0.0):
     h = ctypes.c_void_p()
-    opts = I._Opts(method, prec, max_rhs)
+    opts = I._Opts(method, prec, max_rhs, coef_a)
     rc = I.lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts))
     return rc, h
 
@@ -167,3 +167,40 @@ def test_null_and_state_errors():
     for x in (h, h2, h3):
         I.lib.iffd_plan_destroy(x)
     assert I.lib.iffd_status_string(I.E_BREAKDOWN) == b"PCG breakdown"
+
+
+def band_to_dense(band, m, p):
+    A = np.zeros((m, m))
+    bw = 2 * p + 1
+    for i in range(m):
+        for o in range(bw):
+            j = i + o - p
+            if 0 <= j < m:
+                A[i, j] = band[i * bw + o]
+    return A
+
+
+@pytest.mark.parametrize("n,p,a,method", [(16, 3, 1.0, I.METHOD_FFT), (24, 4, -0.5, I.METHOD_FFT),
+                                          (20, 5, 3.0, I.METHOD_DENSE_FD)])
+def test_system_matrix_stiffness_with_coefficient(n, p, a, method):
+    """The plan's K_c (iffd_opts.coef_a, table 7) equals the oracle's
+    variable-coefficient stiffness; the preconditioner's K (table 2) stays the
+    Laplacian's."""
+    from oracle import bspline
+    from oracle import operator as OP
+    rc, h = host_plan(3, n, p, method=method, coef_a=a)
+    assert rc == 0, I.lib.iffd_last_error()
+    m = n + p - 2
+    Kc = band_to_dense(read(h, 7, m * (2 * p + 1)), m, p)
+    K = band_to_dense(read(h, 2, m * (2 * p + 1)), m, p)
+    Ko = OP.Operator(3, n, p, a).K
+    K0 = bspline.assemble_dirichlet(n, p)[0]
+    assert np.max(np.abs(Kc - Ko)) <= 1e-12 * np.max(np.abs(Ko))
+    assert np.max(np.abs(K - K0)) <= 1e-12 * np.max(np.abs(K0))
+    I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("a", [-1.0, -2.0, 1001.0, float("nan"), float("inf")])
+def test_coefficient_out_of_range_rejected(a):
+    rc, h = host_plan(3, 16, 3, coef_a=a)
+    assert rc == I.E_INVAL and h.value is None
