@@ -18,8 +18,10 @@ graph is timed as well.
 
 Printed as one JSON line: apply throughput (GDoF/s) with the roofline of its
 dominant kernel, PCG solve latency to 1e-8 (FP64 PCG, this apply), the
-dense-FD baseline (apply on the matrix cores and PCG), and the FP64 CPU oracle
-timed on the host cores on a bounded sample.
+dense-FD baseline (apply on the matrix cores and PCG), PCG with both
+preconditioners on a variable-coefficient system matrix (c = 1 + x per
+direction, where neither is exact), and the FP64 CPU oracle timed on the
+host cores on a bounded sample.
 """
 
 from __future__ import annotations
@@ -528,6 +530,25 @@ def main():
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}
         if B == 1:
+            # ---- a system matrix neither preconditioner inverts: A_c with the
+            # coefficient 1 + x per direction, IFFD and dense FD of A-hat ------
+            pc = iffd.Plan(d, n, p, method="fft", precision=args.precision, coef_a=1.0)
+            pc.tune(reps=5)
+            clat, cst = time_solves(torch, pc, f, max(5, args.solves // 3))
+            del pc
+            fc = iffd.Plan(d, n, p, method="dense", precision=args.precision, coef_a=1.0)
+            cflat, cfst = time_solves(torch, fc, f, max(5, args.solves // 3))
+            del fc
+            out["pcg_variable_coefficient"] = {
+                "coef_a": 1.0,
+                "iffd": {"solves_per_s": round(1e3 / statistics.mean(clat), 2),
+                         "p50_ms": round(pct(clat, 0.5), 3), "p99_ms": round(pct(clat, 0.99), 3),
+                         "iterations": cst[0]["iterations"]},
+                "dense_fd": {"solves_per_s": round(1e3 / statistics.mean(cflat), 2),
+                             "p50_ms": round(pct(cflat, 0.5), 3),
+                             "p99_ms": round(pct(cflat, 0.99), 3),
+                             "iterations": cfst[0]["iterations"]},
+                "iffd_solve_speedup": round(statistics.mean(cflat) / statistics.mean(clat), 3)}
             out["serving"] = serving(torch, 200, 60, [0.5, 0.9])
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
