@@ -259,7 +259,7 @@ def main():
                     help="only the IFFD / dense-FD solve comparison at these 3D sizes "
                          "(comma-separated n; p = 3 and 4, smooth right-hand side)")
     ap.add_argument("--coef", type=float, default=0.0,
-                    help="with --sweep-p / --sweep-n: solve with the variable-coefficient "
+                    help="with --sweep-p / --sweep-n / --pcg-only: solve with the variable-coefficient "
                          "system matrix A_c, c(x) = 1 + COEF x per direction (preconditioners "
                          "of A-hat)")
     ap.add_argument("--serve", action="store_true",
@@ -313,7 +313,8 @@ def main():
     if args.pcg_only:
         f_np = make_rhs(args.workload)
         f = torch.from_numpy(f_np[0] if B > 1 else f_np).cuda()
-        pl = iffd.Plan(d, n, p, method=args.pcg_only, precision=args.precision)
+        pl = iffd.Plan(d, n, p, method=args.pcg_only, precision=args.precision,
+                       coef_a=args.coef)
         if args.pcg_only == "fft":
             pl.tune(reps=20)
         for _ in range(2):
@@ -323,7 +324,7 @@ def main():
                           "value": round(statistics.mean(lat), 4), "higher_is_better": False,
                           "p50_ms": round(pct(lat, 0.5), 4), "p99_ms": round(pct(lat, 0.99), 4),
                           "iterations": st[0]["iterations"], "method": args.pcg_only,
-                          "dtype": args.precision, "solves": args.solves,
+                          "dtype": args.precision, "solves": args.solves, "coef_a": args.coef,
                           "config": {"workload": args.workload}}), flush=True)
         return
     r_np = make_rhs(args.workload)
