@@ -25,6 +25,10 @@
 namespace iffd {
 
 constexpr int VT = 256;  // threads per block of the vector kernels
+// The vector kernels take their chunk SU iterations at a time, with all
+// loads of those iterations issued before the first use, so that each
+// thread keeps several loads in flight (the sums keep their order).
+constexpr int SU = 4;
 
 // slot list of one begin call, passed by value (no device allocation)
 constexpr int kBeginMax = 64;
@@ -61,7 +65,18 @@ dot_partials(const double* __restrict__ a, const double* __restrict__ b, int N, 
   const double* ar = a + (size_t)slot * N;
   const double* br = b + (size_t)slot * N;
   double s = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += VT) s += ar[i] * br[i];
+  int i = lo + threadIdx.x;
+  for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+    double av[SU], bv[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      av[u] = ar[i + u * VT];
+      bv[u] = br[i + u * VT];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) s += av[u] * bv[u];
+  }
+  for (; i < hi; i += VT) s += ar[i] * br[i];
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[(size_t)slot * nblk + blk] = s;
 }
@@ -128,7 +143,22 @@ pcg_update_r(double* __restrict__ r, const double* __restrict__ q, int N, int nb
   chunk(N, nblk, blk, lo, hi);
   const size_t o = (size_t)slot * N;
   double s = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += VT) {
+  int i = lo + threadIdx.x;
+  for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+    double rv[SU], qv[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      rv[u] = r[o + i + u * VT];
+      qv[u] = q[o + i + u * VT];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const double v = rv[u] - alpha * qv[u];
+      r[o + i + u * VT] = v;
+      s += v * v;
+    }
+  }
+  for (; i < hi; i += VT) {
     const double rv = r[o + i] - alpha * q[o + i];
     r[o + i] = rv;
     s += rv * rv;
@@ -200,14 +230,39 @@ pcg_update_p(double* __restrict__ x, double* __restrict__ p, const double* __res
   int lo, hi;
   chunk(N, nblk, blk, lo, hi);
   const size_t o = (size_t)slot * N;
+  int i = lo + threadIdx.x;
   if (act) {
-    for (int i = lo + threadIdx.x; i < hi; i += VT) {
+    for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+      double pv[SU], xv[SU], zv[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        pv[u] = p[o + i + u * VT];
+        xv[u] = x[o + i + u * VT];
+        zv[u] = z[o + i + u * VT];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        x[o + i + u * VT] = xv[u] + alpha * pv[u];
+        p[o + i + u * VT] = zv[u] + beta * pv[u];
+      }
+    }
+    for (; i < hi; i += VT) {
       const double pv = p[o + i];
       x[o + i] += alpha * pv;
       p[o + i] = z[o + i] + beta * pv;
     }
   } else {
-    for (int i = lo + threadIdx.x; i < hi; i += VT) x[o + i] += alpha * p[o + i];
+    for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+      double pv[SU], xv[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        pv[u] = p[o + i + u * VT];
+        xv[u] = x[o + i + u * VT];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) x[o + i + u * VT] = xv[u] + alpha * pv[u];
+    }
+    for (; i < hi; i += VT) x[o + i] += alpha * p[o + i];
   }
 }
 
@@ -223,7 +278,19 @@ pcg_begin_copy(double* __restrict__ x, double* __restrict__ r, const double* __r
   const size_t o = (size_t)slot * N;
   const double* fk = f + (size_t)k * N;
   double s = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += VT) {
+  int i = lo + threadIdx.x;
+  for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+    double v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) v[u] = fk[i + u * VT];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      x[o + i + u * VT] = 0.0;
+      r[o + i + u * VT] = v[u];
+      s += v[u] * v[u];
+    }
+  }
+  for (; i < hi; i += VT) {
     const double v = fk[i];
     x[o + i] = 0.0;
     r[o + i] = v;
@@ -268,7 +335,15 @@ pcg_begin_p(double* __restrict__ p, const double* __restrict__ z, int N, int nbl
   int lo, hi;
   chunk(N, nblk, blk, lo, hi);
   const size_t o = (size_t)slot * N;
-  for (int i = lo + threadIdx.x; i < hi; i += VT) p[o + i] = z[o + i];
+  int i = lo + threadIdx.x;
+  for (; i + (SU - 1) * VT < hi; i += SU * VT) {
+    double v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) v[u] = z[o + i + u * VT];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) p[o + i + u * VT] = v[u];
+  }
+  for (; i < hi; i += VT) p[o + i] = z[o + i];
 }
 
 __global__ void __launch_bounds__(VT)
