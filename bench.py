@@ -259,9 +259,9 @@ def main():
                     help="only the IFFD / dense-FD solve comparison at these 3D sizes "
                          "(comma-separated n; p = 3 and 4, smooth right-hand side)")
     ap.add_argument("--coef", type=float, default=0.0,
-                    help="with --sweep-p / --sweep-n / --pcg-only: solve with the variable-coefficient "
-                         "system matrix A_c, c(x) = 1 + COEF x per direction (preconditioners "
-                         "of A-hat)")
+                    help="solve with the variable-coefficient system matrix A_c, "
+                         "c(x) = 1 + COEF x per direction (preconditioners of A-hat); the apply "
+                         "does not depend on it")
     ap.add_argument("--serve", action="store_true",
                     help="only the serving benchmark (Poisson stream of mixed solves)")
     ap.add_argument("--pcg-only", choices=["fft", "dense"],
@@ -330,7 +330,9 @@ def main():
     r_np = make_rhs(args.workload)
     r = torch.from_numpy(r_np).cuda()
     z = torch.empty_like(r)
-    plan = iffd.Plan(d, n, p, method="fft", precision=args.precision, max_rhs=B)
+    # (coef_a changes only the system matrix of the solves, not the apply)
+    plan = iffd.Plan(d, n, p, method="fft", precision=args.precision, max_rhs=B,
+                     coef_a=args.coef)
     N = plan.N
     npass = plan.n_passes()
     variants = plan.tune(reps=20)   # FFT shape per pass, timed on the device
@@ -418,7 +420,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": args.precision, "data": "synthetic",
            "config": {"workload": args.workload, "d": d, "n": n, "p": p, "dofs_per_rhs": N,
-                      "rhs": B, "rhs_recipe": recipe, "apply_io": "f64",
+                      "rhs": B, "rhs_recipe": recipe, "apply_io": "f64", "coef_a": args.coef,
                       "step": f"one preconditioner apply to {B} right-hand side(s)"},
            "graph_ms_per_step": round(graph_ms, 5),
            "graph_gdof_s": round(B * N / (graph_ms * 1e-3) / 1e9, 3),
@@ -463,7 +465,8 @@ def main():
             del gs, U
         # ---- dense FD baseline: apply on the matrix cores, and PCG ---------------
         try:
-            fd = iffd.Plan(d, n, p, method="dense", precision=args.precision, max_rhs=B)
+            fd = iffd.Plan(d, n, p, method="dense", precision=args.precision, max_rhs=B,
+                           coef_a=args.coef)
             zf = torch.empty_like(r)
             for _ in range(5):
                 fd.apply(r, out=zf)
@@ -500,7 +503,8 @@ def main():
                     "iterations": fbst[0]["iterations"]}
             del fd, zf
             # ---- dense FD on the FP16 matrix cores, per-line scaling -------------
-            fh = iffd.Plan(d, n, p, method="dense", precision="f16s", max_rhs=B)
+            fh = iffd.Plan(d, n, p, method="dense", precision="f16s", max_rhs=B,
+                           coef_a=args.coef)
             zh = torch.empty_like(r)
             for _ in range(5):
                 fh.apply(r, out=zh)
@@ -530,7 +534,7 @@ def main():
             del fh, zh
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}
-        if B == 1:
+        if B == 1 and args.coef == 0.0:
             # ---- a system matrix neither preconditioner inverts: A_c with the
             # coefficient 1 + x per direction, IFFD and dense FD of A-hat ------
             pc = iffd.Plan(d, n, p, method="fft", precision=args.precision, coef_a=1.0)
