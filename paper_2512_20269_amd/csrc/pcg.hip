@@ -326,26 +326,6 @@ pcg_begin_scal(double* scal, const double* part, int nblk, BeginSlots slots, dou
   }
 }
 
-// p = z for the started slots
-__global__ void __launch_bounds__(VT)
-pcg_begin_p(double* __restrict__ p, const double* __restrict__ z, int N, int nblk,
-            const double* __restrict__ scal) {
-  const int slot = blockIdx.x / nblk, blk = blockIdx.x - slot * nblk;
-  if (scal[(size_t)slot * kScal + S_NEW] == 0.0) return;
-  int lo, hi;
-  chunk(N, nblk, blk, lo, hi);
-  const size_t o = (size_t)slot * N;
-  int i = lo + threadIdx.x;
-  for (; i + (SU - 1) * VT < hi; i += SU * VT) {
-    double v[SU];
-#pragma unroll
-    for (int u = 0; u < SU; ++u) v[u] = z[o + i + u * VT];
-#pragma unroll
-    for (int u = 0; u < SU; ++u) p[o + i + u * VT] = v[u];
-  }
-  for (; i < hi; i += VT) p[o + i] = z[o + i];
-}
-
 __global__ void __launch_bounds__(VT)
 pcg_begin_finish(double* scal, const double* part, int nused, int stride, int nslots) {
   __shared__ double red[VT / 64];
@@ -442,26 +422,25 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   double* x = (double*)(st + L.x);
   double* r = (double*)(st + L.r);
   double* p = (double*)(st + L.p);
-  double* qz = (double*)(st + L.qz);
   hipLaunchKernelGGL(pcg_begin_copy, dim3(count * nb), dim3(VT), 0, s, x, r, f, bs, N, nb, part);
   hipLaunchKernelGGL(pcg_begin_scal, dim3(count), dim3(VT), 0, s, scal, part, nb, bs, rtol, maxit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // z = P^{-1} r for the new slots only (IFFD: r . z partials from its last pass)
+  // p = z = P^{-1} r for the new slots only, written straight into p (IFFD:
+  // r . z partials from its last pass)
   int nrz = nb;
   if (P.method == IFFD_METHOD_FFT) {
     const PassHook hk{r, part, nb, 0};
-    e = launch_iffd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s,
+    e = launch_iffd_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s,
                           &hk);
     if (e != hipSuccess) return e;
     nrz = hk.tiles;
   } else {
-    e = launch_fd_apply(P, r, qz, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
+    e = launch_fd_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
+    hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, p, N, nb, part, scal,
                        (int)S_NEW);
   }
-  hipLaunchKernelGGL(pcg_begin_p, dim3(nslots * nb), dim3(VT), 0, s, p, qz, N, nb, scal);
   hipLaunchKernelGGL(pcg_begin_finish, dim3(nslots), dim3(VT), 0, s, scal, part, nrz, nb, nslots);
   return hipGetLastError();
 }
