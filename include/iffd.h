@@ -168,15 +168,17 @@ void iffd_plan_destroy(iffd_plan* plan);
 int iffd_precond_apply(const iffd_plan* plan, const double* d_r, double* d_z, int nrhs,
                        void* d_ws, size_t ws_bytes, void* stream);
 
-/* y = Ahat x, Ahat = sum_k M x .. x K (slot k) x .. x M (eq:system_matrix and
- * its 3-term analogue), FP64, matrix-free by sum factorization with the
- * banded 1-D matrices.  d_x, d_y: [nrhs][m]^d FP64, must not overlap.
+/* y = A x with the plan's system matrix A = sum_k M x .. x K_A (slot k) x .. x M
+ * (eq:system_matrix and its 3-term analogue): K_A = K gives Ahat, K_A = K_c
+ * for iffd_opts.coef_a != 0 (see iffd_opts).  FP64, matrix-free by sum
+ * factorization with the banded 1-D matrices.  d_x, d_y: [nrhs][m]^d FP64, must not overlap.
  * d_ws: >= matvec_ws_bytes (for max_rhs), 256-byte aligned (NULL if 0). */
 int iffd_kron_matvec(const iffd_plan* plan, const double* d_x, double* d_y, int nrhs,
                      void* d_ws, size_t ws_bytes, void* stream);
 
-/* Solves Ahat u = f for nrhs right-hand sides by PCG with this plan's
- * preconditioner (Section 3), zero initial guess, stopping when
+/* Solves A u = f (the plan's system matrix, see iffd_kron_matvec) for nrhs
+ * right-hand sides by PCG with this plan's preconditioner (Section 3), which
+ * is always built from Ahat; zero initial guess, stopping when
  * ||r_k||_2 <= rtol ||f||_2 for the recursively updated residual (protocol of
  * Section 7; the norm is the reading documented with the oracle) or after
  * maxit iterations.  All vectors, inner products and scalars are FP64 on the

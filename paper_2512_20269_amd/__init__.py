@@ -9,7 +9,7 @@ importing this package without it raises immediately.
     import torch, paper_2512_20269_amd as iffd
     plan = iffd.Plan(d=3, n=128, p=3, precision="f32")
     z = plan.apply(r)                    # z = P^{-1} r, r: float64 [m]^d on cuda
-    y = plan.matvec(x)                   # y = Ahat x
+    y = plan.matvec(x)                   # y = A x (Ahat, or A_c with coef_a)
     u, stats = plan.solve(f, rtol=1e-8)  # PCG
 """
 
@@ -247,7 +247,7 @@ class Plan:
                                    self._ws.numel(), _stream(stream)), "apply_pass")
 
     def matvec(self, x, out=None, stream=None):
-        """y = Ahat x."""
+        """y = A x, the plan's system matrix (Ahat, or A_c for coef_a != 0)."""
         torch = _torch()
         nrhs = self._batch(x, "x")
         y = out if out is not None else torch.empty_like(x)
@@ -258,7 +258,8 @@ class Plan:
 
     def solve(self, f, rtol: float = 1e-8, maxit: int = 500, check_every: int = 1, out=None,
               stream=None):
-        """PCG for Ahat u = f; returns (u, [stats dict per right-hand side])."""
+        """PCG for A u = f (the plan's system matrix, preconditioner built from
+        Ahat); returns (u, [stats dict per right-hand side])."""
         torch = _torch()
         nrhs = self._batch(f, "f")
         u = out if out is not None else torch.empty_like(f)
