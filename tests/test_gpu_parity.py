@@ -53,7 +53,9 @@ def host(x):
 APPLY_CASES = [(2, 8, 3), (2, 16, 2), (2, 16, 3), (2, 24, 4), (2, 12, 5), (2, 32, 5), (2, 48, 6),
                (2, 64, 3), (2, 64, 7), (2, 96, 8), (2, 128, 4), (2, 192, 3), (2, 256, 6),
                (3, 8, 2), (3, 16, 3), (3, 12, 4), (3, 16, 5), (3, 24, 6), (3, 16, 7), (3, 16, 8),
-               (3, 32, 3), (3, 48, 4), (2, 384, 4), (2, 512, 3)]
+               (3, 32, 3), (3, 48, 4), (2, 384, 4), (2, 512, 3),
+               # smallest n for the degree: the two boundary blocks nearly meet
+               (2, 8, 7), (3, 8, 7), (2, 12, 8)]
 
 
 def tol_apply(prec, n):
