@@ -82,7 +82,7 @@ def test_apply_matches_oracle(d, n, p, prec):
 
 @pytest.mark.parametrize("d,n,p", [(2, 16, 3), (2, 64, 3), (3, 16, 3), (3, 12, 4), (3, 24, 8),
                                    (2, 48, 1), (3, 96, 3), (3, 48, 4), (3, 20, 1), (3, 64, 2),
-                                   (3, 32, 6)])
+                                   (3, 32, 6), (3, 8, 7), (3, 12, 4), (2, 12, 8)])
 def test_matvec_matches_oracle(d, n, p):
     """3D with p <= 4 runs the fused single-pass kernel (several column strips,
     row blocks and plane chunks with ragged tails at n = 96, 64, 48); larger p
