@@ -242,26 +242,24 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
         for (int u = 0; u < UMX; ++u)
           v[a][u] = buf_ld<Tin>(rs, vo + (unsigned)((a * NG * m + jb + RW * u) * (int)sizeof(Tin)));
       if constexpr (FU) {
-        {
-          // r <- r - alpha q, written back once per entry (line l < nv, j < m)
-          double qv[LPT][UMX];
+        // r <- r - alpha q, written back once per entry (line l < nv, j < m)
+        double qv[LPT][UMX];
 #pragma unroll
-          for (int a = 0; a < LPT; ++a)
+        for (int a = 0; a < LPT; ++a)
 #pragma unroll
-            for (int u = 0; u < UMX; ++u)
-              qv[a][u] = buf_ld<double>(qs, vo + (unsigned)((a * NG * m + jb + RW * u) * 8));
+          for (int u = 0; u < UMX; ++u)
+            qv[a][u] = buf_ld<double>(qs, vo + (unsigned)((a * NG * m + jb + RW * u) * 8));
 #pragma unroll
-          for (int a = 0; a < LPT; ++a)
+        for (int a = 0; a < LPT; ++a)
 #pragma unroll
-            for (int u = 0; u < UMX; ++u) {
-              const int j = jb + lane + RW * u, l = grp + a * NG;
-              const bool own = j < m && l < nv;
-              const double rv = (double)v[a][u] - alpha * qv[a][u];
-              v[a][u] = (Tin)rv;
-              buf_st<double>(rv, rw, own ? vo + (unsigned)((a * NG * m + jb + RW * u) * 8) : BUF_OOB);
-              racc += own ? rv * rv : 0.0;
-            }
-        }
+          for (int u = 0; u < UMX; ++u) {
+            const int j = jb + lane + RW * u, l = grp + a * NG;
+            const bool own = j < m && l < nv;
+            const double rv = (double)v[a][u] - alpha * qv[a][u];
+            v[a][u] = (Tin)rv;
+            buf_st<double>(rv, rw, own ? vo + (unsigned)((a * NG * m + jb + RW * u) * 8) : BUF_OOB);
+            racc += own ? rv * rv : 0.0;
+          }
       }
       // entries past the row go to a sink (a select, not a branch, so the
       // compiler keeps every load of the batch ahead of the first write)
@@ -323,24 +321,22 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
     for (int c = t + BCH * NTH; c < tb.nch; c += NTH) B4[c] = buf_ld16(trs, (unsigned)c * 16u);
   }
   __syncthreads();
-  if constexpr (FU) {
-    {   // fixed-order sum of the updated r^2 over the workgroup
-      double* red = reinterpret_cast<double*>(DM);   // NTH doubles fit in DM
-      if constexpr (NTH % 64 == 0) {
-        for (int o = 32; o > 0; o >>= 1) racc += __shfl_xor(racc, o);
-        if ((t & 63) == 0) red[t >> 6] = racc;
-      } else {
-        red[t] = racc;   // a partial wave: no shuffles
-      }
-      __syncthreads();
-      if (t == 0) {
-        constexpr int NR = NTH % 64 == 0 ? NTH / 64 : NTH;
-        double sum = 0.0;
-        for (int k = 0; k < NR; ++k) sum += red[k];
-        g.dpart[(size_t)rhs * g.dnpart + tile] = sum;
-      }
-      __syncthreads();   // DM takes discarded values again below
+  if constexpr (FU) {   // fixed-order sum of the updated r^2 over the workgroup
+    double* red = reinterpret_cast<double*>(DM);   // NTH doubles fit in DM
+    if constexpr (NTH % 64 == 0) {
+      for (int o = 32; o > 0; o >>= 1) racc += __shfl_xor(racc, o);
+      if ((t & 63) == 0) red[t >> 6] = racc;
+    } else {
+      red[t] = racc;   // a partial wave: no shuffles
     }
+    __syncthreads();
+    if (t == 0) {
+      constexpr int NR = NTH % 64 == 0 ? NTH / 64 : NTH;
+      double sum = 0.0;
+      for (int k = 0; k < NR; ++k) sum += red[k];
+      g.dpart[(size_t)rhs * g.dnpart + tile] = sum;
+    }
+    __syncthreads();   // DM takes discarded values again below
   }
   if (MODE == PASS_MID) {
     // spectral indices of each line in the other directions (the middle pass
