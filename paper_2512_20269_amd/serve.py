@@ -145,16 +145,16 @@ class SolveServer:
         if need is None:
             return None
         need += 8 * N          # the entry is only worth creating with room for one request
-        # evict idle shapes (least recently used first) until the entry fits
-        for k in list(self.entries):
+        # evict idle shapes (least recently used first) until the entry fits,
+        # and none at all when evicting every idle shape would not make room
+        idle = [k for k, old in self.entries.items() if not old.busy and not old.inflight]
+        if self.used - sum(self.entries[k].bytes for k in idle) + need > self.budget:
+            return None
+        for k in idle:
             if self.used + need <= self.budget:
                 break
-            old = self.entries[k]
-            if not old.busy and not old.inflight:
-                self.used -= old.bytes
-                del self.entries[k]
-        if self.used + need > self.budget:
-            return None
+            self.used -= self.entries[k].bytes
+            del self.entries[k]
         e = _Entry(key, self.slots, self.tune, self.device, self.k, self.graphs)
         self.entries[key] = e
         self.used += e.bytes
