@@ -31,8 +31,9 @@ Route A (from the definitions)
 Route B (the structured factorization of Sections 5 and 6)
     V_reg in the special basis (eq:special_basis_dirichlet) written on the
     B-spline basis; U = [sin(x_i alpha_j)] (Table 1, D = {0,1}); Dt =
-    diag(U^T V_reg^T M V_reg U)^{1/2} (end of Section 6); L_reg from the
-    Rayleigh quotients (eq:Lambda reg2); V_out = M^{-1} W with W an orthonormal
+    diag(U^T V_reg^T M V_reg U)^{1/2} (end of Section 6); L_reg =
+    |F_j|^2_H1 / ||F_j||^2_L2 (eq:Lambda reg2) by quadrature of F_j' and F_j,
+    F_j = the spline with coefficients V_reg U e_j; V_out = M^{-1} W with W an orthonormal
     basis of range(V_reg)'s Euclidean complement; (L_out, Q_out) by Jacobi on
     the out pencil (eq:eigendecomposition_out).
 
@@ -41,9 +42,10 @@ projected pencil with Cholesky + Jacobi, whose eigenvalues carry absolute
 errors of order eps * ||L^{-1} Ktilde L^{-T}|| ~ eps * n^2; the small
 eigenvalues, which dominate P^{-1} r, therefore lose relative accuracy as n
 grows (A and B differ by ~7e-12 at n = 192).  Route B's regular eigenvalues
-are Rayleigh quotients of exactly known modes and keep full relative
-accuracy, so it is the reference for comparisons at large n; the two routes
-are checked against each other (and against brute force) at small n.
+are the seminorm quotients of exactly known modes, integrated from F_j' (no
+cancellation of O(n^2) terms), and keep their relative accuracy, so it is the
+reference for comparisons at large n; the two routes are checked against each
+other (and against brute force) at small n.
 
 Application (eq:preconditioner, eq:exact_diagonalization)
     z = (Qt x .. x Qt) (sum_k Lt_k)^{-1} (Qt^T x .. x Qt^T) r, with Qt^T
@@ -180,6 +182,24 @@ def sine_matrix(n: int, p: int) -> np.ndarray:
     return np.sin(np.outer(x, a))
 
 
+def mode_seminorms(n: int, p: int, C: np.ndarray):
+    """|F|^2_H1 and ||F||^2_L2 of the splines F = sum_i C[i, j] B_i (reduced
+    basis, one column per function), by Gauss-Legendre quadrature with p+1
+    points per element, which is exact for both integrands (degree 2p-2 and
+    2p).  F' is evaluated from the B-spline derivatives at the quadrature
+    points and squared there, so no large terms cancel in the integral (the
+    bilinear form C^T K C sums terms of size ~ n^2 |C|^2 into a result of size
+    ~ |C|^2 for the smoothest modes)."""
+    knots = bspline.open_knots(n, p)
+    gx, gw = np.polynomial.legendre.leggauss(p + 1)
+    e = np.arange(n)
+    xq = ((e[:, None] + 0.5) + 0.5 * gx[None, :]).ravel() / n
+    wq = np.tile(0.5 * gw / n, n)
+    F = bspline.basis(knots, p, xq)[:, 1:-1] @ C
+    dF = bspline.derivative(knots, p, xq, 1)[:, 1:-1] @ C
+    return wq @ dF ** 2, wq @ F ** 2
+
+
 def factors_route_b(n: int, p: int):
     """Structured factors: dict with V_reg, U, Dt, lam_reg, V_out, Q_out,
     lam_out, Qt (= [V_reg U Dt^{-1}, V_out Q_out]) and lam_t."""
@@ -189,7 +209,8 @@ def factors_route_b(n: int, p: int):
     U = sine_matrix(n, p)
     VU = Vreg @ U
     Dt2 = np.einsum("ij,ij->j", VU, M @ VU)
-    lam_reg = np.einsum("ij,ij->j", VU, K @ VU) / Dt2
+    h1, l2 = mode_seminorms(n, p, VU)
+    lam_reg = h1 / l2
     Dt = np.sqrt(Dt2)
     Qreg_cols = VU / Dt
     if n_out:

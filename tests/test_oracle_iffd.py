@@ -105,6 +105,33 @@ def test_lemma4_corrected_closed_forms(p):
     np.testing.assert_allclose(f["Dt"] ** 2, sM * qn / (4 * n), rtol=1e-12)
 
 
+@pytest.mark.parametrize("n,p", [(256, 3), (192, 4)])
+def test_regular_eigenvalues_keep_relative_accuracy_at_large_n(n, p):
+    """Route B's smooth-mode eigenvalues (seminorm quotients integrated from
+    F_j', eq:Lambda reg2) against Lemma 4's closed form with 2 - 2cos t written
+    as 4 sin^2(t/2), which has no cancellation on smooth modes: 1e-14 on the
+    first modes.  The FP64 quotient x^T K x / x^T M x of the same modes is off
+    by eps * n^2 (4e-13 at n = 256), which this would catch."""
+    h = 1.0 / n
+    f = iffd.factors_route_b(n, p)
+    j = np.arange(1, 9)
+    t = j * np.pi * h
+    lam = 4 * np.sin(t / 2) ** 2 / h ** 2 * symbol(2 * p - 1, p - 1, t) / symbol(2 * p + 1, p, t)
+    np.testing.assert_allclose(f["lam_reg"][:8], lam, rtol=1e-14)
+
+
+def test_p1_route_b_is_fd():
+    """p = 1: S^reg = S (no outliers), the special basis is the B-spline basis
+    and U diagonalizes K and M exactly, so route B is the FD inverse."""
+    for d, n in ((2, 24), (3, 8)):
+        fb = iffd.factors_route_b(n, 1)
+        assert fb["V_out"].shape[1] == 0
+        r = np.random.default_rng(d).uniform(-1, 1, (n - 1,) * d)
+        zb = iffd.Preconditioner(d, n, 1, "iffd_b").apply(r)
+        zf = iffd.Preconditioner(d, n, 1, "fd").apply(r)
+        assert np.linalg.norm(zb - zf) <= 1e-13 * np.linalg.norm(zf)
+
+
 @pytest.mark.parametrize("p", range(1, 9))
 def test_route_a_equals_route_b(p):
     n = 2 * p + 6
