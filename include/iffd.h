@@ -60,7 +60,14 @@ extern "C" {
 
 #define IFFD_PREC_F64         0   /* preconditioner arithmetic in FP64          */
 #define IFFD_PREC_F32         1   /* preconditioner arithmetic in FP32; inputs,
-                                     outputs and all Krylov work stay FP64      */
+                                     outputs and all Krylov work stay FP64.  For
+                                     p >= 5 the IFFD forward pass along
+                                     direction 1, which reads the FP64 input,
+                                     computes in FP64 and stores FP32: the
+                                     small eigenvalues of the high-degree mass
+                                     matrices would otherwise amplify the
+                                     rounding of the input itself (Section 3's
+                                     mass matrix M in every Kronecker factor) */
 #define IFFD_PREC_F16S        2   /* dense FD only: mode products on FP16 matrix
                                      cores (FP32 accumulation), every line along
                                      the transformed direction scaled by its own
@@ -121,11 +128,17 @@ typedef struct {
  * outlier basis V_out (L2-orthogonal to S^reg), the normalisation
  * Dt = diag(U^T V_reg^T M V_reg U)^{1/2} and the regular eigenvalues
  * (eq:Lambda reg2); for DENSE_FD, the full FP64 eigendecomposition of the
- * pencil (K, M) (eq:eigendecomposition).  Valid range: d in {2,3},
+ * pencil (K, M) (eq:eigendecomposition).  The regular eigenvalues come from
+ * the closed form of Lemma 4 (its stiffness symbol scaled by 1/h^2, as in its
+ * proof), which equals the Rayleigh quotients of eq:Lambda reg2 without their
+ * cancellation on smooth modes; Dt from the mass Rayleigh quotients (end of
+ * Section 6).  Valid range: d in {2,3},
  * 1 <= p <= 8, n > p (the paper's standing assumption), m^d*max_rhs < 2^31
  * per pass and m^d < 2^28 (one right-hand side below 2 GiB in FP64, the
  * reach of the kernels' 32-bit buffer offsets); IFFD additionally needs n = 2^a or 3*2^a with 8 <= n <= 512
- * (IFFD_E_UNSUPPORTED otherwise).  *out receives the plan (NULL on error). */
+ * (IFFD_E_UNSUPPORTED otherwise).  For p = 1 IFFD has no outlier space
+ * (S = S^reg, Section 4) and is the exact inverse by the DST-I alone.
+ * *out receives the plan (NULL on error). */
 int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
 
 /* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan. */
@@ -135,7 +148,9 @@ int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info);
  * (>= info.table_bytes bytes, 256-byte aligned), solves the small outlier
  * pencil (V_out^T K V_out, V_out^T M V_out) (eq:eigendecomposition_out) in
  * FP64 on the device, and synchronizes `stream` once.  Must be called before
- * any compute entry point; may be called again with another buffer. */
+ * any compute entry point; may be called again with another buffer.  Returns
+ * IFFD_E_INVAL (plan not ready) if the outlier pencil's mass block is not
+ * positive definite or its eigenpairs are not finite and positive. */
 int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* stream);
 
 /* Copies host-side plan data for inspection (tests, diagnostics).  `what`:
@@ -223,7 +238,11 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
  * state_bytes_fixed + nslots * state_bytes_per_slot.  Slots are independent:
  * a slot's arithmetic does not depend on the other slots (no cross-slot
  * reduction, fixed reduction order), so its result is the same alone or in a
- * batch.  All calls are asynchronous on `stream`. */
+ * batch.  All calls are asynchronous on `stream`.  1 <= nslots <= max_rhs.
+ * The library records the plan and nslots each buffer was initialised with;
+ * begin, iterate, poll, status and take return IFFD_E_STATE for a buffer
+ * that was not initialised, or was initialised with another plan or another
+ * nslots (the offsets inside the buffer follow from both). */
 
 /* Zeroes the state (every slot free).  Must be called once per buffer. */
 int iffd_pcg_state_init(const iffd_plan* plan, void* d_state, size_t state_bytes, int nslots,

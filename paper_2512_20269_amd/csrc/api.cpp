@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "launch.h"
@@ -30,6 +32,27 @@ struct iffd_plan {
 namespace {
 
 thread_local std::string g_err;
+
+// nslots each PCG state buffer was initialised with (iffd_pcg_state_init):
+// every stepped call must name the same plan and slot count, since the
+// offsets inside the buffer follow from them
+struct StateRec {
+  const iffd_plan* plan;
+  int nslots;
+};
+std::mutex g_state_mu;
+std::unordered_map<const void*, StateRec> g_states;
+
+void state_register(const void* st, const iffd_plan* plan, int nslots) {
+  std::lock_guard<std::mutex> lk(g_state_mu);
+  g_states[st] = StateRec{plan, nslots};
+}
+
+bool state_matches(const void* st, const iffd_plan* plan, int nslots) {
+  std::lock_guard<std::mutex> lk(g_state_mu);
+  auto it = g_states.find(st);
+  return it != g_states.end() && it->second.plan == plan && it->second.nslots == nslots;
+}
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -133,7 +156,15 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
   return IFFD_OK;
 }
 
-void iffd_plan_destroy(iffd_plan* plan) { delete plan; }
+void iffd_plan_destroy(iffd_plan* plan) {
+  if (!plan) return;
+  {
+    std::lock_guard<std::mutex> lk(g_state_mu);
+    for (auto it = g_states.begin(); it != g_states.end();)
+      it = it->second.plan == plan ? g_states.erase(it) : std::next(it);
+  }
+  delete plan;
+}
 
 int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info) {
   if (!plan || !info) return fail(IFFD_E_INVAL, "null argument");
@@ -218,10 +249,17 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
   if (e != hipSuccess) return hip_fail(e, "setup sync");
   if (P.method == IFFD_METHOD_FFT && P.n_out > 0) {
     std::vector<double> lam(P.m), vt((size_t)P.n_out * P.m);
-    e = hipMemcpy(lam.data(), (char*)d_tables + t.lam64, 8 * P.m, hipMemcpyDeviceToHost);
+    double stat = 0.0;
+    e = hipMemcpy(&stat, (char*)d_tables + t.stat64, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(lam.data(), (char*)d_tables + t.lam64, 8 * P.m, hipMemcpyDeviceToHost);
     if (e == hipSuccess)
       e = hipMemcpy(vt.data(), (char*)d_tables + t.vt64, 8 * vt.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "setup readback");
+    if (stat > 0.0)
+      return fail(IFFD_E_INVAL, "outlier pencil: mass block not positive definite at pivot " +
+                                    std::to_string((int)stat));
+    if (stat != 0.0) return fail(IFFD_E_INVAL, "outlier pencil: non-finite or non-positive eigenpairs");
     for (int k = P.n_reg; k < P.m; ++k) P.lam[k] = lam[k];
     P.Vt = vt;
   }
@@ -391,11 +429,12 @@ int iffd_pcg_state_init(const iffd_plan* plan, void* d_state, size_t state_bytes
   if (!plan || !d_state) return fail(IFFD_E_INVAL, "null argument");
   const Plan& P = plan->P;
   if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
-  if (nslots < 1) return fail(IFFD_E_INVAL, "nslots must be >= 1");
+  if (nslots < 1 || nslots > P.max_rhs) return fail(IFFD_E_INVAL, "nslots must be in 1..max_rhs");
   if (!aligned256(d_state)) return fail(IFFD_E_INVAL, "state must be 256-byte aligned");
   if (state_bytes < state_layout(P, nslots).total) return fail(IFFD_E_WORKSPACE, "state buffer too small");
   hipError_t e = state_init(P, (char*)d_state, nslots, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "state init");
+  state_register(d_state, plan, nslots);
   return IFFD_OK;
 }
 
@@ -404,6 +443,8 @@ int iffd_pcg_begin(const iffd_plan* plan, void* d_state, int nslots, const int* 
   if (!plan || !d_state || !h_slots || !d_f) return fail(IFFD_E_INVAL, "null argument");
   const Plan& P = plan->P;
   if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (!state_matches(d_state, plan, nslots))
+    return fail(IFFD_E_STATE, "state not initialised for this plan with this nslots");
   if (count < 1 || count > nslots) return fail(IFFD_E_INVAL, "bad slot count");
   if (!(rtol >= 0.0) || maxit < 0) return fail(IFFD_E_INVAL, "bad rtol / maxit");
   std::vector<char> seen(nslots, 0);
@@ -426,6 +467,8 @@ int iffd_pcg_iterate(const iffd_plan* plan, void* d_state, int nslots, int k, vo
   const Plan& P = plan->P;
   if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
   if (nslots < 1 || nslots > P.max_rhs || k < 0) return fail(IFFD_E_INVAL, "bad nslots / k");
+  if (!state_matches(d_state, plan, nslots))
+    return fail(IFFD_E_STATE, "state not initialised for this plan with this nslots");
   hipError_t e = pcg_iterate_dev(P, (char*)d_state, nslots, k, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pcg iterate");
   return IFFD_OK;
@@ -435,6 +478,9 @@ int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double
                   void* stream) {
   if (!plan || !d_state || !h_out) return fail(IFFD_E_INVAL, "null argument");
   const Plan& P = plan->P;
+  if (nslots < 1 || nslots > P.max_rhs) return fail(IFFD_E_INVAL, "nslots must be in 1..max_rhs");
+  if (!state_matches(d_state, plan, nslots))
+    return fail(IFFD_E_STATE, "state not initialised for this plan with this nslots");
   const StateLayout L = state_layout(P, nslots);
   std::vector<double> sc((size_t)nslots * kScal);
   hipStream_t s = (hipStream_t)stream;
@@ -455,8 +501,10 @@ int iffd_pcg_poll(const iffd_plan* plan, const void* d_state, int nslots, double
 int iffd_pcg_status(const iffd_plan* plan, const void* d_state, int nslots, double* d_out,
                     void* stream) {
   if (!plan || !d_state || !d_out) return fail(IFFD_E_INVAL, "null argument");
-  if (nslots < 1) return fail(IFFD_E_INVAL, "nslots must be >= 1");
+  if (nslots < 1 || nslots > plan->P.max_rhs) return fail(IFFD_E_INVAL, "nslots must be in 1..max_rhs");
   if (!plan->P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (!state_matches(d_state, plan, nslots))
+    return fail(IFFD_E_STATE, "state not initialised for this plan with this nslots");
   hipError_t e = pcg_status_dev(plan->P, (const char*)d_state, nslots, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pcg status");
   return IFFD_OK;
@@ -465,7 +513,11 @@ int iffd_pcg_status(const iffd_plan* plan, const void* d_state, int nslots, doub
 int iffd_pcg_take(const iffd_plan* plan, void* d_state, int nslots, int slot, double* d_u,
                   void* stream) {
   if (!plan || !d_state || !d_u) return fail(IFFD_E_INVAL, "null argument");
-  if (slot < -1 || slot >= nslots || nslots < 1) return fail(IFFD_E_INVAL, "slot out of range");
+  if (nslots < 1 || nslots > plan->P.max_rhs) return fail(IFFD_E_INVAL, "nslots must be in 1..max_rhs");
+  if (slot < -1 || slot >= nslots) return fail(IFFD_E_INVAL, "slot out of range");
+  if (!plan->P.ready) return fail(IFFD_E_STATE, "plan not set up");
+  if (!state_matches(d_state, plan, nslots))
+    return fail(IFFD_E_STATE, "state not initialised for this plan with this nslots");
   hipError_t e = pcg_take_dev(plan->P, (char*)d_state, nslots, slot, d_u, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pcg take");
   return IFFD_OK;

@@ -117,7 +117,10 @@ static int tw_min() {
   return w;
 }
 template <int L>
-static int tw_min_p(bool f64) { return f64 ? tw_min<double, L>() : tw_min<float, L>(); }
+static int tw_min_p(bool f64) {
+  const int a = tw_min<double, L>(), b = tw_min<float, L>();
+  return f64 ? a : (a < b ? a : b);   // FP32 plans may run their first pass in FP64
+}
 
 int apply_last_tiles_max(const Plan& P) {
   if (P.method != IFFD_METHOD_FFT) return 1;

@@ -912,6 +912,9 @@ hipError_t line_pass_mode(const Plan& P, int var, int axis, int tin, const void*
     return by_variant<double, double, double, MODE, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
   }
   if constexpr (MODE == PASS_FWD) {
+    // the pass that reads the FP64 input computes in FP64 when first64 is set
+    if (tin == ELEM_F64 && tout == ELEM_F32 && P.first64)
+      return by_variant<double, float, double, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F64 && tout == ELEM_F32)
       return by_variant<double, float, float, PASS_FWD, L>(P, var, axis, in, out, nrhs, a, as, s, hk);
     if (tin == ELEM_F32 && tout == ELEM_F32)

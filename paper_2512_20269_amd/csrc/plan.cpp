@@ -13,7 +13,8 @@
 //               cardinal B-splines at the ends, plain ones inside, for which
 //               Q_reg = U Dt^{-1} with U = [sin(x_i alpha_j)] (Table 1) and
 //               Dt = diag(U^T V_reg^T M V_reg U)^{1/2};
-//   eq:Lambda reg2  regular eigenvalues as Rayleigh quotients of the modes.
+//   Lemma 4     regular eigenvalues in closed form (the Rayleigh quotients
+//               of eq:Lambda reg2 of the exact modes, without cancellation).
 // The small outlier pencil is solved later on the device (setup kernel).
 #include "plan.h"
 
@@ -120,19 +121,46 @@ void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
 
 // Symmetric cardinal B-spline of degree p centred at 0 (support of width
 // p+1), by the Cox-de Boor recursion on the uniform knots k - (p+1)/2.
-double cardinal(int p, double t) {
-  std::vector<double> N(p + 1);
-  double t0 = -(p + 1) / 2.0;
+template <typename R>
+R cardinal_t(int p, R t) {
+  std::vector<R> N(p + 1);
+  R t0 = -(p + 1) / R(2);
   for (int i = 0; i <= p; ++i) {
-    double a = t0 + i;
-    N[i] = (t >= a && t < a + 1) ? 1.0 : 0.0;
+    R a = t0 + i;
+    N[i] = (t >= a && t < a + 1) ? R(1) : R(0);
   }
   for (int q = 1; q <= p; ++q)
     for (int i = 0; i + q <= p; ++i) {
-      double a = t0 + i;
+      R a = t0 + i;
       N[i] = ((t - a) * N[i] + (a + q + 1 - t) * N[i + 1]) / q;
     }
   return N[0];
+}
+double cardinal(int p, double t) { return cardinal_t<double>(p, t); }
+
+// Regular eigenvalue of mode j (Lemma 4, with the stiffness symbol's h
+// scaling taken from its proof): with theta = j pi / n,
+//   lambda_j = (2 - 2 cos theta) / h^2 * sK(theta) / sM(theta),
+//   sM = sum_{|k| <= p} B_{2p+1}(k) cos(k theta),
+//   sK = sum_{|k| <= p-1} B_{2p-1}(k) cos(k theta),
+// B_q the symmetric cardinal B-spline of degree q.  It equals the Rayleigh
+// quotient |F_j|^2_H1 / ||F_j||^2_L2 (eq:Lambda reg2) of the exact mode, but
+// 2 - 2 cos theta is formed as 4 sin^2(theta / 2) in extended precision, so
+// the smooth modes keep full relative accuracy (the quotient x^T K x /
+// x^T M x of the FP64 band matrices cancels like eps * n^2 on them).
+double lambda_reg_closed(int n, int p, int j) {
+  typedef long double R;
+  const R pi = kPi;
+  R sM = cardinal_t<R>(2 * p + 1, R(0)), sK = cardinal_t<R>(2 * p - 1, R(0));
+  for (int k = 1; k <= p; ++k) {
+    // cos(k j pi / n) with the angle reduced exactly modulo 2 pi
+    const long long a = ((long long)k * j) % (2LL * n);
+    const R c = std::cos(pi * (R)a / (R)n);
+    sM += 2 * cardinal_t<R>(2 * p + 1, (R)k) * c;
+    if (k <= p - 1) sK += 2 * cardinal_t<R>(2 * p - 1, (R)k) * c;
+  }
+  const R s = std::sin(pi * (R)j / (R)(2 * n));
+  return (double)(4 * (R)n * (R)n * s * s * sK / sM);
 }
 
 // Dense LU with partial pivoting; solves A X = B in place (A n x n, B n x k),
@@ -269,6 +297,7 @@ void compute_layout(Plan& P) {
   t.qfd16 = take(f16 ? 2 * mm : 8);
   t.qtfd16 = take(f16 ? 2 * mm : 8);
   t.qs16 = take(8);
+  t.stat64 = take(8);
   t.blob64 = take(8 * (size_t)P.blob_len);
   t.blob32 = take(4 * (size_t)P.blob_len);
   t.total = off;
@@ -351,7 +380,9 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   // resources, whose byte offsets stay below 2^31
   if (P.N * 8 >= (int64_t(1) << 31)) { err = "one right-hand side above 2 GiB in FP64 (m^d >= 2^28)"; return IFFD_E_UNSUPPORTED; }
   if (P.method == IFFD_METHOD_FFT) {
-    if (p < 2) { err = "IFFD needs p >= 2 (p = 1 has no outlier split; use DENSE_FD)"; return IFFD_E_UNSUPPORTED; }
+    // p = 1: S = S^reg (n_out = 0), the preconditioner is the exact inverse
+    // by the DST-I alone (no boundary fold, no outliers)
+    P.first64 = P.prec == IFFD_PREC_F32 && p >= 5;
     // odd p: DST-I through a length-2n FFT of the odd extension; even p:
     // DST-II / DST-III through a length-n FFT of a reordered sequence where
     // the kernels have that length, else through the length-2n extension
@@ -652,7 +683,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
       }
   }
 
-  // --- regular modes: Dt and Lambda_reg (Section 6, eq:Lambda reg2) -------
+  // --- regular modes: Dt (end of Section 6) and Lambda_reg (Lemma 4) -------
   // U_ij = sin(x_i alpha_j), alpha_j = j pi: p odd sin(pi i j / n),
   // p even sin(pi (2i-1) j / (2n)); angles are reduced exactly modulo 2 pi.
   const int nr = P.n_reg;
@@ -660,7 +691,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   std::vector<double> sintab(period);
   for (int k = 0; k < period; ++k) sintab[k] = (double)std::sin(2 * kPi * k / period);
   P.Dt.assign(nr, 0.0);
-  std::vector<double> u(nr), v(m), kv(m), mv(m);
+  std::vector<double> u(nr), v(m), mv(m);
   for (int j = 1; j <= nr; ++j) {
     for (int i = 1; i <= nr; ++i) {
       long long k = (p % 2) ? (long long)i * j : (long long)(2 * i - 1) * j;
@@ -678,12 +709,11 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
       v[m - nbd + r] = b;
     }
     for (int i = half; i < nr - half; ++i) v[i + (p - 1 - half)] = u[i];
-    band_mv(P.Kb, v.data(), kv.data());
     band_mv(P.Mb, v.data(), mv.data());
-    double sk = 0, sm = 0;
-    for (int i = 0; i < m; ++i) { sk += v[i] * kv[i]; sm += v[i] * mv[i]; }
+    double sm = 0;
+    for (int i = 0; i < m; ++i) sm += v[i] * mv[i];
     P.Dt[j - 1] = std::sqrt(sm);
-    P.lam[j - 1] = sk / sm;
+    P.lam[j - 1] = lambda_reg_closed(n, p, j);
     P.s[j - 1] = 1.0 / sm;
   }
 

@@ -21,6 +21,7 @@ struct TableLayout {
   size_t lam32, s32, v0_32, v1_32, vt32, twl32, twp32;
   size_t qfd32, qtfd32, lamfd32;
   size_t qfd16, qtfd16, qs16;  // dense FD in FP16: Q / s_Q, Q^T / s_Q, s_Q (FP32)
+  size_t stat64;  // setup status word written by the outlier setup kernel (0 = ok)
   size_t total;
 };
 
@@ -66,6 +67,11 @@ struct Plan {
 
   int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
   bool half_len = false;  // sine transforms through length-n FFTs (L = n), else L = 2n
+  // FP32 apply: the forward pass along direction 1 (the one that reads the
+  // FP64 input) computes in FP64 and writes FP32, so the input is never
+  // rounded to FP32 before its first transform (set for p >= 5, where the
+  // mass matrices' small eigenvalues amplify that rounding)
+  bool first64 = false;
 
   TableLayout lay{};
   char* d_tables = nullptr;

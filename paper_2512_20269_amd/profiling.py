@@ -82,6 +82,8 @@ def line_pass_name(d: int, prec: str, k: int, L: int, variant: int, n: int, p: i
     template argument is the sine-transform route (length n or 2n, parity)."""
     t = "double" if prec == "f64" else "float"
     tin = "double" if k == 0 else t
+    if k == 0 and p >= 5:
+        t = "double"   # FP32 plans of degree >= 5 take the FP64 input into an FP64 first pass
     tout = "double" if k == 2 * d - 2 else t
     mode = 0 if k < d - 1 else (2 if k == d - 1 else 1)
     route = (3 if p % 2 else 2) if L == n else (0 if p % 2 else 1)
