@@ -6,8 +6,9 @@
 A step is one application z = P^{-1} r of the FFT-based Fast Diagonalization
 preconditioner (forward line transforms along every direction, Kronecker-sum
 scaling, backward transforms) to the workload's right-hand sides, already
-resident in HBM.  Default workload: 3D unit cube, n = 128 elements per
-direction, degree p = 3 (2,146,689 DoFs), FP32 transform arithmetic with FP64
+resident in HBM.  Default workload: 3D unit cube, n = 256 elements per
+direction, degree p = 3 (16,974,593 DoFs, the largest single-GPU
+configuration), smooth right-hand side, FP32 transform arithmetic with FP64
 input and output.
 
 The K timed steps are enqueued back to back behind a device-side spin (so the
@@ -17,11 +18,13 @@ average duration (the roofline figure).  The same apply replayed from a HIP
 graph is timed as well.
 
 Printed as one JSON line: apply throughput (GDoF/s) with the roofline of its
-dominant kernel, PCG solve latency to 1e-8 (FP64 PCG, this apply), the
-dense-FD baseline (apply on the matrix cores and PCG), PCG with both
-preconditioners on a variable-coefficient system matrix (c = 1 + x per
-direction, where neither is exact), and the FP64 CPU oracle timed on the
-host cores on a bounded sample.
+dominant kernel, the same apply in FP64, PCG solve latency to 1e-8 (FP64 PCG,
+this apply), the dense-FD baseline (apply on the matrix cores and PCG), PCG
+with both preconditioners on a variable-coefficient system matrix (c = 1 + x
+per direction, where neither is exact), the serving stream (Poisson arrivals
+of mixed solves at four fractions of saturation), and the FP64 CPU oracle
+timed on the host cores (all cores and one thread), whose result also gives
+the GPU applies' error against the oracle.
 """
 
 from __future__ import annotations
@@ -110,25 +113,41 @@ def pct(xs, q):
 
 def cpu_baseline(d, n, p, r_np, budget_s=12.0):
     """The FP64 oracle (dense O(m^2)-per-line mode products) on the host cores,
-    applied to the first right-hand side."""
-    from threadpoolctl import threadpool_info
+    applied to the first right-hand side: as many repetitions as fit the
+    budget with all cores, then one with a single thread.  Returns the record
+    and the oracle's result (for the GPU applies' error against it)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import iffd as O
-    pre = O.Preconditioner(d, n, p, "iffd_b")
     t0 = time.perf_counter()
-    pre.apply(r_np)
+    pre = O.Preconditioner(d, n, p, "iffd_b")
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    zo = pre.apply(r_np)
     t1 = time.perf_counter() - t0
     reps = max(1, min(20, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    ts = [t1]
+    for _ in range(reps - 1):
+        t0 = time.perf_counter()
         pre.apply(r_np)
-    dt = (time.perf_counter() - t0) / reps
+        ts.append(time.perf_counter() - t0)
+    dt = statistics.median(ts)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pre.apply(r_np)
+        dt1 = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     N = r_np.size
     return {"value": round(N / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{reps} FP64 oracle applies (structured route, dense mode products) "
-                      f"of one {d}D n={n} p={p} right-hand side; {dt * 1e3:.1f} ms per apply; "
-                      f"host nproc={os.cpu_count()}"}
+                      f"of one {d}D n={n} p={p} right-hand side with all threads (median "
+                      f"{dt * 1e3:.1f} ms), then one with a single thread",
+            "ms_per_apply_all_threads": round(dt * 1e3, 2),
+            "ms_per_apply_one_thread": round(dt1 * 1e3, 2),
+            "single_thread_gdof_s": round(N / dt1 / 1e9, 6),
+            "oracle_setup_s": round(t_setup, 2),
+            "host_nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}, zo
 
 
 def time_solves(torch, plan, f, count, rtol=1e-8):
@@ -244,7 +263,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cube_n128_p3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube_n256_p3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--solves", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -426,13 +445,51 @@ def main():
            "graph_gdof_s": round(B * N / (graph_ms * 1e-3) / 1e9, 3),
            "wall_s_timed": round(wall, 4), "roofline": roofline}
 
+    z64 = None
     if not args.no_extras:
+        # ---- the same apply in FP64 arithmetic: throughput and its passes --------
+        if args.precision == "f32":
+            ref = iffd.Plan(d, n, p, method="fft", precision="f64", max_rhs=B)
+            v64 = ref.tune(reps=10)
+            z64 = ref.apply(r)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda._sleep(int(cpm * 5.0))
+            e0.record()
+            for _ in range(args.steps):
+                ref.apply(r, out=z64)
+            e1.record()
+            torch.cuda.synchronize()
+            ms64 = e0.elapsed_time(e1) / args.steps
+            pp64 = []
+            for k in range(npass):
+                a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda._sleep(int(cpm * (2.0 + 0.03 * args.steps)))
+                a_.record()
+                for _ in range(args.steps):
+                    ref.apply_pass(k, r, z64)
+                b_.record()
+                torch.cuda.synchronize()
+                pp64.append(a_.elapsed_time(b_) / args.steps)
+            ref.apply(r, out=z64)
+            pb64 = [B * x for x in pass_bytes(d, N, "f64")]
+            dom64 = max(range(npass), key=lambda k: pp64[k])
+            ach64 = pb64[dom64] / (pp64[dom64] * 1e-3) / 1e9
+            out["apply_f64"] = {
+                "gdof_s": round(B * N / (ms64 * 1e-3) / 1e9, 3), "ms_per_apply": round(ms64, 5),
+                "roofline": {"bound": "hbm", "achieved": round(ach64, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(ach64 / HBM_PEAK_GBS, 4),
+                             "kernel": f"line_pass {names[dom64]}",
+                             "alg_bytes_per_launch": pb64[dom64],
+                             "per_pass_us": {names[k]: round(pp64[k] * 1e3, 2)
+                                             for k in range(npass)},
+                             "apply_alg_GBs": round(sum(pb64) / (ms64 * 1e-3) / 1e9, 1)},
+                "fft_variant_per_pass": v64}
+            del ref
         # ---- accuracy of this apply against the FP64 apply -----------------------
-        ref = iffd.Plan(d, n, p, method="fft", precision="f64", max_rhs=B)
-        z64 = ref.apply(r)
         plan.apply(r, out=z)
-        out["apply_relerr_vs_f64"] = float((z - z64).norm() / z64.norm())
-        del ref, z64
+        if z64 is not None:
+            out["apply_relerr_vs_f64"] = float((z - z64).norm() / z64.norm())
         f = r[0] if B > 1 else r
         # ---- PCG solves to 1e-8 (FP64 PCG, this apply) ---------------------------
         lat, st = time_solves(torch, plan, f, args.solves)
@@ -517,9 +574,9 @@ def main():
             torch.cuda.synchronize()
             hms = a.elapsed_time(b) / reps
             ref = iffd.Plan(d, n, p, method="dense", precision="f64", max_rhs=B)
-            z64 = ref.apply(r)
-            herr = float((zh - z64).norm() / z64.norm())
-            del ref, z64
+            zd64 = ref.apply(r)
+            herr = float((zh - zd64).norm() / zd64.norm())
+            del ref, zd64
             hlat, hst = time_solves(torch, fh, f, max(5, args.solves // 3))
             htf = flops / (hms * 1e-3) / 1e12
             out["dense_fd_f16s"] = {
@@ -554,7 +611,8 @@ def main():
                              "p99_ms": round(pct(cflat, 0.99), 3),
                              "iterations": cfst[0]["iterations"]},
                 "iffd_solve_speedup": round(statistics.mean(cflat) / statistics.mean(clat), 3)}
-            out["serving"] = serving(torch, 200, 60, [0.5, 0.9])
+            out["serving"] = serving(torch, args.serve_requests, args.serve_warmup,
+                                     [float(x) for x in args.serve_fracs.split(",")])
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -564,7 +622,19 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": nel * 8, "write": nel * 8}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, n, p, r_np[0] if B > 1 else r_np)
+        r0 = r_np[0] if B > 1 else r_np
+        out["cpu_baseline"], zo = cpu_baseline(d, n, p, r0)
+        # the GPU applies against the oracle's result for the same input
+        import numpy as np
+        plan.apply(r, out=z)
+        zs = {args.precision: (z[0] if B > 1 else z).cpu().numpy()}
+        if z64 is not None:
+            zs["f64"] = (z64[0] if B > 1 else z64).cpu().numpy()
+        out["apply_error_vs_oracle"] = {
+            k: {"rel_2norm": float(np.linalg.norm(v - zo) / np.linalg.norm(zo)),
+                "rel_maxnorm": float(np.abs(v - zo).max() / np.abs(zo).max())}
+            for k, v in zs.items()}
+        out["apply_error_vs_oracle"]["tolerance"] = {"f32": 1e-5, "f64": 1e-12}
     print(json.dumps(out), flush=True)
 
 
