@@ -268,6 +268,7 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     std::vector<double> blob((size_t)P.blob_len, 0.0);
     std::copy(P.twl.begin(), P.twl.end(), blob.begin() + P.bo_twl);
     std::copy(P.twp.begin(), P.twp.end(), blob.begin() + P.bo_twp);
+    std::copy(P.sn.begin(), P.sn.end(), blob.begin() + P.bo_sn);
     std::copy(P.Vt.begin(), P.Vt.end(), blob.begin() + P.bo_vt);
     std::copy(P.V0.begin(), P.V0.end(), blob.begin() + P.bo_v0);
     std::copy(P.V1.begin(), P.V1.end(), blob.begin() + P.bo_v1);

@@ -49,15 +49,18 @@ enum { PK_ODD = 0, PK_EVEN_2N = 1, PK_EVEN_N = 2, PK_ODD_N = 3 };
 
 template <typename T>
 struct Tabs {
-  const T* blob;  // twl | twp | Vt | V0 | V1 | lam | s, element offsets below
+  const T* blob;  // twl | Vt | V0 | V1 | sn | twp | lam | s, element offsets below
   int o_twl, o_twp, o_vt, o_v0, o_v1, o_lam, o_s, len;
+  int o_sn;
   int nch;  // 16-byte chunks covering the staged prefix (the blob is padded)
 };
 
 struct Geom {
   int m, n, p, n_reg, n_out, half, nbd, c0;
   int S;       // element stride along the axis
-  int lpr;     // lines per right-hand side
+  int lpr;     // lines per right-hand side (padded line space for S > 1, see line_at)
+  int mr;      // S > 1: lines per row of the padded line space (m, or m + 1 for odd m)
+  int sm;      // S > 1: S / m
   int tpr;     // tiles per right-hand side
   int N;       // elements per right-hand side
   int d;
@@ -133,6 +136,25 @@ __device__ __forceinline__ void to_lds(T* dst, const T* src, int count, int t, i
 template <int V>
 constexpr int ilog2() { return V <= 1 ? 0 : 1 + ilog2<V / 2>(); }
 
+// Line q of a pass along a strided direction (S > 1).  Its lines are indexed
+// by (outer, i2, a): a the index along direction 1 (fastest), i2 along the
+// directions between 1 and the pass's own, outer along the slower ones.  The
+// line space is padded so that every run of lines with the same (outer, i2)
+// has an even length mr (a dummy line a = m when m is odd): the two lines of
+// an FFT pair (2f, 2f+1) then never straddle two runs.  A straddling pair
+// would share one complex FFT between the last line of a run (for a spectral
+// direction 1 an outlier coefficient, often near zero) and the first line of
+// the next (the smoothest mode, the largest), and FP32 rounding of the large
+// line would leak into the small one.  Returns whether q is a real line; base
+// is its first entry, inner its index in [0, S).
+__device__ __forceinline__ bool line_at(const Geom& g, int q, int& base, int& inner) {
+  const int a = q % g.mr, rest = q / g.mr;
+  const int i2 = rest % g.sm, outer = rest / g.sm;
+  inner = i2 * g.m + a;
+  base = outer * g.m * g.S + inner;
+  return a < g.m;
+}
+
 // Tile layout in LDS: row l of X holds line l (m entries, row stride MP).
 // The folded sequence g = V_reg^T x (n_reg entries) is kept in place at
 // X[l][c0 + idx], c0 = p-1-floor(p/2): interior entries of x already sit
@@ -174,6 +196,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   T* BL = reinterpret_cast<T*>(smem + mp.blob);
   cpx<T>* twl = reinterpret_cast<cpx<T>*>(BL + tb.o_twl);
   cpx<T>* twp = reinterpret_cast<cpx<T>*>(BL + tb.o_twp);
+  const T* SN = BL + tb.o_sn;   // sin(pi h / n): contiguous, so the pre-twist reads hit distinct banks
   T* GB = reinterpret_cast<T*>(smem + mp.g);  // per-line boundary values
   T* CO = reinterpret_cast<T*>(smem + mp.co);
   T* LO = reinterpret_cast<T*>(smem + mp.lo);
@@ -206,8 +229,9 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   if constexpr (NTH % TW != 0) {   // line bases for the generic strided path
     if (S > 1)
       for (int l = t; l < TW; l += NTH) {
-        const int ql = q0 + l;
-        LB[l] = (l < nv) ? rhs * g.N + (ql / S) * m * S + (ql % S) : 0;
+        int base, inner;
+        const bool real = line_at(g, q0 + l, base, inner);
+        LB[l] = (l < nv && real) ? rhs * g.N + base : -1;
       }
   }
   // issue the table loads (16-byte chunks) now; they land in LDS after the
@@ -278,10 +302,10 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
     // (rows of the tile are runs of TW consecutive entries of the tensor)
     constexpr int JS = NTH / TW;
     const int l = t & (TW - 1), j0 = t >> LTW;
-    const int q = q0 + l;
+    int base, inner;
+    const bool real = line_at(g, q0 + l, base, inner) && l < nv;
     const auto rs = buf_rsrc(in + (size_t)rhs * g.N, (unsigned)(g.N * (int)sizeof(Tin)));
-    const unsigned vo = l < nv ? (unsigned)((q / S) * m * S + (q % S) + j0 * S) * sizeof(Tin)
-                               : BUF_OOB;
+    const unsigned vo = real ? (unsigned)(base + j0 * S) * sizeof(Tin) : BUF_OOB;
     T* dst = X + l * MP + j0;
     const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
     const int step = JS * S * (int)sizeof(Tin);
@@ -303,7 +327,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       for (int u = 0; u < CH; ++u) {
         const int e = e0 + u * NTH;
         const int l = e & (TW - 1), j = e >> LTW;
-        v[u] = (e < cnt && l < nv) ? in[LB[l] + j * S] : Tin(0);
+        v[u] = (e < cnt && l < nv && LB[l] >= 0) ? in[LB[l] + j * S] : Tin(0);
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -344,8 +368,8 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
     // read after the next barrier, by the forward transform's output stage
     for (int l = t; l < TW; l += NTH) {
       T lo = T(0), so = T(1);
-      if (l < nv) {
-        const int i = (q0 + l) % S;
+      int base, i;
+      if (l < nv && line_at(g, q0 + l, base, i)) {
         const int j1 = i % m, j2 = i / m;
         lo = LAM[j1];
         so = SS[j1];
@@ -393,7 +417,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       const T va = sa[jj - 1], vb = sb[jj - 1];
       const T wa = sa[N - jj - 1], wb = sb[N - jj - 1];
       const int h = jj <= N / 2 ? jj : N - jj;
-      const T sj = -twp[2 * h].y;
+      const T sj = SN[h];
       const T ya = sj * (va + wa) + T(0.5) * (va - wa);
       const T yb = sj * (vb + wb) + T(0.5) * (vb - wb);
       return j0 ? cpx<T>{T(0), T(0)} : cpx<T>{ya, yb};
@@ -740,12 +764,13 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   } else if constexpr (NTH % TW == 0) {
     constexpr int JS = NTH / TW;
     const int l = t & (TW - 1), j0 = t >> LTW;
-    const int q = q0 + l;
-    if (l < nv && j0 < m) {
+    int base, inner;
+    const bool real = line_at(g, q0 + l, base, inner);
+    if (l < nv && real && j0 < m) {
       T co[MAXO];
       load_co(l, co);
       const auto rs = buf_rsrc(out + (size_t)rhs * g.N, (unsigned)(g.N * (int)sizeof(Tout)));
-      const unsigned vo = (unsigned)((q / S) * m * S + (q % S) + j0 * S) * sizeof(Tout);
+      const unsigned vo = (unsigned)(base + j0 * S) * sizeof(Tout);
       const int cnt = (m - j0 + JS - 1) / JS;
       const int step = JS * S * (int)sizeof(Tout);
       for (int k = 0; k < cnt; ++k)
@@ -758,7 +783,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       for (int u = 0; u < CH; ++u) {
         const int e = e0 + u * NTH;
         const int l = e & (TW - 1), j = e >> LTW;
-        if (e < cnt && l < nv) {
+        if (e < cnt && l < nv && LB[l] >= 0) {
           T co[MAXO];
           load_co(l, co);
           out[LB[l] + j * S] = (Tout)value(l, j, co);
@@ -785,9 +810,11 @@ line_pass_upd(const Tin* __restrict__ in, Tout* __restrict__ out, Geom g, Tabs<T
 template <typename T>
 static Tabs<T> tables_of(const Plan& P, int mode) {
   const char* b = P.d_tables + (sizeof(T) == 8 ? P.lay.blob64 : P.lay.blob32);
-  const int len = mode == PASS_MID ? P.blob_len : (((P.p & 1) && !P.half_len) ? P.bo_twp : P.bo_lam);
+  const int len = mode == PASS_MID ? P.blob_len
+                                    : ((P.p & 1) ? (P.half_len ? P.bo_twp : P.bo_sn) : P.bo_lam);
   const int nch = (int)((len * sizeof(T) + 15) / 16);
-  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len, nch};
+  return {(const T*)b, P.bo_twl, P.bo_twp, P.bo_vt, P.bo_v0, P.bo_v1, P.bo_lam, P.bo_s, len, P.bo_sn,
+          nch};
 }
 
 template <typename Tin, typename Tout, typename T, int MODE, int L, int V, int PK>
@@ -802,6 +829,12 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.S = S;
   g.N = (int)P.N;
   g.lpr = (int)(P.N / P.m);
+  g.mr = P.m;
+  g.sm = S > 1 ? S / P.m : 1;
+  if (S > 1 && (P.m & 1)) {   // pad every run of lines to an even length (see line_at)
+    g.mr = P.m + 1;
+    g.lpr = (int)(P.N / P.m / P.m) * g.mr;
+  }
   g.tpr = (g.lpr + C::TW - 1) / C::TW;
   g.d = P.d;
   g.active = active;

@@ -245,12 +245,14 @@ void compute_layout(Plan& P) {
   {
     const int nbh = (P.p - 1) * P.half;
     int o = 0;
-    // ordered by use: every pass reads twl, Vt, V0, V1; even p also twp; only
-    // the middle pass reads lam and s (a pass stages just its prefix in LDS)
+    // ordered by use: every pass reads twl, Vt, V0, V1; odd p through
+    // length-n FFTs also sn, even p twp; only the middle pass reads lam and s
+    // (a pass stages just its prefix in LDS)
     P.bo_twl = o; o += 2 * std::max(P.L, 1);
     P.bo_vt = o;  o += P.n_out * P.m;
     P.bo_v0 = o;  o += nbh;
     P.bo_v1 = o;  o += nbh;
+    P.bo_sn = o;  o += P.n / 2 + 1;
     o += o & 1;
     P.bo_twp = o; o += 2 * (P.n + 1);
     P.bo_lam = o; o += P.m;
@@ -723,6 +725,8 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     P.twl[2 * k] = (double)std::cos(2 * kPi * k / P.L);
     P.twl[2 * k + 1] = (double)-std::sin(2 * kPi * k / P.L);
   }
+  P.sn.assign((size_t)n / 2 + 1, 0.0);
+  for (int h = 0; h <= n / 2; ++h) P.sn[h] = (double)std::sin(kPi * h / n);
   P.twp.assign((size_t)2 * (n + 1), 0.0);
   for (int j = 0; j <= n; ++j) {
     P.twp[2 * j] = (double)std::cos(kPi * j / (2 * n));

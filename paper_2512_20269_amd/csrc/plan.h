@@ -61,9 +61,12 @@ struct Plan {
   std::vector<double> Qfd, lamfd;   // dense FD: m x m (column j = eigvec j)
   std::vector<double> Kc, Mc;       // compact band tables (crows x (2p+1))
   int nbr = 0, crows = 0;
+  std::vector<double> sn;           // sin(pi h / n), h = 0..n/2 (odd-p pre-twist)
   // element offsets of the line-pass tables inside one contiguous blob:
-  // twl (2L) | Vt (n_out m) | V0 | V1 ((p-1) floor(p/2) each) | twp (2(n+1)) | lam (m) | s (m)
+  // twl (2L) | Vt (n_out m) | V0 | V1 ((p-1) floor(p/2) each) | sn (n/2+1) |
+  // twp (2(n+1)) | lam (m) | s (m)
   int bo_twl = 0, bo_twp = 0, bo_vt = 0, bo_v0 = 0, bo_v1 = 0, bo_lam = 0, bo_s = 0, blob_len = 0;
+  int bo_sn = 0;
 
   int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
   bool half_len = false;  // sine transforms through length-n FFTs (L = n), else L = 2n
