@@ -204,6 +204,23 @@ int iffd_pcg_solve(const iffd_plan* plan, const double* d_f, double* d_u, int nr
                    double rtol, int maxit, int check_every, iffd_pcg_stats* h_stats,
                    void* d_ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free form of iffd_precond_apply, for callers that cannot
+ * allocate or pass device memory of their own (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same kernels
+ * and the same result, bit for bit, with the apply's workspace taken from a
+ * device array inside the library of IFFD_NOALLOC_SCRATCH_BYTES bytes (one
+ * per device, held until the process ends).  The caller passes only r and z
+ * (same layout and rules as iffd_precond_apply).  Returns IFFD_E_WORKSPACE
+ * when the call needs more workspace than that (apply_ws_bytes scaled to
+ * nrhs: 4 N nrhs bytes for the FP32 IFFD apply, none for the FP64 one,
+ * 8 N nrhs for dense FD in FP32, 10 N nrhs + 4 N nrhs / m in FP16).  It calls
+ * no allocating routine.  Calls on one device share its array: calls that
+ * overlap on one device (other streams, other host threads) race and must be
+ * serialized by the caller. */
+#define IFFD_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int iffd_precond_apply_noalloc(const iffd_plan* plan, const double* d_r, double* d_z, int nrhs,
+                               void* stream);
+
 /* One pass of iffd_precond_apply (IFFD only), for per-kernel timing: the
  * apply is the sequence pass = 0 .. iffd_apply_pass_count()-1, where pass k
  * < d-1 is the forward line transform along direction k+1, pass d-1 the fused

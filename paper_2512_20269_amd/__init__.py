@@ -27,6 +27,7 @@ OK, W_NOT_CONVERGED = 0, 1
 E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
 PREC_F64, PREC_F32, PREC_F16S = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
 
@@ -68,6 +69,7 @@ SIGNATURES = {
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
     "iffd_precond_apply": (_I, [_P, _P, _P, _I, _P, _Z, _P]),
+    "iffd_precond_apply_noalloc": (_I, [_P, _P, _P, _I, _P]),
     "iffd_kron_matvec": (_I, [_P, _P, _P, _I, _P, _Z, _P]),
     "iffd_apply_pass_count": (_I, [_P]),
     "iffd_plan_set_variant": (_I, [_P, _I, _I]),
@@ -218,6 +220,17 @@ class Plan:
         _need(z, self.shape, torch.float64, "out")
         _check(lib.iffd_precond_apply(self._h, _ptr(r), _ptr(z), nrhs, _ptr(self._ws),
                                       self._ws.numel(), _stream(stream)), "precond_apply")
+        return z
+
+    def apply_noalloc(self, r, out=None, stream=None):
+        """z = P^{-1} r through iffd_precond_apply_noalloc: no workspace
+        argument, the library's per-device scratch array serves instead."""
+        torch = _torch()
+        nrhs = self._batch(r, "r")
+        z = out if out is not None else torch.empty_like(r)
+        _need(z, self.shape, torch.float64, "out")
+        _check(lib.iffd_precond_apply_noalloc(self._h, _ptr(r), _ptr(z), nrhs, _stream(stream)),
+               "precond_apply_noalloc")
         return z
 
     def set_variant(self, k: int, v: int):

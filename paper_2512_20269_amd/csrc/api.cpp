@@ -25,9 +25,6 @@ hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out
 
 using namespace iffd;
 
-struct iffd_plan {
-  Plan P;
-};
 
 namespace {
 
@@ -115,6 +112,10 @@ void put(std::vector<char>& buf, size_t off, const std::vector<double>& v) {
 }
 
 }  // namespace
+
+namespace iffd {
+int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace iffd
 
 extern "C" {
 

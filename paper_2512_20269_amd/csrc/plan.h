@@ -95,4 +95,12 @@ size_t matvec_ws_bytes(const Plan& P, int nrhs);
 // whether an FFT length is supported by the built kernels
 bool fft_len_supported(int L);
 
+// records the thread-local message of iffd_last_error() and returns code
+int set_last_error(int code, const std::string& msg);
+
 }  // namespace iffd
+
+// the opaque handle of the C ABI
+struct iffd_plan {
+  iffd::Plan P;
+};

@@ -235,3 +235,17 @@ def test_stepped_pcg_slot_counts_checked_on_the_host():
     assert I.lib.iffd_pcg_status(h, fake, 4, fake, None) == I.E_STATE
     assert I.lib.iffd_pcg_poll(h, fake, 4, optr, None) == I.E_STATE
     I.lib.iffd_plan_destroy(h)
+
+
+def test_noalloc_scratch_limit_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define IFFD_NOALLOC_SCRATCH_BYTES \((\d+)u \* 1024u \* 1024u\)", text)
+    assert m and int(m.group(1)) * 1024 * 1024 == I.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_validates_before_any_launch():
+    rc, h = host_plan(2, 16, 3)
+    fake = ctypes.c_void_p(256)
+    assert I.lib.iffd_precond_apply_noalloc(None, fake, fake, 1, None) == I.E_INVAL
+    assert I.lib.iffd_precond_apply_noalloc(h, fake, ctypes.c_void_p(512), 1, None) == I.E_STATE
+    I.lib.iffd_plan_destroy(h)
