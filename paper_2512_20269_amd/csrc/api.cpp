@@ -264,6 +264,27 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     for (int k = P.n_reg; k < P.m; ++k) P.lam[k] = lam[k];
     P.Vt = vt;
   }
+  // outlier windows: the entries of the rotated outlier basis decay
+  // geometrically away from the two ends; entries below 2^-30 (FP32 apply) or
+  // 2^-60 (FP64 apply) of the largest contribute below the working precision
+  // to the dots and the rank-n_out update, so only the two end windows are used
+  for (int w = 0; w < 2; ++w) {
+    int* win = w == 0 ? P.win32 : P.win64;
+    win[0] = P.m;
+    win[1] = P.m;
+    if (P.method != IFFD_METHOD_FFT || P.n_out == 0) continue;
+    const double thr = std::ldexp(1.0, w == 0 ? -30 : -60);
+    double mx = 0.0;
+    for (double v : P.Vt) mx = std::max(mx, std::fabs(v));
+    int lo = 0, hi = P.m;   // left window [0, lo), right window [hi, m)
+    for (int j = 0; j < P.m; ++j)
+      for (int q = 0; q < P.n_out; ++q)
+        if (std::fabs(P.Vt[(size_t)q * P.m + j]) > thr * mx) {
+          if (j < P.m / 2) lo = std::max(lo, j + 1);
+          else hi = std::min(hi, j);
+        }
+    if (lo < hi) { win[0] = lo; win[1] = hi; }
+  }
   if (P.method == IFFD_METHOD_FFT) {
     // the line-pass tables as one contiguous blob (one load sweep per block)
     std::vector<double> blob((size_t)P.blob_len, 0.0);

@@ -65,6 +65,10 @@ struct Geom {
   int N;       // elements per right-hand side
   int d;
   int tpd_log;  // log2 of the threads per outlier dot
+  int wl, wr;   // outlier rows Vt[q][j] are used for j < wl and j >= wr only: beyond
+                // these windows at the two ends every entry is below the working
+                // precision relative to the largest (the outlier basis decays
+                // geometrically away from the ends)
   const double* dr;  // fused dr . out partials (backward pass along direction 1), or null
   const double* fq;  // fused in <- in - alpha q (forward pass along direction 1), or null
   const double* falpha;
@@ -92,7 +96,7 @@ struct Cfg {
 __host__ __device__ inline size_t up16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct LdsMap {
-  size_t x, blob, g, co, lo, so, lb, dm, total;
+  size_t x, blob, g, co, lo, so, lb, dm, pd, total;
 };
 
 template <typename T, int L, int V>
@@ -111,6 +115,8 @@ __host__ __device__ inline LdsMap lds_map(int m, int n, int n_out, int half, int
   r.so = off;  off = up16(off + sizeof(T) * C::TW);
   r.lb = off;  off = up16(off + sizeof(int) * C::TW);
   r.dm = off;  off = up16(off + sizeof(T) * 2 * C::NTH);
+  // per-wave partial outlier dots of the strided tiles: [waves][n_out][TW]
+  r.pd = off;  off = up16(off + sizeof(T) * ((C::NTH + 63) / 64) * (n_out > 0 ? n_out : 1) * C::TW);
   r.total = off;
   return r;
 }
@@ -224,6 +230,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   const int S = g.S;
   const int c0 = g.c0;
   constexpr bool odd = PK == PK_ODD || PK == PK_ODD_N;
+  constexpr int MAXO = 6;   // n_out <= 6 (p <= 8)
 
   // ---- tables, twiddles and per-line data into LDS ---------------------------
   if constexpr (NTH % TW != 0) {   // line bases for the generic strided path
@@ -405,8 +412,9 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   // F_2k+1 = F_2k-1 + A_k with F_-1 = -F_1, i.e. F_2k+1 = A_0 + .. + A_k - A_0/2
   // (the sine part of y is odd about n/2 and the difference part even, and
   // 2 sin(pi j/n) cos(2 pi jk/n) = sin(pi j(2k+1)/n) - sin(pi j(2k-1)/n)).
-  // The two lines go in as y_a + i y_b; each thread then takes E/2
-  // consecutive k, the prefix sums of A run through the pair's NT lanes.
+  // The two lines go in as y_a + i y_b; thread tid of the pair then takes
+  // k = tid + NT c, and the prefix sums of A run as cross-lane scans over the
+  // pair's NT lanes, block by block.
   // Input v_j at sa/sb[j-1], output F_k at da/db[k-1] (times the Kronecker-sum
   // factor when SCALE).
   auto dst1n = [&](const T* sa, const T* sb, T* da, T* db, auto scale_tag) {
@@ -425,60 +433,105 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
     auto sto = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
     fft_forward<T, L, V>(buf, tid, twl, ldo, sto);
     __syncthreads();
-    constexpr int CK = N / (2 * NT);   // k values per thread (E / 2)
-    const int k0 = tid * CK;
-    T ea[CK], eb[CK], oa[CK], ob[CK];  // F_2k and running sums of A
-    T pa = T(0), pb = T(0), a0a = T(0), a0b = T(0);
+    // thread tid takes k = tid + NT c (c < CK): the reads of W_k and W_{n-k}
+    // and the writes below run over consecutive k across lanes; the prefix
+    // sums of A run as a cross-lane scan per block of NT values plus the
+    // running total of the blocks before
+    constexpr int CK = N / (2 * NT);
+    T fo_a[CK], fo_b[CK], fe_a[CK], fe_b[CK];   // F_2k+1 and F_2k of both lines
+    T carry_a = T(0), carry_b = T(0), a0a = T(0), a0b = T(0);
 #pragma unroll
     for (int c = 0; c < CK; ++c) {
-      const int k = k0 + c;
+      const int k = tid + NT * c;
       const cpx<T> wk = buf[fpad<L>(k)], wm = buf[fpad<L>(k == 0 ? 0 : N - k)];
       // line a: (W_k + conj W_{n-k}) / 2, line b: -i (W_k - conj W_{n-k}) / 2
       const T aa = T(0.5) * (wk.x + wm.x), ab = T(0.5) * (wk.y + wm.y);
-      ea[c] = T(0.5) * (wm.y - wk.y);
-      eb[c] = T(0.5) * (wk.x - wm.x);
-      pa += aa;
-      pb += ab;
-      oa[c] = pa;
-      ob[c] = pb;
-      if (c == 0) { a0a = aa; a0b = ab; }
+      fe_a[c] = T(0.5) * (wm.y - wk.y);
+      fe_b[c] = T(0.5) * (wk.x - wm.x);
+      if (c == 0) {   // A_0 from the group's first lane
+        a0a = __shfl(aa, 0, NT);
+        a0b = __shfl(ab, 0, NT);
+      }
+      const T sa = group_inclusive_scan<NT>(aa, tid), sb = group_inclusive_scan<NT>(ab, tid);
+      fo_a[c] = carry_a + sa;
+      fo_b[c] = carry_b + sb;
+      if (c + 1 < CK) {
+        carry_a += __shfl(sa, NT - 1, NT);
+        carry_b += __shfl(sb, NT - 1, NT);
+      }
     }
-    // exclusive prefix of the block sums over the pair's lanes, and A_0
-    T ta = pa, tb = pb;
-#pragma unroll
-    for (int dd = 1; dd < NT; dd <<= 1) {
-      const T ua = __shfl_up(ta, dd, NT), ub = __shfl_up(tb, dd, NT);
-      if (tid >= dd) { ta += ua; tb += ub; }
-    }
-    const T offa = (ta - pa) - T(0.5) * __shfl(a0a, 0, NT);
-    const T offb = (tb - pb) - T(0.5) * __shfl(a0b, 0, NT);
     __syncthreads();   // every W is read before the rows (aliasing the regions) are written
+    // one write instruction covers the odd coefficient of half the lanes and
+    // the even one of the other half (positions 2k and 2k - 1), so a group's
+    // lanes hit distinct banks
+    const bool hi16 = (tid & 16) != 0;
 #pragma unroll
     for (int c = 0; c < CK; ++c) {
-      const int k = k0 + c;
-      T fa = oa[c] + offa, fb = ob[c] + offb;   // F_2k+1 at position 2k
-      if constexpr (SCALE) { fa *= fac(la, 2 * k); fb *= fac(lb, 2 * k); }
-      da[2 * k] = fa;
-      db[2 * k] = fb;
-      if (k >= 1) {                              // F_2k at position 2k-1
-        T ga = ea[c], gb = eb[c];
-        if constexpr (SCALE) { ga *= fac(la, 2 * k - 1); gb *= fac(lb, 2 * k - 1); }
-        da[2 * k - 1] = ga;
-        db[2 * k - 1] = gb;
+      const int k = tid + NT * c;
+      T fa = fo_a[c] - T(0.5) * a0a, fb = fo_b[c] - T(0.5) * a0b;   // F_2k+1, position 2k
+      T ga = fe_a[c], gb = fe_b[c];                                   // F_2k, position 2k-1
+      if constexpr (SCALE) {
+        fa *= fac(la, 2 * k); fb *= fac(lb, 2 * k);
+        if (k >= 1) { ga *= fac(la, 2 * k - 1); gb *= fac(lb, 2 * k - 1); }
+      }
+      const bool ev = k >= 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool odd_now = (h == 0) != hi16;
+        const int pos = odd_now ? 2 * k : 2 * k - 1;
+        const bool ok = odd_now || ev;
+        *(ok ? da + pos : dmy) = odd_now ? fa : ga;
+        *(ok ? db + pos : dmy + 1) = odd_now ? fb : gb;
       }
     }
   };
 
   if (MODE == PASS_FWD || MODE == PASS_MID) {
     // ---- outlier dots; boundary fold into the g slots ----------------------
-    if (n_out > 0) {
+    // strided tiles (S > 1): each thread forms partial dots over the rows it
+    // loaded (rows j0 + k JS of line l) inside the two windows; the partials
+    // of the lanes that share a line are summed by shuffles within each wave
+    // and across waves after the next barrier, in a fixed order
+    constexpr bool REGDOT = NTH % TW == 0;
+    const bool regdot = REGDOT && S > 1 && n_out > 0;
+    T* PD = reinterpret_cast<T*>(smem + mp.pd);
+    if (regdot) {
+      constexpr int JS = REGDOT ? NTH / TW : 1;
+      const int l = t & (TW - 1), j0 = t >> LTW;
+      const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
+      const int kl = min(cnt, j0 < g.wl ? (g.wl - 1 - j0) / JS + 1 : 0);
+      const int kr = max(kl, g.wr <= j0 ? 0 : (g.wr - j0 + JS - 1) / JS);
+      T acc[MAXO];
+#pragma unroll
+      for (int q = 0; q < MAXO; ++q) acc[q] = T(0);
+      auto row = [&](int k) {
+        const int j = j0 + k * JS;
+        const T x = X[l * MP + j];
+#pragma unroll
+        for (int q = 0; q < MAXO; ++q)
+          if (q < n_out) acc[q] += VT[q * m + j] * x;
+      };
+      for (int k = 0; k < kl; ++k) row(k);
+      for (int k = kr; k < cnt; ++k) row(k);
+      constexpr int WL = NTH < 64 ? NTH : 64;   // lanes of a wave
+#pragma unroll
+      for (int q = 0; q < MAXO; ++q) {
+        if (q < n_out) {
+          T a = acc[q];
+          for (int o = TW; o < WL; o <<= 1) a += __shfl_xor(a, o);
+          if ((t & 63) < TW) PD[((t >> 6) * n_out + q) * TW + l] = a;
+        }
+      }
+    } else if (n_out > 0) {
       // 1 << tl threads per dot (chosen on the host), every thread runs the
-      // same number of rounds so the shuffles see all lanes
+      // same number of rounds so the shuffles see all lanes; the dot runs over
+      // the window entries u < nw, entry j = u (left) or u - wl + wr (right)
       const int tl = g.tpd_log, tpd = 1 << tl;
       const int ndots = TW * n_out;
       const int per = NTH >> tl;
       const int rounds = (ndots + per - 1) / per;
       const int sub = t & (tpd - 1);
+      const int wl = g.wl, nw = g.wl + (m - g.wr), sh = g.wr - g.wl;
       for (int rd = 0; rd < rounds; ++rd) {
         const int di = (t >> tl) + rd * per;
         T acc = T(0);
@@ -488,14 +541,19 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
           const T* xr = X + l * MP;
           // four independent partial sums keep several LDS reads in flight
           T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-          int j = sub;
-          for (; j + 3 * tpd < m; j += 4 * tpd) {
-            a0 += vr[j] * xr[j];
-            a1 += vr[j + tpd] * xr[j + tpd];
-            a2 += vr[j + 2 * tpd] * xr[j + 2 * tpd];
-            a3 += vr[j + 3 * tpd] * xr[j + 3 * tpd];
+          int u = sub;
+          auto jx = [&](int uu) { return uu < wl ? uu : uu + sh; };
+          for (; u + 3 * tpd < nw; u += 4 * tpd) {
+            const int j_0 = jx(u), j_1 = jx(u + tpd), j_2 = jx(u + 2 * tpd), j_3 = jx(u + 3 * tpd);
+            a0 += vr[j_0] * xr[j_0];
+            a1 += vr[j_1] * xr[j_1];
+            a2 += vr[j_2] * xr[j_2];
+            a3 += vr[j_3] * xr[j_3];
           }
-          for (; j < m; j += tpd) a0 += vr[j] * xr[j];
+          for (; u < nw; u += tpd) {
+            const int j_0 = jx(u);
+            a0 += vr[j_0] * xr[j_0];
+          }
           acc = (a0 + a1) + (a2 + a3);
         }
         for (int o = 1; o < tpd; o <<= 1) acc += __shfl_xor(acc, o);
@@ -518,11 +576,22 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       const int pos = c < half ? c0 + c : m - nbd + (c - half);
       X[l * MP + pos] = GB[l * GW + c];
     }
-    if (MODE == PASS_MID)   // the outlier coefficients take the same scaling
+    if (regdot) {   // the strided tiles' partial dots, summed wave by wave
+      constexpr int NWV = (NTH + 63) / 64;
+      for (int e = t; e < TW * n_out; e += NTH) {
+        const int l = e & (TW - 1), q = e >> LTW;
+        T sum = T(0);
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) sum += PD[(w * n_out + q) * TW + l];
+        if (MODE == PASS_MID) sum *= fac(l, n_reg + q);   // the outliers take the same scaling
+        CO[l * n_out + q] = sum;
+      }
+    } else if (MODE == PASS_MID) {   // the outlier coefficients take the same scaling
       for (int e = t; e < TW * n_out; e += NTH) {
         const int l = e & (TW - 1), q = e >> LTW;
         CO[l * n_out + q] *= fac(l, n_reg + q);
       }
+    }
     __syncthreads();
 
     // ---- forward transform: X[l][0..n_reg) = U^T g_l (scaled in the middle) --
@@ -706,15 +775,14 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
   }
 
   // ---- store: the tile row, plus the outlier block after the backward pass --
-  // n_out <= 6 (p <= 8); a line's outlier coefficients are held in registers
-  constexpr int MAXO = 6;
+  // a line's outlier coefficients are held in registers (n_out <= MAXO)
   auto load_co = [&](int l, T* co) {
 #pragma unroll
     for (int q = 0; q < MAXO; ++q) co[q] = (MODE != PASS_FWD && q < n_out) ? CO[l * n_out + q] : T(0);
   };
   auto value = [&](int l, int j, const T* co) -> T {
     T v = X[l * MP + j];
-    if (MODE != PASS_FWD) {
+    if (MODE != PASS_FWD && (j < g.wl || j >= g.wr)) {
 #pragma unroll
       for (int q = 0; q < MAXO; ++q)
         if (q < n_out) v += VT[q * m + j] * co[q];
@@ -839,6 +907,8 @@ static hipError_t launch_t(const Plan& P, int axis, const void* in, void* out, i
   g.d = P.d;
   g.active = active;
   g.active_stride = astride;
+  g.wl = sizeof(T) == 8 ? P.win64[0] : P.win32[0];
+  g.wr = sizeof(T) == 8 ? P.win64[1] : P.win32[1];
   g.dr = nullptr;
   g.fq = nullptr;
   g.falpha = nullptr;

@@ -163,6 +163,43 @@ template <int L> struct FftPlan<L, 4> : FftPlan<L, 3> {};
 // (a transform then spans at most one wave, which the DST-I prefix sums need)
 template <int L> constexpr bool fft_has_v3() { return (L & (L - 1)) == 0 && L >= 16 && L <= 256; }
 
+// ---- cross-lane prefix sums over the NT lanes of one transform -------------
+// Lane index mod NT is the position in the transform's group of threads.
+// Groups of 16, 32 or 64 lanes use DPP row shifts (row_shr:1,2,4,8 within
+// each row of 16 lanes, then row_bcast:15 / row_bcast:31 to carry row totals
+// into the following rows): VALU work only, no LDS traffic.  Smaller groups
+// use shuffles bounded to the group.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                              ROWMASK, 0xF, true));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int NT, typename T>
+__device__ __forceinline__ T group_inclusive_scan(T x, int tid) {
+  if constexpr (NT >= 16) {
+    x += dpp_f<0x111, 0xF>(x);   // row_shr:1
+    x += dpp_f<0x112, 0xF>(x);   // row_shr:2
+    x += dpp_f<0x114, 0xF>(x);   // row_shr:4
+    x += dpp_f<0x118, 0xF>(x);   // row_shr:8
+    if constexpr (NT >= 32) x += dpp_f<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
+    if constexpr (NT >= 64) x += dpp_f<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
+  } else {
+#pragma unroll
+    for (int dd = 1; dd < NT; dd <<= 1) {
+      const T u = __shfl_up(x, dd, NT);
+      if (tid >= dd) x += u;
+    }
+  }
+  return x;
+}
+
 // padded LDS index of FFT element k of a length-L transform: for power-of-two
 // lengths one spare slot every 16 entries keeps the strided Stockham writes
 // off a single bank; lengths with a factor 3 (radix-3 last stage) measured

@@ -67,6 +67,9 @@ struct Plan {
   // twp (2(n+1)) | lam (m) | s (m)
   int bo_twl = 0, bo_twp = 0, bo_vt = 0, bo_v0 = 0, bo_v1 = 0, bo_lam = 0, bo_s = 0, blob_len = 0;
   int bo_sn = 0;
+  // outlier windows per apply precision: Vt[q][j] is used for j < win[0] and
+  // j >= win[1] (set at setup from Vt; the full row until then)
+  int win32[2] = {0, 0}, win64[2] = {0, 0};
 
   int variant[5] = {1, 1, 1, 1, 1};  // FFT shape per apply pass (see fft_device.h)
   bool half_len = false;  // sine transforms through length-n FFTs (L = n), else L = 2n
