@@ -992,6 +992,11 @@ static hipError_t by_variant(const Plan& P, int var, int axis, const void* in, v
       }
       return by_shape<Tin, Tout, T, MODE, L, PK_EVEN_2N>(P, var, axis, in, out, nrhs, a, as, s, hk);
     }
+  } else if constexpr (sizeof(Tin) == 4 || sizeof(Tout) == 4) {
+    // FP32 plans of odd degree >= 5: the odd extension of length 2n (no
+    // prefix sums over FFT outputs, see build_plan)
+    if (!P.half_len && odd)
+      return by_shape<Tin, Tout, T, MODE, L, PK_ODD>(P, var, axis, in, out, nrhs, a, as, s, hk);
   }
   if constexpr (L <= 512) {
     if (P.half_len) {

@@ -398,19 +398,21 @@ def test_graph_solver_batch_of_64_full_size():
         assert s1[0]["relres_true"] <= 1.01e-8
 
 
-ODD_PREFIX_XFAIL = pytest.mark.xfail(
+P7_XFAIL = pytest.mark.xfail(
     strict=False,
-    reason="odd p >= 5, smooth data: the FP32 DST-I through a length-n FFT forms the odd "
-           "coefficients as prefix sums of FFT outputs, which carries the FFT's rounding "
-           "into the high-frequency coefficients ~5x amplified; measured 1.03e-5 at p = 5")
+    reason="FP32 apply at p = 7 on smooth data: 1.78e-5 against the oracle (2-norm; a dense "
+           "FP32 mode-product apply with the same FP64 first pass reaches 1.0e-6), the only "
+           "FP32 case above 1e-5; the degrees of the n = 256 sweep (2, 3, 4, 6, 8) and p = 5 "
+           "pass")
 
 
-@pytest.mark.parametrize("p", [4, pytest.param(5, marks=ODD_PREFIX_XFAIL), 6,
-                               pytest.param(7, marks=ODD_PREFIX_XFAIL), 8])
+@pytest.mark.parametrize("p", [4, 5, 6, pytest.param(7, marks=P7_XFAIL), 8])
 def test_smooth_rhs_fp32_high_degree(p):
     """Smooth right-hand side at high degree (3D n = 64): the input's FP32
     rounding alone would cost ~3e-5 (printed e_in); the FP32 apply takes the
-    FP64 input into its first pass for p >= 5 and meets 1e-5."""
+    FP64 input into its first pass for p >= 5 and meets 1e-5, and for odd
+    p >= 5 runs the DST-I through the length-2n odd extension (the length-n
+    route's prefix sums cost 1.2e-5 at p = 5 and 1.3e-4 at p = 7 here)."""
     d, n = 3, 64
     r = workloads.smooth_rhs(d, n, p, seed=3)
     pre = oracle(d, n, p)

@@ -87,8 +87,12 @@ def test_host_tables_match_oracle(n, p):
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
     m, n_reg, n_out = O.dims(n, p)
     # the sine transforms run through length-n FFTs where that length is built
-    # (n >= 16), else through length-2n ones
-    L = n if n in (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512) else 2 * n
+    # (n >= 16), else through length-2n ones; FP32 plans of odd degree >= 5
+    # through the length-2n odd extension where 2n is built
+    built = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+    L = n if n in built else 2 * n
+    if p % 2 and p >= 5 and 2 * n in built:
+        L = 2 * n
     assert (info.m, info.n_reg, info.n_out, info.N, info.fft_len) == (m, n_reg, n_out, m ** 3, L)
     fb = O.factors_route_b(n, p)
     lam = read(h, I.TABLE_LAM, m)[:n_reg]
