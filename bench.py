@@ -559,36 +559,45 @@ def main():
                     "solves_per_s": round(B * 1e3 / statistics.mean(fblat), 2),
                     "iterations": fbst[0]["iterations"]}
             del fd, zf
-            # ---- dense FD on the FP16 matrix cores, per-line scaling -------------
-            fh = iffd.Plan(d, n, p, method="dense", precision="f16s", max_rhs=B,
-                           coef_a=args.coef)
-            zh = torch.empty_like(r)
-            for _ in range(5):
-                fh.apply(r, out=zh)
-            torch.cuda.synchronize()
-            torch.cuda._sleep(int(cpm * 5.0))
-            a.record()
-            for _ in range(reps):
-                fh.apply(r, out=zh)
-            b.record()
-            torch.cuda.synchronize()
-            hms = a.elapsed_time(b) / reps
+            # ---- dense FD on the FP16 / BF16 matrix cores, per-line scaling ------
             ref = iffd.Plan(d, n, p, method="dense", precision="f64", max_rhs=B)
             zd64 = ref.apply(r)
-            herr = float((zh - zd64).norm() / zd64.norm())
-            del ref, zd64
-            hlat, hst = time_solves(torch, fh, f, max(5, args.solves // 3))
-            htf = flops / (hms * 1e-3) / 1e12
-            out["dense_fd_f16s"] = {
-                "gdof_s": round(B * N / (hms * 1e-3) / 1e9, 3), "ms_per_apply": round(hms, 5),
-                "apply_relerr_vs_f64": herr,
-                "roofline": {"bound": "mfma", "achieved": round(htf, 2), "peak": 2500.0,
-                             "unit": "TFLOP/s", "frac": round(htf / 2500.0, 4),
-                             "note": "GEMMs on v_mfma_f32_32x32x8f16 plus one FP16 "
-                                     "quantization sweep per mode product"},
-                "pcg": {"solves_per_s": round(1e3 / statistics.mean(hlat), 2),
-                        "p50_ms": round(pct(hlat, 0.5), 3), "iterations": hst[0]["iterations"]}}
-            del fh, zh
+            del ref
+            for hp, mfma in (("f16s", "v_mfma_f32_32x32x16_f16"),
+                             ("bf16s", "v_mfma_f32_32x32x16_bf16")):
+                fh = iffd.Plan(d, n, p, method="dense", precision=hp, max_rhs=B,
+                               coef_a=args.coef)
+                zh = torch.empty_like(r)
+                for _ in range(5):
+                    fh.apply(r, out=zh)
+                torch.cuda.synchronize()
+                torch.cuda._sleep(int(cpm * 5.0))
+                a.record()
+                for _ in range(reps):
+                    fh.apply(r, out=zh)
+                b.record()
+                torch.cuda.synchronize()
+                hms = a.elapsed_time(b) / reps
+                herr = float((zh - zd64).norm() / zd64.norm())
+                hlat, hst = time_solves(torch, fh, f, max(5, args.solves // 3))
+                htf = flops / (hms * 1e-3) / 1e12
+                # the 16-bit mode products are bound by HBM, not the matrix
+                # cores: each moves the FP32 tensor in and out plus its 16-bit
+                # copy (a quantization sweep reads FP32 and writes 16 bits)
+                hbytes = B * N * 2 * d * (4 + 2 + 2 + 4) + B * N * 8 * 2
+                out[f"dense_fd_{hp}"] = {
+                    "gdof_s": round(B * N / (hms * 1e-3) / 1e9, 3),
+                    "ms_per_apply": round(hms, 5), "apply_relerr_vs_f64": herr,
+                    "roofline": {"bound": "mfma", "achieved": round(htf, 2), "peak": 2500.0,
+                                 "unit": "TFLOP/s", "frac": round(htf / 2500.0, 4),
+                                 "hbm_GBs": round(hbytes / (hms * 1e-3) / 1e9, 1),
+                                 "note": f"GEMMs on {mfma} plus one quantization sweep "
+                                         "per mode product"},
+                    "pcg": {"solves_per_s": round(1e3 / statistics.mean(hlat), 2),
+                            "p50_ms": round(pct(hlat, 0.5), 3),
+                            "iterations": hst[0]["iterations"]}}
+                del fh, zh
+            del zd64
         except iffd.IffdError as e:
             out["dense_fd"] = {"error": str(e)}
         if B == 1 and args.coef == 0.0:

@@ -73,6 +73,9 @@ extern "C" {
                                      the transformed direction scaled by its own
                                      max |value| before rounding to FP16, Q by
                                      its max |entry|; FP32 in between          */
+#define IFFD_PREC_BF16S       3   /* dense FD only: as IFFD_PREC_F16S with BF16
+                                     operands (8-bit significand: larger error,
+                                     no overflow concern)                      */
 
 typedef struct iffd_plan iffd_plan;
 

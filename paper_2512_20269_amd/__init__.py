@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libiffd.so")
 OK, W_NOT_CONVERGED = 0, 1
 E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
-PREC_F64, PREC_F32, PREC_F16S = 0, 1, 2
+PREC_F64, PREC_F32, PREC_F16S, PREC_BF16S = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
@@ -140,7 +140,8 @@ class Plan:
 
     method: "fft" (IFFD) or "dense" (classical FD); precision: "f32" or "f64"
     for the preconditioner arithmetic (vectors and Krylov work are FP64), or
-    "f16s" (dense FD only: FP16 matrix cores with per-line scaling).
+    "f16s" / "bf16s" (dense FD only: FP16 / BF16 matrix cores with per-line
+    scaling).
     coef_a: the system matrix of matvec() and solve() (iffd_opts.coef_a): 0
     for A-hat, else the variable-coefficient A_c with c(x) = 1 + coef_a x in
     every direction; the preconditioner is built from A-hat either way."""
@@ -150,7 +151,8 @@ class Plan:
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
-                     {"f32": PREC_F32, "f64": PREC_F64, "f16s": PREC_F16S}[precision], max_rhs,
+                     {"f32": PREC_F32, "f64": PREC_F64, "f16s": PREC_F16S,
+                      "bf16s": PREC_BF16S}[precision], max_rhs,
                      float(coef_a))
         self.coef_a = float(coef_a)
         h = ctypes.c_void_p()

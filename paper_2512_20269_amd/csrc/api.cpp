@@ -224,16 +224,25 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     put<float>(buf, t.qfd32, P.Qfd);
     put<float>(buf, t.qtfd32, QT);
     put<float>(buf, t.lamfd32, P.lamfd);
-    if (P.prec == IFFD_PREC_F16S) {
-      // Q and Q^T in FP16, scaled by the largest |entry| (in [-1, 1] after)
+    if (P.prec == IFFD_PREC_F16S || P.prec == IFFD_PREC_BF16S) {
+      // Q and Q^T in FP16 or BF16, scaled by the largest |entry| (in [-1, 1] after)
       double sq = 0.0;
       for (double v : P.Qfd) sq = std::max(sq, std::fabs(v));
       if (!(sq > 0.0)) sq = 1.0;
-      _Float16* q16 = (_Float16*)(buf.data() + t.qfd16);
-      _Float16* qt16 = (_Float16*)(buf.data() + t.qtfd16);
-      for (size_t k = 0; k < (size_t)m * m; ++k) {
-        q16[k] = (_Float16)(P.Qfd[k] / sq);
-        qt16[k] = (_Float16)(QT[k] / sq);
+      if (P.prec == IFFD_PREC_F16S) {
+        _Float16* q16 = (_Float16*)(buf.data() + t.qfd16);
+        _Float16* qt16 = (_Float16*)(buf.data() + t.qtfd16);
+        for (size_t k = 0; k < (size_t)m * m; ++k) {
+          q16[k] = (_Float16)(P.Qfd[k] / sq);
+          qt16[k] = (_Float16)(QT[k] / sq);
+        }
+      } else {
+        __bf16* q16 = (__bf16*)(buf.data() + t.qfd16);
+        __bf16* qt16 = (__bf16*)(buf.data() + t.qtfd16);
+        for (size_t k = 0; k < (size_t)m * m; ++k) {
+          q16[k] = (__bf16)(float)(P.Qfd[k] / sq);
+          qt16[k] = (__bf16)(float)(QT[k] / sq);
+        }
       }
       *(float*)(buf.data() + t.qs16) = (float)sq;
     }

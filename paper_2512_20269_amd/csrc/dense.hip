@@ -9,12 +9,14 @@
 //                              (forward) or Q (backward), X_o an m x S slab
 //                              (S = m^{k-1})
 // The division by sum_k lambda_{j_k} is fused into the epilogue of the last
-// forward product.  FP32 uses v_mfma_f32_32x32x2f32 (a wave owns a 32 x 32
-// tile), FP64 v_mfma_f64_16x16x4f64 (16 x 16 per wave), FP16 (IFFD_PREC_F16S)
-// v_mfma_f32_32x32x8f16 with FP32 accumulation; four waves per workgroup, K
-// staged through LDS in chunks.  In FP16 every line along the transformed
-// direction is first divided by its largest |value| and rounded (quant_lines),
-// Q carries one scale s_Q, and the epilogue multiplies both back.
+// forward product.  FP32 uses v_mfma_f32_16x16x4f32 with large workgroup
+// tiles (gemm_f32_t16; small problems v_mfma_f32_32x32x2f32 with one 32 x 32
+// tile per wave), FP64 v_mfma_f64_16x16x4f64 (16 x 16 per wave), FP16 and
+// BF16 (IFFD_PREC_F16S / IFFD_PREC_BF16S) gfx950's v_mfma_f32_32x32x16_f16 /
+// _bf16 with FP32 accumulation; four waves per workgroup, K staged through
+// LDS in chunks.  In FP16 / BF16 every line along the transformed direction is
+// first divided by its largest |value| and rounded (quant_lines), Q carries
+// one scale s_Q, and the epilogue multiplies both back.
 #include <type_traits>
 #include <utility>
 
@@ -24,7 +26,8 @@ namespace iffd {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct GemmArgs {
   int M, N, K;
@@ -48,6 +51,7 @@ template <typename T> struct MfmaCfg;
 template <> struct MfmaCfg<float> { static constexpr int WT = 32, BK = 16; };   // wave tile
 template <> struct MfmaCfg<double> { static constexpr int WT = 16, BK = 16; };
 template <> struct MfmaCfg<_Float16> { static constexpr int WT = 32, BK = 16; };
+template <> struct MfmaCfg<__bf16> { static constexpr int WT = 32, BK = 16; };
 
 // C = A * B (all row-major), one workgroup of 4 waves per (2 WT) x (2 WT) tile
 template <typename TA, typename TB, typename TC, typename T>
@@ -116,17 +120,19 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
     __syncthreads();
     if (k0 + BK < g.K) fetch(k0 + BK);
     if constexpr (sizeof(T) == 2) {
-      // 32x32x8 f16: lane l supplies row (column) l%32, k = 4(l/32) .. +3
+      // gfx950 32x32x16 (FP16 or BF16): lane l supplies row (column) l%32,
+      // k = 8(l/32) .. +7; one product per chunk of 16
+      using V8 = std::conditional_t<std::is_same<T, __bf16>::value, bf16x8, f16x8>;
+      V8 a, b;
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 8) {
-        f16x4 a, b;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u] = As[kk + 4 * (lane >> 5) + u][wm + (lane & 31)];
-          b[u] = Bs[kk + 4 * (lane >> 5) + u][wn + (lane & 31)];
-        }
-        accf = __builtin_amdgcn_mfma_f32_32x32x8f16(a, b, accf, 0, 0, 0);
+      for (int u = 0; u < 8; ++u) {
+        a[u] = As[8 * (lane >> 5) + u][wm + (lane & 31)];
+        b[u] = Bs[8 * (lane >> 5) + u][wn + (lane & 31)];
       }
+      if constexpr (std::is_same<T, __bf16>::value)
+        accf = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, accf, 0, 0, 0);
+      else
+        accf = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, accf, 0, 0, 0);
     } else if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
@@ -176,6 +182,136 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
   }
 }
 
+// FP32 mode products on v_mfma_f32_16x16x4f32 with large workgroup tiles.
+// Four waves in a 2 x 2 grid, each owning a WM x WN tile of 16 x 16 blocks
+// (one accumulator per block), so the workgroup tile is 2 WM x 2 WN and a
+// dimension of size m pads only to the next multiple of the tile chosen for
+// it (m = 257: 288 with 96-wide tiles, against 320 with 64-wide ones).  K runs
+// in chunks of 16 staged in LDS, two buffers: the next chunk's loads are in
+// flight in registers during the current chunk's products and land in the
+// other buffer after them (one barrier per chunk); the K tail skips its empty
+// k-steps.  LDS rows are padded to 17 mod 32 words, so the transposing stores
+// and the fragment reads of two k rows per half-wave stay within two-way
+// bank conflicts.
+template <int WM, int WN>
+struct Tile16 {
+  static constexpr int BM = 2 * WM, BN = 2 * WN, BK = 16;
+  static constexpr int PA = (17 - BM % 32 + 32) % 32, PB = (17 - BN % 32 + 32) % 32;
+  static constexpr int LDA = BM + PA, LDB = BN + PB;   // LDS row strides, == 17 mod 32
+  static constexpr int RB = WM / 16, CB = WN / 16;     // 16 x 16 blocks per wave
+  static constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+};
+
+template <typename TA, typename TB, typename TC, int WM, int WN>
+__global__ void __launch_bounds__(256) gemm_f32_t16(const TA* __restrict__ A,
+                                                    const TB* __restrict__ B,
+                                                    TC* __restrict__ Cm, GemmArgs g) {
+  using Tl = Tile16<WM, WN>;
+  constexpr int BM = Tl::BM, BN = Tl::BN, BK = Tl::BK, LDA = Tl::LDA, LDB = Tl::LDB;
+  constexpr int RB = Tl::RB, CB = Tl::CB, NA = Tl::NA, NB = Tl::NB;
+  __shared__ float As[2][BK * LDA];
+  __shared__ float Bs[2][BK * LDB];
+  const int bat = blockIdx.z;
+  const int rhs = bat / g.batch_per_rhs;
+  if (g.active && g.active[(size_t)rhs * g.astride] == 0.0) return;
+  const TA* Ab = A + bat * g.sA;
+  const TB* Bb = B + bat * g.sB;
+  TC* Cb = Cm + bat * g.sC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w >> 1) * WM, wn = (w & 1) * WN;
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  f32x4 acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const auto ra_ = buf_rsrc(Ab, (unsigned)(((long long)(g.M - 1) * g.lda + g.K) * sizeof(TA)));
+  const auto rb_ = buf_rsrc(Bb, (unsigned)(((long long)(g.K - 1) * g.ldb + g.N) * sizeof(TB)));
+  TA va[NA];
+  TB vb[NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
+      const int i = e / BK, k = e % BK;
+      const int gi = m0 + i, gk = k0 + k;
+      const unsigned off = (gi < g.M && gk < g.K)
+                               ? (unsigned)(((long long)gi * g.lda + gk) * sizeof(TA)) : BUF_OOB;
+      va[u] = buf_ld<TA>(ra_, off);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
+      const int k = e / BN, j = e % BN;
+      const int gk = k0 + k, gj = n0 + j;
+      const unsigned off = (gk < g.K && gj < g.N)
+                               ? (unsigned)(((long long)gk * g.ldb + gj) * sizeof(TB)) : BUF_OOB;
+      vb[u] = buf_ld<TB>(rb_, off);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
+      As[buf][(e % BK) * LDA + e / BK] = (float)va[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
+      Bs[buf][(e / BN) * LDB + e % BN] = (float)vb[u];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    const bool more = k0 + BK < g.K;
+    if (more) fetch(k0 + BK);
+    const int ksteps = min(4, (g.K - k0 + 3) >> 2);   // k-steps of 4 that hold data
+    const float* Ab_ = As[buf];
+    const float* Bb_ = Bs[buf];
+    for (int s = 0; s < 4; ++s) {
+      if (s < ksteps) {
+        const int kk = 4 * s + (lane >> 4);
+        float a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) a[i] = Ab_[kk * LDA + wm + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) b[j] = Bb_[kk * LDB + wn + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (more) {
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  const float* lam = (const float*)g.lam;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // 16x16x4 f32: register v of lane l holds row 4 (l / 16) + v, column l % 16
+        const int gi = m0 + wm + 16 * i + 4 * (lane >> 4) + v;
+        const int gj = n0 + wn + 16 * j + (lane & 15);
+        if (gi < g.M && gj < g.N) {
+          float x = acc[i][j][v];
+          if (g.scale_mode == 2) x /= lam[gi] + lam[gj];
+          else if (g.scale_mode == 3) x /= lam[gi] + lam[gj % g.m] + lam[gj / g.m];
+          Cb[(long long)gi * g.ldc + gj] = (TC)x;
+        }
+      }
+}
+
 // FP16 operand of a mode product along a direction with stride S > 1: line q
 // of a right-hand side (q = o S + j, entries o m S + i S + j, i < m) is
 // divided by its largest |value| and rounded to FP16; scale[rhs][q] keeps
@@ -183,9 +319,9 @@ __global__ void __launch_bounds__(256) gemm_mfma(const TA* __restrict__ A, const
 // (neighbouring addresses) with QG threads per line, each on every QG-th
 // entry; the partial maxima meet in LDS.
 constexpr int QL = 32, QG = 256 / QL;
-template <typename TI>
+template <typename TI, typename TQ>
 __global__ void __launch_bounds__(256)
-quant_lines(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restrict__ scale,
+quant_lines(const TI* __restrict__ in, TQ* __restrict__ out, float* __restrict__ scale,
             int m, int S, int lines, long long N, int nrhs, const double* __restrict__ active,
             int astride) {
   __shared__ float red[QG][QL];
@@ -207,14 +343,14 @@ quant_lines(const TI* __restrict__ in, _Float16* __restrict__ out, float* __rest
   const float sc = mx > 0.0f ? mx : 1.0f;
   const float inv = 1.0f / sc;
   for (int i = gq; i < m; i += QG)
-    out[base + (long long)i * S] = (_Float16)((float)in[base + (long long)i * S] * inv);
+    out[base + (long long)i * S] = (TQ)((float)in[base + (long long)i * S] * inv);
   if (gq == 0) scale[q] = sc;
 }
 
 // direction 1 (lines contiguous): one wave per line, lanes stride the line
-template <typename TI>
+template <typename TI, typename TQ>
 __global__ void __launch_bounds__(256)
-quant_rows(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restrict__ scale,
+quant_rows(const TI* __restrict__ in, TQ* __restrict__ out, float* __restrict__ scale,
            int m, int lines, long long N, int nrhs, const double* __restrict__ active,
            int astride) {
   const long long q = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -229,12 +365,49 @@ quant_rows(const TI* __restrict__ in, _Float16* __restrict__ out, float* __restr
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
   const float sc = mx > 0.0f ? mx : 1.0f;
   const float inv = 1.0f / sc;
-  for (int i = lane; i < m; i += 64) out[base + i] = (_Float16)((float)in[base + i] * inv);
+  for (int i = lane; i < m; i += 64) out[base + i] = (TQ)((float)in[base + i] * inv);
   if (lane == 0) scale[q] = sc;
+}
+
+// workgroup tile (64, 96 or 128) for a GEMM dimension of size x: the least
+// padding, the larger tile on ties
+static int tile16_for(int x) {
+  int best = 128, pad = ((x + 127) / 128) * 128;
+  for (int tsz : {96, 64}) {
+    const int pd = ((x + tsz - 1) / tsz) * tsz;
+    if (pd < pad) { pad = pd; best = tsz; }
+  }
+  return best;
+}
+
+template <typename TA, typename TB, typename TC, int WM, int WN>
+static hipError_t gemm_t16(const TA* A, const TB* B, TC* C, const GemmArgs& g, int batches,
+                           hipStream_t s) {
+  dim3 grid((g.N + 2 * WN - 1) / (2 * WN), (g.M + 2 * WM - 1) / (2 * WM), batches);
+  hipLaunchKernelGGL((gemm_f32_t16<TA, TB, TC, WM, WN>), grid, dim3(256), 0, s, A, B, C, g);
+  return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TC, int WM>
+static hipError_t gemm_t16_n(int bn, const TA* A, const TB* B, TC* C, const GemmArgs& g,
+                             int batches, hipStream_t s) {
+  if (bn == 64) return gemm_t16<TA, TB, TC, WM, 32>(A, B, C, g, batches, s);
+  if (bn == 96) return gemm_t16<TA, TB, TC, WM, 48>(A, B, C, g, batches, s);
+  return gemm_t16<TA, TB, TC, WM, 64>(A, B, C, g, batches, s);
 }
 
 template <typename TA, typename TB, typename TC, typename T>
 static hipError_t gemm(const TA* A, const TB* B, TC* C, GemmArgs g, int batches, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    // large tiles where both dimensions fill them (the small problems keep the
+    // 64 x 64 kernel below)
+    if (g.M >= 64 && g.N >= 64 && g.K >= 16) {
+      const int bm = tile16_for(g.M), bn = tile16_for(g.N);
+      if (bm == 64) return gemm_t16_n<TA, TB, TC, 32>(bn, A, B, C, g, batches, s);
+      if (bm == 96) return gemm_t16_n<TA, TB, TC, 48>(bn, A, B, C, g, batches, s);
+      return gemm_t16_n<TA, TB, TC, 64>(bn, A, B, C, g, batches, s);
+    }
+  }
   constexpr int BM = 2 * MfmaCfg<T>::WT, BN = BM;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batches);
   hipLaunchKernelGGL((gemm_mfma<TA, TB, TC, T>), grid, dim3(256), 0, s, A, B, C, g);
@@ -303,15 +476,15 @@ static hipError_t fd_apply_t(const Plan& P, const double* r, double* z, int nrhs
   return mode_product<T, double, T>(P, 1, false, cur, z, nrhs, 0, a, as, s);
 }
 
-// FP16 mode product along `axis`: in (TI) -> quantized lines -> FP16 GEMM ->
+// FP16 / BF16 (TQ) mode product along `axis`: in (TI) -> quantized lines -> GEMM ->
 // out (TO), line scales and s_Q restored in the epilogue
-template <typename TI, typename TO>
+template <typename TQ, typename TI, typename TO>
 static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in, TO* out,
-                                 _Float16* x16, float* ls, int nrhs, int scale, const double* act,
+                                 TQ* x16, float* ls, int nrhs, int scale, const double* act,
                                  int as, hipStream_t s) {
   const char* tb = P.d_tables;
-  const _Float16* Q = (const _Float16*)(tb + P.lay.qfd16);
-  const _Float16* QT = (const _Float16*)(tb + P.lay.qtfd16);
+  const TQ* Q = (const TQ*)(tb + P.lay.qfd16);
+  const TQ* QT = (const TQ*)(tb + P.lay.qtfd16);
   const float* qs = (const float*)(tb + P.lay.qs16);
   const float* lam = (const float*)(tb + P.lay.lamfd32);
   const int m = P.m;
@@ -321,10 +494,10 @@ static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in
   const int lines = (int)(N / m);
   const long long nq = (long long)lines * nrhs;
   if (S == 1)
-    hipLaunchKernelGGL(quant_rows<TI>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, in, x16,
+    hipLaunchKernelGGL((quant_rows<TI, TQ>), dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, in, x16,
                        ls, m, lines, N, nrhs, act, as);
   else
-    hipLaunchKernelGGL(quant_lines<TI>, dim3((unsigned)((nq + QL - 1) / QL)), dim3(256), 0, s, in,
+    hipLaunchKernelGGL((quant_lines<TI, TQ>), dim3((unsigned)((nq + QL - 1) / QL)), dim3(256), 0, s, in,
                        x16, ls, m, S, lines, N, nrhs, act, as);
   GemmArgs g{};
   g.active = act;
@@ -340,7 +513,7 @@ static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in
     g.sA = N; g.sB = 0; g.sC = N;
     g.batch_per_rhs = 1;
     g.ls_mode = 1;
-    return gemm<_Float16, _Float16, TO, _Float16>(x16, fwd ? Q : QT, out, g, nrhs, s);
+    return gemm<TQ, TQ, TO, TQ>(x16, fwd ? Q : QT, out, g, nrhs, s);
   }
   const int outer = (int)(N / ((long long)S * m));
   g.M = m; g.N = S; g.K = m;
@@ -348,9 +521,10 @@ static hipError_t mode_product16(const Plan& P, int axis, bool fwd, const TI* in
   g.sA = 0; g.sB = (long long)S * m; g.sC = (long long)S * m;
   g.batch_per_rhs = outer;
   g.ls_mode = 2;
-  return gemm<_Float16, _Float16, TO, _Float16>(fwd ? QT : Q, x16, out, g, outer * nrhs, s);
+  return gemm<TQ, TQ, TO, TQ>(fwd ? QT : Q, x16, out, g, outer * nrhs, s);
 }
 
+template <typename TQ>
 static hipError_t fd_apply_f16(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                                const double* a, int as, hipStream_t s) {
   const int d = P.d;
@@ -358,30 +532,31 @@ static hipError_t fd_apply_f16(const Plan& P, const double* r, double* z, int nr
   const size_t b32 = (8 * N + 255) & ~(size_t)255, b16 = (2 * N + 255) & ~(size_t)255;
   float* t1 = (float*)ws;
   float* t2 = t1 + N;
-  _Float16* x16 = (_Float16*)((char*)ws + b32);
+  TQ* x16 = (TQ*)((char*)ws + b32);
   float* ls = (float*)((char*)ws + b32 + b16);
-  hipError_t e = mode_product16<double, float>(P, 1, true, r, t1, x16, ls, nrhs, d == 1 ? d : 0,
+  hipError_t e = mode_product16<TQ, double, float>(P, 1, true, r, t1, x16, ls, nrhs, d == 1 ? d : 0,
                                                a, as, s);
   if (e != hipSuccess) return e;
   float* cur = t1;
   float* nxt = t2;
   for (int k = 2; k <= d; ++k) {
-    e = mode_product16<float, float>(P, k, true, cur, nxt, x16, ls, nrhs, k == d ? d : 0, a, as, s);
+    e = mode_product16<TQ, float, float>(P, k, true, cur, nxt, x16, ls, nrhs, k == d ? d : 0, a, as, s);
     if (e != hipSuccess) return e;
     std::swap(cur, nxt);
   }
   for (int k = d; k >= 2; --k) {
-    e = mode_product16<float, float>(P, k, false, cur, nxt, x16, ls, nrhs, 0, a, as, s);
+    e = mode_product16<TQ, float, float>(P, k, false, cur, nxt, x16, ls, nrhs, 0, a, as, s);
     if (e != hipSuccess) return e;
     std::swap(cur, nxt);
   }
-  return mode_product16<float, double>(P, 1, false, cur, z, x16, ls, nrhs, 0, a, as, s);
+  return mode_product16<TQ, float, double>(P, 1, false, cur, z, x16, ls, nrhs, 0, a, as, s);
 }
 
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                            const double* active, int astride, hipStream_t s) {
   if (P.method != IFFD_METHOD_DENSE_FD) return hipErrorInvalidValue;
-  if (P.prec == IFFD_PREC_F16S) return fd_apply_f16(P, r, z, nrhs, ws, active, astride, s);
+  if (P.prec == IFFD_PREC_F16S) return fd_apply_f16<_Float16>(P, r, z, nrhs, ws, active, astride, s);
+  if (P.prec == IFFD_PREC_BF16S) return fd_apply_f16<__bf16>(P, r, z, nrhs, ws, active, astride, s);
   if (P.prec == IFFD_PREC_F64) return fd_apply_t<double>(P, r, z, nrhs, ws, active, astride, s);
   return fd_apply_t<float>(P, r, z, nrhs, ws, active, astride, s);
 }

@@ -295,7 +295,7 @@ void compute_layout(Plan& P) {
   t.qfd32 = take(4 * mm);
   t.qtfd32 = take(4 * mm);
   t.lamfd32 = take(4 * m);
-  const bool f16 = fd && P.prec == IFFD_PREC_F16S;
+  const bool f16 = fd && (P.prec == IFFD_PREC_F16S || P.prec == IFFD_PREC_BF16S);
   t.qfd16 = take(f16 ? 2 * mm : 8);
   t.qtfd16 = take(f16 ? 2 * mm : 8);
   t.qs16 = take(8);
@@ -316,7 +316,7 @@ size_t apply_ws_bytes(const Plan& P, int nrhs) {
   // IFFD: one FP32 buffer (the FP64 apply works in place on the output)
   // FD in FP16: the two FP32 buffers, an FP16 copy of the operand and one FP32
   // scale per line
-  if (P.method == IFFD_METHOD_DENSE_FD && P.prec == IFFD_PREC_F16S)
+  if (P.method == IFFD_METHOD_DENSE_FD && (P.prec == IFFD_PREC_F16S || P.prec == IFFD_PREC_BF16S))
     return align256((size_t)8 * P.N * nrhs) + align256((size_t)2 * P.N * nrhs) +
            align256((size_t)4 * (P.N / P.m) * nrhs);
   if (P.method == IFFD_METHOD_DENSE_FD) return align256((size_t)8 * P.N * nrhs);
@@ -372,8 +372,12 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   }
   if (!(P.coef_a > -1.0 && P.coef_a <= 1000.0)) { err = "coef_a must lie in (-1, 1000]"; return IFFD_E_INVAL; }
   if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
-  if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64 && P.prec != IFFD_PREC_F16S) { err = "bad apply_prec"; return IFFD_E_INVAL; }
-  if (P.prec == IFFD_PREC_F16S && P.method != IFFD_METHOD_DENSE_FD) { err = "IFFD_PREC_F16S is for dense FD only"; return IFFD_E_INVAL; }
+  if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64 && P.prec != IFFD_PREC_F16S &&
+      P.prec != IFFD_PREC_BF16S) { err = "bad apply_prec"; return IFFD_E_INVAL; }
+  if ((P.prec == IFFD_PREC_F16S || P.prec == IFFD_PREC_BF16S) && P.method != IFFD_METHOD_DENSE_FD) {
+    err = "IFFD_PREC_F16S and IFFD_PREC_BF16S are for dense FD only";
+    return IFFD_E_INVAL;
+  }
   if (P.max_rhs < 1) { err = "max_rhs must be >= 1"; return IFFD_E_INVAL; }
   P.N = 1;
   for (int k = 0; k < d; ++k) P.N *= P.m;

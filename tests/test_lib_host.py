@@ -45,11 +45,12 @@ def read(h, what, count):
     return buf
 
 
-def test_fp16_scaled_option_is_dense_fd_only():
-    opts = I._Opts(I.METHOD_FFT, I.PREC_F16S, 1)
+@pytest.mark.parametrize("prec", [I.PREC_F16S, I.PREC_BF16S])
+def test_fp16_scaled_option_is_dense_fd_only(prec):
+    opts = I._Opts(I.METHOD_FFT, prec, 1)
     h = ctypes.c_void_p()
     assert I.lib.iffd_plan_create(ctypes.byref(h), 3, 16, 3, ctypes.byref(opts)) == I.E_INVAL
-    rc, h = host_plan(3, 16, 3, I.METHOD_DENSE_FD, I.PREC_F16S)
+    rc, h = host_plan(3, 16, 3, I.METHOD_DENSE_FD, prec)
     assert rc == 0, I.lib.iffd_last_error()
     info = I._Info()
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
