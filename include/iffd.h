@@ -9,7 +9,11 @@
  * homogeneous Dirichlet conditions on every face, tensor-product B-splines
  * of degree p and maximal smoothness C^{p-1} on a uniform grid of n elements
  * per direction.  Per direction the reduced spline space has dimension
- * m = n + p - 2; a coefficient vector has N = m^d entries.
+ * m = n + p - 2; a coefficient vector has N = m^d entries.  General plans
+ * (iffd_plan_create_general) give every direction its own n_k, p_k and a
+ * Dirichlet or natural (Neumann) condition at each of its two ends (Section 4,
+ * "other boundary conditions", Table 1): m_k = n_k + p_k - (number of
+ * Dirichlet ends of direction k) and N = m_1 .. m_d.
  *
  * Conventions that hold for every entry point
  *   Layout     a d-dimensional coefficient tensor is stored C-contiguous with
@@ -144,8 +148,52 @@ typedef struct {
  * *out receives the plan (NULL on error). */
 int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
 
-/* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan. */
+/* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan.
+ * For a general plan the scalar n, p, m, n_reg, n_out and fft_len are those
+ * of direction 1 (iffd_plan_query_dirs gives every direction). */
 int iffd_plan_query(const iffd_plan* plan, iffd_plan_info* info);
+
+/* ---- general plans: per-direction n, p and boundary conditions ----------- */
+typedef struct {
+  int n, p;                       /* elements and degree of this direction    */
+  int dirichlet_lo, dirichlet_hi; /* 1: Dirichlet at x_k = 0 / x_k = 1,
+                                     0: natural (Neumann) condition            */
+  int m;                          /* n + p - dirichlet_lo - dirichlet_hi       */
+  int n_reg, n_out;               /* eq:reg_space_dim: n_reg = n - 1 (p odd,
+                                     both ends Dirichlet), n + 1 (p odd, no
+                                     Dirichlet end), n otherwise; n_out = m -
+                                     n_reg                                     */
+  int fft_len;                    /* complex FFT length of its transforms      */
+} iffd_dir_info;
+
+/* Host-only.  A plan whose direction k (1-based k = 1..d, direction 1 the
+ * fastest index) has n[k-1] elements, degree p[k-1], and the boundary
+ * conditions dirichlet[2(k-1)] (end x_k = 0) and dirichlet[2(k-1)+1] (end
+ * x_k = 1), each 1 for a homogeneous Dirichlet and 0 for a natural (Neumann)
+ * condition.  The spline space of direction k drops B_0 at a Dirichlet end 0
+ * and the last B-spline at a Dirichlet end 1 (Section 2).  IFFD per
+ * direction (Section 4 "other boundary conditions", Section 6): S^reg carries
+ * the derivative conditions of eq:reg_space (even orders at Dirichlet ends,
+ * odd orders at Neumann ends), its special basis reflects the cardinal
+ * B-splines oddly at Dirichlet and evenly at Neumann ends (eq:special_basis),
+ * U is the sine or cosine transform of Table 1 (DST-I..IV, DCT-I..IV),
+ * computed through complex FFTs of length 2 n_k, and the regular eigenvalues
+ * come from Lemma 4's closed form at the frequencies alpha_j / n_k of Table 1.
+ * Every entry point takes general plans except iffd_plan_set_variant and
+ * iffd_plan_tune (single FFT shape; tune is a no-op).  Valid range: d in
+ * {2,3}; per direction 1 <= p <= 8, n > p, n = 2^a or 3*2^a with
+ * 8 <= n <= 256 (IFFD_E_UNSUPPORTED otherwise); at least one Dirichlet end
+ * (Neumann conditions on every face make the operator singular: the
+ * constants; IFFD_E_UNSUPPORTED); opts: method IFFD_METHOD_FFT, apply_prec
+ * IFFD_PREC_F32 or IFFD_PREC_F64, coef_a = 0 (IFFD_E_UNSUPPORTED or
+ * IFFD_E_INVAL otherwise).  iffd_kron_matvec and the PCG use the operator
+ * Ahat = sum_k M_d x .. x K_k x .. x M_1 with each direction's own K, M. */
+int iffd_plan_create_general(iffd_plan** out, int d, const int* n, const int* p,
+                             const int* dirichlet, const iffd_opts* opts);
+
+/* Per-direction sizes: h_out[k-1] describes direction k, for every plan
+ * (uniform plans report Dirichlet ends).  count: capacity of h_out (>= d). */
+int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count);
 
 /* Uploads the plan's tables into the caller's device buffer d_tables
  * (>= info.table_bytes bytes, 256-byte aligned), solves the small outlier
@@ -168,6 +216,16 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
  * `count` is the capacity of h_out in doubles; returns IFFD_E_WORKSPACE if
  * too small. */
 int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream);
+
+/* iffd_plan_read for direction `direction` (1..d) of a general plan (for a
+ * uniform plan every direction reads the same tables).  Sizes use that
+ * direction's m, n_reg, n_out and p; tables 4 and 5 are its end blocks AL
+ * (rl x cl) and AR (rr x cr) of V_reg = blkdiag(AL, I, AR), rl = p - (Dirichlet
+ * at 0), cl = floor(p/2) (Dirichlet or p even) or (p+1)/2 (Neumann, p odd),
+ * and the same for the end at 1; table 7 equals table 2.  For a general plan
+ * iffd_plan_read reads direction 1. */
+int iffd_plan_read_dir(const iffd_plan* plan, int direction, int what, double* h_out,
+                       size_t count, void* stream);
 
 void iffd_plan_destroy(iffd_plan* plan);
 

@@ -9,6 +9,8 @@ importing this package without it raises immediately.
     import torch, paper_2512_20269_amd as iffd
     plan = iffd.Plan(d=3, n=128, p=3, precision="f32")
     z = plan.apply(r)                    # z = P^{-1} r, r: float64 [m]^d on cuda
+    mixed = iffd.Plan(d=3, n=64, p=3,    # per-direction conditions (and n, p)
+                      dirichlet=[(1, 0), (0, 1), (0, 0)])
     y = plan.matvec(x)                   # y = A x (Ahat, or A_c with coef_a)
     u, stats = plan.solve(f, rtol=1e-8)  # PCG
 """
@@ -53,6 +55,12 @@ class _Info(ctypes.Structure):
                 ("state_bytes_per_slot", ctypes.c_size_t), ("state_bytes_fixed", ctypes.c_size_t)]
 
 
+class _DirInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("dirichlet_lo", ctypes.c_int),
+                ("dirichlet_hi", ctypes.c_int), ("m", ctypes.c_int), ("n_reg", ctypes.c_int),
+                ("n_out", ctypes.c_int), ("fft_len", ctypes.c_int)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("status", ctypes.c_int),
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
@@ -64,7 +72,10 @@ class _Stats(ctypes.Structure):
 _P, _I, _D, _Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
 SIGNATURES = {
     "iffd_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, ctypes.POINTER(_Opts)]),
+    "iffd_plan_create_general": (_I, [ctypes.POINTER(_P), _I, _P, _P, _P, ctypes.POINTER(_Opts)]),
     "iffd_plan_query": (_I, [_P, ctypes.POINTER(_Info)]),
+    "iffd_plan_query_dirs": (_I, [_P, ctypes.POINTER(_DirInfo), _I]),
+    "iffd_plan_read_dir": (_I, [_P, _I, _I, _P, _Z, _P]),
     "iffd_plan_setup": (_I, [_P, _P, _Z, _P]),
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
@@ -135,6 +146,37 @@ def _need(t, shape, dtype, name):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape})")
 
 
+def _ints(v, d, name):
+    v = [int(x) for x in (v if hasattr(v, "__len__") else [v] * d)]
+    if len(v) != d:
+        raise ValueError(f"{name} needs {d} entries (direction 1 first)")
+    return v
+
+
+def create_general(d: int, n, p, dirichlet, opts=None):
+    """iffd_plan_create_general: a host-side plan handle (no device work);
+    n, p: one value or d values, dirichlet: d pairs (end 0, end 1) of 0/1,
+    direction 1 first.  Returns (status, handle)."""
+    nv, pv = _ints(n, d, "n"), _ints(p, d, "p")
+    dv = []
+    for pair in dirichlet:
+        a, b = pair
+        dv += [int(a), int(b)]
+    if len(dv) != 2 * d:
+        raise ValueError(f"dirichlet needs {d} (end 0, end 1) pairs")
+    arr = lambda v: (ctypes.c_int * len(v))(*v)
+    h = ctypes.c_void_p()
+    o = opts if opts is not None else _Opts(METHOD_FFT, PREC_F32, 1, 0.0)
+    rc = lib.iffd_plan_create_general(ctypes.byref(h), d, arr(nv), arr(pv), arr(dv), ctypes.byref(o))
+    return rc, h
+
+
+def query_dirs(h, d: int):
+    info = (_DirInfo * d)()
+    _check(lib.iffd_plan_query_dirs(h, info, d), "plan_query_dirs")
+    return [{f: getattr(x, f) for f, _ in _DirInfo._fields_} for x in info]
+
+
 class Plan:
     """One (d, n, p) problem with its device tables, workspace and PCG state.
 
@@ -144,10 +186,14 @@ class Plan:
     scaling).
     coef_a: the system matrix of matvec() and solve() (iffd_opts.coef_a): 0
     for A-hat, else the variable-coefficient A_c with c(x) = 1 + coef_a x in
-    every direction; the preconditioner is built from A-hat either way."""
+    every direction; the preconditioner is built from A-hat either way.
+    dirichlet: d pairs (end x_k = 0, end x_k = 1), 1 = Dirichlet, 0 = natural
+    (Neumann), direction 1 first; given (or n, p given per direction as
+    sequences) it makes a general plan (iffd_plan_create_general) whose
+    tensors have shape (m_d, .., m_1)."""
 
-    def __init__(self, d: int, n: int, p: int, method: str = "fft", precision: str = "f32",
-                 max_rhs: int = 1, device=None, coef_a: float = 0.0):
+    def __init__(self, d: int, n, p, method: str = "fft", precision: str = "f32",
+                 max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
@@ -155,16 +201,23 @@ class Plan:
                       "bf16s": PREC_BF16S}[precision], max_rhs,
                      float(coef_a))
         self.coef_a = float(coef_a)
+        self.general = dirichlet is not None or hasattr(n, "__len__") or hasattr(p, "__len__")
         h = ctypes.c_void_p()
-        _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
+        if self.general:
+            dl = dirichlet if dirichlet is not None else [(1, 1)] * d
+            rc, h = create_general(d, n, p, dl, opts)
+            _check(rc, "plan_create_general")
+        else:
+            _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h
         info = _Info()
         _check(lib.iffd_plan_query(h, ctypes.byref(info)), "plan_query")
         self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.dirs = query_dirs(h, d)
         self.d, self.n, self.p, self.m = d, n, p, info.m
         self.N, self.max_rhs = info.N, max_rhs
         self.method, self.precision = method, precision
-        self.shape = (self.m,) * d
+        self.shape = tuple(x["m"] for x in reversed(self.dirs))
         with torch.cuda.device(self.device):
             self.tables = torch.empty(info.table_bytes, dtype=torch.uint8, device=self.device)
             assert self.tables.data_ptr() % 256 == 0
@@ -194,15 +247,25 @@ class Plan:
             self._h = None
 
     # ---- tables ----------------------------------------------------------
-    def read_table(self, what: int) -> np.ndarray:
-        cap = 4 * self.m * (2 * self.p + 1) + 8 * self.m + 64
+    def read_table(self, what: int, direction: int = 1) -> np.ndarray:
+        """A host table of direction `direction` (iffd_plan_read_dir)."""
+        di = self.dirs[direction - 1]
+        m, p = di["m"], di["p"]
+        cap = 4 * m * (2 * p + 1) + 8 * m + 64
         buf = np.zeros(cap)
-        _check(lib.iffd_plan_read(self._h, what, buf.ctypes.data_as(ctypes.c_void_p), cap,
-                                  _stream()), "plan_read")
-        sizes = {TABLE_LAM: self.m, TABLE_DT: self.info["n_reg"],
-                 TABLE_KBAND: self.m * (2 * self.p + 1), TABLE_MBAND: self.m * (2 * self.p + 1),
-                 TABLE_V0: (self.p - 1) * (self.p // 2), TABLE_V1: (self.p - 1) * (self.p // 2),
-                 TABLE_VT: self.info["n_out"] * self.m}
+        _check(lib.iffd_plan_read_dir(self._h, direction, what,
+                                      buf.ctypes.data_as(ctypes.c_void_p), cap, _stream()),
+               "plan_read_dir")
+        if self.general:
+            rows = lambda dch: p - dch
+            cols = lambda dch: p // 2 if (dch or p % 2 == 0) else (p + 1) // 2
+            v0 = rows(di["dirichlet_lo"]) * cols(di["dirichlet_lo"])
+            v1 = rows(di["dirichlet_hi"]) * cols(di["dirichlet_hi"])
+        else:
+            v0 = v1 = (p - 1) * (p // 2)
+        sizes = {TABLE_LAM: m, TABLE_DT: di["n_reg"], TABLE_KBAND: m * (2 * p + 1),
+                 TABLE_MBAND: m * (2 * p + 1), TABLE_V0: v0, TABLE_V1: v1,
+                 TABLE_VT: di["n_out"] * m}
         return buf[:sizes[what]].copy()
 
     # ---- compute ----------------------------------------------------------

@@ -31,6 +31,8 @@ SOURCES = ["plan.cpp", "api.cpp", "apply.hip",
            "apply_le_fwd.hip", "apply_le_bwd.hip", "apply_le_mid.hip",
            "apply_lf_fwd.hip", "apply_lf_bwd.hip", "apply_lf_mid.hip",
            "apply_lg_fwd.hip", "apply_lg_bwd.hip", "apply_lg_mid.hip",
+           "gen.hip", "gen_la.hip", "gen_lb.hip", "gen_lc.hip", "gen_ld.hip", "gen_le.hip",
+           "gen_lf.hip", "gen_lg.hip",
            "setup.hip", "matvec.hip", "pcg.hip", "dense.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -117,6 +117,100 @@ namespace iffd {
 int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
 }  // namespace iffd
 
+
+namespace {
+
+// outlier windows of one rotated outlier block (n_out x m): the entries decay
+// geometrically away from the two ends; entries below 2^-30 (FP32 apply) or
+// 2^-60 (FP64 apply) of the largest contribute below the working precision
+// to the dots and the rank-n_out update, so only the two end windows are used
+void outlier_windows(const std::vector<double>& Vt, int n_out, int m, int* win32, int* win64) {
+  for (int w = 0; w < 2; ++w) {
+    int* win = w == 0 ? win32 : win64;
+    win[0] = m;
+    win[1] = m;
+    if (n_out == 0) continue;
+    const double thr = std::ldexp(1.0, w == 0 ? -30 : -60);
+    double mx = 0.0;
+    for (double v : Vt) mx = std::max(mx, std::fabs(v));
+    int lo = 0, hi = m;   // left window [0, lo), right window [hi, m)
+    for (int j = 0; j < m; ++j)
+      for (int q = 0; q < n_out; ++q)
+        if (std::fabs(Vt[(size_t)q * m + j]) > thr * mx) {
+          if (j < m / 2) lo = std::max(lo, j + 1);
+          else hi = std::min(hi, j);
+        }
+    if (lo < hi) { win[0] = lo; win[1] = hi; }
+  }
+}
+
+// table upload and outlier setup of a general plan: per direction one FP64
+// and one FP32 blob (tw | tf | AL | AR | Vt | lam | s | Kb | Mb), the outlier
+// pencil solved on the device straight into both blobs
+int setup_general(Plan& P, void* d_tables, hipStream_t s) {
+  std::vector<char> buf(P.lay.total, 0);
+  for (int k = 0; k < P.d; ++k) {
+    const GDir& G = P.dirs[k];
+    std::vector<double> blob((size_t)G.len, 0.0);
+    std::copy(G.tw.begin(), G.tw.end(), blob.begin() + G.o_tw);
+    std::copy(G.tf.begin(), G.tf.end(), blob.begin() + G.o_tf);
+    std::copy(G.AL.begin(), G.AL.end(), blob.begin() + G.o_al);
+    std::copy(G.AR.begin(), G.AR.end(), blob.begin() + G.o_ar);
+    std::copy(G.lam.begin(), G.lam.end(), blob.begin() + G.o_lam);
+    std::copy(G.s.begin(), G.s.end(), blob.begin() + G.o_s);
+    std::copy(G.Kb.begin(), G.Kb.end(), blob.begin() + G.o_kb);
+    std::copy(G.Mb.begin(), G.Mb.end(), blob.begin() + G.o_mb);
+    put<double>(buf, G.blob64, blob);
+    put<float>(buf, G.blob32, blob);
+    put<double>(buf, G.ao64, G.Ao);
+    put<double>(buf, G.bo64, G.Bo);
+    put<double>(buf, G.vout64, G.Vout);
+  }
+  hipError_t e = hipMemcpyAsync(d_tables, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  char* b = (char*)d_tables;
+  for (int k = 0; k < P.d && e == hipSuccess; ++k) {
+    const GDir& G = P.dirs[k];
+    e = launch_setup_outliers_at((const double*)(b + G.ao64), (const double*)(b + G.bo64),
+                                 (const double*)(b + G.vout64), G.n_out, G.m, G.n_reg,
+                                 (double*)(b + G.blob64) + G.o_lam, (float*)(b + G.blob32) + G.o_lam,
+                                 (double*)(b + G.blob64) + G.o_vt, (float*)(b + G.blob32) + G.o_vt,
+                                 (double*)(b + G.stat64), s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "outlier setup");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "setup sync");
+  for (int k = 0; k < P.d; ++k) {
+    GDir& G = P.dirs[k];
+    if (G.n_out == 0) {
+      G.Vt.clear();
+      outlier_windows(G.Vt, 0, G.m, G.win32, G.win64);
+      continue;
+    }
+    std::vector<double> lam(G.m), vt((size_t)G.n_out * G.m);
+    double stat = 0.0;
+    e = hipMemcpy(&stat, b + G.stat64, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(lam.data(), b + G.blob64 + 8 * (size_t)G.o_lam, 8 * G.m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(vt.data(), b + G.blob64 + 8 * (size_t)G.o_vt, 8 * vt.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "setup readback");
+    if (stat > 0.0)
+      return fail(IFFD_E_INVAL, "direction " + std::to_string(k + 1) +
+                                    ": outlier pencil mass block not positive definite at pivot " +
+                                    std::to_string((int)stat));
+    if (stat != 0.0)
+      return fail(IFFD_E_INVAL, "direction " + std::to_string(k + 1) +
+                                    ": outlier pencil eigenpairs not finite and positive");
+    for (int j = G.n_reg; j < G.m; ++j) G.lam[j] = lam[j];
+    G.Vt = vt;
+    outlier_windows(G.Vt, G.n_out, G.m, G.win32, G.win64);
+  }
+  return IFFD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* iffd_last_error(void) { return g_err.c_str(); }
@@ -157,6 +251,41 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
   return IFFD_OK;
 }
 
+int iffd_plan_create_general(iffd_plan** out, int d, const int* n, const int* p,
+                             const int* dirichlet, const iffd_opts* opts) {
+  if (!out) return fail(IFFD_E_INVAL, "out is null");
+  *out = nullptr;
+  iffd_plan* pl = new iffd_plan();
+  std::string err;
+  int rc = build_plan_general(pl->P, d, n, p, dirichlet, opts, err);
+  if (rc != IFFD_OK) {
+    delete pl;
+    return fail(rc, err);
+  }
+  *out = pl;
+  return IFFD_OK;
+}
+
+int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count) {
+  if (!plan || !h_out) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (count < P.d) return fail(IFFD_E_WORKSPACE, "fewer entries than directions");
+  for (int k = 0; k < P.d; ++k) {
+    iffd_dir_info& I = h_out[k];
+    if (P.gen) {
+      const GDir& G = P.dirs[k];
+      I.n = G.n; I.p = G.p; I.dirichlet_lo = G.dlo; I.dirichlet_hi = G.dhi;
+      I.m = G.m; I.n_reg = G.n_reg; I.n_out = G.n_out; I.fft_len = G.L;
+    } else {
+      const bool fft = P.method == IFFD_METHOD_FFT;
+      I.n = P.n; I.p = P.p; I.dirichlet_lo = 1; I.dirichlet_hi = 1;
+      I.m = P.m; I.n_reg = fft ? P.n_reg : P.m; I.n_out = fft ? P.n_out : 0;
+      I.fft_len = fft ? P.L : 0;
+    }
+  }
+  return IFFD_OK;
+}
+
 void iffd_plan_destroy(iffd_plan* plan) {
   if (!plan) return;
   {
@@ -192,6 +321,15 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
   if (table_bytes < P.lay.total) return fail(IFFD_E_WORKSPACE, "table buffer too small");
   if (!aligned256(d_tables)) return fail(IFFD_E_INVAL, "table buffer must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
+  if (P.gen) {
+    P.ready = false;
+    const int rc = setup_general(P, d_tables, s);
+    if (rc != IFFD_OK) return rc;
+    P.d_tables = (char*)d_tables;
+    P.table_bytes = table_bytes;
+    P.ready = true;
+    return IFFD_OK;
+  }
   const TableLayout& t = P.lay;
   std::vector<char> buf(t.total, 0);
   put<double>(buf, t.lam64, P.lam);
@@ -273,27 +411,7 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     for (int k = P.n_reg; k < P.m; ++k) P.lam[k] = lam[k];
     P.Vt = vt;
   }
-  // outlier windows: the entries of the rotated outlier basis decay
-  // geometrically away from the two ends; entries below 2^-30 (FP32 apply) or
-  // 2^-60 (FP64 apply) of the largest contribute below the working precision
-  // to the dots and the rank-n_out update, so only the two end windows are used
-  for (int w = 0; w < 2; ++w) {
-    int* win = w == 0 ? P.win32 : P.win64;
-    win[0] = P.m;
-    win[1] = P.m;
-    if (P.method != IFFD_METHOD_FFT || P.n_out == 0) continue;
-    const double thr = std::ldexp(1.0, w == 0 ? -30 : -60);
-    double mx = 0.0;
-    for (double v : P.Vt) mx = std::max(mx, std::fabs(v));
-    int lo = 0, hi = P.m;   // left window [0, lo), right window [hi, m)
-    for (int j = 0; j < P.m; ++j)
-      for (int q = 0; q < P.n_out; ++q)
-        if (std::fabs(P.Vt[(size_t)q * P.m + j]) > thr * mx) {
-          if (j < P.m / 2) lo = std::max(lo, j + 1);
-          else hi = std::min(hi, j);
-        }
-    if (lo < hi) { win[0] = lo; win[1] = hi; }
-  }
+  outlier_windows(P.Vt, P.method == IFFD_METHOD_FFT ? P.n_out : 0, P.m, P.win32, P.win64);
   if (P.method == IFFD_METHOD_FFT) {
     // the line-pass tables as one contiguous blob (one load sweep per block)
     std::vector<double> blob((size_t)P.blob_len, 0.0);
@@ -321,10 +439,36 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
   return IFFD_OK;
 }
 
-int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream) {
-  (void)stream;
+int iffd_plan_read_dir(const iffd_plan* plan, int direction, int what, double* h_out,
+                       size_t count, void* stream) {
   if (!plan || !h_out) return fail(IFFD_E_INVAL, "null argument");
   const Plan& P = plan->P;
+  if (direction < 1 || direction > P.d) return fail(IFFD_E_INVAL, "direction out of range");
+  if (!P.gen) return iffd_plan_read(plan, what, h_out, count, stream);
+  const GDir& G = P.dirs[direction - 1];
+  const std::vector<double>* v = nullptr;
+  switch (what) {
+    case 0: v = &G.lam; break;
+    case 1: v = &G.Dt; break;
+    case 2: case 7: v = &G.Kb; break;
+    case 3: v = &G.Mb; break;
+    case 4: v = &G.AL; break;
+    case 5: v = &G.AR; break;
+    case 6:
+      if (!P.ready) return fail(IFFD_E_STATE, "Vt is available after iffd_plan_setup");
+      v = &G.Vt;
+      break;
+    default: return fail(IFFD_E_INVAL, "unknown table id");
+  }
+  if (count < v->size()) return fail(IFFD_E_WORKSPACE, "output array too small");
+  std::copy(v->begin(), v->end(), h_out);
+  return IFFD_OK;
+}
+
+int iffd_plan_read(const iffd_plan* plan, int what, double* h_out, size_t count, void* stream) {
+  if (!plan || !h_out) return fail(IFFD_E_INVAL, "null argument");
+  const Plan& P = plan->P;
+  if (P.gen) return iffd_plan_read_dir(plan, 1, what, h_out, count, stream);
   const std::vector<double>* v = nullptr;
   switch (what) {
     case 0: v = &P.lam; break;
@@ -385,6 +529,7 @@ int iffd_apply_pass(const iffd_plan* plan, int pass, const double* d_r, double* 
 
 int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant) {
   if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  if (plan->P.gen) return fail(IFFD_E_UNSUPPORTED, "general plans have a single FFT shape");
   if (pass < 0 || pass >= 2 * plan->P.d - 1 || variant < 0 || variant > 4)
     return fail(IFFD_E_INVAL, "pass or variant out of range");
   plan->P.variant[pass] = variant;
@@ -394,6 +539,7 @@ int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant) {
 int iffd_plan_get_variant(const iffd_plan* plan, int pass) {
   if (!plan) return fail(IFFD_E_INVAL, "null argument");
   if (pass < 0 || pass >= 2 * plan->P.d - 1) return fail(IFFD_E_INVAL, "pass out of range");
+  if (plan->P.gen) return 1;
   return plan->P.variant[pass];
 }
 
@@ -401,7 +547,7 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
   if (!plan || !d_scratch) return fail(IFFD_E_INVAL, "null argument");
   Plan& P = plan->P;
   if (!P.ready) return fail(IFFD_E_STATE, "plan not set up");
-  if (P.method != IFFD_METHOD_FFT) return IFFD_OK;
+  if (P.method != IFFD_METHOD_FFT || P.gen) return IFFD_OK;
   const size_t need = 16 * (size_t)P.N + apply_ws_bytes(P, 1);
   if (scratch_bytes < need) return fail(IFFD_E_WORKSPACE, "tuning scratch too small");
   if (!aligned256(d_scratch)) return fail(IFFD_E_INVAL, "scratch must be 256-byte aligned");

@@ -76,6 +76,10 @@ hipError_t launch_line_pass(const Plan& P, int mode, int axis, int tin, const vo
 hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z, int nrhs,
                             void* ws, const double* a, int as, hipStream_t s,
                             const PassHook* last, const PassHook* first) {
+  if (P.gen) {
+    if (last || first) return hipErrorInvalidValue;   // general plans fuse nothing
+    return launch_gen_pass(P, pass, r, z, nrhs, ws, a, as, s);
+  }
   const int d = P.d;
   const bool f64 = P.prec == IFFD_PREC_F64;
   const int et = f64 ? ELEM_F64 : ELEM_F32;
@@ -123,7 +127,7 @@ static int tw_min_p(bool f64) {
 }
 
 int apply_last_tiles_max(const Plan& P) {
-  if (P.method != IFFD_METHOD_FFT) return 1;
+  if (P.method != IFFD_METHOD_FFT || P.gen) return 1;
   const bool f64 = P.prec == IFFD_PREC_F64;
   int tw = 1;
   switch (P.L) {

@@ -1,0 +1,451 @@
+#pragma once
+// IFFD line passes of general plans on gfx950: every direction has its own n,
+// p and Dirichlet / Neumann ends (Section 4, "other boundary conditions";
+// Table 1; Section 6).  Kernel templates; instantiated per FFT length in
+// gen_l*.hip, dispatched in gen.hip.
+//
+// Per line along direction k (length m), with V_reg = blkdiag(AL, I, AR) in
+// the special basis and U_{s,t} = sin(pi (s + sig)(t + tau) / n + beta) the
+// transform of Table 1 (sig, tau in {0, 1/2, 1}, beta in {0, pi/2}):
+//   forward   y_reg = U^T fold(x),  y_out = Vt x
+//   backward  x = unfold(U y_reg) + Vt^T y_out
+// fold = V_reg^T (AL^T on the first rl entries, AR^T on the last rr, the
+// interior passes through), unfold = V_reg.  Both products with U run through
+// one complex FFT of length L = 2n per pair of real lines a, b:
+//   y_t = -Im[ post_t * A_t ],  A_t = sum_s g_s pre_s e^{-2 pi i s t / L},
+// with pre_s = e^{-i pi s tau / n}, post_t = e^{-i (beta + pi sig (t + tau) / n)}
+// (forward; sig and tau swap roles backward).  A_t has the symmetry
+// conj(A_t) = A_{-t - 2 tau}, so the transform Z of (g_a + i g_b) pre splits
+// into A = (Z_t + conj Z_t') / 2 and B = (Z_t - conj Z_t') / (2i), t' = -t -
+// 2 tau mod L, which gives y_a = -Im[post (Z_t + conj Z_t')] / 2 and
+// y_b = Re[post (Z_t - conj Z_t')] / 2.
+//
+// One workgroup owns TW lines of one right-hand side, staged through LDS with
+// coalesced loads (lines along direction 1 are contiguous rows; lines along a
+// strided direction are taken TW at a time from consecutive positions of the
+// faster directions, each padded run of direction-1 positions having an even
+// length so that the two lines of an FFT pair always belong to one run).  The
+// middle pass (along direction d) runs forward, scales by the Kronecker sum
+// of the eigenvalues and runs backward without leaving LDS.
+#include "fft_device.h"
+#include "launch.h"
+
+namespace iffd {
+
+template <int L>
+struct GCfg {
+  static constexpr int E = FftPlan<L, 1>::E;
+  static constexpr int NT = L / E;   // threads per transform
+  static constexpr int CAP = 256 / NT;
+  static constexpr int FPW = CAP >= 32 ? 32 : (CAP < 1 ? 1 : CAP);  // line pairs per workgroup
+  static constexpr int TW = 2 * FPW;  // lines per workgroup (a power of two)
+  static constexpr int NTH = FPW * NT;
+};
+
+// one direction's tables in its blob (element offsets) and sizes
+template <typename T>
+struct GDirDev {
+  const T* blob;  // tw | tf | AL | AR | Vt | lam | s | ...
+  int o_tw, o_tf, o_al, o_ar, o_vt, o_lam, o_s;
+  int m, n_reg, n_out, rl, cl, rr, cr;
+  int mir_f, mir_b;  // 2 tau, 2 sig: the index shift of the spectral symmetry
+  int wl, wr;        // outlier windows: Vt[q][j] used for j < wl and j >= wr
+};
+
+template <typename T>
+struct GPassArgs {
+  GDirDev<T> dir;
+  int S;    // element stride along the pass's direction
+  int m1;   // extent of direction 1
+  int mr;   // S > 1: padded run of direction-1 positions (m1 rounded up to even)
+  int sm;   // S > 1: S / m1
+  int lpr;  // lines per right-hand side (padded for S > 1)
+  int tpr;  // tiles per right-hand side
+  int N;    // elements per right-hand side
+  // middle pass: eigenvalues and scalings of direction 1 and (3D) direction 2
+  const T* lam1;
+  const T* s1;
+  const T* lam2;
+  const T* s2;
+  const double* active;  // per-RHS flags (0 = skip) or null
+  int astride;
+};
+
+struct GLds {
+  size_t tw, x, f, gb, yo, lb, lo, so, total;
+};
+
+__host__ __device__ inline size_t gup16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+template <typename T, int L>
+__host__ __device__ inline GLds gen_lds(int m) {
+  using C = GCfg<L>;
+  const int MP = m | 1;
+  GLds r;
+  size_t o = 0;
+  r.tw = o; o = gup16(o + 2 * sizeof(T) * L);
+  r.x = o;  o = gup16(o + sizeof(T) * C::TW * MP);
+  r.f = o;  o = gup16(o + 2 * sizeof(T) * C::FPW * fft_region<L>());
+  r.gb = o; o = gup16(o + sizeof(T) * C::TW * 8);
+  r.yo = o; o = gup16(o + sizeof(T) * C::TW * 8);
+  r.lb = o; o = gup16(o + sizeof(int) * C::TW);
+  r.lo = o; o = gup16(o + sizeof(T) * C::TW);
+  r.so = o; o = gup16(o + sizeof(T) * C::TW);
+  r.total = o;
+  return r;
+}
+
+// First element of line q of the pass (-1 if q is a padding line); for the
+// middle pass also the line's spectral positions along directions 1 and 2.
+template <typename T>
+__device__ __forceinline__ int gen_line(const GPassArgs<T>& a, int q, int& i1, int& i2) {
+  i1 = 0;
+  i2 = 0;
+  if (q >= a.lpr) return -1;
+  if (a.S == 1) return q * a.dir.m;
+  const int r = q % a.mr, rest = q / a.mr;
+  if (r >= a.m1) return -1;
+  const int j2 = rest % a.sm, outer = rest / a.sm;
+  i1 = r;
+  i2 = j2;
+  return outer * a.dir.m * a.S + j2 * a.m1 + r;
+}
+
+// g_s of the folded line (forward input of U^T): AL^T x on the first cl
+// entries, AR^T x on the last cr (held in gb), x itself in between
+template <typename T>
+__device__ __forceinline__ T fold_at(const T* x, const T* gb, int s, int cl, int ncr, int off) {
+  if (s < cl) return gb[s];
+  if (s >= ncr) return gb[cl + s - ncr];
+  return x[s + off];
+}
+
+template <typename Tin, typename Tout, typename T, int MODE, int L>
+__global__ void __launch_bounds__(GCfg<L>::NTH)
+gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a) {
+  using C = GCfg<L>;
+  constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
+  extern __shared__ __align__(16) char smem[];
+  const GDirDev<T>& D = a.dir;
+  const int m = D.m, nr = D.n_reg, no = D.n_out, cl = D.cl, cr = D.cr, rl = D.rl, rr = D.rr;
+  const int MP = m | 1, off = rl - cl, ncr = nr - cr;
+  const GLds ly = gen_lds<T, L>(m);
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + ly.tw);
+  T* X = reinterpret_cast<T*>(smem + ly.x);
+  cpx<T>* F = reinterpret_cast<cpx<T>*>(smem + ly.f);
+  T* GB = reinterpret_cast<T*>(smem + ly.gb);
+  T* YO = reinterpret_cast<T*>(smem + ly.yo);
+  int* LB = reinterpret_cast<int*>(smem + ly.lb);
+  T* LO = reinterpret_cast<T*>(smem + ly.lo);
+  T* SO = reinterpret_cast<T*>(smem + ly.so);
+  const int tid = threadIdx.x;
+
+  const int b = xcd_linear(blockIdx.x, gridDim.x);
+  const int rhs = b / a.tpr, tile = b - rhs * a.tpr;
+  if (a.active && a.active[(size_t)rhs * a.astride] == 0.0) return;
+  const int q0 = tile * TW;
+  const Tin* src = in + (size_t)rhs * a.N;
+  Tout* dst = out + (size_t)rhs * a.N;
+
+  {
+    const cpx<T>* g = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tw);
+    for (int k = tid; k < L; k += NTH) tw[k] = g[k];
+  }
+  if (tid < TW) {
+    int i1, i2;
+    LB[tid] = gen_line(a, q0 + tid, i1, i2);
+    if constexpr (MODE == PASS_MID) {
+      T lo = a.lam1[i1], so = a.s1[i1];
+      if (a.lam2) {
+        lo += a.lam2[i2];
+        so *= a.s2[i2];
+      }
+      LO[tid] = lo;
+      SO[tid] = so;
+    }
+  }
+  __syncthreads();
+
+  // ---- load the tile: X[l][i] = line l, entry i ----
+  if (a.S == 1) {
+    const int nl = min(TW, a.lpr - q0);
+    const size_t base = (size_t)q0 * m;
+    for (int e = tid; e < TW * m; e += NTH) {
+      const int l = e / m;
+      X[l * MP + (e - l * m)] = l < nl ? (T)src[base + e] : T(0);
+    }
+  } else {
+    for (int e = tid; e < TW * m; e += NTH) {
+      const int l = e & (TW - 1), i = e / TW;
+      const int bl = LB[l];
+      X[l * MP + i] = bl >= 0 ? (T)src[(size_t)bl + (size_t)i * a.S] : T(0);
+    }
+  }
+  __syncthreads();
+
+  const T* AL = D.blob + D.o_al;
+  const T* AR = D.blob + D.o_ar;
+  const T* Vt = D.blob + D.o_vt;
+  const cpx<T>* TF = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tf);
+  const int f = tid / NT, lane = tid - (tid / NT) * NT;
+  cpx<T>* buf = F + f * fft_region<L>();
+  const int la = 2 * f, lb = 2 * f + 1;
+
+  if constexpr (MODE != PASS_BWD) {
+    // ---- boundary fold values and outlier coefficients ----
+    const int nbv = cl + cr;
+    for (int w = tid; w < TW * (nbv + no); w += NTH) {
+      const int l = w & (TW - 1), k = w / TW;
+      const T* x = X + l * MP;
+      T acc = T(0);
+      if (k < cl) {
+        for (int r = 0; r < rl; ++r) acc += AL[r * cl + k] * x[r];
+        GB[l * 8 + k] = acc;
+      } else if (k < nbv) {
+        const int kk = k - cl;
+        for (int r = 0; r < rr; ++r) acc += AR[r * cr + kk] * x[m - rr + r];
+        GB[l * 8 + k] = acc;
+      } else {
+        const int q = k - nbv;
+        const T* v = Vt + q * m;
+        for (int j = 0; j < D.wl; ++j) acc += v[j] * x[j];
+        for (int j = D.wr; j < m; ++j) acc += v[j] * x[j];
+        YO[l * 8 + q] = acc;
+      }
+    }
+    __syncthreads();
+    // ---- y_reg = U^T g ----
+    {
+      const T* xa = X + la * MP;
+      const T* xb = X + lb * MP;
+      const T* ga = GB + la * 8;
+      const T* gbb = GB + lb * 8;
+      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
+        if (k >= nr) return cpx<T>{T(0), T(0)};
+        const cpx<T> v{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
+        return c_mul(v, TF[k]);
+      };
+      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
+      fft_forward<T, L, 1>(buf, lane, tw, ld, st);
+    }
+    __syncthreads();
+    {
+      const cpx<T>* post = TF + nr;
+      const int mir = D.mir_f;
+      const T* lamd = D.blob + D.o_lam;
+      const T* sd = D.blob + D.o_s;
+      for (int t = lane; t < nr; t += NT) {
+        const cpx<T> z1 = buf[fpad<L>(t)];
+        int t2 = L - t - mir;
+        if (t2 >= L) t2 -= L;
+        cpx<T> z2 = buf[fpad<L>(t2)];
+        z2.y = -z2.y;
+        const cpx<T> P = post[t];
+        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
+        T ya = -sp.y * T(0.5), yb = sm.x * T(0.5);
+        if constexpr (MODE == PASS_MID) {
+          const T l = lamd[t], s = sd[t];
+          ya *= s * SO[la] / (l + LO[la]);
+          yb *= s * SO[lb] / (l + LO[lb]);
+        }
+        X[la * MP + t] = ya;
+        X[lb * MP + t] = yb;
+      }
+      if constexpr (MODE == PASS_MID) {
+        for (int w = tid; w < TW * no; w += NTH) {
+          const int l = w & (TW - 1), q = w / TW;
+          YO[l * 8 + q] *= SO[l] / (lamd[nr + q] + LO[l]);
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (MODE == PASS_FWD) {
+      // ---- store y = [y_reg; y_out] ----
+      if (a.S == 1) {
+        const int nl = min(TW, a.lpr - q0);
+        const size_t base = (size_t)q0 * m;
+        for (int e = tid; e < nl * m; e += NTH) {
+          const int l = e / m, i = e - l * m;
+          dst[base + e] = (Tout)(i < nr ? X[l * MP + i] : YO[l * 8 + i - nr]);
+        }
+      } else {
+        for (int e = tid; e < TW * m; e += NTH) {
+          const int l = e & (TW - 1), i = e / TW;
+          const int bl = LB[l];
+          if (bl >= 0) dst[(size_t)bl + (size_t)i * a.S] = (Tout)(i < nr ? X[l * MP + i] : YO[l * 8 + i - nr]);
+        }
+      }
+      return;
+    }
+  } else {
+    // outlier coefficients of the spectral input
+    for (int w = tid; w < TW * no; w += NTH) {
+      const int l = w & (TW - 1), q = w / TW;
+      YO[l * 8 + q] = X[l * MP + nr + q];
+    }
+    __syncthreads();
+  }
+
+  if constexpr (MODE != PASS_FWD) {
+    // ---- c = U y_reg ----
+    {
+      const T* xa = X + la * MP;
+      const T* xb = X + lb * MP;
+      const cpx<T>* pre = TF + 2 * nr;
+      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
+        if (k >= nr) return cpx<T>{T(0), T(0)};
+        return c_mul(cpx<T>{xa[k], xb[k]}, pre[k]);
+      };
+      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
+      fft_forward<T, L, 1>(buf, lane, tw, ld, st);
+    }
+    __syncthreads();
+    {
+      // c_s lands at X[l][off + s]: the interior rows of x = V_reg c read it in place
+      const cpx<T>* post = TF + 3 * nr;
+      const int mir = D.mir_b;
+      for (int t = lane; t < nr; t += NT) {
+        const cpx<T> z1 = buf[fpad<L>(t)];
+        int t2 = L - t - mir;
+        if (t2 >= L) t2 -= L;
+        cpx<T> z2 = buf[fpad<L>(t2)];
+        z2.y = -z2.y;
+        const cpx<T> P = post[t];
+        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
+        X[la * MP + off + t] = -sp.y * T(0.5);
+        X[lb * MP + off + t] = sm.x * T(0.5);
+      }
+    }
+    __syncthreads();
+    // ---- x = V_reg c + Vt^T y_out, stored ----
+    auto value = [&](int l, int r) -> T {
+      const T* x = X + l * MP;
+      T v;
+      if (r < rl) {
+        v = T(0);
+        for (int c = 0; c < cl; ++c) v += AL[r * cl + c] * x[off + c];
+      } else if (r >= m - rr) {
+        const int rr0 = r - (m - rr);
+        v = T(0);
+        for (int c = 0; c < cr; ++c) v += AR[rr0 * cr + c] * x[m - rr + c];
+      } else {
+        v = x[r];
+      }
+      if (r < D.wl || r >= D.wr) {
+        const T* yo = YO + l * 8;
+        for (int q = 0; q < no; ++q) v += Vt[q * m + r] * yo[q];
+      }
+      return v;
+    };
+    if (a.S == 1) {
+      const int nl = min(TW, a.lpr - q0);
+      const size_t base = (size_t)q0 * m;
+      for (int e = tid; e < nl * m; e += NTH) {
+        const int l = e / m, r = e - l * m;
+        dst[base + e] = (Tout)value(l, r);
+      }
+    } else {
+      for (int e = tid; e < TW * m; e += NTH) {
+        const int l = e & (TW - 1), r = e / TW;
+        const int bl = LB[l];
+        if (bl >= 0) dst[(size_t)bl + (size_t)r * a.S] = (Tout)value(l, r);
+      }
+    }
+  }
+}
+
+// launch of one pass (host side); the plan's direction `axis` (1-based)
+template <typename Tin, typename Tout, typename T, int MODE, int L>
+hipError_t gen_launch(const Plan& P, int axis, const void* in, void* out, int nrhs,
+                      const double* active, int astride, hipStream_t s) {
+  using C = GCfg<L>;
+  const GDir& G = P.dirs[axis - 1];
+  if (G.L != L || G.n_out > 8 || G.cl + G.cr > 8) return hipErrorInvalidValue;
+  const bool f64 = sizeof(T) == 8;
+  GPassArgs<T> a;
+  const char* tb = P.d_tables;
+  auto blob_of = [&](const GDir& g) { return (const T*)(tb + (f64 ? g.blob64 : g.blob32)); };
+  a.dir.blob = blob_of(G);
+  a.dir.o_tw = G.o_tw; a.dir.o_tf = G.o_tf; a.dir.o_al = G.o_al; a.dir.o_ar = G.o_ar;
+  a.dir.o_vt = G.o_vt; a.dir.o_lam = G.o_lam; a.dir.o_s = G.o_s;
+  a.dir.m = G.m; a.dir.n_reg = G.n_reg; a.dir.n_out = G.n_out;
+  a.dir.rl = G.rl; a.dir.cl = G.cl; a.dir.rr = G.rr; a.dir.cr = G.cr;
+  a.dir.mir_f = G.tau2;
+  a.dir.mir_b = G.sig2;
+  a.dir.wl = f64 ? G.win64[0] : G.win32[0];
+  a.dir.wr = f64 ? G.win64[1] : G.win32[1];
+  int S = 1;
+  for (int k = 0; k < axis - 1; ++k) S *= P.dirs[k].m;
+  a.S = S;
+  a.m1 = P.dirs[0].m;
+  a.N = (int)P.N;
+  if (S == 1) {
+    a.mr = a.m1;
+    a.sm = 1;
+    a.lpr = (int)(P.N / G.m);
+  } else {
+    a.mr = a.m1 + (a.m1 & 1);
+    a.sm = S / a.m1;
+    a.lpr = (int)(P.N / G.m / a.m1) * a.mr;
+  }
+  a.tpr = (a.lpr + C::TW - 1) / C::TW;
+  a.lam1 = a.s1 = a.lam2 = a.s2 = nullptr;
+  if (MODE == PASS_MID) {
+    const GDir& g1 = P.dirs[0];
+    a.lam1 = blob_of(g1) + g1.o_lam;
+    a.s1 = blob_of(g1) + g1.o_s;
+    if (P.d == 3) {
+      const GDir& g2 = P.dirs[1];
+      a.lam2 = blob_of(g2) + g2.o_lam;
+      a.s2 = blob_of(g2) + g2.o_s;
+    }
+  }
+  a.active = active;
+  a.astride = astride;
+  const GLds ly = gen_lds<T, L>(G.m);
+  static bool attr = false;
+  if (ly.total > 65536 && !attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)gen_line_pass<Tin, Tout, T, MODE, L>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((gen_line_pass<Tin, Tout, T, MODE, L>), dim3((unsigned)(a.tpr * nrhs)),
+                     dim3(C::NTH), ly.total, s, (const Tin*)in, (Tout*)out, a);
+  return hipGetLastError();
+}
+
+// element types of one pass for one FFT length (instantiated per length)
+template <int L>
+hipError_t gen_pass_len(const Plan& P, int mode, int axis, int tin, const void* in, int tout,
+                        void* out, int nrhs, const double* a, int as, hipStream_t s) {
+  if (P.prec == IFFD_PREC_F64) {
+    if (tin != ELEM_F64 || tout != ELEM_F64) return hipErrorInvalidValue;
+    if (mode == PASS_FWD) return gen_launch<double, double, double, PASS_FWD, L>(P, axis, in, out, nrhs, a, as, s);
+    if (mode == PASS_MID) return gen_launch<double, double, double, PASS_MID, L>(P, axis, in, out, nrhs, a, as, s);
+    return gen_launch<double, double, double, PASS_BWD, L>(P, axis, in, out, nrhs, a, as, s);
+  }
+  if (mode == PASS_FWD) {
+    if (tin == ELEM_F64 && tout == ELEM_F32 && P.first64)
+      return gen_launch<double, float, double, PASS_FWD, L>(P, axis, in, out, nrhs, a, as, s);
+    if (tin == ELEM_F64 && tout == ELEM_F32)
+      return gen_launch<double, float, float, PASS_FWD, L>(P, axis, in, out, nrhs, a, as, s);
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return gen_launch<float, float, float, PASS_FWD, L>(P, axis, in, out, nrhs, a, as, s);
+  } else if (mode == PASS_BWD) {
+    if (tin == ELEM_F32 && tout == ELEM_F64)
+      return gen_launch<float, double, float, PASS_BWD, L>(P, axis, in, out, nrhs, a, as, s);
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return gen_launch<float, float, float, PASS_BWD, L>(P, axis, in, out, nrhs, a, as, s);
+  } else {
+    if (tin == ELEM_F32 && tout == ELEM_F32)
+      return gen_launch<float, float, float, PASS_MID, L>(P, axis, in, out, nrhs, a, as, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define IFFD_GEN_PASS_LEN(L)                                                                  \
+  hipError_t gen_pass_len<L>(const Plan&, int, int, int, const void*, int, void*, int,        \
+                             const double*, int, hipStream_t)
+
+}  // namespace iffd

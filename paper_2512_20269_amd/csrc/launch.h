@@ -98,6 +98,24 @@ hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, 
 
 // Outlier pencil eigensolve + table completion (FP64, on device).
 hipError_t launch_setup_outliers(const Plan& P, hipStream_t s);
+// The same for one pencil given by pointers (n_out <= 8): writes the outlier
+// eigenvalues at lam[n_reg ..], the rotated basis Vt (n_out x m) and a status
+// word (0 = ok).
+hipError_t launch_setup_outliers_at(const double* Ao, const double* Bo, const double* Vout, int no,
+                                    int m, int n_reg, double* lam64, float* lam32, double* vt64,
+                                    float* vt32, double* stat, hipStream_t s);
+
+// General plans (gen.hip): one pass of the apply (as launch_iffd_pass), the
+// whole apply, and the operator (as launch_matvec).
+hipError_t launch_gen_pass(const Plan& P, int pass, const double* r, double* z, int nrhs, void* ws,
+                           const double* active, int active_stride, hipStream_t s);
+hipError_t launch_gen_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
+                            const double* active, int active_stride, hipStream_t s);
+hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
+                             double* part, int npart, const double* active, int active_stride,
+                             hipStream_t s, const double* fres);
+int gen_matvec_blocks(const Plan& P);
+size_t gen_matvec_ws_bytes(const Plan& P, int nrhs);
 
 // y = Ahat x; ws: matvec_ws_bytes(P, nrhs); optional fused partial sums per
 // workgroup: part[b][blk] = sum x.y, or sum (f - y)^2 when fres (the true

@@ -395,6 +395,14 @@ hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// the preconditioner without fused PCG steps: dense FD, or the line passes of
+// a general plan (the r . z and residual updates then run as kernels of their own)
+static hipError_t plain_apply(const Plan& P, const double* r, double* z, int nslots, void* ws,
+                              const double* a, int as, hipStream_t s) {
+  return P.gen ? launch_gen_apply(P, r, z, nslots, ws, a, as, s)
+               : launch_fd_apply(P, r, z, nslots, ws, a, as, s);
+}
+
 hipError_t state_init(const Plan& P, char* st, int nslots, hipStream_t s) {
   const StateLayout L = state_layout(P, nslots);
   const size_t n = (L.part - L.scal) / 8;  // scalars + history
@@ -429,14 +437,14 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   // p = z = P^{-1} r for the new slots only, written straight into p (IFFD:
   // r . z partials from its last pass)
   int nrz = nb;
-  if (P.method == IFFD_METHOD_FFT) {
+  if (P.method == IFFD_METHOD_FFT && !P.gen) {
     const PassHook hk{r, part, nb, 0};
     e = launch_iffd_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s,
                           &hk);
     if (e != hipSuccess) return e;
     nrz = hk.tiles;
   } else {
-    e = launch_fd_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
+    e = plain_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, p, N, nb, part, scal,
                        (int)S_NEW);
@@ -464,7 +472,7 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pcg_alpha, dim3(nslots), dim3(VT), 0, s, scal, part2, nmv, nb, nslots);
     int nrz = nb;
-    if (P.method == IFFD_METHOD_FFT) {
+    if (P.method == IFFD_METHOD_FFT && !P.gen) {
       // the apply's first pass takes r <- r - alpha q on its way in (r.r
       // partials), the residual test follows it, so the other passes skip the
       // slots that converged; r.z partials come from the last pass
@@ -486,7 +494,7 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
       hipLaunchKernelGGL(pcg_update_r, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, scal,
                          part);
       hipLaunchKernelGGL(pcg_check, dim3(nslots), dim3(VT), 0, s, scal, hist, part, nb, nb, nslots);
-      e = launch_fd_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
+      e = plain_apply(P, r, qz, nslots, ws, scal + S_ACTIVE, kScal, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(dot_partials, dim3(nslots * nb), dim3(VT), 0, s, r, qz, N, nb, part, scal,
                          (int)S_ACTIVE);

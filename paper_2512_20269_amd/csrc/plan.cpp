@@ -163,6 +163,23 @@ double lambda_reg_closed(int n, int p, int j) {
   return (double)(4 * (R)n * (R)n * s * s * sK / sM);
 }
 
+// The same closed form at theta = j2 pi / (2n) (j2 an integer), the
+// frequencies alpha_j / n of every row of Table 1: j pi / n (Dirichlet at both
+// ends), (j - 1/2) pi / n (one Dirichlet end), (j - 1) pi / n (none).
+double lambda_reg_half(int n, int p, int j2) {
+  typedef long double R;
+  const R pi = kPi;
+  R sM = cardinal_t<R>(2 * p + 1, R(0)), sK = cardinal_t<R>(2 * p - 1, R(0));
+  for (int k = 1; k <= p; ++k) {
+    const long long a = ((long long)k * j2) % (4LL * n);
+    const R c = std::cos(pi * (R)a / (R)(2 * n));
+    sM += 2 * cardinal_t<R>(2 * p + 1, (R)k) * c;
+    if (k <= p - 1) sK += 2 * cardinal_t<R>(2 * p - 1, (R)k) * c;
+  }
+  const R s = std::sin(pi * (R)j2 / (R)(4 * n));
+  return (double)(4 * (R)n * (R)n * s * s * sK / sM);
+}
+
 // Dense LU with partial pivoting; solves A X = B in place (A n x n, B n x k),
 // both row-major.  Returns false if singular.
 bool lu_solve(int n, std::vector<double> A, std::vector<double>& B, int k) {
@@ -744,6 +761,415 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     P.twp[2 * j + 1] = (double)-std::sin(kPi * j / (2 * n));
   }
   compute_layout(P);
+  return IFFD_OK;
+}
+
+}  // namespace iffd
+
+// ===========================================================================
+// General plans: per direction its own n, p and Dirichlet / Neumann ends
+// (Section 4, "other boundary conditions"; Table 1; Section 6).
+// ===========================================================================
+namespace iffd {
+namespace {
+
+// Left-end block of the special basis for one end type (eq:special_basis):
+// the functions of B_L as combinations of the reduced B-splines 0 .. rows-1,
+// rows = p - dir (dir = 1 for a Dirichlet end, whose B_0 is dropped).
+//   Dirichlet:        Bt_i - Bt_{dp-i}, i = 1 .. floor(p/2)   (odd reflection)
+//   Neumann, p even:  Bt_i + Bt_{1-i}, i = 1 .. p/2           (even reflection)
+//   Neumann, p odd:   Bt_0, then Bt_i + Bt_{-i}, i = 1 .. (p-1)/2
+// with Bt_k the cardinal B-spline centred at k h (p odd) or (k - 1/2) h (p
+// even) and dp = 1 for even p, 0 for odd p.  The coefficients come from
+// collocation at the Greville points of those B-splines and are checked at
+// the element midpoints of the end region (each function must lie in their
+// span).
+int end_block(int n, int p, int dir, const std::vector<double>& U, std::vector<double>& A,
+              int& rows, int& cols, std::string& err) {
+  const double h = 1.0 / n;
+  const int nb = n + p, dp = (p % 2) ? 0 : 1;
+  std::vector<std::vector<std::pair<int, int>>> F;  // (sign, k) terms per function
+  if (dir) {
+    for (int i = 1; i <= p / 2; ++i) F.push_back({{1, i}, {-1, dp - i}});
+  } else if (p % 2 == 0) {
+    for (int i = 1; i <= p / 2; ++i) F.push_back({{1, i}, {1, 1 - i}});
+  } else {
+    F.push_back({{1, 0}});
+    for (int i = 1; i <= (p - 1) / 2; ++i) F.push_back({{1, i}, {1, -i}});
+  }
+  rows = p - dir;
+  cols = (int)F.size();
+  A.assign((size_t)rows * cols, 0.0);
+  if (rows == 0 || cols == 0) return IFFD_OK;
+  auto fval = [&](int c, double x) {
+    double v = 0.0;
+    for (auto& t : F[c]) {
+      const double ck = (p % 2) ? t.second * h : (t.second - 0.5) * h;
+      v += t.first * cardinal(p, (x - ck) / h);
+    }
+    return v;
+  };
+  std::vector<double> val, der;
+  auto bvals = [&](double x, std::vector<double>& row) {  // reduced B-splines 0..rows-1 at x
+    const int s = find_span(nb, p, x, U);
+    basis_and_derivative(s, x, p, U, val, der);
+    row.assign(rows, 0.0);
+    for (int c = 0; c < rows; ++c) {
+      const int j = c + dir - (s - p);
+      if (j >= 0 && j <= p) row[c] = val[j];
+    }
+  };
+  std::vector<double> C((size_t)rows * rows), R((size_t)rows * cols), row;
+  for (int r = 0; r < rows; ++r) {
+    const int gi = r + dir;
+    double tau = 0.0;
+    for (int k = 1; k <= p; ++k) tau += U[gi + k];
+    tau /= p;
+    bvals(tau, row);
+    for (int c = 0; c < rows; ++c) C[(size_t)r * rows + c] = row[c];
+    for (int c = 0; c < cols; ++c) R[(size_t)r * cols + c] = fval(c, tau);
+  }
+  if (!lu_solve(rows, C, R, cols)) { err = "special basis collocation singular"; return IFFD_E_INVAL; }
+  A = R;
+  for (int e = 0; e < std::min(n, 2 * p + 2); ++e) {
+    const double x = (e + 0.5) * h;
+    bvals(x, row);
+    for (int c = 0; c < cols; ++c) {
+      double v = 0.0;
+      for (int r = 0; r < rows; ++r) v += A[(size_t)r * cols + c] * row[r];
+      if (std::fabs(v - fval(c, x)) > 1e-11) {
+        err = "special basis function outside the end B-splines' span";
+        return IFFD_E_INVAL;
+      }
+    }
+  }
+  return IFFD_OK;
+}
+
+// Orthonormal basis (rows x (rows - cols), row-major) of the orthogonal
+// complement of range(A), A rows x cols of full column rank: the trailing
+// columns of the Householder QR's Q.
+std::vector<double> complement(const std::vector<double>& A0, int rows, int cols) {
+  const int nc = rows - cols;
+  std::vector<double> W((size_t)rows * std::max(nc, 0), 0.0);
+  if (nc <= 0) return W;
+  std::vector<double> A = A0;
+  std::vector<std::vector<double>> vs;
+  for (int c = 0; c < cols; ++c) {
+    std::vector<double> v(rows, 0.0);
+    double nrm = 0;
+    for (int r = c; r < rows; ++r) nrm += A[(size_t)r * cols + c] * A[(size_t)r * cols + c];
+    nrm = std::sqrt(nrm);
+    const double alpha = A[(size_t)c * cols + c] >= 0 ? -nrm : nrm;
+    for (int r = c; r < rows; ++r) v[r] = A[(size_t)r * cols + c];
+    v[c] -= alpha;
+    double vn = 0;
+    for (int r = c; r < rows; ++r) vn += v[r] * v[r];
+    if (vn > 0)
+      for (int cc = c; cc < cols; ++cc) {
+        double dot = 0;
+        for (int r = c; r < rows; ++r) dot += v[r] * A[(size_t)r * cols + cc];
+        for (int r = c; r < rows; ++r) A[(size_t)r * cols + cc] -= 2 * dot / vn * v[r];
+      }
+    vs.push_back(v);
+  }
+  for (int j = 0; j < nc; ++j) {
+    std::vector<double> e(rows, 0.0);
+    e[cols + j] = 1.0;
+    for (int c = cols - 1; c >= 0; --c) {
+      const std::vector<double>& v = vs[c];
+      double vn = 0, dot = 0;
+      for (int r = 0; r < rows; ++r) { vn += v[r] * v[r]; dot += v[r] * e[r]; }
+      if (vn > 0)
+        for (int r = 0; r < rows; ++r) e[r] -= 2 * dot / vn * v[r];
+    }
+    for (int r = 0; r < rows; ++r) W[(size_t)r * nc + j] = e[r];
+  }
+  return W;
+}
+
+int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
+  G.n = n; G.p = p; G.dlo = dlo; G.dhi = dhi;
+  const int nb = n + p, bw = 2 * p + 1;
+  const int m = nb - dlo - dhi;
+  G.m = m;
+  // eq:reg_space_dim
+  if ((p % 2) && dlo && dhi) G.n_reg = n - 1;
+  else if ((p % 2) && !dlo && !dhi) G.n_reg = n + 1;
+  else G.n_reg = n;
+  G.n_out = m - G.n_reg;
+  G.L = 2 * n;
+  const double h = 1.0 / n;
+
+  // knots, 1-D matrices of the full basis (Sections 2, 3), reduction
+  std::vector<double> U(n + 2 * p + 1);
+  for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
+  for (int k = 1; k < n; ++k) U[p + k] = (double)k / n;
+  std::vector<double> gx, gw, val, der;
+  gauss_legendre(p + 1, gx, gw);
+  std::vector<double> Kf((size_t)nb * bw, 0.0), Mf((size_t)nb * bw, 0.0);
+  for (int e = 0; e < n; ++e) {
+    const int s = p + e;
+    for (int g = 0; g < p + 1; ++g) {
+      const double x = e * h + 0.5 * h * (gx[g] + 1.0), wq = 0.5 * h * gw[g];
+      basis_and_derivative(s, x, p, U, val, der);
+      for (int i = 0; i <= p; ++i)
+        for (int j = 0; j <= p; ++j) {
+          const int gi = s - p + i, gj = s - p + j;
+          Mf[(size_t)gi * bw + (gj - gi + p)] += wq * val[i] * val[j];
+          Kf[(size_t)gi * bw + (gj - gi + p)] += wq * der[i] * der[j];
+        }
+    }
+  }
+  G.Kb.assign((size_t)m * bw, 0.0);
+  G.Mb.assign((size_t)m * bw, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int o = 0; o < bw; ++o) {
+      const int j = i + o - p;
+      if (j < 0 || j >= m) continue;
+      G.Kb[(size_t)i * bw + o] = Kf[(size_t)(i + dlo) * bw + o];
+      G.Mb[(size_t)i * bw + o] = Mf[(size_t)(i + dlo) * bw + o];
+    }
+
+  // end blocks of V_reg; the right end is the mirror image (x -> 1 - x) of a
+  // left end of its type: B_j(1 - x) = B_{nb-1-j}(x), Bt_k(1 - x) = Bt_{n+dp-k}(x)
+  std::vector<double> Bl, Br;
+  int rows, cols;
+  int rc = end_block(n, p, dlo, U, Bl, rows, cols, err);
+  if (rc != IFFD_OK) return rc;
+  G.rl = rows; G.cl = cols; G.AL = Bl;
+  rc = end_block(n, p, dhi, U, Br, rows, cols, err);
+  if (rc != IFFD_OK) return rc;
+  G.rr = rows; G.cr = cols;
+  G.AR.assign((size_t)rows * cols, 0.0);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c)
+      G.AR[(size_t)(rows - 1 - r) * cols + (cols - 1 - c)] = Br[(size_t)r * cols + c];
+  const int nint = G.n_reg - G.cl - G.cr;
+  if (nint < 0 || nint != m - G.rl - G.rr) { err = "special basis does not fit the space"; return IFFD_E_INVAL; }
+
+  // Table 1 with 0-based indices: x_s = (s + sig) h, alpha_t = (t + tau) pi
+  G.sig2 = (p % 2) ? (dlo ? 2 : 0) : 1;
+  G.tau2 = (dlo && dhi) ? 2 : ((dlo || dhi) ? 1 : 0);
+  G.beta = dlo ? 0 : 1;
+
+  // outlier basis V_out = M^{-1} [W_L; 0; W_R] (Section 4)
+  const std::vector<double> WL = complement(G.AL, G.rl, G.cl), WR = complement(G.AR, G.rr, G.cr);
+  const int nl = G.rl - G.cl, nr_ = G.rr - G.cr;
+  if (nl + nr_ != G.n_out) { err = "outlier dimension mismatch"; return IFFD_E_INVAL; }
+  std::vector<double> Lb((size_t)m * (p + 1), 0.0);
+  auto Lat = [&](int i, int j) -> double& { return Lb[(size_t)i * (p + 1) + (j - i + p)]; };
+  for (int i = 0; i < m; ++i)
+    for (int j = std::max(0, i - p); j <= i; ++j) {
+      double sum = G.Mb[(size_t)i * bw + (j - i + p)];
+      for (int k = std::max(0, i - p); k < j; ++k) sum -= Lat(i, k) * Lat(j, k);
+      if (i == j) {
+        if (!(sum > 0)) { err = "mass matrix not SPD"; return IFFD_E_INVAL; }
+        Lat(i, i) = std::sqrt(sum);
+      } else {
+        Lat(i, j) = sum / Lat(j, j);
+      }
+    }
+  const int no = G.n_out;
+  G.Vout.assign((size_t)no * m, 0.0);
+  for (int c = 0; c < no; ++c) {
+    std::vector<double> b(m, 0.0);
+    if (c < nl) for (int r = 0; r < G.rl; ++r) b[r] = WL[(size_t)r * nl + c];
+    else for (int r = 0; r < G.rr; ++r) b[m - G.rr + r] = WR[(size_t)r * nr_ + (c - nl)];
+    for (int i = 0; i < m; ++i) {
+      double sum = b[i];
+      for (int k = std::max(0, i - p); k < i; ++k) sum -= Lat(i, k) * b[k];
+      b[i] = sum / Lat(i, i);
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double sum = b[i];
+      for (int k = i + 1; k < std::min(m, i + p + 1); ++k) sum -= Lat(k, i) * b[k];
+      b[i] = sum / Lat(i, i);
+    }
+    for (int i = 0; i < m; ++i) G.Vout[(size_t)c * m + i] = b[i];
+  }
+  auto band_mv = [&](const std::vector<double>& Bd, const double* x, double* y) {
+    for (int i = 0; i < m; ++i) {
+      double sum = 0;
+      for (int o = 0; o < bw; ++o) {
+        const int j = i + o - p;
+        if (j >= 0 && j < m) sum += Bd[(size_t)i * bw + o] * x[j];
+      }
+      y[i] = sum;
+    }
+  };
+  G.Ao.assign((size_t)no * no, 0.0);
+  G.Bo.assign((size_t)no * no, 0.0);
+  {
+    std::vector<double> kv(m), mv(m);
+    for (int a = 0; a < no; ++a) {
+      band_mv(G.Kb, &G.Vout[(size_t)a * m], kv.data());
+      band_mv(G.Mb, &G.Vout[(size_t)a * m], mv.data());
+      for (int b = 0; b < no; ++b) {
+        double sk = 0, sm = 0;
+        for (int i = 0; i < m; ++i) {
+          sk += G.Vout[(size_t)b * m + i] * kv[i];
+          sm += G.Vout[(size_t)b * m + i] * mv[i];
+        }
+        G.Ao[(size_t)a * no + b] = sk;
+        G.Bo[(size_t)a * no + b] = sm;
+      }
+    }
+    for (int a = 0; a < no; ++a)
+      for (int b = a + 1; b < no; ++b) {
+        const double k2 = 0.5 * (G.Ao[(size_t)a * no + b] + G.Ao[(size_t)b * no + a]);
+        const double m2 = 0.5 * (G.Bo[(size_t)a * no + b] + G.Bo[(size_t)b * no + a]);
+        G.Ao[(size_t)a * no + b] = G.Ao[(size_t)b * no + a] = k2;
+        G.Bo[(size_t)a * no + b] = G.Bo[(size_t)b * no + a] = m2;
+      }
+  }
+
+  // regular modes: Dt = ||V_reg U e_t||_M, Lambda_reg by the closed form at
+  // theta_t = alpha_t / n (Lemma 4).  Angles in units of 2 pi / (8n), reduced
+  // exactly; beta = pi/2 is 2n units.
+  const int nrg = G.n_reg, per = 8 * n;
+  std::vector<double> sintab(per), costab(per);
+  for (int k = 0; k < per; ++k) {
+    sintab[k] = (double)std::sin(2 * kPi * k / per);
+    costab[k] = (double)std::cos(2 * kPi * k / per);
+  }
+  G.lam.assign(m, 0.0);
+  G.s.assign(m, 1.0);
+  G.Dt.assign(nrg, 0.0);
+  std::vector<double> u(nrg), v(m), mv(m);
+  for (int t = 0; t < nrg; ++t) {
+    for (int s = 0; s < nrg; ++s) {
+      const long long a = ((long long)(2 * s + G.sig2) * (2 * t + G.tau2) + 2LL * n * G.beta) % per;
+      u[s] = sintab[a];
+    }
+    std::fill(v.begin(), v.end(), 0.0);
+    for (int r = 0; r < G.rl; ++r) {
+      double acc = 0;
+      for (int c = 0; c < G.cl; ++c) acc += G.AL[(size_t)r * G.cl + c] * u[c];
+      v[r] = acc;
+    }
+    for (int i = 0; i < nint; ++i) v[G.rl + i] = u[G.cl + i];
+    for (int r = 0; r < G.rr; ++r) {
+      double acc = 0;
+      for (int c = 0; c < G.cr; ++c) acc += G.AR[(size_t)r * G.cr + c] * u[nrg - G.cr + c];
+      v[m - G.rr + r] = acc;
+    }
+    band_mv(G.Mb, v.data(), mv.data());
+    double sm = 0;
+    for (int i = 0; i < m; ++i) sm += v[i] * mv[i];
+    G.Dt[t] = std::sqrt(sm);
+    G.s[t] = 1.0 / sm;
+    G.lam[t] = lambda_reg_half(n, p, 2 * t + G.tau2);
+  }
+
+  // FFT twiddles and the four twists of the transforms through length-2n FFTs:
+  //   forward  y_t = sum_s g_s U_{s,t}:  pre  e^{-i pi s tau / n},
+  //                                       post e^{-i (beta + pi sig (t + tau) / n)};
+  //   backward c_s = sum_t y_t U_{s,t}:  pre  e^{-i pi t sig / n},
+  //                                       post e^{-i (beta + pi tau (s + sig) / n)}
+  G.tw.assign((size_t)2 * G.L, 0.0);
+  for (int k = 0; k < G.L; ++k) {
+    G.tw[2 * k] = (double)std::cos(2 * kPi * k / G.L);
+    G.tw[2 * k + 1] = (double)-std::sin(2 * kPi * k / G.L);
+  }
+  G.tf.assign((size_t)8 * nrg, 0.0);
+  auto put = [&](int slot, int i, long long a) {
+    a %= per;
+    G.tf[(size_t)2 * (slot * nrg + i)] = costab[a];
+    G.tf[(size_t)2 * (slot * nrg + i) + 1] = -sintab[a];
+  };
+  for (int i = 0; i < nrg; ++i) {
+    put(0, i, 2LL * i * G.tau2);
+    put(1, i, (long long)G.sig2 * (2 * i + G.tau2) + 2LL * n * G.beta);
+    put(2, i, 2LL * i * G.sig2);
+    put(3, i, (long long)G.tau2 * (2 * i + G.sig2) + 2LL * n * G.beta);
+  }
+  return IFFD_OK;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void compute_layout_general(Plan& P) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = al256(off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  for (int k = 0; k < P.d; ++k) {
+    GDir& G = P.dirs[k];
+    const int bw = 2 * G.p + 1;
+    int o = 0;
+    G.o_tw = o;  o += 2 * G.L;
+    G.o_tf = o;  o += 8 * G.n_reg;
+    G.o_al = o;  o += G.rl * G.cl;
+    G.o_ar = o;  o += G.rr * G.cr;
+    G.o_vt = o;  o += G.n_out * G.m;
+    G.o_lam = o; o += G.m;
+    G.o_s = o;   o += G.m;
+    G.o_kb = o;  o += G.m * bw;
+    G.o_mb = o;  o += G.m * bw;
+    G.len = o + (o & 1);
+    G.blob64 = take((size_t)8 * G.len);
+    G.blob32 = take((size_t)4 * G.len);
+    G.ao64 = take((size_t)8 * G.n_out * G.n_out);
+    G.bo64 = take((size_t)8 * G.n_out * G.n_out);
+    G.vout64 = take((size_t)8 * G.n_out * G.m);
+    G.stat64 = take(8);
+  }
+  P.lay = TableLayout{};
+  P.lay.total = off;
+}
+
+}  // namespace
+
+int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* dirichlet,
+                       const iffd_opts* opts, std::string& err) {
+  if (d != 2 && d != 3) { err = "d must be 2 or 3"; return IFFD_E_INVAL; }
+  if (!nv || !pv || !dirichlet) { err = "null n, p or dirichlet array"; return IFFD_E_INVAL; }
+  if (opts) {
+    P.method = opts->method;
+    P.prec = opts->apply_prec;
+    P.max_rhs = opts->max_rhs;
+    P.coef_a = opts->coef_a;
+  }
+  if (P.method != IFFD_METHOD_FFT) { err = "general plans support the IFFD method only"; return IFFD_E_UNSUPPORTED; }
+  if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64) { err = "general plans take IFFD_PREC_F32 or IFFD_PREC_F64"; return IFFD_E_INVAL; }
+  if (P.coef_a != 0.0) { err = "general plans take coef_a = 0 (the Kronecker-sum operator)"; return IFFD_E_UNSUPPORTED; }
+  if (P.max_rhs < 1) { err = "max_rhs must be >= 1"; return IFFD_E_INVAL; }
+  bool any_dirichlet = false;
+  int pmax = 0;
+  for (int k = 0; k < d; ++k) {
+    const int n = nv[k], p = pv[k], a = dirichlet[2 * k], b = dirichlet[2 * k + 1];
+    if (p < 1 || p > 8) { err = "p must be in 1..8"; return IFFD_E_INVAL; }
+    if (n <= p) { err = "n must exceed p"; return IFFD_E_INVAL; }
+    if ((a != 0 && a != 1) || (b != 0 && b != 1)) { err = "dirichlet flags must be 0 or 1"; return IFFD_E_INVAL; }
+    if (n > 256 || !fft_len_supported(2 * n)) {
+      err = "general plans need n = 2^a or 3*2^a with 8 <= n <= 256 in every direction";
+      return IFFD_E_UNSUPPORTED;
+    }
+    any_dirichlet = any_dirichlet || a || b;
+    pmax = std::max(pmax, p);
+  }
+  if (!any_dirichlet) {
+    err = "Neumann conditions on every face: the operator is singular (the constants)";
+    return IFFD_E_UNSUPPORTED;
+  }
+  P.gen = true;
+  P.d = d;
+  P.N = 1;
+  for (int k = 0; k < d; ++k) {
+    const int rc = build_dir(P.dirs[k], nv[k], pv[k], dirichlet[2 * k], dirichlet[2 * k + 1], err);
+    if (rc != IFFD_OK) return rc;
+    P.N *= P.dirs[k].m;
+  }
+  if (P.N * (int64_t)P.max_rhs >= (int64_t(1) << 31)) { err = "problem too large for 32-bit indexing"; return IFFD_E_UNSUPPORTED; }
+  if (P.N * 8 >= (int64_t(1) << 31)) { err = "one right-hand side above 2 GiB in FP64"; return IFFD_E_UNSUPPORTED; }
+  const GDir& G = P.dirs[0];
+  P.n = G.n; P.p = G.p; P.m = G.m; P.n_reg = G.n_reg; P.n_out = G.n_out; P.L = G.L;
+  P.half = G.p / 2;
+  P.first64 = P.prec == IFFD_PREC_F32 && pmax >= 5;
+  compute_layout_general(P);
   return IFFD_OK;
 }
 

@@ -41,6 +41,35 @@ struct StateLayout {
 
 constexpr int kHist = 256;  // alpha/beta history kept per slot for Lanczos
 
+// One direction of a general plan (iffd_plan_create_general): its own n, p and
+// boundary conditions.  The spline space drops B_0 when x = 0 is a Dirichlet
+// end and the last B-spline when x = 1 is, so m = n + p - #Dirichlet ends.
+// V_reg = blkdiag(AL, I, AR) in the special basis of Section 6 (end blocks of
+// rl x cl and rr x cr entries, identity in between), U_{s,t} =
+// sin(pi (s + sig)(t + tau) / n + beta), s, t = 0 .. n_reg - 1 (Table 1 with
+// 0-based indices: sig = node offset, tau = frequency offset, beta = 0 or
+// pi/2), S^out the L2-complement of S^reg.
+struct GDir {
+  int n = 0, p = 0, dlo = 1, dhi = 1;  // dlo / dhi: Dirichlet (1) or Neumann (0) at x = 0 / 1
+  int m = 0, n_reg = 0, n_out = 0, L = 0;  // L = 2n: complex FFT length of the transforms
+  int rl = 0, cl = 0, rr = 0, cr = 0;
+  int sig2 = 0, tau2 = 0, beta = 0;  // 2 sig, 2 tau, beta / (pi / 2)
+  std::vector<double> Kb, Mb;        // m x (2p+1) band rows
+  std::vector<double> AL, AR;        // rl x cl, rr x cr (row-major)
+  std::vector<double> Vout, Ao, Bo;  // n_out x m; outlier pencil n_out x n_out
+  std::vector<double> Vt;            // n_out x m, Q_out-rotated (after setup)
+  std::vector<double> lam, s, Dt;    // m, m, n_reg (lam's outlier part after setup)
+  std::vector<double> tw;            // L complex twiddles e^{-2 pi i k / L}
+  std::vector<double> tf;            // 4 n_reg complex twists: pre/post forward, pre/post backward
+  int win32[2] = {0, 0}, win64[2] = {0, 0};  // outlier windows (as Plan::win32 / win64)
+  // element offsets of this direction's tables inside its blob (FP64 blob and
+  // FP32 blob share them): tw | tf | AL | AR | Vt | lam | s | Kb | Mb
+  int o_tw = 0, o_tf = 0, o_al = 0, o_ar = 0, o_vt = 0, o_lam = 0, o_s = 0, o_kb = 0, o_mb = 0;
+  int len = 0;
+  size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
+  size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)
+};
+
 struct Plan {
   int d = 0, n = 0, p = 0, m = 0, n_reg = 0, n_out = 0, half = 0, L = 0;
   int method = IFFD_METHOD_FFT, prec = IFFD_PREC_F32, max_rhs = 1;
@@ -79,6 +108,12 @@ struct Plan {
   // mass matrices' small eigenvalues amplify that rounding)
   bool first64 = false;
 
+  // general plans: per-direction n, p and boundary conditions (dirs[0] is
+  // direction 1, the fastest index); n, p, m, n_reg, n_out above then hold
+  // direction 1's values
+  bool gen = false;
+  GDir dirs[3];
+
   TableLayout lay{};
   char* d_tables = nullptr;
   size_t table_bytes = 0;
@@ -87,6 +122,8 @@ struct Plan {
 
 // host setup (plan.cpp)
 int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string& err);
+int build_plan_general(Plan& P, int d, const int* n, const int* p, const int* dirichlet,
+                       const iffd_opts* opts, std::string& err);
 void compute_layout(Plan& P);
 StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);

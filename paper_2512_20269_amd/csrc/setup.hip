@@ -2,7 +2,7 @@
 // the outlier block (eq:eigendecomposition_out)
 //     Q_out^T (V_out^T K V_out) Q_out = Lambda_out,
 //     Q_out^T (V_out^T M V_out) Q_out = I,
-// solved in FP64 (n_out <= 6) by a Cholesky reduction and cyclic Jacobi, then
+// solved in FP64 (n_out <= 8) by a Cholesky reduction and cyclic Jacobi, then
 // Vt = (V_out Q_out)^T and the outlier eigenvalues are written into the
 // tables in FP64 and FP32.  A status word reports a pencil whose mass block
 // is not positive definite (the Cholesky pivot that failed, 1-based) or a
@@ -122,6 +122,15 @@ __global__ void setup_outliers_kernel(const double* Ao, const double* Bo, const 
     lam64[n_reg + threadIdx.x] = ls[threadIdx.x];
     lam32[n_reg + threadIdx.x] = (float)ls[threadIdx.x];
   }
+}
+
+hipError_t launch_setup_outliers_at(const double* Ao, const double* Bo, const double* Vout, int no,
+                                    int m, int n_reg, double* lam64, float* lam32, double* vt64,
+                                    float* vt32, double* stat, hipStream_t s) {
+  if (no == 0) return hipSuccess;
+  hipLaunchKernelGGL(setup_outliers_kernel, dim3(1), dim3(256), 0, s, Ao, Bo, Vout, no, m, n_reg,
+                     lam64, lam32, vt64, vt32, stat);
+  return hipGetLastError();
 }
 
 hipError_t launch_setup_outliers(const Plan& P, hipStream_t s) {

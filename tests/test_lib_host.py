@@ -254,3 +254,111 @@ def test_noalloc_validates_before_any_launch():
     assert I.lib.iffd_precond_apply_noalloc(None, fake, fake, 1, None) == I.E_INVAL
     assert I.lib.iffd_precond_apply_noalloc(h, fake, ctypes.c_void_p(512), 1, None) == I.E_STATE
     I.lib.iffd_plan_destroy(h)
+
+
+# ---- general plans: per-direction n, p and Dirichlet / natural ends -------
+
+GEN_ENDS = [(1, 1), (1, 0), (0, 1), (0, 0)]
+
+
+def read_dir(h, k, what, count):
+    buf = np.zeros(max(count, 1))
+    rc = I.lib.iffd_plan_read_dir(h, k, what, buf.ctypes.data_as(ctypes.c_void_p), len(buf), None)
+    assert rc == 0, I.lib.iffd_last_error()
+    return buf[:count]
+
+
+def band_dense(band, m, p):
+    A = np.zeros((m, m))
+    for i in range(m):
+        for o in range(2 * p + 1):
+            j = i + o - p
+            if 0 <= j < m:
+                A[i, j] = band[i * (2 * p + 1) + o]
+    return A
+
+
+@pytest.mark.parametrize("n", [16, 24, 64])
+@pytest.mark.parametrize("ends", GEN_ENDS)
+def test_general_host_tables_match_oracle(n, ends):
+    """Every table the general plan builds on the host for one direction
+    against the oracle's general route: dimensions (eq:reg_space_dim), K and
+    M (Section 3), the special-basis end blocks AL and AR of V_reg
+    (eq:special_basis, the oracle by least-squares collocation, the plan by
+    Greville collocation and reflection), Dt (end of Section 6) and the
+    regular eigenvalues (Lemma 4's closed form at alpha_j / n vs the
+    oracle's seminorm quotients)."""
+    from oracle import general as G
+    D = {e for e, f in zip((0, 1), ends) if f}
+    for p in range(1, 9):
+        if n <= p:
+            continue
+        rc, h = I.create_general(2, [n, 16], [p, 2], [ends, (1, 1)])
+        assert rc == 0, I.lib.iffd_last_error()
+        di = I.query_dirs(h, 2)[0]
+        m, nr, no = G.dims(n, p, D)
+        assert (di["m"], di["n_reg"], di["n_out"], di["fft_len"]) == (m, nr, no, 2 * n)
+        f = G.factors_route_b(n, p, D)
+        lam = read_dir(h, 1, I.TABLE_LAM, m)[:nr]
+        ref = f["lam_reg"]
+        big = np.abs(ref) > 1e-12
+        assert np.all(np.abs(lam[big] - ref[big]) <= 1e-13 * np.abs(ref[big])), p
+        assert np.all(np.abs(lam[~big]) <= 1e-12)          # the constant mode of D = {}
+        assert np.allclose(read_dir(h, 1, I.TABLE_DT, nr), f["Dt"], rtol=1e-12, atol=0)
+        V = f["V_reg"]
+        rl, rr = p - ends[0], p - ends[1]
+        cl = p // 2 if (ends[0] or p % 2 == 0) else (p + 1) // 2
+        cr = p // 2 if (ends[1] or p % 2 == 0) else (p + 1) // 2
+        AL = read_dir(h, 1, I.TABLE_V0, rl * cl).reshape(rl, cl)
+        AR = read_dir(h, 1, I.TABLE_V1, rr * cr).reshape(rr, cr)
+        assert np.abs(V[:rl, :cl] - AL).max(initial=0) <= 1e-13
+        assert np.abs(V[m - rr:, nr - cr:] - AR).max(initial=0) <= 1e-13
+        # the rest of V_reg is the identity on the interior block
+        Vi = V[rl:m - rr, cl:nr - cr]
+        assert np.abs(Vi - np.eye(m - rl - rr)).max(initial=0) <= 1e-12
+        K = band_dense(read_dir(h, 1, I.TABLE_KBAND, m * (2 * p + 1)), m, p)
+        M = band_dense(read_dir(h, 1, I.TABLE_MBAND, m * (2 * p + 1)), m, p)
+        assert np.abs(K - f["K"]).max() <= 1e-12 * np.abs(f["K"]).max()
+        assert np.abs(M - f["M"]).max() <= 1e-12 * np.abs(f["M"]).max()
+        I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("n,p,dl,opts,code", [
+    ([16, 16], [3, 3], [(0, 0), (0, 0)], None, I.E_UNSUPPORTED),       # singular
+    ([512, 16], [3, 3], [(1, 0), (0, 1)], None, I.E_UNSUPPORTED),      # L = 1024
+    ([20, 16], [3, 3], [(1, 0), (0, 1)], None, I.E_UNSUPPORTED),       # n not 2^a, 3 2^a
+    ([16, 16], [9, 3], [(1, 0), (0, 1)], None, I.E_INVAL),
+    ([16, 8], [3, 8], [(1, 0), (0, 1)], None, I.E_INVAL),              # n <= p
+    ([16, 16], [3, 3], [(2, 0), (0, 1)], None, I.E_INVAL),
+    ([16, 16], [3, 3], [(1, 0), (0, 1)], (I.METHOD_DENSE_FD, I.PREC_F32), I.E_UNSUPPORTED),
+    ([16, 16], [3, 3], [(1, 0), (0, 1)], (I.METHOD_FFT, I.PREC_F16S), I.E_INVAL),
+])
+def test_invalid_general_plans_rejected(n, p, dl, opts, code):
+    o = I._Opts(opts[0], opts[1], 1, 0.0) if opts else None
+    rc, h = I.create_general(2, n, p, dl, o)
+    assert rc == code, (rc, I.lib.iffd_last_error())
+    assert not h.value
+
+
+def test_general_plan_sizes_and_errors():
+    rc, h = I.create_general(3, [16, 24, 32], [3, 2, 4], [(1, 0), (0, 1), (0, 0)],
+                             I._Opts(I.METHOD_FFT, I.PREC_F32, 2, 0.0))
+    assert rc == 0
+    dirs = I.query_dirs(h, 3)
+    ms = [d["m"] for d in dirs]
+    assert ms == [16 + 3 - 1, 24 + 2 - 1, 32 + 4]
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    N = ms[0] * ms[1] * ms[2]
+    assert info.N == N and info.m == ms[0]
+    assert info.apply_ws_bytes >= 4 * N * 2            # one FP32 tensor per RHS
+    assert info.matvec_ws_bytes >= 4 * 8 * N * 2       # four FP64 tensors per RHS
+    # a single FFT shape: variants cannot be forced; tuning is a no-op
+    assert I.lib.iffd_plan_set_variant(h, 0, 0) == I.E_UNSUPPORTED
+    buf = np.zeros(8)
+    assert I.lib.iffd_plan_read_dir(h, 4, 0, buf.ctypes.data_as(ctypes.c_void_p), 8, None) == I.E_INVAL
+    assert I.lib.iffd_plan_read_dir(h, 1, 0, buf.ctypes.data_as(ctypes.c_void_p), 8, None) == I.E_WORKSPACE
+    # compute entry points before setup
+    assert I.lib.iffd_precond_apply(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1,
+                                    ctypes.c_void_p(1024), 1 << 30, None) == I.E_STATE
+    I.lib.iffd_plan_destroy(h)

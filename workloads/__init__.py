@@ -66,6 +66,13 @@ def smooth_rhs(d: int, n: int, p: int, seed: int, modes: int = 8,
     return f + noise * xi
 
 
+def uniform_tensor(shape, seed: int) -> np.ndarray:
+    """f ~ U[-1, 1] of a given shape (m_d, .., m_1): right-hand sides of
+    problems whose directions differ in size (mixed boundary conditions,
+    per-direction n and p)."""
+    return rng(seed).uniform(-1.0, 1.0, size=tuple(shape))
+
+
 def batched_uniform_rhs(d: int, n: int, p: int, seeds) -> np.ndarray:
     """One independent generator per right-hand side, so a RHS is the same
     whether it is drawn alone or inside a batch."""
@@ -87,6 +94,11 @@ WORKLOADS = {
     # 64 right-hand sides on the 3D cube, n = 96, p = 4
     "cube_n96_p4_b64": dict(d=3, n=96, p=4, nrhs=64, seed0=4000, rhs="uniform"),
 }
+
+# Section 7's cube with mixed boundary conditions (Table 3): Dirichlet on the
+# faces x = 0 and y = 1, natural conditions elsewhere, i.e. per direction
+# (Dirichlet at 0, Dirichlet at 1) = (1, 0), (0, 1), (0, 0).
+MIXED_CUBE_DIRICHLET = ((1, 0), (0, 1), (0, 0))
 
 
 def workload_rhs(name: str, p: int | None = None) -> np.ndarray:
