@@ -223,6 +223,64 @@ def serving(torch, count, warm, fracs, budget_gb=96.0, slots=8, iters=2, check=4
             "runs": runs, "sampled_same_bits_as_alone": same, "sampled": check}
 
 
+def mixed_bc(torch, iffd, ps=(3,), n=256, steps=20, solves=10, prec="f32"):
+    """Section 7's cube with mixed boundary conditions (Table 3: Dirichlet on
+    x = 0 and y = 1, natural conditions elsewhere) through a general plan:
+    apply throughput with per-pass durations and the roofline of the
+    dominant pass, and PCG to 1e-8 (iterations against Table 3)."""
+    import workloads
+    cpm = sleep_cycles_per_ms(torch)
+    rows = []
+    for p in ps:
+        pl = iffd.Plan(3, [n] * 3, [p] * 3, precision=prec,
+                       dirichlet=workloads.MIXED_CUBE_DIRICHLET)
+        N = pl.N
+        f = torch.from_numpy(workloads.uniform_tensor(pl.shape, seed=1)).cuda()
+        z = torch.empty_like(f)
+        for _ in range(3):
+            pl.apply(f, out=z)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(int(cpm * 5.0))
+        a.record()
+        for _ in range(steps):
+            pl.apply(f, out=z)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        npass = pl.n_passes()
+        pp = []
+        for k in range(npass):
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda._sleep(int(cpm * (2.0 + 0.03 * steps)))
+            a_.record()
+            for _ in range(steps):
+                pl.apply_pass(k, f, z)
+            b_.record()
+            torch.cuda.synchronize()
+            pp.append(a_.elapsed_time(b_) / steps)
+        pb = pass_bytes(3, N, prec)
+        names = pass_names(3)
+        dom = max(range(npass), key=lambda k: pp[k])
+        ach = pb[dom] / (pp[dom] * 1e-3) / 1e9
+        lat, st = time_solves(torch, pl, f, solves)
+        rows.append({
+            "n": n, "p": p, "shape": list(pl.shape), "dofs": N, "dtype": prec,
+            "gdof_s": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 5),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "kernel": f"gen_line_pass {names[dom]}",
+                         "alg_bytes_per_launch": pb[dom],
+                         "per_pass_us": {names[k]: round(pp[k] * 1e3, 2) for k in range(npass)},
+                         "apply_alg_GBs": round(sum(pb) / (ms * 1e-3) / 1e9, 1)},
+            "pcg": {"solves_per_s": round(1e3 / statistics.mean(lat), 2),
+                    "p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
+                    "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"]}})
+        del pl, f, z
+        torch.cuda.empty_cache()
+    return rows
+
+
 def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256, coef=0.0):
     """3D with the smooth right-hand side (8 random-phase sine modes plus 1e-3
     noise, seed 3), degree sweep: FP32 apply error against the FP64 apply, PCG
@@ -286,6 +344,8 @@ def main():
     ap.add_argument("--pcg-only", choices=["fft", "dense"],
                     help="only PCG solves of the workload's first right-hand side with this "
                          "preconditioner (3 warm-up + --solves timed; for kernel traces)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="only the mixed-boundary cube of Table 3 (n = 256, p = 2..5)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
@@ -317,6 +377,15 @@ def main():
                           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": f"cube_n256_p2-8_smooth{cs}"}, "rows": rows}),
               flush=True)
+        return
+    if args.mixed:
+        rows = mixed_bc(torch, iffd, ps=(2, 3, 4, 5), steps=args.steps, solves=args.solves,
+                        prec=args.precision)
+        print(json.dumps({"metric": "mixed-boundary cube apply GDoF/s and PCG iterations",
+                          "unit": "GDoF/s", "n_gpus": 1, "dtype": args.precision,
+                          "data": "synthetic",
+                          "config": {"workload": "mixed_cube_n256_p2-5_uniform"},
+                          "rows": rows}), flush=True)
         return
     if args.serve:
         res = serving(torch, args.serve_requests, args.serve_warmup,
@@ -622,6 +691,9 @@ def main():
                 "iffd_solve_speedup": round(statistics.mean(cflat) / statistics.mean(clat), 3)}
             out["serving"] = serving(torch, args.serve_requests, args.serve_warmup,
                                      [float(x) for x in args.serve_fracs.split(",")])
+            # ---- the mixed-boundary cube of Table 3 through a general plan ------
+            out["mixed_bc"] = mixed_bc(torch, iffd, ps=(3,), n=256, steps=min(args.steps, 50),
+                                       solves=max(5, args.solves // 3), prec=args.precision)[0]
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")

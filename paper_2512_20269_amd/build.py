@@ -33,7 +33,7 @@ SOURCES = ["plan.cpp", "api.cpp", "apply.hip",
            "apply_lg_fwd.hip", "apply_lg_bwd.hip", "apply_lg_mid.hip",
            "gen.hip", "gen_la.hip", "gen_lb.hip", "gen_lc.hip", "gen_ld.hip", "gen_le.hip",
            "gen_lf.hip", "gen_lg.hip",
-           "setup.hip", "matvec.hip", "pcg.hip", "dense.hip", "noalloc.hip"]
+           "setup.hip", "matvec.hip", "mvroll.hip", "pcg.hip", "dense.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -43,8 +43,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(HERE, '..', 'include')}"]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs.append(os.path.join(HERE, "..", "include", "iffd.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, changed_only: bool = False) -> str:
     obj = os.path.join(BUILD, src + ".o")
+    if changed_only and os.path.exists(obj):
+        newest = max(os.path.getmtime(os.path.join(CSRC, src)), _headers_mtime())
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -52,11 +62,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, changed_only: bool = False) -> str:
+    """Compile every source (changed_only: skip objects newer than their
+    source and every header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, changed_only), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -76,4 +88,4 @@ if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "clean":
         clean()
     else:
-        build()
+        build(changed_only=len(sys.argv) > 1 and sys.argv[1] == "--changed")

@@ -158,13 +158,24 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
     std::copy(G.AR.begin(), G.AR.end(), blob.begin() + G.o_ar);
     std::copy(G.lam.begin(), G.lam.end(), blob.begin() + G.o_lam);
     std::copy(G.s.begin(), G.s.end(), blob.begin() + G.o_s);
-    std::copy(G.Kb.begin(), G.Kb.end(), blob.begin() + G.o_kb);
-    std::copy(G.Mb.begin(), G.Mb.end(), blob.begin() + G.o_mb);
+    // band rows padded from 2p+1 to 2pm+1 columns (centred)
+    const int bw = 2 * G.p + 1, bwp = 2 * G.pm + 1, sh = G.pm - G.p;
+    for (int i = 0; i < G.m; ++i)
+      for (int o = 0; o < bw; ++o) {
+        blob[(size_t)G.o_kb + (size_t)i * bwp + sh + o] = G.Kb[(size_t)i * bw + o];
+        blob[(size_t)G.o_mb + (size_t)i * bwp + sh + o] = G.Mb[(size_t)i * bw + o];
+      }
     put<double>(buf, G.blob64, blob);
     put<float>(buf, G.blob32, blob);
     put<double>(buf, G.ao64, G.Ao);
     put<double>(buf, G.bo64, G.Bo);
     put<double>(buf, G.vout64, G.Vout);
+  }
+  {
+    const int bwp = 2 * P.dirs[0].pm + 1;
+    std::vector<double> unit((size_t)2 * bwp, 0.0);   // K = 0 | M = e_pm
+    unit[(size_t)bwp + P.dirs[0].pm] = 1.0;
+    put<double>(buf, P.lay.unit64, unit);
   }
   hipError_t e = hipMemcpyAsync(d_tables, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "table upload");

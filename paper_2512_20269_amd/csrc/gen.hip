@@ -1,6 +1,8 @@
 // General plans (per direction n, p and Dirichlet / Neumann ends): the
 // sequence of line passes that forms z = P^{-1} r, the matrix-free operator
 // and the device part of the setup.
+#include <algorithm>
+
 #include "gen_impl.h"
 
 namespace iffd {
@@ -69,120 +71,46 @@ hipError_t launch_gen_apply(const Plan& P, const double* r, double* z, int nrhs,
 }
 
 // ---- the operator y = Ahat x with per-direction banded K_k, M_k -------------
-// Sum factorization, one banded product per direction and pass:
-//   2D:  a = M1 x, b = K1 x;           y = K2 a + M2 b
-//   3D:  a = M1 x, b = K1 x;  c = M2 a, e = K2 a + M2 b;  y = K3 c + M3 e
-// i.e. sum_k (x) of K in slot k and M elsewhere (eq:system_matrix and its
-// 3-term analogue).  One thread per output entry; the last pass also forms
-// per-workgroup partial sums of x . y (or (f - y)^2 for a true residual) in
-// a fixed order.
+// one pass of mvroll.hip over band tables padded to the largest degree (a 2D
+// plan adds the one-entry third direction M_3 = 1, K_3 = 0)
 
-constexpr int GMV_T = 256;
-
-__device__ __forceinline__ double gmv_sum(const double* __restrict__ B, const double* __restrict__ u,
-                                          int i, int p, int m, size_t base, int S) {
-  const int bw = 2 * p + 1;
-  const int j0 = i - p < 0 ? 0 : i - p, j1 = i + p > m - 1 ? m - 1 : i + p;
-  const double* row = B + (size_t)i * bw + (p - i);
-  double acc = 0.0;
-  for (int j = j0; j <= j1; ++j) acc += row[j] * u[base + (size_t)j * S];
-  return acc;
-}
-
-__global__ void __launch_bounds__(GMV_T)
-gmv_pass(const double* __restrict__ u, const double* __restrict__ v, double* __restrict__ o1,
-         double* __restrict__ o2, const double* __restrict__ A, const double* __restrict__ B,
-         const double* __restrict__ Cm, const double* __restrict__ Dm, int p, int m, int S, int N,
-         int nblk, const double* __restrict__ xd, const double* __restrict__ fres,
-         double* __restrict__ part, int npart, const double* __restrict__ active, int astride) {
-  __shared__ double red[GMV_T / 64];
-  const int rhs = blockIdx.x / nblk, blk = blockIdx.x - rhs * nblk;
-  if (active && active[(size_t)rhs * astride] == 0.0) return;
-  const int c = (N + nblk - 1) / nblk;
-  const int lo = min(N, blk * c), hi = min(N, lo + c);
-  const size_t ro = (size_t)rhs * N;
-  double dot = 0.0;
-  for (int e = lo + (int)threadIdx.x; e < hi; e += GMV_T) {
-    const int i = (e / S) % m;
-    const size_t base = ro + (size_t)(e - i * S);
-    double y1 = gmv_sum(A, u, i, p, m, base, S);
-    if (v && B) y1 += gmv_sum(B, v, i, p, m, base, S);
-    o1[ro + e] = y1;
-    if (o2) {
-      double y2 = gmv_sum(Cm, u, i, p, m, base, S);
-      if (v && Dm) y2 += gmv_sum(Dm, v, i, p, m, base, S);
-      o2[ro + e] = y2;
-    }
-    if (part) {
-      if (fres) {
-        const double rr = fres[ro + e] - y1;
-        dot += rr * rr;
-      } else {
-        dot += xd[ro + e] * y1;
-      }
+static RollBands gen_bands(const Plan& P) {
+  RollBands B;
+  int pm = 1;
+  for (int k = 0; k < P.d; ++k) pm = std::max(pm, P.dirs[k].p);
+  B.pm = pm;
+  for (int k = 0; k < 3; ++k) {
+    if (k < P.d) {
+      const GDir& G = P.dirs[k];
+      const double* b = (const double*)(P.d_tables + G.blob64);
+      B.k[k] = b + G.o_kb;
+      B.m[k] = b + G.o_mb;
+      B.n[k] = G.m;
+    } else {
+      const double* u = (const double*)(P.d_tables + P.lay.unit64);
+      B.k[k] = u;                 // zeros
+      B.m[k] = u + (2 * pm + 1);  // e_pm
+      B.n[k] = 1;
     }
   }
-  if (!part) return;
-  for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < GMV_T / 64; ++w) s += red[w];
-    part[(size_t)rhs * npart + blk] = s;
-  }
+  return B;
 }
 
 int gen_matvec_blocks(const Plan& P) {
-  const int64_t b = (P.N + 4 * GMV_T - 1) / (4 * GMV_T);
-  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+  RollBands B{};
+  int pm = 1;
+  for (int k = 0; k < P.d; ++k) pm = std::max(pm, P.dirs[k].p);
+  B.pm = pm;
+  for (int k = 0; k < 3; ++k) B.n[k] = k < P.d ? P.dirs[k].m : 1;
+  return mv_roll_blocks(B);
 }
 
-size_t gen_matvec_ws_bytes(const Plan& P, int nrhs) {
-  return (size_t)(P.d == 3 ? 4 : 2) * 8 * P.N * nrhs;
-}
+size_t gen_matvec_ws_bytes(const Plan&, int) { return 0; }
 
-hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
+hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs, void*,
                              double* part, int npart, const double* act, int as, hipStream_t s,
                              const double* fres) {
-  const int N = (int)P.N, nb = gen_matvec_blocks(P);
-  if (part && npart < nb) return hipErrorInvalidValue;
-  if (!ws) return hipErrorInvalidValue;
-  double* wa = (double*)ws;
-  double* wb = wa + (size_t)N * nrhs;
-  auto band = [&](int k, bool stiff) {
-    const GDir& G = P.dirs[k];
-    return (const double*)(P.d_tables + G.blob64) + (stiff ? G.o_kb : G.o_mb);
-  };
-  const dim3 grid((unsigned)(nb * nrhs)), block(GMV_T);
-  const GDir& g1 = P.dirs[0];
-  const GDir& g2 = P.dirs[1];
-  // direction 1: a = M1 x, b = K1 x
-  hipLaunchKernelGGL(gmv_pass, grid, block, 0, s, x, (const double*)nullptr, wa, wb, band(0, false),
-                     (const double*)nullptr, band(0, true), (const double*)nullptr, g1.p, g1.m, 1,
-                     N, nb, (const double*)nullptr, (const double*)nullptr, (double*)nullptr, 0,
-                     act, as);
-  if (P.d == 2) {
-    hipLaunchKernelGGL(gmv_pass, grid, block, 0, s, (const double*)wa, (const double*)wb, y,
-                       (double*)nullptr, band(1, true), band(1, false), (const double*)nullptr,
-                       (const double*)nullptr, g2.p, g2.m, g1.m, N, nb, x, fres, part, npart, act,
-                       as);
-    return hipGetLastError();
-  }
-  double* wc = wb + (size_t)N * nrhs;
-  double* we = wc + (size_t)N * nrhs;
-  const GDir& g3 = P.dirs[2];
-  // direction 2: c = M2 a, e = K2 a + M2 b
-  hipLaunchKernelGGL(gmv_pass, grid, block, 0, s, (const double*)wa, (const double*)wb, wc, we,
-                     band(1, false), (const double*)nullptr, band(1, true), band(1, false), g2.p,
-                     g2.m, g1.m, N, nb, (const double*)nullptr, (const double*)nullptr,
-                     (double*)nullptr, 0, act, as);
-  // direction 3: y = K3 c + M3 e
-  hipLaunchKernelGGL(gmv_pass, grid, block, 0, s, (const double*)wc, (const double*)we, y,
-                     (double*)nullptr, band(2, true), band(2, false), (const double*)nullptr,
-                     (const double*)nullptr, g3.p, g3.m, g1.m * g2.m, N, nb, x, fres, part, npart,
-                     act, as);
-  return hipGetLastError();
+  return launch_mv_roll(gen_bands(P), x, y, nrhs, (int)P.N, part, npart, act, as, s, fres);
 }
 
 }  // namespace iffd

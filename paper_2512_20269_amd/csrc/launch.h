@@ -18,6 +18,15 @@ __device__ __forceinline__ int xcd_linear(int b, int nblocks) {
   const int x = b & 7, k = b >> 3;
   return x * q8 + (x < r8 ? x : r8) + k;
 }
+// Workgroup barrier that orders LDS only: LDS writes before it are visible to
+// LDS reads after it, while global loads and stores stay in flight across it
+// (__syncthreads also drains every outstanding global access).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Raw buffer access (gfx9 buffer resource, 32-bit data format): the hardware
 // checks each lane's offset (`voff` plus the instruction's immediate offset)
 // against `bytes`; a load beyond returns 0 and a store beyond is dropped, so
@@ -116,6 +125,21 @@ hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs
                              hipStream_t s, const double* fres);
 int gen_matvec_blocks(const Plan& P);
 size_t gen_matvec_ws_bytes(const Plan& P, int nrhs);
+
+// One-pass operator of mvroll.hip: per-direction band tables K_k, M_k of
+// n[k] x (2 pm + 1) FP64 entries (row i holds columns i - pm .. i + pm;
+// pm >= every direction's p, padded with zeros), direction 1 fastest; a 2D
+// operator passes n[2] = 1 with M_3 = 1, K_3 = 0.
+struct RollBands {
+  const double* k[3];
+  const double* m[3];
+  int n[3];
+  int pm;
+};
+int mv_roll_blocks(const RollBands& B);
+hipError_t launch_mv_roll(const RollBands& B, const double* x, double* y, int nrhs, int N,
+                          double* part, int npart, const double* active, int active_stride,
+                          hipStream_t s, const double* fres);
 
 // y = Ahat x; ws: matvec_ws_bytes(P, nrhs); optional fused partial sums per
 // workgroup: part[b][blk] = sum x.y, or sum (f - y)^2 when fres (the true

@@ -406,6 +406,11 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
 
 // workgroups of the operator per right-hand side (the pass that produces the
 // partials)
+// Uniform plans keep the kernels above: measured at n = 256 against the
+// one-pass rolling kernel of mvroll.hip (which serves general plans), the
+// fused tile ties it for p <= 4 (182 vs 185 us at p = 3) and the two passes
+// beat it for p >= 6 (283 vs 488 us at p = 6, 379 vs 1602 us at p = 8, where
+// its register windows spill).
 int matvec_blocks(const Plan& P_) {
   if (P_.gen) return gen_matvec_blocks(P_);
   if (mv_fused(P_)) {

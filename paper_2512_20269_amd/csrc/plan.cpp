@@ -1096,9 +1096,12 @@ void compute_layout_general(Plan& P) {
     off = al256(off + std::max<size_t>(bytes, 8));
     return o;
   };
+  int pm = 1;
+  for (int k = 0; k < P.d; ++k) pm = std::max(pm, P.dirs[k].p);
   for (int k = 0; k < P.d; ++k) {
     GDir& G = P.dirs[k];
-    const int bw = 2 * G.p + 1;
+    G.pm = pm;
+    const int bw = 2 * pm + 1;
     int o = 0;
     G.o_tw = o;  o += 2 * G.L;
     G.o_tf = o;  o += 8 * G.n_reg;
@@ -1117,7 +1120,9 @@ void compute_layout_general(Plan& P) {
     G.vout64 = take((size_t)8 * G.n_out * G.m);
     G.stat64 = take(8);
   }
+  const size_t unit = take((size_t)8 * 2 * (2 * pm + 1));
   P.lay = TableLayout{};
+  P.lay.unit64 = unit;
   P.lay.total = off;
 }
 

@@ -22,6 +22,7 @@ struct TableLayout {
   size_t qfd32, qtfd32, lamfd32;
   size_t qfd16, qtfd16, qs16;  // dense FD in FP16: Q / s_Q, Q^T / s_Q, s_Q (FP32)
   size_t stat64;  // setup status word written by the outlier setup kernel (0 = ok)
+  size_t unit64;  // general 2D plans: the third direction's band rows, K = 0 and M = 1
   size_t total;
 };
 
@@ -56,6 +57,7 @@ struct GDir {
   int sig2 = 0, tau2 = 0, beta = 0;  // 2 sig, 2 tau, beta / (pi / 2)
   std::vector<double> Kb, Mb;        // m x (2p+1) band rows
   std::vector<double> AL, AR;        // rl x cl, rr x cr (row-major)
+  int pm = 0;                        // band width of the device copies: 2 pm + 1 (pm = max p)
   std::vector<double> Vout, Ao, Bo;  // n_out x m; outlier pencil n_out x n_out
   std::vector<double> Vt;            // n_out x m, Q_out-rotated (after setup)
   std::vector<double> lam, s, Dt;    // m, m, n_reg (lam's outlier part after setup)
@@ -63,7 +65,8 @@ struct GDir {
   std::vector<double> tf;            // 4 n_reg complex twists: pre/post forward, pre/post backward
   int win32[2] = {0, 0}, win64[2] = {0, 0};  // outlier windows (as Plan::win32 / win64)
   // element offsets of this direction's tables inside its blob (FP64 blob and
-  // FP32 blob share them): tw | tf | AL | AR | Vt | lam | s | Kb | Mb
+  // FP32 blob share them): tw | tf | AL | AR | Vt | lam | s | Kb | Mb (the band
+  // tables padded to 2 pm + 1 columns)
   int o_tw = 0, o_tf = 0, o_al = 0, o_ar = 0, o_vt = 0, o_lam = 0, o_s = 0, o_kb = 0, o_mb = 0;
   int len = 0;
   size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
