@@ -32,9 +32,13 @@
 
 namespace iffd {
 
-template <int L>
+// FFT shape: 8 (or 12) elements per thread (variant 1 of fft_device.h; the
+// 16-element shape measured 1.6x slower on these passes), up to 32 line pairs
+// and 256 threads per workgroup
+template <typename T, int L>
 struct GCfg {
-  static constexpr int E = FftPlan<L, 1>::E;
+  static constexpr int V = 1;
+  static constexpr int E = FftPlan<L, V>::E;
   static constexpr int NT = L / E;   // threads per transform
   static constexpr int CAP = 256 / NT;
   static constexpr int FPW = CAP >= 32 ? 32 : (CAP < 1 ? 1 : CAP);  // line pairs per workgroup
@@ -79,7 +83,7 @@ __host__ __device__ inline size_t gup16(size_t x) { return (x + 15) & ~(size_t)1
 
 template <typename T, int L>
 __host__ __device__ inline GLds gen_lds(int m) {
-  using C = GCfg<L>;
+  using C = GCfg<T, L>;
   const int MP = m | 1;
   GLds r;
   size_t o = 0;
@@ -121,9 +125,9 @@ __device__ __forceinline__ T fold_at(const T* x, const T* gb, int s, int cl, int
 }
 
 template <typename Tin, typename Tout, typename T, int MODE, int L>
-__global__ void __launch_bounds__(GCfg<L>::NTH)
+__global__ void __launch_bounds__((GCfg<T, L>::NTH))
 gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a) {
-  using C = GCfg<L>;
+  using C = GCfg<T, L>;
   constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
   extern __shared__ __align__(16) char smem[];
   const GDirDev<T>& D = a.dir;
@@ -226,7 +230,7 @@ gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a
         return c_mul(v, TF[k]);
       };
       auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
-      fft_forward<T, L, 1>(buf, lane, tw, ld, st);
+      fft_forward<T, L, GCfg<T, L>::V>(buf, lane, tw, ld, st);
     }
     __syncthreads();
     {
@@ -297,7 +301,7 @@ gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a
         return c_mul(cpx<T>{xa[k], xb[k]}, pre[k]);
       };
       auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
-      fft_forward<T, L, 1>(buf, lane, tw, ld, st);
+      fft_forward<T, L, GCfg<T, L>::V>(buf, lane, tw, ld, st);
     }
     __syncthreads();
     {
@@ -358,7 +362,7 @@ gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 hipError_t gen_launch(const Plan& P, int axis, const void* in, void* out, int nrhs,
                       const double* active, int astride, hipStream_t s) {
-  using C = GCfg<L>;
+  using C = GCfg<T, L>;
   const GDir& G = P.dirs[axis - 1];
   if (G.L != L || G.n_out > 8 || G.cl + G.cr > 8) return hipErrorInvalidValue;
   const bool f64 = sizeof(T) == 8;
@@ -403,6 +407,7 @@ hipError_t gen_launch(const Plan& P, int axis, const void* in, void* out, int nr
   a.active = active;
   a.astride = astride;
   const GLds ly = gen_lds<T, L>(G.m);
+  if (ly.total > 160 * 1024) return hipErrorInvalidValue;   // beyond a workgroup's LDS
   static bool attr = false;
   if (ly.total > 65536 && !attr) {
     hipError_t e = hipFuncSetAttribute((const void*)gen_line_pass<Tin, Tout, T, MODE, L>,
