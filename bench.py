@@ -437,8 +437,7 @@ def main():
     torch.cuda._sleep(int(cpm * (5.0 + 0.03 * args.steps * npass)))
     evs[0].record()
     for s in range(args.steps):
-        for k in range(npass):
-            plan.apply_pass(k, r, z)
+        plan.apply(r, out=z)
         evs[s + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0

@@ -61,15 +61,6 @@ hipError_t launch_gen_pass(const Plan& P, int pass, const double* r, double* z, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gen_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
-                            const double* a, int as, hipStream_t s) {
-  for (int k = 0; k < 2 * P.d - 1; ++k) {
-    hipError_t e = launch_gen_pass(P, k, r, z, nrhs, ws, a, as, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
 // ---- the operator y = Ahat x with per-direction banded K_k, M_k -------------
 // one pass of mvroll.hip over band tables padded to the largest degree (a 2D
 // plan adds the one-entry third direction M_3 = 1, K_3 = 0)

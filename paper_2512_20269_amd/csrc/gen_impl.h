@@ -81,9 +81,8 @@ struct GLds {
 
 __host__ __device__ inline size_t gup16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-template <typename T, int L>
+template <typename T, int L, class C = GCfg<T, L>>
 __host__ __device__ inline GLds gen_lds(int m) {
-  using C = GCfg<T, L>;
   const int MP = m | 1;
   GLds r;
   size_t o = 0;
@@ -124,21 +123,199 @@ __device__ __forceinline__ T fold_at(const T* x, const T* gb, int s, int cl, int
   return x[s + off];
 }
 
+// The transforms of one tile of TW lines held in LDS (X[l][i], row pitch MP).
+// All threads of the workgroup call each step; every step ends with a barrier.
+template <typename T, int L, class C>
+struct GTile {
+  cpx<T>* tw;  // L twiddles
+  T* X;        // TW x MP
+  cpx<T>* F;   // FPW FFT regions
+  T* GB;       // TW x 8: folded end values
+  T* YO;       // TW x 8: outlier coefficients
+  const T* LO; // TW: sum of the other directions' eigenvalues (middle pass)
+  const T* SO; // TW: product of their scalings (middle pass)
+  int MP;
+
+  // X[l][0..m) = x  ->  X[l][0..n_reg) = U^T V_reg^T x, YO[l] = Vt x; with MID
+  // both scaled by s_t * SO[l] / (lambda_t + LO[l])
+  template <bool MID>
+  __device__ __forceinline__ void forward(const GDirDev<T>& D) const {
+    constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
+    const int m = D.m, nr = D.n_reg, no = D.n_out, cl = D.cl, cr = D.cr, rl = D.rl, rr = D.rr;
+    const int off = rl - cl, ncr = nr - cr;
+    const T* AL = D.blob + D.o_al;
+    const T* AR = D.blob + D.o_ar;
+    const T* Vt = D.blob + D.o_vt;
+    const cpx<T>* TF = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tf);
+    const int tid = threadIdx.x;
+    const int f = tid / NT, lane = tid - f * NT;
+    cpx<T>* buf = F + f * fft_region<L>();
+    const int la = 2 * f, lb = 2 * f + 1;
+    // boundary fold values and outlier coefficients
+    const int nbv = cl + cr;
+    for (int w = tid; w < TW * (nbv + no); w += NTH) {
+      const int l = w & (TW - 1), k = w / TW;
+      const T* x = X + l * MP;
+      T acc = T(0);
+      if (k < cl) {
+        for (int r = 0; r < rl; ++r) acc += AL[r * cl + k] * x[r];
+        GB[l * 8 + k] = acc;
+      } else if (k < nbv) {
+        const int kk = k - cl;
+        for (int r = 0; r < rr; ++r) acc += AR[r * cr + kk] * x[m - rr + r];
+        GB[l * 8 + k] = acc;
+      } else {
+        const int q = k - nbv;
+        const T* v = Vt + q * m;
+        for (int j = 0; j < D.wl; ++j) acc += v[j] * x[j];
+        for (int j = D.wr; j < m; ++j) acc += v[j] * x[j];
+        YO[l * 8 + q] = acc;
+      }
+    }
+    __syncthreads();
+    {
+      const T* xa = X + la * MP;
+      const T* xb = X + lb * MP;
+      const T* ga = GB + la * 8;
+      const T* gbb = GB + lb * 8;
+      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
+        if (k >= nr) return cpx<T>{T(0), T(0)};
+        const cpx<T> v{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
+        return c_mul(v, TF[k]);
+      };
+      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
+      fft_forward<T, L, C::V>(buf, lane, tw, ld, st);
+    }
+    __syncthreads();
+    {
+      const cpx<T>* post = TF + nr;
+      const int mir = D.mir_f;
+      const T* lamd = D.blob + D.o_lam;
+      const T* sd = D.blob + D.o_s;
+      for (int t = lane; t < nr; t += NT) {
+        const cpx<T> z1 = buf[fpad<L>(t)];
+        int t2 = L - t - mir;
+        if (t2 >= L) t2 -= L;
+        cpx<T> z2 = buf[fpad<L>(t2)];
+        z2.y = -z2.y;
+        const cpx<T> P = post[t];
+        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
+        T ya = -sp.y * T(0.5), yb = sm.x * T(0.5);
+        if constexpr (MID) {
+          const T l = lamd[t], s = sd[t];
+          ya *= s * SO[la] / (l + LO[la]);
+          yb *= s * SO[lb] / (l + LO[lb]);
+        }
+        X[la * MP + t] = ya;
+        X[lb * MP + t] = yb;
+      }
+      if constexpr (MID) {
+        for (int w = tid; w < TW * no; w += NTH) {
+          const int l = w & (TW - 1), q = w / TW;
+          YO[l * 8 + q] *= SO[l] / (lamd[nr + q] + LO[l]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // entry i of the spectral line l after forward(): y_reg, then y_out
+  __device__ __forceinline__ T spectral(const GDirDev<T>& D, int l, int i) const {
+    return i < D.n_reg ? X[l * MP + i] : YO[l * 8 + i - D.n_reg];
+  }
+
+  // X[l][0..n_reg) = y_reg and YO[l] = y_out  ->  c = U y_reg at X[l][off + s]
+  // (off = rl - cl), where the interior rows of x = V_reg c read it in place
+  __device__ __forceinline__ void backward(const GDirDev<T>& D) const {
+    constexpr int NT = C::NT;
+    const int nr = D.n_reg, off = D.rl - D.cl;
+    const cpx<T>* TF = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tf);
+    const int tid = threadIdx.x;
+    const int f = tid / NT, lane = tid - f * NT;
+    cpx<T>* buf = F + f * fft_region<L>();
+    const int la = 2 * f, lb = 2 * f + 1;
+    {
+      const T* xa = X + la * MP;
+      const T* xb = X + lb * MP;
+      const cpx<T>* pre = TF + 2 * nr;
+      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
+        if (k >= nr) return cpx<T>{T(0), T(0)};
+        return c_mul(cpx<T>{xa[k], xb[k]}, pre[k]);
+      };
+      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
+      fft_forward<T, L, C::V>(buf, lane, tw, ld, st);
+    }
+    __syncthreads();
+    {
+      const cpx<T>* post = TF + 3 * nr;
+      const int mir = D.mir_b;
+      for (int t = lane; t < nr; t += NT) {
+        const cpx<T> z1 = buf[fpad<L>(t)];
+        int t2 = L - t - mir;
+        if (t2 >= L) t2 -= L;
+        cpx<T> z2 = buf[fpad<L>(t2)];
+        z2.y = -z2.y;
+        const cpx<T> P = post[t];
+        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
+        X[la * MP + off + t] = -sp.y * T(0.5);
+        X[lb * MP + off + t] = sm.x * T(0.5);
+      }
+    }
+    __syncthreads();
+  }
+
+  // entry r of line l after backward(): x = V_reg c + Vt^T y_out
+  __device__ __forceinline__ T value(const GDirDev<T>& D, int l, int r) const {
+    const int m = D.m, cl = D.cl, cr = D.cr, rl = D.rl, rr = D.rr, off = rl - cl;
+    const T* AL = D.blob + D.o_al;
+    const T* AR = D.blob + D.o_ar;
+    const T* Vt = D.blob + D.o_vt;
+    const T* x = X + l * MP;
+    T v;
+    if (r < rl) {
+      v = T(0);
+      for (int c = 0; c < cl; ++c) v += AL[r * cl + c] * x[off + c];
+    } else if (r >= m - rr) {
+      const int rr0 = r - (m - rr);
+      v = T(0);
+      for (int c = 0; c < cr; ++c) v += AR[rr0 * cr + c] * x[m - rr + c];
+    } else {
+      v = x[r];
+    }
+    if (r < D.wl || r >= D.wr) {
+      const T* yo = YO + l * 8;
+      for (int q = 0; q < D.n_out; ++q) v += Vt[q * m + r] * yo[q];
+    }
+    return v;
+  }
+};
+
+template <typename T, int L, class C>
+__device__ __forceinline__ GTile<T, L, C> gen_tile(char* smem, const GLds& ly, int m) {
+  GTile<T, L, C> g;
+  g.tw = reinterpret_cast<cpx<T>*>(smem + ly.tw);
+  g.X = reinterpret_cast<T*>(smem + ly.x);
+  g.F = reinterpret_cast<cpx<T>*>(smem + ly.f);
+  g.GB = reinterpret_cast<T*>(smem + ly.gb);
+  g.YO = reinterpret_cast<T*>(smem + ly.yo);
+  g.LO = reinterpret_cast<const T*>(smem + ly.lo);
+  g.SO = reinterpret_cast<const T*>(smem + ly.so);
+  g.MP = m | 1;
+  return g;
+}
+
 template <typename Tin, typename Tout, typename T, int MODE, int L>
 __global__ void __launch_bounds__((GCfg<T, L>::NTH))
 gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a) {
   using C = GCfg<T, L>;
-  constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
+  constexpr int TW = C::TW, NTH = C::NTH;
   extern __shared__ __align__(16) char smem[];
   const GDirDev<T>& D = a.dir;
-  const int m = D.m, nr = D.n_reg, no = D.n_out, cl = D.cl, cr = D.cr, rl = D.rl, rr = D.rr;
-  const int MP = m | 1, off = rl - cl, ncr = nr - cr;
+  const int m = D.m, nr = D.n_reg, no = D.n_out;
+  const int MP = m | 1;
   const GLds ly = gen_lds<T, L>(m);
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + ly.tw);
-  T* X = reinterpret_cast<T*>(smem + ly.x);
-  cpx<T>* F = reinterpret_cast<cpx<T>*>(smem + ly.f);
-  T* GB = reinterpret_cast<T*>(smem + ly.gb);
-  T* YO = reinterpret_cast<T*>(smem + ly.yo);
+  const GTile<T, L, C> G = gen_tile<T, L, C>(smem, ly, m);
+  T* X = G.X;
   int* LB = reinterpret_cast<int*>(smem + ly.lb);
   T* LO = reinterpret_cast<T*>(smem + ly.lo);
   T* SO = reinterpret_cast<T*>(smem + ly.so);
@@ -153,7 +330,7 @@ gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a
 
   {
     const cpx<T>* g = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tw);
-    for (int k = tid; k < L; k += NTH) tw[k] = g[k];
+    for (int k = tid; k < L; k += NTH) G.tw[k] = g[k];
   }
   if (tid < TW) {
     int i1, i2;
@@ -187,175 +364,69 @@ gen_line_pass(const Tin* __restrict__ in, Tout* __restrict__ out, GPassArgs<T> a
   }
   __syncthreads();
 
-  const T* AL = D.blob + D.o_al;
-  const T* AR = D.blob + D.o_ar;
-  const T* Vt = D.blob + D.o_vt;
-  const cpx<T>* TF = reinterpret_cast<const cpx<T>*>(D.blob + D.o_tf);
-  const int f = tid / NT, lane = tid - (tid / NT) * NT;
-  cpx<T>* buf = F + f * fft_region<L>();
-  const int la = 2 * f, lb = 2 * f + 1;
-
-  if constexpr (MODE != PASS_BWD) {
-    // ---- boundary fold values and outlier coefficients ----
-    const int nbv = cl + cr;
-    for (int w = tid; w < TW * (nbv + no); w += NTH) {
-      const int l = w & (TW - 1), k = w / TW;
-      const T* x = X + l * MP;
-      T acc = T(0);
-      if (k < cl) {
-        for (int r = 0; r < rl; ++r) acc += AL[r * cl + k] * x[r];
-        GB[l * 8 + k] = acc;
-      } else if (k < nbv) {
-        const int kk = k - cl;
-        for (int r = 0; r < rr; ++r) acc += AR[r * cr + kk] * x[m - rr + r];
-        GB[l * 8 + k] = acc;
-      } else {
-        const int q = k - nbv;
-        const T* v = Vt + q * m;
-        for (int j = 0; j < D.wl; ++j) acc += v[j] * x[j];
-        for (int j = D.wr; j < m; ++j) acc += v[j] * x[j];
-        YO[l * 8 + q] = acc;
+  if constexpr (MODE == PASS_FWD) {
+    G.template forward<false>(D);
+    // ---- store y = [y_reg; y_out] ----
+    if (a.S == 1) {
+      const int nl = min(TW, a.lpr - q0);
+      const size_t base = (size_t)q0 * m;
+      for (int e = tid; e < nl * m; e += NTH) {
+        const int l = e / m, i = e - l * m;
+        dst[base + e] = (Tout)G.spectral(D, l, i);
+      }
+    } else {
+      for (int e = tid; e < TW * m; e += NTH) {
+        const int l = e & (TW - 1), i = e / TW;
+        const int bl = LB[l];
+        if (bl >= 0) dst[(size_t)bl + (size_t)i * a.S] = (Tout)G.spectral(D, l, i);
       }
     }
-    __syncthreads();
-    // ---- y_reg = U^T g ----
-    {
-      const T* xa = X + la * MP;
-      const T* xb = X + lb * MP;
-      const T* ga = GB + la * 8;
-      const T* gbb = GB + lb * 8;
-      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
-        if (k >= nr) return cpx<T>{T(0), T(0)};
-        const cpx<T> v{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
-        return c_mul(v, TF[k]);
-      };
-      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
-      fft_forward<T, L, GCfg<T, L>::V>(buf, lane, tw, ld, st);
-    }
-    __syncthreads();
-    {
-      const cpx<T>* post = TF + nr;
-      const int mir = D.mir_f;
-      const T* lamd = D.blob + D.o_lam;
-      const T* sd = D.blob + D.o_s;
-      for (int t = lane; t < nr; t += NT) {
-        const cpx<T> z1 = buf[fpad<L>(t)];
-        int t2 = L - t - mir;
-        if (t2 >= L) t2 -= L;
-        cpx<T> z2 = buf[fpad<L>(t2)];
-        z2.y = -z2.y;
-        const cpx<T> P = post[t];
-        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
-        T ya = -sp.y * T(0.5), yb = sm.x * T(0.5);
-        if constexpr (MODE == PASS_MID) {
-          const T l = lamd[t], s = sd[t];
-          ya *= s * SO[la] / (l + LO[la]);
-          yb *= s * SO[lb] / (l + LO[lb]);
-        }
-        X[la * MP + t] = ya;
-        X[lb * MP + t] = yb;
-      }
-      if constexpr (MODE == PASS_MID) {
-        for (int w = tid; w < TW * no; w += NTH) {
-          const int l = w & (TW - 1), q = w / TW;
-          YO[l * 8 + q] *= SO[l] / (lamd[nr + q] + LO[l]);
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (MODE == PASS_FWD) {
-      // ---- store y = [y_reg; y_out] ----
-      if (a.S == 1) {
-        const int nl = min(TW, a.lpr - q0);
-        const size_t base = (size_t)q0 * m;
-        for (int e = tid; e < nl * m; e += NTH) {
-          const int l = e / m, i = e - l * m;
-          dst[base + e] = (Tout)(i < nr ? X[l * MP + i] : YO[l * 8 + i - nr]);
-        }
-      } else {
-        for (int e = tid; e < TW * m; e += NTH) {
-          const int l = e & (TW - 1), i = e / TW;
-          const int bl = LB[l];
-          if (bl >= 0) dst[(size_t)bl + (size_t)i * a.S] = (Tout)(i < nr ? X[l * MP + i] : YO[l * 8 + i - nr]);
-        }
-      }
-      return;
-    }
+    return;
   } else {
-    // outlier coefficients of the spectral input
-    for (int w = tid; w < TW * no; w += NTH) {
-      const int l = w & (TW - 1), q = w / TW;
-      YO[l * 8 + q] = X[l * MP + nr + q];
-    }
-    __syncthreads();
-  }
-
-  if constexpr (MODE != PASS_FWD) {
-    // ---- c = U y_reg ----
-    {
-      const T* xa = X + la * MP;
-      const T* xb = X + lb * MP;
-      const cpx<T>* pre = TF + 2 * nr;
-      auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
-        if (k >= nr) return cpx<T>{T(0), T(0)};
-        return c_mul(cpx<T>{xa[k], xb[k]}, pre[k]);
-      };
-      auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
-      fft_forward<T, L, GCfg<T, L>::V>(buf, lane, tw, ld, st);
-    }
-    __syncthreads();
-    {
-      // c_s lands at X[l][off + s]: the interior rows of x = V_reg c read it in place
-      const cpx<T>* post = TF + 3 * nr;
-      const int mir = D.mir_b;
-      for (int t = lane; t < nr; t += NT) {
-        const cpx<T> z1 = buf[fpad<L>(t)];
-        int t2 = L - t - mir;
-        if (t2 >= L) t2 -= L;
-        cpx<T> z2 = buf[fpad<L>(t2)];
-        z2.y = -z2.y;
-        const cpx<T> P = post[t];
-        const cpx<T> sp = c_mul(P, c_add(z1, z2)), sm = c_mul(P, c_sub(z1, z2));
-        X[la * MP + off + t] = -sp.y * T(0.5);
-        X[lb * MP + off + t] = sm.x * T(0.5);
+    if constexpr (MODE == PASS_MID) {
+      G.template forward<true>(D);
+    } else {
+      // outlier coefficients of the spectral input
+      for (int w = tid; w < TW * no; w += NTH) {
+        const int l = w & (TW - 1), q = w / TW;
+        G.YO[l * 8 + q] = X[l * MP + nr + q];
       }
+      __syncthreads();
     }
-    __syncthreads();
+    G.backward(D);
     // ---- x = V_reg c + Vt^T y_out, stored ----
-    auto value = [&](int l, int r) -> T {
-      const T* x = X + l * MP;
-      T v;
-      if (r < rl) {
-        v = T(0);
-        for (int c = 0; c < cl; ++c) v += AL[r * cl + c] * x[off + c];
-      } else if (r >= m - rr) {
-        const int rr0 = r - (m - rr);
-        v = T(0);
-        for (int c = 0; c < cr; ++c) v += AR[rr0 * cr + c] * x[m - rr + c];
-      } else {
-        v = x[r];
-      }
-      if (r < D.wl || r >= D.wr) {
-        const T* yo = YO + l * 8;
-        for (int q = 0; q < no; ++q) v += Vt[q * m + r] * yo[q];
-      }
-      return v;
-    };
     if (a.S == 1) {
       const int nl = min(TW, a.lpr - q0);
       const size_t base = (size_t)q0 * m;
       for (int e = tid; e < nl * m; e += NTH) {
         const int l = e / m, r = e - l * m;
-        dst[base + e] = (Tout)value(l, r);
+        dst[base + e] = (Tout)G.value(D, l, r);
       }
     } else {
       for (int e = tid; e < TW * m; e += NTH) {
         const int l = e & (TW - 1), r = e / TW;
         const int bl = LB[l];
-        if (bl >= 0) dst[(size_t)bl + (size_t)r * a.S] = (Tout)value(l, r);
+        if (bl >= 0) dst[(size_t)bl + (size_t)r * a.S] = (Tout)G.value(D, l, r);
       }
     }
   }
+}
+
+// device view of one direction's tables
+template <typename T>
+GDirDev<T> gen_dir_dev(const Plan& P, const GDir& G) {
+  const bool f64 = sizeof(T) == 8;
+  GDirDev<T> d;
+  d.blob = (const T*)(P.d_tables + (f64 ? G.blob64 : G.blob32));
+  d.o_tw = G.o_tw; d.o_tf = G.o_tf; d.o_al = G.o_al; d.o_ar = G.o_ar;
+  d.o_vt = G.o_vt; d.o_lam = G.o_lam; d.o_s = G.o_s;
+  d.m = G.m; d.n_reg = G.n_reg; d.n_out = G.n_out;
+  d.rl = G.rl; d.cl = G.cl; d.rr = G.rr; d.cr = G.cr;
+  d.mir_f = G.tau2;
+  d.mir_b = G.sig2;
+  d.wl = f64 ? G.win64[0] : G.win32[0];
+  d.wr = f64 ? G.win64[1] : G.win32[1];
+  return d;
 }
 
 // launch of one pass (host side); the plan's direction `axis` (1-based)
@@ -369,15 +440,7 @@ hipError_t gen_launch(const Plan& P, int axis, const void* in, void* out, int nr
   GPassArgs<T> a;
   const char* tb = P.d_tables;
   auto blob_of = [&](const GDir& g) { return (const T*)(tb + (f64 ? g.blob64 : g.blob32)); };
-  a.dir.blob = blob_of(G);
-  a.dir.o_tw = G.o_tw; a.dir.o_tf = G.o_tf; a.dir.o_al = G.o_al; a.dir.o_ar = G.o_ar;
-  a.dir.o_vt = G.o_vt; a.dir.o_lam = G.o_lam; a.dir.o_s = G.o_s;
-  a.dir.m = G.m; a.dir.n_reg = G.n_reg; a.dir.n_out = G.n_out;
-  a.dir.rl = G.rl; a.dir.cl = G.cl; a.dir.rr = G.rr; a.dir.cr = G.cr;
-  a.dir.mir_f = G.tau2;
-  a.dir.mir_b = G.sig2;
-  a.dir.wl = f64 ? G.win64[0] : G.win32[0];
-  a.dir.wr = f64 ? G.win64[1] : G.win32[1];
+  a.dir = gen_dir_dev<T>(P, G);
   int S = 1;
   for (int k = 0; k < axis - 1; ++k) S *= P.dirs[k].m;
   a.S = S;
@@ -452,5 +515,6 @@ hipError_t gen_pass_len(const Plan& P, int mode, int axis, int tin, const void* 
 #define IFFD_GEN_PASS_LEN(L)                                                                  \
   hipError_t gen_pass_len<L>(const Plan&, int, int, int, const void*, int, void*, int,        \
                              const double*, int, hipStream_t)
+
 
 }  // namespace iffd

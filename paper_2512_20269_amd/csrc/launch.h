@@ -114,12 +114,10 @@ hipError_t launch_setup_outliers_at(const double* Ao, const double* Bo, const do
                                     int m, int n_reg, double* lam64, float* lam32, double* vt64,
                                     float* vt32, double* stat, hipStream_t s);
 
-// General plans (gen.hip): one pass of the apply (as launch_iffd_pass), the
-// whole apply, and the operator (as launch_matvec).
+// General plans (gen.hip): one pass of the apply (as launch_iffd_pass) and the
+// operator (as launch_matvec).
 hipError_t launch_gen_pass(const Plan& P, int pass, const double* r, double* z, int nrhs, void* ws,
                            const double* active, int active_stride, hipStream_t s);
-hipError_t launch_gen_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
-                            const double* active, int active_stride, hipStream_t s);
 hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
                              double* part, int npart, const double* active, int active_stride,
                              hipStream_t s, const double* fres);

@@ -395,12 +395,12 @@ hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// the preconditioner without fused PCG steps: dense FD, or the line passes of
-// a general plan (the r . z and residual updates then run as kernels of their own)
+// the preconditioner without fused PCG steps: dense FD or the line passes of a
+// general plan (the r . z and residual updates then run as kernels of their own)
 static hipError_t plain_apply(const Plan& P, const double* r, double* z, int nslots, void* ws,
                               const double* a, int as, hipStream_t s) {
-  return P.gen ? launch_gen_apply(P, r, z, nslots, ws, a, as, s)
-               : launch_fd_apply(P, r, z, nslots, ws, a, as, s);
+  return P.method == IFFD_METHOD_FFT ? launch_iffd_apply(P, r, z, nslots, ws, a, as, s)
+                                     : launch_fd_apply(P, r, z, nslots, ws, a, as, s);
 }
 
 hipError_t state_init(const Plan& P, char* st, int nslots, hipStream_t s) {

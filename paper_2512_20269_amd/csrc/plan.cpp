@@ -1121,7 +1121,6 @@ void compute_layout_general(Plan& P) {
     G.stat64 = take(8);
   }
   const size_t unit = take((size_t)8 * 2 * (2 * pm + 1));
-  P.lay = TableLayout{};
   P.lay.unit64 = unit;
   P.lay.total = off;
 }
@@ -1174,6 +1173,7 @@ int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* 
   P.n = G.n; P.p = G.p; P.m = G.m; P.n_reg = G.n_reg; P.n_out = G.n_out; P.L = G.L;
   P.half = G.p / 2;
   P.first64 = P.prec == IFFD_PREC_F32 && pmax >= 5;
+  P.lay = TableLayout{};
   compute_layout_general(P);
   return IFFD_OK;
 }
