@@ -81,6 +81,11 @@ extern "C" {
                                      operands (8-bit significand: larger error,
                                      no overflow concern)                      */
 
+/* system matrix of a mapped domain (iffd_plan_set_geometry) */
+#define IFFD_GEOMETRY_NONE     0  /* A-hat (or A_c of iffd_opts.coef_a)          */
+#define IFFD_GEOMETRY_BUMP     1  /* the unit cube with an interior bump map      */
+#define IFFD_GEOMETRY_ANNULUS  2  /* the thick quarter of annulus                 */
+
 typedef struct iffd_plan iffd_plan;
 
 typedef struct {
@@ -147,6 +152,31 @@ typedef struct {
  * (S = S^reg, Section 4) and is the exact inverse by the DST-I alone.
  * *out receives the plan (NULL on error). */
 int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts);
+
+/* Host-only, before iffd_plan_setup (IFFD_E_STATE after).  Makes the plan's
+ * system matrix (iffd_kron_matvec, the PCG entry points) the Galerkin matrix of
+ * the Poisson problem on Omega = F([0,1]^3) pulled back to the parameter cube
+ * (Section 2):
+ *   A_ij = int grad B_i^T G grad B_j dxi,  G = |det J| J^{-1} J^{-T},  J = dF/dxi,
+ * with Gauss-Legendre rules of p_k + 1 points per element and direction,
+ * applied matrix-free (per element sum factorization, then a fixed-order
+ * gather).  The preconditioners stay those of A-hat, whose condition number
+ * against A is bounded by the extremes of G (Section 3).  d = 3, coef_a = 0.
+ *   IFFD_GEOMETRY_BUMP     params {eps}, |eps| < 0.1: F(xi) = xi + eps phi(xi)
+ *                          (1, 1, 1), phi = sin(pi xi1) sin(pi xi2) sin(pi xi3):
+ *                          the unit cube with a non-separable parametrization
+ *                          (A has no Kronecker structure).
+ *   IFFD_GEOMETRY_ANNULUS  params {r_in, r_out, H}, 0 < r_in < r_out, H > 0:
+ *                          F(xi) = (r c1(xi2), r c2(xi2), H xi3), r = r_in +
+ *                          (r_out - r_in) xi1, c the quarter circle as the
+ *                          rational quadratic with control points (1,0), (1,1),
+ *                          (0,1) and weights 1, 1/sqrt(2), 1 (the thick quarter
+ *                          of annulus of Section 7).
+ *   IFFD_GEOMETRY_NONE     restores A-hat.
+ * The operator needs a workspace of 8 * n1 n2 n3 (p1+1)(p2+1)(p3+1) bytes per
+ * right-hand side (iffd_plan_info.matvec_ws_bytes, included in the PCG
+ * state sizes). */
+int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, int nparams);
 
 /* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan.
  * For a general plan the scalar n, p, m, n_reg, n_out and fft_len are those

@@ -29,6 +29,7 @@ OK, W_NOT_CONVERGED = 0, 1
 E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
 PREC_F64, PREC_F32, PREC_F16S, PREC_BF16S = 0, 1, 2, 3
+GEOMETRY_NONE, GEOMETRY_BUMP, GEOMETRY_ANNULUS = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
@@ -76,6 +77,7 @@ SIGNATURES = {
     "iffd_plan_query": (_I, [_P, ctypes.POINTER(_Info)]),
     "iffd_plan_query_dirs": (_I, [_P, ctypes.POINTER(_DirInfo), _I]),
     "iffd_plan_read_dir": (_I, [_P, _I, _I, _P, _Z, _P]),
+    "iffd_plan_set_geometry": (_I, [_P, _I, _P, _I]),
     "iffd_plan_setup": (_I, [_P, _P, _Z, _P]),
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
@@ -190,10 +192,15 @@ class Plan:
     dirichlet: d pairs (end x_k = 0, end x_k = 1), 1 = Dirichlet, 0 = natural
     (Neumann), direction 1 first; given (or n, p given per direction as
     sequences) it makes a general plan (iffd_plan_create_general) whose
-    tensors have shape (m_d, .., m_1)."""
+    tensors have shape (m_d, .., m_1).
+    geometry: None, or (kind, params) with kind "bump" ({eps}) or "annulus"
+    ({r_in, r_out, H}): the system matrix becomes the Galerkin matrix of the
+    mapped domain (iffd_plan_set_geometry, d = 3); the preconditioner stays
+    that of A-hat."""
 
     def __init__(self, d: int, n, p, method: str = "fft", precision: str = "f32",
-                 max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None):
+                 max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None,
+                 geometry=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
@@ -210,6 +217,14 @@ class Plan:
         else:
             _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h
+        self.geometry = None
+        if geometry is not None:
+            kind, params = geometry
+            code = {"none": GEOMETRY_NONE, "bump": GEOMETRY_BUMP,
+                    "annulus": GEOMETRY_ANNULUS}[kind]
+            par = (ctypes.c_double * max(len(params), 1))(*[float(v) for v in params])
+            _check(lib.iffd_plan_set_geometry(h, code, par, len(params)), "plan_set_geometry")
+            self.geometry = (kind, tuple(float(v) for v in params))
         info = _Info()
         _check(lib.iffd_plan_query(h, ctypes.byref(info)), "plan_query")
         self.info = {f: getattr(info, f) for f, _ in _Info._fields_}

@@ -147,6 +147,13 @@ void outlier_windows(const std::vector<double>& Vt, int n_out, int m, int* win32
 // table upload and outlier setup of a general plan: per direction one FP64
 // and one FP32 blob (tw | tf | AL | AR | Vt | lam | s | Kb | Mb), the outlier
 // pencil solved on the device straight into both blobs
+// the element tables of a mapped domain's system matrix
+hipError_t upload_geometry(const Plan& P, void* d_tables, hipStream_t s) {
+  if (P.geo.kind == 0) return hipSuccess;
+  return hipMemcpyAsync((char*)d_tables + P.geo.off, P.geo.tab.data(), 8 * P.geo.tab.size(),
+                        hipMemcpyHostToDevice, s);
+}
+
 int setup_general(Plan& P, void* d_tables, hipStream_t s) {
   std::vector<char> buf(P.lay.total, 0);
   for (int k = 0; k < P.d; ++k) {
@@ -178,6 +185,7 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
     put<double>(buf, P.lay.unit64, unit);
   }
   hipError_t e = hipMemcpyAsync(d_tables, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = upload_geometry(P, d_tables, s);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   char* b = (char*)d_tables;
   for (int k = 0; k < P.d && e == hipSuccess; ++k) {
@@ -297,6 +305,16 @@ int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count)
   return IFFD_OK;
 }
 
+int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, int nparams) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  Plan& P = plan->P;
+  if (P.ready) return fail(IFFD_E_STATE, "set the geometry before iffd_plan_setup");
+  std::string err;
+  const int rc = build_geometry(P, kind, h_params, nparams, err);
+  if (rc != IFFD_OK) return fail(rc, err);
+  return IFFD_OK;
+}
+
 void iffd_plan_destroy(iffd_plan* plan) {
   if (!plan) return;
   {
@@ -397,6 +415,7 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
     }
   }
   hipError_t e = hipMemcpyAsync(d_tables, buf.data(), t.total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = upload_geometry(P, d_tables, s);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   P.d_tables = (char*)d_tables;
   P.table_bytes = table_bytes;

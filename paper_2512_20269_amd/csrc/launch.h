@@ -122,6 +122,13 @@ hipError_t launch_gen_matvec(const Plan& P, const double* x, double* y, int nrhs
                              double* part, int npart, const double* active, int active_stride,
                              hipStream_t s, const double* fres);
 int gen_matvec_blocks(const Plan& P);
+
+// The system matrix of a mapped domain (geo.hip), as launch_matvec.
+hipError_t launch_geo_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
+                             double* part, int npart, const double* active, int active_stride,
+                             hipStream_t s, const double* fres);
+int geo_matvec_blocks(const Plan& P);
+size_t geo_matvec_ws_bytes(const Plan& P, int nrhs);
 size_t gen_matvec_ws_bytes(const Plan& P, int nrhs);
 
 // One-pass operator of mvroll.hip: per-direction band tables K_k, M_k of

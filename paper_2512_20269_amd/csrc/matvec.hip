@@ -412,6 +412,7 @@ mv_fused3(const double* __restrict__ x, double* __restrict__ y, int m, int N, in
 // beat it for p >= 6 (283 vs 488 us at p = 6, 379 vs 1602 us at p = 8, where
 // its register windows spill).
 int matvec_blocks(const Plan& P_) {
+  if (P_.geo.kind) return geo_matvec_blocks(P_);
   if (P_.gen) return gen_matvec_blocks(P_);
   if (mv_fused(P_)) {
     int ncs, nrb, n3c;
@@ -424,6 +425,7 @@ int matvec_blocks(const Plan& P_) {
 }
 
 size_t matvec_ws_bytes(const Plan& P_, int nrhs) {
+  if (P_.geo.kind) return geo_matvec_ws_bytes(P_, nrhs);
   if (P_.gen) return gen_matvec_ws_bytes(P_, nrhs);
   return (P_.d == 3 && !mv_fused(P_)) ? (size_t)2 * 8 * P_.N * nrhs : 0;
 }
@@ -472,6 +474,7 @@ static hipError_t mv_launch(const Plan& P_, const double* x, double* y, int nrhs
 hipError_t launch_matvec(const Plan& P_, const double* x, double* y, int nrhs, void* ws,
                          double* part, int npart, const double* a, int as, hipStream_t s,
                          const double* fres) {
+  if (P_.geo.kind) return launch_geo_matvec(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
   if (P_.gen) return launch_gen_matvec(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);
   switch (P_.p) {
     case 1: return mv_launch<1>(P_, x, y, nrhs, ws, part, npart, a, as, s, fres);

@@ -1178,4 +1178,80 @@ int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* 
   return IFFD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Geometry-mapped system matrix: per-direction element tables
+// ---------------------------------------------------------------------------
+int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& err) {
+  if (P.geo.kind == 0) P.geo.base_total = P.lay.total;
+  if (kind == IFFD_GEOMETRY_NONE) {
+    P.lay.total = P.geo.base_total;
+    P.geo = GeoPlan{};
+    return IFFD_OK;
+  }
+  if (P.d != 3) { err = "a mapped domain needs d = 3"; return IFFD_E_UNSUPPORTED; }
+  if (P.coef_a != 0.0) { err = "a mapped domain replaces coef_a; create the plan with coef_a = 0"; return IFFD_E_INVAL; }
+  if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
+  GeoPlan G;
+  G.kind = kind;
+  G.base_total = P.geo.kind == 0 ? P.lay.total : P.geo.base_total;
+  if (kind == IFFD_GEOMETRY_BUMP) {
+    if (!par || npar < 1 || !(std::fabs(par[0]) < 0.1)) { err = "bump map: params {eps}, |eps| < 0.1"; return IFFD_E_INVAL; }
+    G.par[0] = par[0];
+  } else if (kind == IFFD_GEOMETRY_ANNULUS) {
+    if (!par || npar < 3 || !(par[0] > 0.0 && par[1] > par[0] && par[2] > 0.0)) {
+      err = "annulus map: params {r_in, r_out, H}, 0 < r_in < r_out, H > 0";
+      return IFFD_E_INVAL;
+    }
+    for (int i = 0; i < 3; ++i) G.par[i] = par[i];
+  } else {
+    err = "unknown geometry kind";
+    return IFFD_E_INVAL;
+  }
+  int o = 0;
+  for (int k = 0; k < 3; ++k) {
+    GeoPlanDir& g = G.dir[k];
+    int n, p, lo, m;
+    if (P.gen) {
+      n = P.dirs[k].n; p = P.dirs[k].p; lo = P.dirs[k].dlo; m = P.dirs[k].m;
+    } else {
+      n = P.n; p = P.p; lo = 1; m = P.m;
+    }
+    if (p + 1 > 9) { err = "p <= 8"; return IFFD_E_INVAL; }
+    g.n = n; g.P = p + 1; g.lo = lo; g.m = m;
+    g.o_x = o; o += n * g.P;
+    g.o_w = o; o += n * g.P;
+    g.o_v = o; o += n * g.P * g.P;
+    g.o_d = o; o += n * g.P * g.P;
+  }
+  G.tab.assign((size_t)o, 0.0);
+  std::vector<double> gx, gw, val, der;
+  for (int k = 0; k < 3; ++k) {
+    GeoPlanDir& g = G.dir[k];
+    const int n = g.n, p = g.P - 1, nb = n + p;
+    std::vector<double> U(n + 2 * p + 1);
+    for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
+    for (int j = 1; j < n; ++j) U[p + j] = (double)j / n;
+    gauss_legendre(p + 1, gx, gw);
+    const double h = 1.0 / n;
+    for (int e = 0; e < n; ++e) {
+      const int s = p + e;   // span of element e: B-splines e .. e+p
+      for (int q = 0; q <= p; ++q) {
+        const double x = e * h + 0.5 * h * (gx[q] + 1.0);
+        G.tab[(size_t)g.o_x + e * g.P + q] = x;
+        G.tab[(size_t)g.o_w + e * g.P + q] = 0.5 * h * gw[q];
+        basis_and_derivative(s, x, p, U, val, der);
+        for (int a = 0; a <= p; ++a) {
+          G.tab[(size_t)g.o_v + ((size_t)e * g.P + q) * g.P + a] = val[a];
+          G.tab[(size_t)g.o_d + ((size_t)e * g.P + q) * g.P + a] = der[a];
+        }
+      }
+    }
+    (void)nb;
+  }
+  G.off = (G.base_total + 255) & ~(size_t)255;
+  P.lay.total = G.off + (((size_t)8 * o + 255) & ~(size_t)255);
+  P.geo = G;
+  return IFFD_OK;
+}
+
 }  // namespace iffd

@@ -73,6 +73,22 @@ struct GDir {
   size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)
 };
 
+// Geometry-mapped system matrix (iffd_plan_set_geometry): per direction the
+// Gauss points, weights, and the values and derivatives of the p+1 B-splines of
+// every element there (element offsets inside the tables at `off`)
+struct GeoPlanDir {
+  int n = 0, P = 0, lo = 0, m = 0;   // elements, p + 1, full index of kept entry 0, kept
+  int o_x = 0, o_w = 0, o_v = 0, o_d = 0;
+};
+struct GeoPlan {
+  int kind = 0;   // IFFD_GEOMETRY_*
+  double par[4] = {0, 0, 0, 0};
+  GeoPlanDir dir[3];
+  std::vector<double> tab;
+  size_t off = 0;         // byte offset of the tables
+  size_t base_total = 0;  // table bytes of the plan without them
+};
+
 struct Plan {
   int d = 0, n = 0, p = 0, m = 0, n_reg = 0, n_out = 0, half = 0, L = 0;
   int method = IFFD_METHOD_FFT, prec = IFFD_PREC_F32, max_rhs = 1;
@@ -117,6 +133,8 @@ struct Plan {
   bool gen = false;
   GDir dirs[3];
 
+  GeoPlan geo;
+
   TableLayout lay{};
   char* d_tables = nullptr;
   size_t table_bytes = 0;
@@ -127,6 +145,7 @@ struct Plan {
 int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string& err);
 int build_plan_general(Plan& P, int d, const int* n, const int* p, const int* dirichlet,
                        const iffd_opts* opts, std::string& err);
+int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& err);
 void compute_layout(Plan& P);
 StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);

@@ -1,0 +1,146 @@
+"""GPU parity of the mapped-domain system matrix (Section 2's problem on
+Omega = F([0,1]^3), Section 7's thick quarter of annulus) against the
+oracle's assembled Galerkin matrix (oracle/geometry.py), and PCG with the
+A-hat preconditioners on it (Section 3: the preconditioner is built from the
+parameter-domain matrix; Table 4).
+
+Tolerance: the operator is FP64 on both sides and differs only in the order
+of the sums (sum factorization and a fixed-order gather here, dense local
+matrices there): 1e-13 relative in the 2-norm and the max-norm.  PCG in FP64
+takes the same number of iterations as the oracle's on the same right-hand
+side; Table 4's counts are reproduced within +-1 (tests/golden)."""
+
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import general as G
+from oracle import geometry as Gm
+from oracle import krylov
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2512_20269_amd as I  # noqa: E402
+from test_gpu_parity import dev, host, rel  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DSET = {(1, 1): {0, 1}, (1, 0): {0}, (0, 1): {1}, (0, 0): set()}
+ANNULUS = ("annulus", (1.0, 2.0, 1.0))
+BOTTOM = ((0, 0), (0, 0), (1, 0))   # Dirichlet on the face xi_3 = 0 only
+
+
+def specs_of(n, p, dl):
+    return tuple((nk, pk, frozenset(DSET[tuple(dk)])) for nk, pk, dk in zip(n, p, dl))
+
+
+@functools.lru_cache(maxsize=None)
+def geo_oracle(specs, geometry):
+    return Gm.GeometryOperator([(n, p, set(D)) for n, p, D in specs], geometry[0], geometry[1])
+
+
+def make_plan(n, p, dl, geometry, method="fft", prec="f64", max_rhs=1):
+    if dl is None:   # a uniform plan: Dirichlet everywhere, one n and p
+        return I.Plan(3, n, p, method=method, precision=prec, max_rhs=max_rhs,
+                      geometry=geometry)
+    return I.Plan(3, list(n), list(p), method=method, precision=prec, max_rhs=max_rhs,
+                  dirichlet=[tuple(x) for x in dl], geometry=geometry)
+
+
+def plan_specs(n, p, dl):
+    if dl is None:
+        return specs_of((n,) * 3, (p,) * 3, ((1, 1),) * 3)
+    return specs_of(n, p, dl)
+
+
+# (n, p, ends or None for a uniform Dirichlet plan, geometry, method)
+MATVEC_CASES = [
+    (8, 2, None, ("bump", (0.05,)), "fft"),
+    (8, 3, None, ("bump", (-0.08,)), "fft"),
+    (12, 4, None, ("bump", (0.03,)), "dense"),
+    ((8, 12, 16), (2, 3, 4), ((1, 0), (0, 1), (0, 0)), ("bump", (0.06,)), "fft"),
+    ((8, 8, 8), (2, 2, 2), BOTTOM, ANNULUS, "fft"),
+    ((8, 8, 8), (5, 5, 5), BOTTOM, ANNULUS, "fft"),
+    ((12, 8, 16), (3, 4, 2), BOTTOM, ANNULUS, "fft"),
+    ((16, 8, 8), (1, 3, 2), ((1, 1), (0, 0), (1, 0)), ("annulus", (0.5, 3.0, 2.0)), "fft"),
+]
+
+
+@pytest.mark.parametrize("n,p,dl,geometry,method", MATVEC_CASES)
+def test_geometry_matvec_matches_oracle(n, p, dl, geometry, method):
+    op = geo_oracle(plan_specs(n, p, dl), geometry)
+    pl = make_plan(n, p, dl, geometry, method=method, max_rhs=2)
+    assert pl.shape == op.shape
+    X = np.stack([workloads.uniform_tensor(pl.shape, seed=s) for s in (3, 4)])
+    y = host(pl.matvec(dev(X)))
+    yo = op.matvec(X)
+    e2, emax = rel(y, yo), float(np.abs(y - yo).max() / np.abs(yo).max())
+    print(f"geometry {geometry[0]} n={n} p={p} ends={dl} {method}: rel2 {e2:.2e} max {emax:.2e}",
+          flush=True)
+    assert e2 <= 1e-13 and emax <= 1e-13
+
+
+def test_geometry_matvec_is_deterministic_and_batched():
+    n, p, dl = (12, 8, 16), (3, 4, 2), BOTTOM
+    pl = make_plan(n, p, dl, ANNULUS, max_rhs=3)
+    X = np.stack([workloads.uniform_tensor(pl.shape, seed=s) for s in (5, 6, 7)])
+    y3 = host(pl.matvec(dev(X)))
+    y1 = host(pl.matvec(dev(X[1:2])))
+    assert np.array_equal(y3[1:2], y1)
+    assert np.array_equal(y3, host(pl.matvec(dev(X))))
+
+
+# (n, p, ends, geometry, method, oracle preconditioner)
+PCG_CASES = [
+    (8, 3, None, ("bump", (0.07,)), "fft", "iffd_b"),
+    (8, 3, None, ("bump", (0.07,)), "dense", "fd"),
+    ((16, 16, 16), (2, 2, 2), BOTTOM, ANNULUS, "fft", "iffd_b"),
+    ((16, 16, 16), (3, 3, 3), BOTTOM, ANNULUS, "fft", "iffd_b"),
+]
+
+
+@pytest.mark.parametrize("n,p,dl,geometry,method,kind", PCG_CASES)
+def test_geometry_pcg_matches_oracle(n, p, dl, geometry, method, kind):
+    specs = plan_specs(n, p, dl)
+    op = geo_oracle(specs, geometry)
+    pre = G.GeneralPreconditioner([(a, b, set(D)) for a, b, D in specs], kind)
+    pl = make_plan(n, p, dl, geometry, method=method, prec="f64")
+    f = workloads.uniform_tensor(pl.shape, seed=1)
+    uo, it_o, conv_o, hist, *_ = krylov.pcg(op.matvec, pre.apply, f, tol=1e-8, maxit=200)
+    u, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+    s = st[0]
+    u = host(u)
+    print(f"PCG {geometry[0]} n={n} p={p} {method}: {s['iterations']} iterations "
+          f"(oracle {it_o}), relres {s['relres']:.3e} (oracle {hist[-1]:.3e})", flush=True)
+    assert conv_o and s["converged"]
+    assert s["iterations"] == it_o
+    assert abs(s["relres"] - hist[-1]) <= 1e-6 * hist[-1]
+    assert rel(u, uo) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_table4_iffd_counts_on_gpu(n):
+    """Table 4 (thick quarter of annulus, Dirichlet on the bottom face,
+    natural elsewhere): IFFD PCG iterations with the FP32 apply within +-1
+    of the printed counts for p = 2..5."""
+    g = json.load(open(os.path.join(HERE, "golden", "table4_annulus.json")))
+    printed = g["iffd"][g["n"].index(n)]
+    for p, it_p in zip(g["p"], printed):
+        pl = make_plan((n,) * 3, (p,) * 3, BOTTOM, ANNULUS, prec="f32")
+        f = workloads.uniform_tensor(pl.shape, seed=1)
+        _, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+        s = st[0]
+        print(f"Table 4 n={n} p={p}: IFFD {s['iterations']} (printed {it_p})", flush=True)
+        assert s["converged"] and abs(s["iterations"] - it_p) <= 1
+        del pl
+        torch.cuda.empty_cache()
+
+
+def test_geometry_state_rules():
+    pl = make_plan(8, 2, None, ("bump", (0.05,)))
+    rc = I.lib.iffd_plan_set_geometry(pl._h, I.GEOMETRY_NONE, None, 0)
+    assert rc == I.E_STATE   # after setup

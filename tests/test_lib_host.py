@@ -362,3 +362,36 @@ def test_general_plan_sizes_and_errors():
     assert I.lib.iffd_precond_apply(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1,
                                     ctypes.c_void_p(1024), 1 << 30, None) == I.E_STATE
     I.lib.iffd_plan_destroy(h)
+
+
+def test_geometry_host_rules():
+    """iffd_plan_set_geometry: the kinds and their parameter ranges, d = 3,
+    coef_a = 0, the operator workspace 8 n1 n2 n3 (p+1)^3 bytes per RHS, and
+    IFFD_GEOMETRY_NONE restoring the table size."""
+    par = lambda *v: (ctypes.c_double * len(v))(*v)
+    rc, h = host_plan(3, 8, 3, max_rhs=2)
+    assert rc == 0
+    info0 = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info0)) == 0
+    assert I.lib.iffd_plan_set_geometry(h, 7, par(0.0), 1) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_BUMP, par(0.2), 1) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_BUMP, None, 0) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par(2.0, 1.0, 1.0), 3) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par(1.0, 2.0, 0.0), 3) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par(1.0, 2.0), 2) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par(1.0, 2.0, 1.0), 3) == 0
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.matvec_ws_bytes == 8 * 8 ** 3 * 4 ** 3 * 2
+    assert info.table_bytes > info0.table_bytes
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_NONE, None, 0) == 0
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.table_bytes == info0.table_bytes
+    assert info.matvec_ws_bytes == info0.matvec_ws_bytes
+    I.lib.iffd_plan_destroy(h)
+    _, h2 = host_plan(2, 8, 3)
+    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_UNSUPPORTED
+    I.lib.iffd_plan_destroy(h2)
+    _, h3 = host_plan(3, 8, 3, coef_a=0.5)
+    assert I.lib.iffd_plan_set_geometry(h3, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_INVAL
+    I.lib.iffd_plan_destroy(h3)

@@ -1,0 +1,166 @@
+"""Pins for oracle.geometry, the Galerkin matrix on a mapped domain (Section
+2's problem on Omega = F([0,1]^3); Section 3's bound on kappa(A-hat^{-1} A);
+Section 7's thick quarter of annulus, Table 4).
+
+  * eps = 0 (the identity map) gives A-hat, the Kronecker sum of the exact
+    one-dimensional stiffness and mass matrices;
+  * F(xi) = B xi with a non-symmetric B: the energy of u = a . F(xi) (exactly
+    representable with natural ends) is |a|^2 |det B|, the integral of
+    |grad_x u|^2 over B([0,1]^3); a transposed or inverted G fails it;
+  * the annulus: the energies of u = x_3 = H xi_3 and of the radial u = xi_1
+    are vol(Omega) and vol(Omega) / (r_out - r_in)^2 (quadrature error only);
+  * the Jacobians against central differences of the maps, written here from
+    their definitions (the rational quadratic as a weighted sum of the three
+    control points, which is a quarter of the unit circle);
+  * Section 3's bound: every generalized eigenvalue of (A, A-hat) lies in
+    [min lambda_min(G), max lambda_max(G)] over the quadrature points (the
+    rule integrates |grad u|^2 exactly, so the bound holds without slack);
+  * Table 4's iteration counts at n = 16, p = 2, for FD and IFFD.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads
+from oracle import geometry as Gm
+from oracle import general as G
+from oracle import krylov
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ANNULUS = (1.0, 2.0, 1.0)
+
+
+def bump_map(eps, X):
+    phi = np.prod(np.sin(np.pi * X), axis=1)
+    return X + eps * phi[:, None]
+
+
+def circle_arc(t):
+    """The rational quadratic with control points (1,0), (1,1), (0,1) and
+    weights 1, 1/sqrt(2), 1, as the weighted sum of its control points."""
+    P = np.array([[1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    w = np.array([1.0, 1.0 / np.sqrt(2.0), 1.0])
+    B = np.stack([(1 - t) ** 2, 2 * t * (1 - t), t ** 2], axis=1) * w
+    return (B @ P) / B.sum(axis=1)[:, None]
+
+
+def annulus_map(par, X):
+    r_in, r_out, H = par
+    r = r_in + (r_out - r_in) * X[:, 0]
+    c = circle_arc(X[:, 1])
+    return np.stack([r * c[:, 0], r * c[:, 1], H * X[:, 2]], axis=1)
+
+
+def fd_jacobian(F, X, h=1e-6):
+    J = np.zeros((X.shape[0], 3, 3))
+    for k in range(3):
+        E = np.zeros(3)
+        E[k] = h
+        J[:, :, k] = (F(X + E) - F(X - E)) / (2 * h)
+    return J
+
+
+def test_maps_jacobians_against_differences():
+    X = np.random.default_rng(0).uniform(0.05, 0.95, (40, 3))
+    Jb = Gm.jacobian("bump", [0.07], X)
+    assert np.abs(Jb - fd_jacobian(lambda Y: bump_map(0.07, Y), X)).max() < 1e-8
+    Ja = Gm.jacobian("annulus", ANNULUS, X)
+    assert np.abs(Ja - fd_jacobian(lambda Y: annulus_map(ANNULUS, Y), X)).max() < 1e-8
+    t = np.linspace(0, 1, 101)
+    c = circle_arc(t)
+    assert np.abs(np.hypot(c[:, 0], c[:, 1]) - 1).max() < 1e-15   # a quarter of the unit circle
+    assert np.allclose(c[0], [1, 0]) and np.allclose(c[-1], [0, 1])
+    # G is |det J| (J^T J)^{-1}: symmetric positive definite
+    Gq = Gm.coefficient("annulus", ANNULUS, X)
+    assert np.abs(Gq - np.transpose(Gq, (0, 2, 1))).max() < 1e-14
+    assert np.linalg.eigvalsh(Gq).min() > 0
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_identity_map_gives_A_hat(p):
+    n = 5
+    specs = [(n, p, {0, 1}), (n + 1, p, {0}), (n, p, set())]
+    A = Gm.GeometryOperator(specs, "bump", [0.0])
+    Ahat = G.GeneralPreconditioner(specs, "fd")
+    X = np.random.default_rng(p).standard_normal(A.shape)
+    ref = Ahat.matvec(X)
+    assert A.shape == Ahat.shape
+    assert np.abs(A.matvec(X) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_linear_map_energy(p):
+    B = np.array([[1.3, 0.4, -0.2], [0.1, 0.9, 0.3], [-0.5, 0.2, 1.7]])
+    n = 4
+    specs = [(n, p, set())] * 3
+    A = Gm.GeometryOperator(specs, "linear", B.reshape(-1))
+    # Greville abscissae reproduce linear functions: u(xi) = sum_i g_i B_i(xi) = xi
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    g = np.array([knots[i + 1:i + p + 1].mean() for i in range(n + p)])
+    G3, G2, G1 = np.meshgrid(g, g, g, indexing="ij")   # (i3, i2, i1)
+    a = np.array([0.7, -1.1, 0.4])
+    c = a @ B   # u = a . (B xi) = (a B) . xi
+    U = c[0] * G1 + c[1] * G2 + c[2] * G3
+    energy = float(np.vdot(U, A.matvec(U)))
+    exact = float(a @ a) * abs(np.linalg.det(B))
+    assert abs(energy - exact) <= 1e-12 * exact
+    # constants carry no energy (natural ends)
+    assert np.abs(A.matvec(np.ones(A.shape))).max() < 1e-12
+
+
+def test_annulus_energies():
+    r_in, r_out, H = ANNULUS
+    vol = np.pi / 4 * (r_out ** 2 - r_in ** 2) * H
+    n, p = 6, 2
+    specs = [(n, p, set())] * 3
+    A = Gm.GeometryOperator(specs, "annulus", ANNULUS)
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    g = np.array([knots[i + 1:i + p + 1].mean() for i in range(n + p)])
+    G3, G2, G1 = np.meshgrid(g, g, g, indexing="ij")
+    e3 = float(np.vdot(H * G3, A.matvec(H * G3)))   # u = x_3: |grad u| = 1
+    e1 = float(np.vdot(G1, A.matvec(G1)))           # u = (r - r_in) / (r_out - r_in)
+    assert abs(e3 - vol) < 1e-6 * vol
+    assert abs(e1 - vol / (r_out - r_in) ** 2) < 1e-6 * vol
+
+
+@pytest.mark.parametrize("kind,par", [("bump", [0.08]), ("annulus", ANNULUS)])
+def test_section3_bound(kind, par):
+    n, p = 4, 2
+    specs = [(n, p, {0, 1}), (n, p, {0, 1}), (n, p, {0})]
+    A = Gm.GeometryOperator(specs, kind, par).A.toarray()
+    Ahat = G.GeneralPreconditioner(specs, "fd")
+    N = A.shape[0]
+    Ah = np.stack([Ahat.matvec(e.reshape(Ahat.shape)).reshape(-1) for e in np.eye(N)], axis=1)
+    assert np.abs(A - A.T).max() < 1e-13 * np.abs(A).max()
+    lam = sla.eigh(A, Ah, eigvals_only=True)
+    # the extremes of G over the quadrature points of every element
+    pts = []
+    for (nk, pk, _) in specs:
+        x, _, _, _ = Gm.element_tables(nk, pk)
+        pts.append(x.reshape(-1))
+    X = np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).reshape(-1, 3)
+    ev = np.linalg.eigvalsh(Gm.coefficient(kind, par, X))
+    lo, hi = ev.min(), ev.max()
+    assert lam.min() >= lo * (1 - 1e-10) and lam.max() <= hi * (1 + 1e-10)
+    assert lam.max() / lam.min() > 1.0 + 1e-3   # A is not A-hat
+
+
+def test_table4_annulus_n16_p2():
+    gold = json.load(open(os.path.join(HERE, "golden", "table4_annulus.json")))
+    n, p = 16, 2
+    specs = [(n, p, set()), (n, p, set()), (n, p, {0})]   # Dirichlet on the bottom face xi_3 = 0
+    A = Gm.GeometryOperator(specs, "annulus", ANNULUS)
+    f = workloads.uniform_tensor(A.shape, seed=1)
+    its = {}
+    for kind in ("fd", "iffd_b"):
+        pre = G.GeneralPreconditioner(specs, kind)
+        _, it, conv, *_ = krylov.pcg(A.matvec, pre.apply, f, tol=1e-8, maxit=200)
+        assert conv
+        its[kind] = it
+    i, j = gold["n"].index(n), gold["p"].index(p)
+    assert abs(its["fd"] - gold["fd"][i][j]) <= 1, its
+    assert abs(its["iffd_b"] - gold["iffd"][i][j]) <= 1, its
