@@ -5,65 +5,84 @@
 // Gauss-Legendre rules with p_k + 1 points per element and direction.
 //
 // Matrix-free, in two kernels:
-//   geo_element  one workgroup per element: gather the (p_1+1)(p_2+1)(p_3+1)
-//                local coefficients, sum factorization to the gradients at
-//                the Gauss points (three contractions), G(xi) from the map at
-//                each point, the transposed contractions back to the local
-//                functions; the local result is written to a workspace slot
-//                of its own (no atomics);
+//   geo_element  one workgroup per element with a lane per local index (64,
+//                128 or 256 lanes; two and eight elements per 64 lanes for
+//                p = 2 and p = 1): gather the (p_1+1)(p_2+1)(p_3+1) local
+//                coefficients, sum factorization to the
+//                gradients at the Gauss points (three contractions), G from
+//                the map at each point, the transposed contractions back to
+//                the local functions; the local result goes to a workspace
+//                slot of its own (no atomics), stored local index major
+//                (all elements of one local index contiguous) so that the
+//                gather reads whole cache lines;
 //   geo_gather   one thread per kept coefficient: the sum of the (at most
 //                (p+1)^3) element contributions in a fixed order, plus
 //                per-block partial sums of x . y or (f - y)^2 for PCG.
 // Deterministic: no result depends on scheduling.
+//
+// Both maps are products of one-dimensional factors (the bump's
+// sin(pi xi_k), the annulus' radius and circle), so each workgroup first
+// evaluates those factors at the p_k + 1 Gauss points of each direction; the
+// Jacobian at a point is then a few products of them.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
 
 namespace iffd {
 
-// the map's Jacobian J[i][k] = dF_i / dxi_k at xi
-__device__ __forceinline__ void geo_jacobian(int kind, const double* par, const double* xi,
-                                             double J[3][3]) {
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 3; ++k) J[i][k] = 0.0;
+// per-direction factors of the map at one Gauss point
+//   bump:     f = (sin(pi xi), cos(pi xi))
+//   annulus:  direction 1: f = (r(xi)), direction 2: f = (c1, c2, c1', c2')
+//             of the quarter circle at t = xi (rational quadratic, weights
+//             1, 1/sqrt 2, 1), direction 3: unused
+__device__ __forceinline__ void geo_factors(int kind, const double* par, int k, double xi,
+                                           double f[4]) {
+  f[0] = f[1] = f[2] = f[3] = 0.0;
   if (kind == IFFD_GEOMETRY_BUMP) {
-    // F = xi + eps phi (1, 1, 1), phi = sin(pi xi1) sin(pi xi2) sin(pi xi3)
-    const double pi = 3.14159265358979323846;
-    const double eps = par[0];
-    double s[3], c[3];
-    for (int k = 0; k < 3; ++k) sincos(pi * xi[k], &s[k], &c[k]);
-    const double g[3] = {pi * c[0] * s[1] * s[2], pi * s[0] * c[1] * s[2], pi * s[0] * s[1] * c[2]};
-    for (int i = 0; i < 3; ++i) {
-      for (int k = 0; k < 3; ++k) J[i][k] = eps * g[k];
-      J[i][i] += 1.0;
-    }
-  } else {
-    // thick quarter of annulus: F = (r c1(t), r c2(t), H xi3), r = r_in + (r_out - r_in) xi1,
-    // t = xi2, c the quarter circle as a rational quadratic (weights 1, 1/sqrt 2, 1)
-    const double r_in = par[0], r_out = par[1], H = par[2];
-    const double t = xi[1], w = 0.70710678118654752440;
+    sincos(3.14159265358979323846 * xi, &f[0], &f[1]);
+  } else if (k == 0) {
+    f[0] = par[0] + (par[1] - par[0]) * xi;
+  } else if (k == 1) {
+    const double t = xi, w = 0.70710678118654752440;
     const double b0 = (1 - t) * (1 - t), b1 = 2 * t * (1 - t), b2 = t * t;
     const double db0 = -2 * (1 - t), db1 = 2 - 4 * t, db2 = 2 * t;
     const double den = b0 + w * b1 + b2, dden = db0 + w * db1 + db2;
     const double n1 = b0 + w * b1, n2 = w * b1 + b2;
     const double dn1 = db0 + w * db1, dn2 = w * db1 + db2;
-    const double c1 = n1 / den, c2 = n2 / den;
-    const double dc1 = (dn1 * den - n1 * dden) / (den * den);
-    const double dc2 = (dn2 * den - n2 * dden) / (den * den);
-    const double r = r_in + (r_out - r_in) * xi[0];
-    J[0][0] = (r_out - r_in) * c1;
-    J[1][0] = (r_out - r_in) * c2;
-    J[0][1] = r * dc1;
-    J[1][1] = r * dc2;
-    J[2][2] = H;
+    f[0] = n1 / den;
+    f[1] = n2 / den;
+    f[2] = (dn1 * den - n1 * dden) / (den * den);
+    f[3] = (dn2 * den - n2 * dden) / (den * den);
   }
 }
 
-// G = |det J| (J^T J)^{-1} = |det J| J^{-1} J^{-T}, symmetric: G00 G11 G22 G01 G02 G12
-__device__ __forceinline__ void geo_coefficient(int kind, const double* par, const double* xi,
-                                                double G[6]) {
-  double J[3][3];
-  geo_jacobian(kind, par, xi, J);
+// J[i][k] = dF_i / dxi_k from the factors of the three directions
+__device__ __forceinline__ void geo_jacobian(int kind, const double* par, const double* f1,
+                                             const double* f2, const double* f3, double J[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) J[i][k] = 0.0;
+  if (kind == IFFD_GEOMETRY_BUMP) {
+    // F = xi + eps phi (1, 1, 1), phi = sin(pi xi1) sin(pi xi2) sin(pi xi3)
+    const double pe = 3.14159265358979323846 * par[0];
+    const double g[3] = {pe * f1[1] * f2[0] * f3[0], pe * f1[0] * f2[1] * f3[0],
+                         pe * f1[0] * f2[0] * f3[1]};
+    for (int i = 0; i < 3; ++i) {
+      for (int k = 0; k < 3; ++k) J[i][k] = g[k];
+      J[i][i] += 1.0;
+    }
+  } else {
+    // F = (r c1(xi2), r c2(xi2), H xi3), r = r_in + (r_out - r_in) xi1
+    const double dr = par[1] - par[0], r = f1[0];
+    J[0][0] = dr * f2[0];
+    J[1][0] = dr * f2[1];
+    J[0][1] = r * f2[2];
+    J[1][1] = r * f2[3];
+    J[2][2] = par[2];
+  }
+}
+
+// G = |det J| J^{-1} J^{-T}, symmetric: G00 G11 G22 G01 G02 G12
+__device__ __forceinline__ void geo_coefficient(const double J[3][3], double G[6]) {
   // cofactors: J^{-1} = adj(J) / det, so J^{-1} J^{-T} = adj adj^T / det^2
   double C[3][3];
   C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
@@ -106,136 +125,457 @@ struct GeoArgs {
   int nel;    // n1 n2 n3
 };
 
-constexpr int GEO_T = 256;
-constexpr int GEO_MAXP = 9;   // p <= 8
-constexpr int GEO_CUBE = GEO_MAXP * GEO_MAXP * GEO_MAXP;
+constexpr int GEO_T = 256;     // gather threads per block
+constexpr int GEO_MAXP = 9;    // p <= 8
 
-__global__ void __launch_bounds__(GEO_T)
+template <int PM>
+struct GeoCfg {
+  static constexpr int CUBE = PM * PM * PM;
+  // lanes: one per local index up to 256 (one to four wavefronts)
+  static constexpr int NT = CUBE <= 64 ? 64 : (CUBE <= 128 ? 128 : 256);
+  static constexpr int E = 2 * CUBE > NT ? 1 : NT / CUBE;   // elements per workgroup
+  static constexpr int PP = PM * PM;
+};
+
+// PM >= max_k P_k.  Lane t of the workgroup takes the items t, t + NT, ... of
+// the E * nloc (element, local index) pairs; every stage ends in a barrier.
+// UNI: P_1 = P_2 = P_3 = PM, known at compile time (every index split by a
+// constant); otherwise the P_k <= PM come from the plan.
+template <int PM, bool UNI>
+__global__ void __launch_bounds__(GeoCfg<PM>::NT)
 geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
             const double* __restrict__ active, int astride) {
-  __shared__ double U[GEO_CUBE], A1[GEO_CUBE], A2[GEO_CUBE];
-  __shared__ double B1[GEO_CUBE], B2[GEO_CUBE], B3[GEO_CUBE];
-  __shared__ double tv[3][GEO_MAXP * GEO_MAXP], td[3][GEO_MAXP * GEO_MAXP];
-  __shared__ double tx[3][GEO_MAXP], tw[3][GEO_MAXP];
-  const int el = blockIdx.x, rhs = blockIdx.y;
+  using C = GeoCfg<PM>;
+  constexpr int E = C::E, CU = C::CUBE, PP = C::PP, NT = C::NT;
+  __shared__ double U[E * CU], A1[E * CU], A2[E * CU];
+  __shared__ double B1[E * CU], B2[E * CU], B3[E * CU];
+  __shared__ double tv[E][3][PP], td[E][3][PP];
+  __shared__ double tw[E][3][PM], tf[E][3][PM][4];
+  const int rhs = blockIdx.y;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
   const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
-  const int e1 = el % d1.n, e2 = (el / d1.n) % d2.n, e3 = el / (d1.n * d2.n);
-  const int P1 = d1.P, P2 = d2.P, P3 = d3.P;
+  const int P1 = UNI ? PM : d1.P, P2 = UNI ? PM : d2.P, P3 = UNI ? PM : d3.P;
+  const int nloc = UNI ? CU : a.nloc;
   const int tid = threadIdx.x;
-  const int e[3] = {e1, e2, e3};
-  for (int k = 0; k < 3; ++k) {
+  const int el0 = xcd_linear(blockIdx.x, gridDim.x) * E;
+  const int ne = min(E, a.nel - el0);   // elements of this workgroup
+  const int items = ne * nloc;
+  // element tables and the map's factors at the Gauss points
+  for (int t = tid; t < ne * 3 * PP; t += NT) {
+    const int ee = t / (3 * PP), r = t - ee * 3 * PP, k = r / PP, j = r - k * PP;
     const GeoDir& g = a.d[k];
-    const int PP = g.P * g.P;
-    for (int i = tid; i < PP; i += GEO_T) {
-      tv[k][i] = g.V[(size_t)e[k] * PP + i];
-      td[k][i] = g.D[(size_t)e[k] * PP + i];
+    const int el = el0 + ee;
+    const int ek = k == 0 ? el % d1.n : (k == 1 ? (el / d1.n) % d2.n : el / (d1.n * d2.n));
+    if (UNI || j < g.P * g.P) {
+      tv[ee][k][j] = g.V[(size_t)ek * g.P * g.P + j];
+      td[ee][k][j] = g.D[(size_t)ek * g.P * g.P + j];
     }
-    if (tid < g.P) {
-      tx[k][tid] = g.x[(size_t)e[k] * g.P + tid];
-      tw[k][tid] = g.w[(size_t)e[k] * g.P + tid];
+  }
+  for (int t = tid; t < ne * 3 * PM; t += NT) {
+    const int ee = t / (3 * PM), r = t - ee * 3 * PM, k = r / PM, q = r - k * PM;
+    const GeoDir& g = a.d[k];
+    const int el = el0 + ee;
+    const int ek = k == 0 ? el % d1.n : (k == 1 ? (el / d1.n) % d2.n : el / (d1.n * d2.n));
+    if (UNI || q < g.P) {
+      tw[ee][k][q] = g.w[(size_t)ek * g.P + q];
+      geo_factors(a.kind, a.par, k, g.x[(size_t)ek * g.P + q], tf[ee][k][q]);
     }
   }
   // local coefficients U[a3][a2][a1] (0 for dropped B-splines)
   const double* xr = x + (size_t)rhs * a.N;
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
+    const int el = el0 + ee;
+    const int e1 = el % d1.n, e2 = (el / d1.n) % d2.n, e3 = el / (d1.n * d2.n);
     const int a1 = i % P1, a2 = (i / P1) % P2, a3 = i / (P1 * P2);
     const int r1 = e1 + a1 - d1.lo, r2 = e2 + a2 - d2.lo, r3 = e3 + a3 - d3.lo;
     const bool ok = r1 >= 0 && r1 < d1.m && r2 >= 0 && r2 < d2.m && r3 >= 0 && r3 < d3.m;
-    U[i] = ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
+    U[ee * CU + i] = ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
   }
   __syncthreads();
   // direction 1: A1 = V1 U, A2 = D1 U   ([a3][a2][q1])
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int q1 = i % P1, rest = i / P1;
-    double s = 0.0, t = 0.0;
+    const double* u = U + ee * CU + rest * P1;
+    const double *v = tv[ee][0] + q1 * P1, *dd = td[ee][0] + q1 * P1;
+    double s = 0.0, w = 0.0;
     for (int a1 = 0; a1 < P1; ++a1) {
-      const double u = U[rest * P1 + a1];
-      s += tv[0][q1 * P1 + a1] * u;
-      t += td[0][q1 * P1 + a1] * u;
+      s += v[a1] * u[a1];
+      w += dd[a1] * u[a1];
     }
-    A1[i] = s;
-    A2[i] = t;
+    A1[ee * CU + i] = s;
+    A2[ee * CU + i] = w;
   }
   __syncthreads();
   // direction 2: B1 = V2 A1, B2 = D2 A1, B3 = V2 A2   ([a3][q2][q1])
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int q1 = i % P1, q2 = (i / P1) % P2, a3 = i / (P1 * P2);
-    double s = 0.0, t = 0.0, u = 0.0;
+    const double *v = tv[ee][1] + q2 * P2, *dd = td[ee][1] + q2 * P2;
+    const double* x1 = A1 + ee * CU + a3 * P2 * P1 + q1;
+    const double* x2 = A2 + ee * CU + a3 * P2 * P1 + q1;
+    double s = 0.0, w = 0.0, u = 0.0;
     for (int a2 = 0; a2 < P2; ++a2) {
-      const int j = (a3 * P2 + a2) * P1 + q1;
-      s += tv[1][q2 * P2 + a2] * A1[j];
-      t += td[1][q2 * P2 + a2] * A1[j];
-      u += tv[1][q2 * P2 + a2] * A2[j];
+      s += v[a2] * x1[a2 * P1];
+      w += dd[a2] * x1[a2 * P1];
+      u += v[a2] * x2[a2 * P1];
     }
-    B1[i] = s;
-    B2[i] = t;
-    B3[i] = u;
+    B1[ee * CU + i] = s;
+    B2[ee * CU + i] = w;
+    B3[ee * CU + i] = u;
   }
   __syncthreads();
   // direction 3 and the coefficient: gradients at the Gauss points, then
-  // F = w G grad u ([q3][q2][q1]), kept in U, A1, A2
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  // w G grad u ([q3][q2][q1]), kept in U, A1, A2
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int q1 = i % P1, q2 = (i / P1) % P2, q3 = i / (P1 * P2);
+    const double *v = tv[ee][2] + q3 * P3, *dd = td[ee][2] + q3 * P3;
+    const int base = ee * CU + q2 * P1 + q1;
     double g1 = 0.0, g2 = 0.0, g3 = 0.0;
     for (int a3 = 0; a3 < P3; ++a3) {
-      const int j = (a3 * P2 + q2) * P1 + q1;
-      const double v3 = tv[2][q3 * P3 + a3], d3v = td[2][q3 * P3 + a3];
-      g1 += v3 * B3[j];   // D1 V2 V3
-      g2 += v3 * B2[j];   // V1 D2 V3
-      g3 += d3v * B1[j];  // V1 V2 D3
+      const int j = base + a3 * P2 * P1;
+      g1 += v[a3] * B3[j];    // D1 V2 V3
+      g2 += v[a3] * B2[j];    // V1 D2 V3
+      g3 += dd[a3] * B1[j];   // V1 V2 D3
     }
-    const double xi[3] = {tx[0][q1], tx[1][q2], tx[2][q3]};
-    double G[6];
-    geo_coefficient(a.kind, a.par, xi, G);
-    const double wq = tw[0][q1] * tw[1][q2] * tw[2][q3];
-    U[i] = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
-    A1[i] = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
-    A2[i] = wq * (G[4] * g1 + G[5] * g2 + G[2] * g3);
+    double J[3][3], G[6];
+    geo_jacobian(a.kind, a.par, tf[ee][0][q1], tf[ee][1][q2], tf[ee][2][q3], J);
+    geo_coefficient(J, G);
+    const double wq = tw[ee][0][q1] * tw[ee][1][q2] * tw[ee][2][q3];
+    U[ee * CU + i] = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
+    A1[ee * CU + i] = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
+    A2[ee * CU + i] = wq * (G[4] * g1 + G[5] * g2 + G[2] * g3);
   }
   __syncthreads();
   // back along direction 3: B1 = V3^T F1, B2 = V3^T F2, B3 = D3^T F3   ([a3][q2][q1])
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int q1 = i % P1, q2 = (i / P1) % P2, a3 = i / (P1 * P2);
-    double s = 0.0, t = 0.0, u = 0.0;
+    const int base = ee * CU + q2 * P1 + q1;
+    double s = 0.0, w = 0.0, u = 0.0;
     for (int q3 = 0; q3 < P3; ++q3) {
-      const int j = (q3 * P2 + q2) * P1 + q1;
-      s += tv[2][q3 * P3 + a3] * U[j];
-      t += tv[2][q3 * P3 + a3] * A1[j];
-      u += td[2][q3 * P3 + a3] * A2[j];
+      const int j = base + q3 * P2 * P1;
+      const double v = tv[ee][2][q3 * P3 + a3], dd = td[ee][2][q3 * P3 + a3];
+      s += v * U[j];
+      w += v * A1[j];
+      u += dd * A2[j];
     }
-    B1[i] = s;
-    B2[i] = t;
-    B3[i] = u;
+    B1[ee * CU + i] = s;
+    B2[ee * CU + i] = w;
+    B3[ee * CU + i] = u;
   }
   __syncthreads();
   // back along direction 2: A1 = V2^T B1 (takes D1), A2 = D2^T B2 + V2^T B3 (takes V1)
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int q1 = i % P1, a2 = (i / P1) % P2, a3 = i / (P1 * P2);
-    double s = 0.0, t = 0.0;
+    const int base = ee * CU + a3 * P2 * P1 + q1;
+    double s = 0.0, w = 0.0;
     for (int q2 = 0; q2 < P2; ++q2) {
-      const int j = (a3 * P2 + q2) * P1 + q1;
-      s += tv[1][q2 * P2 + a2] * B1[j];
-      t += td[1][q2 * P2 + a2] * B2[j] + tv[1][q2 * P2 + a2] * B3[j];
+      const int j = base + q2 * P1;
+      const double v = tv[ee][1][q2 * P2 + a2], dd = td[ee][1][q2 * P2 + a2];
+      s += v * B1[j];
+      w += dd * B2[j] + v * B3[j];
     }
-    A1[i] = s;
-    A2[i] = t;
+    A1[ee * CU + i] = s;
+    A2[ee * CU + i] = w;
   }
   __syncthreads();
-  // back along direction 1: the element's contribution to its local functions
-  double* out = loc + ((size_t)rhs * a.nel + el) * a.nloc;
-  for (int i = tid; i < a.nloc; i += GEO_T) {
+  // back along direction 1: the element's contribution to its local functions,
+  // stored at loc[(rhs nloc + i) nel + el]
+  double* out = loc + (size_t)rhs * nloc * a.nel;
+  for (int t = tid; t < items; t += NT) {
+    const int ee = t / nloc, i = t - ee * nloc;
     const int a1 = i % P1, rest = i / P1;
+    const double* y1 = A1 + ee * CU + rest * P1;
+    const double* y2 = A2 + ee * CU + rest * P1;
     double s = 0.0;
-    for (int q1 = 0; q1 < P1; ++q1) {
-      const int j = rest * P1 + q1;
-      s += td[0][q1 * P1 + a1] * A1[j] + tv[0][q1 * P1 + a1] * A2[j];
-    }
-    out[i] = s;
+    for (int q1 = 0; q1 < P1; ++q1) s += td[ee][0][q1 * P1 + a1] * y1[q1] + tv[ee][0][q1 * P1 + a1] * y2[q1];
+    out[(size_t)i * a.nel + el0 + ee] = s;
   }
 }
 
-// y at every kept coefficient: the element contributions in a fixed order;
+// Line-wise sum factorization for P_1 = P_2 = P_3 = P: lane (element, line)
+// holds one line of the element's P^3 tensor in registers and applies the
+// one-dimensional factor along it; the result goes back to the same line
+// positions, so three LDS arrays serve all stages and only the change of
+// direction between stages needs a barrier.  Direction 3's forward
+// contraction, the coefficient G at the P points of the line and the
+// backward contraction along direction 3 are one stage.
+//   stage 1  lines along xi_1 (a2, a3):  A1 = V1 U, A2 = D1 U
+//   stage 2  lines along xi_2 (q1, a3):  B1 = V2 A1, B2 = D2 A1, B3 = V2 A2
+//   stage 3  lines along xi_3 (q1, q2):  grad u at the points, F = w G grad u,
+//                                        C1 = V3^T F1, C2 = V3^T F2, C3 = D3^T F3
+//   stage 4  lines along xi_2 (q1, a3):  A1 = V2^T C1, A2 = D2^T C2 + V2^T C3
+//   stage 5  lines along xi_1 (a2, a3):  y_loc = D1^T A1 + V1^T A2 -> workspace
+template <int P>
+struct GeoLineCfg {
+  static constexpr int L = P * P;                         // lines per element
+  static constexpr int E = L > 32 ? 1 : 64 / L;           // elements per workgroup
+  static constexpr int NT = E * L <= 64 ? 64 : 128;       // lanes
+  // LDS strides (doubles) of a2 and a3, odd so that lanes on different lines
+  // fall on different banks
+  static constexpr int S1 = P | 1;
+  static constexpr int S2 = (S1 * P) | 1;
+  static constexpr int ES = (S2 * P) | 1;                 // per element
+};
+
+template <int P>
+__global__ void __launch_bounds__(GeoLineCfg<P>::NT)
+geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
+                  const double* __restrict__ active, int astride) {
+  using C = GeoLineCfg<P>;
+  constexpr int E = C::E, L = C::L, NT = C::NT, S1 = C::S1, S2 = C::S2, ES = C::ES;
+  constexpr int PP = P * P, CU = P * P * P;
+  __shared__ double X0[E * ES], X1[E * ES], X2[E * ES];
+  __shared__ double tv[E][3][PP], td[E][3][PP];
+  __shared__ double tw[E][3][P], tf[E][3][P][4];
+  const int rhs = blockIdx.y;
+  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
+  const int tid = threadIdx.x;
+  const int el0 = xcd_linear(blockIdx.x, gridDim.x) * E;
+  const int ne = min(E, a.nel - el0);
+  auto coords = [&](int el, int& e1, int& e2, int& e3) {
+    e1 = el % d1.n;
+    e2 = (el / d1.n) % d2.n;
+    e3 = el / (d1.n * d2.n);
+  };
+  for (int t = tid; t < ne * 3 * PP; t += NT) {
+    const int ee = t / (3 * PP), r = t - ee * 3 * PP, k = r / PP, j = r - k * PP;
+    int e[3];
+    coords(el0 + ee, e[0], e[1], e[2]);
+    const GeoDir& g = a.d[k];
+    tv[ee][k][j] = g.V[(size_t)e[k] * PP + j];
+    td[ee][k][j] = g.D[(size_t)e[k] * PP + j];
+  }
+  for (int t = tid; t < ne * 3 * P; t += NT) {
+    const int ee = t / (3 * P), r = t - ee * 3 * P, k = r / P, q = r - k * P;
+    int e[3];
+    coords(el0 + ee, e[0], e[1], e[2]);
+    const GeoDir& g = a.d[k];
+    tw[ee][k][q] = g.w[(size_t)e[k] * P + q];
+    geo_factors(a.kind, a.par, k, g.x[(size_t)e[k] * P + q], tf[ee][k][q]);
+  }
+  const double* xr = x + (size_t)rhs * a.N;
+  for (int t = tid; t < ne * CU; t += NT) {
+    const int ee = t / CU, i = t - ee * CU;
+    int e1, e2, e3;
+    coords(el0 + ee, e1, e2, e3);
+    const int a1 = i % P, a2 = (i / P) % P, a3 = i / PP;
+    const int r1 = e1 + a1 - d1.lo, r2 = e2 + a2 - d2.lo, r3 = e3 + a3 - d3.lo;
+    const bool ok = r1 >= 0 && r1 < d1.m && r2 >= 0 && r2 < d2.m && r3 >= 0 && r3 < d3.m;
+    X0[ee * ES + a1 + S1 * a2 + S2 * a3] =
+        ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
+  }
+  __syncthreads();
+  const int ee = tid / L, ln = tid - ee * L;
+  const bool live = ee < ne;
+  const int la = ln % P, lb = ln / P;     // the line's two fixed indices
+  double* Y0 = X0 + ee * ES;
+  double* Y1 = X1 + ee * ES;
+  double* Y2 = X2 + ee * ES;
+  // In every stage the outer loop runs over the output (or input) index along
+  // the line without unrolling; what it indexes is read from LDS as it goes
+  // (this lane owns the line, so reading and rewriting it in place is safe),
+  // and only the unrolled inner index lives in registers.
+  // stage 1: line (a2, a3) = (la, lb) along a1
+  if (live) {
+    const int o = S1 * la + S2 * lb;
+    double u[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) u[j] = Y0[o + j];
+#pragma unroll 1
+    for (int q = 0; q < P; ++q) {
+      double s = 0.0, w = 0.0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        s += tv[ee][0][q * P + j] * u[j];
+        w += td[ee][0][q * P + j] * u[j];
+      }
+      Y0[o + q] = s;
+      Y1[o + q] = w;
+    }
+  }
+  __syncthreads();
+  // stage 2: line (q1, a3) = (la, lb) along a2
+  if (live) {
+    const int o = la + S2 * lb;
+    double u1[P], u2[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      u1[j] = Y0[o + S1 * j];
+      u2[j] = Y1[o + S1 * j];
+    }
+#pragma unroll 1
+    for (int q = 0; q < P; ++q) {
+      double s = 0.0, w = 0.0, v = 0.0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double vv = tv[ee][1][q * P + j], dd = td[ee][1][q * P + j];
+        s += vv * u1[j];
+        w += dd * u1[j];
+        v += vv * u2[j];
+      }
+      Y0[o + S1 * q] = s;
+      Y1[o + S1 * q] = w;
+      Y2[o + S1 * q] = v;
+    }
+  }
+  __syncthreads();
+  // stage 3: line (q1, q2) = (la, lb) along a3 / q3
+  if (live) {
+    const int o = la + S1 * lb;
+    double b1[P], b2[P], b3[P], c1[P], c2[P], c3[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      b1[j] = Y0[o + S2 * j];
+      b2[j] = Y1[o + S2 * j];
+      b3[j] = Y2[o + S2 * j];
+      c1[j] = c2[j] = c3[j] = 0.0;
+    }
+    const double w12 = tw[ee][0][la] * tw[ee][1][lb];
+#pragma unroll 1
+    for (int q = 0; q < P; ++q) {
+      double g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double vv = tv[ee][2][q * P + j], dd = td[ee][2][q * P + j];
+        g1 += vv * b3[j];   // D1 V2 V3
+        g2 += vv * b2[j];   // V1 D2 V3
+        g3 += dd * b1[j];   // V1 V2 D3
+      }
+      double J[3][3], G[6];
+      geo_jacobian(a.kind, a.par, tf[ee][0][la], tf[ee][1][lb], tf[ee][2][q], J);
+      geo_coefficient(J, G);
+      const double wq = w12 * tw[ee][2][q];
+      const double f1 = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
+      const double f2 = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
+      const double f3 = wq * (G[4] * g1 + G[5] * g2 + G[2] * g3);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double vv = tv[ee][2][q * P + j], dd = td[ee][2][q * P + j];
+        c1[j] += vv * f1;
+        c2[j] += vv * f2;
+        c3[j] += dd * f3;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      Y0[o + S2 * j] = c1[j];
+      Y1[o + S2 * j] = c2[j];
+      Y2[o + S2 * j] = c3[j];
+    }
+  }
+  __syncthreads();
+  // stage 4: line (q1, a3) = (la, lb) along q2 -> a2
+  if (live) {
+    const int o = la + S2 * lb;
+    double s1[P], s2[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) s1[j] = s2[j] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < P; ++q) {
+      const double c1 = Y0[o + S1 * q], c2 = Y1[o + S1 * q], c3 = Y2[o + S1 * q];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double vv = tv[ee][1][q * P + j], dd = td[ee][1][q * P + j];
+        s1[j] += vv * c1;
+        s2[j] += dd * c2 + vv * c3;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      Y0[o + S1 * j] = s1[j];
+      Y1[o + S1 * j] = s2[j];
+    }
+  }
+  __syncthreads();
+  // stage 5: line (a2, a3) = (la, lb) along q1 -> a1, to loc[(rhs nloc + i) nel + el]
+  if (live) {
+    const int o = S1 * la + S2 * lb;
+    double s[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) s[j] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < P; ++q) {
+      const double y1 = Y0[o + q], y2 = Y1[o + q];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        s[j] += td[ee][0][q * P + j] * y1 + tv[ee][0][q * P + j] * y2;
+    }
+    double* out = loc + ((size_t)rhs * CU + (size_t)P * ln) * a.nel + el0 + ee;
+#pragma unroll
+    for (int j = 0; j < P; ++j) out[(size_t)j * a.nel] = s[j];
+  }
+}
+
+// the gather for P_1 = P_2 = P_3 = P: the same fixed order, every load of a
+// row issued unconditionally from a clamped address
+template <int P>
+__global__ void __launch_bounds__(GEO_T)
+geo_gather_uni(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, int nblk,
+               const double* __restrict__ xd, const double* __restrict__ fres,
+               double* __restrict__ part, int npart, const double* __restrict__ active,
+               int astride) {
+  __shared__ double red[GEO_T / 64];
+  const int rhs = blockIdx.x / nblk, blk = blockIdx.x - rhs * nblk;
+  if (active && active[(size_t)rhs * astride] == 0.0) return;
+  const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
+  const int c = (a.N + nblk - 1) / nblk;
+  const int lo = min(a.N, blk * c), hi = min(a.N, lo + c);
+  const size_t ro = (size_t)rhs * a.N;
+  const size_t nel = (size_t)a.nel;
+  const double* lr = loc + (size_t)rhs * (P * P * P) * nel;
+  double dot = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += GEO_T) {
+    const int r1 = i % d1.m, r2 = (i / d1.m) % d2.m, r3 = i / (d1.m * d2.m);
+    const int g1 = r1 + d1.lo, g2 = r2 + d2.lo, g3 = r3 + d3.lo;   // full indices
+    double s = 0.0;
+    for (int a3 = 0; a3 < P; ++a3) {
+      const int e3 = g3 - a3;
+      if (e3 < 0 || e3 >= d3.n) continue;
+      for (int a2 = 0; a2 < P; ++a2) {
+        const int e2 = g2 - a2;
+        if (e2 < 0 || e2 >= d2.n) continue;
+        const double* row = lr + (size_t)((a3 * P + a2) * P) * nel + (size_t)d1.n * (e2 + (size_t)d2.n * e3);
+        double v[P];
+#pragma unroll
+        for (int a1 = 0; a1 < P; ++a1) {
+          const int e1 = g1 - a1;
+          const bool ok = e1 >= 0 && e1 < d1.n;
+          v[a1] = row[(size_t)a1 * nel + (ok ? e1 : 0)];
+          v[a1] = ok ? v[a1] : 0.0;
+        }
+#pragma unroll
+        for (int a1 = 0; a1 < P; ++a1) s += v[a1];
+      }
+    }
+    y[ro + i] = s;
+    if (part) {
+      if (fres) {
+        const double dv = fres[ro + i] - s;
+        dot += dv * dv;
+      } else {
+        dot += xd[ro + i] * s;
+      }
+    }
+  }
+  if (!part) return;
+  for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int w = 0; w < GEO_T / 64; ++w) s2 += red[w];
+    part[(size_t)rhs * npart + blk] = s2;
+  }
+}
+
+// y at every kept coefficient: the element contributions in a fixed order
+// (local index a3, a2, a1 descending through the elements e = g - a);
 // per-block partial sums (x . y, or (f - y)^2 when fres is given)
 __global__ void __launch_bounds__(GEO_T)
 geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, int nblk,
@@ -248,19 +588,26 @@ geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, in
   const int c = (a.N + nblk - 1) / nblk;
   const int lo = min(a.N, blk * c), hi = min(a.N, lo + c);
   const size_t ro = (size_t)rhs * a.N;
-  const double* lr = loc + (size_t)rhs * a.nel * a.nloc;
+  const double* lr = loc + (size_t)rhs * a.nloc * a.nel;
   double dot = 0.0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += GEO_T) {
     const int r1 = i % d1.m, r2 = (i / d1.m) % d2.m, r3 = i / (d1.m * d2.m);
     const int g1 = r1 + d1.lo, g2 = r2 + d2.lo, g3 = r3 + d3.lo;   // full indices
     double s = 0.0;
-    for (int e3 = max(0, g3 - d3.P + 1); e3 <= min(d3.n - 1, g3); ++e3)
-      for (int e2 = max(0, g2 - d2.P + 1); e2 <= min(d2.n - 1, g2); ++e2)
-        for (int e1 = max(0, g1 - d1.P + 1); e1 <= min(d1.n - 1, g1); ++e1) {
-          const size_t el = (size_t)e1 + (size_t)d1.n * (e2 + (size_t)d2.n * e3);
-          const int a1 = g1 - e1, a2 = g2 - e2, a3 = g3 - e3;
-          s += lr[el * a.nloc + (a3 * d2.P + a2) * d1.P + a1];
+    for (int a3 = 0; a3 < d3.P; ++a3) {
+      const int e3 = g3 - a3;
+      if (e3 < 0 || e3 >= d3.n) continue;
+      for (int a2 = 0; a2 < d2.P; ++a2) {
+        const int e2 = g2 - a2;
+        if (e2 < 0 || e2 >= d2.n) continue;
+        const double* row = lr + (size_t)((a3 * d2.P + a2) * d1.P) * a.nel +
+                            (size_t)d1.n * (e2 + (size_t)d2.n * e3);
+        for (int a1 = 0; a1 < d1.P; ++a1) {
+          const int e1 = g1 - a1;
+          if (e1 >= 0 && e1 < d1.n) s += row[(size_t)a1 * a.nel + e1];
         }
+      }
+    }
     y[ro + i] = s;
     if (part) {
       if (fres) {
@@ -315,19 +662,53 @@ size_t geo_matvec_ws_bytes(const Plan& P, int nrhs) {
 
 int geo_matvec_blocks(const Plan& P) { return pcg_blocks(P); }
 
+template <int PM>
+static void launch_geo_element(const GeoArgs& a, const double* x, double* loc, double* y,
+                               int nrhs, int nb, double* part, int npart, const double* act,
+                               int as, hipStream_t s, const double* fres) {
+  const bool uni = a.d[0].P == PM && a.d[1].P == PM && a.d[2].P == PM;
+  if (uni) {
+    constexpr int E = GeoLineCfg<PM>::E, NT = GeoLineCfg<PM>::NT;
+    const unsigned nwg = (unsigned)((a.nel + E - 1) / E);
+    hipLaunchKernelGGL(geo_element_lines<PM>, dim3(nwg, (unsigned)nrhs), dim3(NT), 0, s, x, loc,
+                       a, act, as);
+    hipLaunchKernelGGL(geo_gather_uni<PM>, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,
+                       (const double*)loc, y, a, nb, x, fres, part, npart, act, as);
+  } else {
+    constexpr int E = GeoCfg<PM>::E, NT = GeoCfg<PM>::NT;
+    const unsigned nwg = (unsigned)((a.nel + E - 1) / E);
+    hipLaunchKernelGGL((geo_element<PM, false>), dim3(nwg, (unsigned)nrhs), dim3(NT), 0, s, x,
+                       loc, a, act, as);
+    hipLaunchKernelGGL(geo_gather, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,
+                       (const double*)loc, y, a, nb, x, fres, part, npart, act, as);
+  }
+}
+
 hipError_t launch_geo_matvec(const Plan& P, const double* x, double* y, int nrhs, void* ws,
                              double* part, int npart, const double* act, int as, hipStream_t s,
                              const double* fres) {
   if (!ws) return hipErrorInvalidValue;
   const GeoArgs a = geo_args(P);
-  if (a.nloc > GEO_CUBE) return hipErrorInvalidValue;
+  const int pm = std::max(a.d[0].P, std::max(a.d[1].P, a.d[2].P));
+  if (pm < 2 || pm > GEO_MAXP) return hipErrorInvalidValue;
   const int nb = geo_matvec_blocks(P);
   if (part && npart < nb) return hipErrorInvalidValue;
   double* loc = (double*)ws;
-  hipLaunchKernelGGL(geo_element, dim3((unsigned)a.nel, (unsigned)nrhs), dim3(GEO_T), 0, s, x,
-                     loc, a, act, as);
-  hipLaunchKernelGGL(geo_gather, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,
-                     (const double*)loc, y, a, nb, x, fres, part, npart, act, as);
+#define IFFD_GEO_CASE(PM_)                                                                   \
+  case PM_:                                                                                  \
+    launch_geo_element<PM_>(a, x, loc, y, nrhs, nb, part, npart, act, as, s, fres);            \
+    break;
+  switch (pm) {
+    IFFD_GEO_CASE(2)
+    IFFD_GEO_CASE(3)
+    IFFD_GEO_CASE(4)
+    IFFD_GEO_CASE(5)
+    IFFD_GEO_CASE(6)
+    IFFD_GEO_CASE(7)
+    IFFD_GEO_CASE(8)
+    default: launch_geo_element<9>(a, x, loc, y, nrhs, nb, part, npart, act, as, s, fres); break;
+  }
+#undef IFFD_GEO_CASE
   return hipGetLastError();
 }
 

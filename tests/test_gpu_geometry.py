@@ -67,6 +67,11 @@ MATVEC_CASES = [
     ((8, 8, 8), (5, 5, 5), BOTTOM, ANNULUS, "fft"),
     ((12, 8, 16), (3, 4, 2), BOTTOM, ANNULUS, "fft"),
     ((16, 8, 8), (1, 3, 2), ((1, 1), (0, 0), (1, 0)), ("annulus", (0.5, 3.0, 2.0)), "fft"),
+    # one degree in all directions from p = 1 to p = 8 (the line-wise element kernel)
+    ((16, 8, 8), (1, 1, 1), BOTTOM, ANNULUS, "fft"),
+    ((8, 8, 8), (4, 4, 4), ((1, 0), (0, 1), (0, 0)), ("bump", (-0.04,)), "fft"),
+    ((8, 8, 8), (6, 6, 6), BOTTOM, ANNULUS, "fft"),
+    ((8, 8, 8), (7, 7, 7), ((0, 0), (1, 1), (0, 1)), ("bump", (0.09,)), "fft"),
 ]
 
 
@@ -82,6 +87,32 @@ def test_geometry_matvec_matches_oracle(n, p, dl, geometry, method):
     print(f"geometry {geometry[0]} n={n} p={p} ends={dl} {method}: rel2 {e2:.2e} max {emax:.2e}",
           flush=True)
     assert e2 <= 1e-13 and emax <= 1e-13
+
+
+def greville(n, p):
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    return np.array([knots[i + 1:i + p + 1].mean() for i in range(n + p)])
+
+
+@pytest.mark.parametrize("p", [7, 8])
+def test_geometry_high_degree_properties(p):
+    """Where the oracle's dense assembly is out of reach (p = 8 needs n >= 12):
+    the energy of u = x_3 = H xi_3 (in the space: it vanishes on the Dirichlet
+    face xi_3 = 0) is the volume of the domain up to the quadrature error, and
+    the operator is symmetric."""
+    n = 12
+    r_in, r_out, H = 1.0, 2.0, 1.5
+    pl = make_plan((n,) * 3, (p,) * 3, BOTTOM, ("annulus", (r_in, r_out, H)), max_rhs=2)
+    g3 = greville(n, p)[1:]   # kept B-splines of direction 3 (Dirichlet at 0)
+    U = np.broadcast_to(H * g3[:, None, None], pl.shape).copy()
+    e = float(np.vdot(U, host(pl.matvec(dev(U)))))
+    vol = np.pi / 4 * (r_out ** 2 - r_in ** 2) * H
+    X = np.stack([workloads.uniform_tensor(pl.shape, seed=s) for s in (11, 12)])
+    Y = host(pl.matvec(dev(X)))
+    asym = abs(np.vdot(X[0], Y[1]) - np.vdot(Y[0], X[1])) / (np.linalg.norm(X[0]) * np.linalg.norm(Y[1]))
+    print(f"p={p}: energy {e:.15f} vs volume {vol:.15f}, asymmetry {asym:.1e}", flush=True)
+    assert abs(e - vol) <= 1e-9 * vol
+    assert asym <= 1e-14
 
 
 def test_geometry_matvec_is_deterministic_and_batched():
