@@ -5,10 +5,10 @@
 // Gauss-Legendre rules with p_k + 1 points per element and direction.
 //
 // Matrix-free, in two kernels:
-//   geo_element  one workgroup per element with a lane per local index (64,
-//                128 or 256 lanes; two and eight elements per 64 lanes for
-//                p = 2 and p = 1): gather the (p_1+1)(p_2+1)(p_3+1) local
-//                coefficients, sum factorization to the
+//   geo_element  per element (several per workgroup; one lane per line of the
+//                element tensor when p_1 = p_2 = p_3, geo_element_lines,
+//                else one lane per local index): gather the (p_1+1)(p_2+1)
+//                (p_3+1) local coefficients, sum factorization to the
 //                gradients at the Gauss points (three contractions), G from
 //                the map at each point, the transposed contractions back to
 //                the local functions; the local result goes to a workspace
@@ -22,8 +22,8 @@
 //
 // Both maps are products of one-dimensional factors (the bump's
 // sin(pi xi_k), the annulus' radius and circle), so each workgroup first
-// evaluates those factors at the p_k + 1 Gauss points of each direction; the
-// Jacobian at a point is then a few products of them.
+// evaluates those factors at the p_k + 1 Gauss points of each direction; G at
+// a point is then a few products of them (closed forms in geo_metric).
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -56,53 +56,46 @@ __device__ __forceinline__ void geo_factors(int kind, const double* par, int k, 
   }
 }
 
-// J[i][k] = dF_i / dxi_k from the factors of the three directions
-__device__ __forceinline__ void geo_jacobian(int kind, const double* par, const double* f1,
-                                             const double* f2, const double* f3, double J[3][3]) {
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 3; ++k) J[i][k] = 0.0;
+// G = |det J| J^{-1} J^{-T} at one point from the factors of the three
+// directions, stored G00 G11 G22 G01 G02 G12 (symmetric), in closed form for
+// each map:
+//   bump     J = I + 1 g^T with g = eps grad phi (every row of dF/dxi - I is
+//            grad of eps phi): det J = 1 + g . 1 (matrix determinant lemma),
+//            J^{-1} = I - 1 g^T / det (Sherman-Morrison), so
+//            G_kl = det delta_kl - (g_k + g_l) + |g|^2 / det; det >= 1 - 3 pi
+//            |eps| > 0 for the admitted |eps| < 0.1;
+//   annulus  J = [[dr c1, r c1', 0], [dr c2, r c2', 0], [0, 0, H]]: with the
+//            2 x 2 block K and k = det K, G = (H / |k|) adj(K) adj(K)^T on
+//            that block and G22 = |k| / H.
+__device__ __forceinline__ void geo_metric(int kind, const double* par, const double* f1,
+                                           const double* f2, const double* f3, double G[6]) {
   if (kind == IFFD_GEOMETRY_BUMP) {
     // F = xi + eps phi (1, 1, 1), phi = sin(pi xi1) sin(pi xi2) sin(pi xi3)
     const double pe = 3.14159265358979323846 * par[0];
-    const double g[3] = {pe * f1[1] * f2[0] * f3[0], pe * f1[0] * f2[1] * f3[0],
-                         pe * f1[0] * f2[0] * f3[1]};
-    for (int i = 0; i < 3; ++i) {
-      for (int k = 0; k < 3; ++k) J[i][k] = g[k];
-      J[i][i] += 1.0;
-    }
+    const double g0 = pe * f1[1] * f2[0] * f3[0], g1 = pe * f1[0] * f2[1] * f3[0],
+                 g2 = pe * f1[0] * f2[0] * f3[1];
+    const double det = 1.0 + g0 + g1 + g2;
+    const double q = (g0 * g0 + g1 * g1 + g2 * g2) / det;
+    G[0] = det - 2.0 * g0 + q;
+    G[1] = det - 2.0 * g1 + q;
+    G[2] = det - 2.0 * g2 + q;
+    G[3] = q - g0 - g1;
+    G[4] = q - g0 - g2;
+    G[5] = q - g1 - g2;
   } else {
     // F = (r c1(xi2), r c2(xi2), H xi3), r = r_in + (r_out - r_in) xi1
-    const double dr = par[1] - par[0], r = f1[0];
-    J[0][0] = dr * f2[0];
-    J[1][0] = dr * f2[1];
-    J[0][1] = r * f2[2];
-    J[1][1] = r * f2[3];
-    J[2][2] = par[2];
+    const double dr = par[1] - par[0], r = f1[0], H = par[2];
+    const double k00 = dr * f2[0], k10 = dr * f2[1], k01 = r * f2[2], k11 = r * f2[3];
+    const double k = fabs(k00 * k11 - k01 * k10);
+    const double h = H / k;
+    G[0] = h * (k11 * k11 + k01 * k01);
+    G[1] = h * (k10 * k10 + k00 * k00);
+    G[3] = -h * (k11 * k10 + k01 * k00);
+    G[2] = k / H;
+    G[4] = 0.0;
+    G[5] = 0.0;
   }
-}
-
-// G = |det J| J^{-1} J^{-T}, symmetric: G00 G11 G22 G01 G02 G12
-__device__ __forceinline__ void geo_coefficient(const double J[3][3], double G[6]) {
-  // cofactors: J^{-1} = adj(J) / det, so J^{-1} J^{-T} = adj adj^T / det^2
-  double C[3][3];
-  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  C[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-  C[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-  C[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-  C[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-  C[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  C[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-  const double det = J[0][0] * C[0][0] + J[0][1] * C[1][0] + J[0][2] * C[2][0];
-  const double f = 1.0 / fabs(det);   // |det| / det^2
-  auto row = [&](int a, int b) { return C[a][0] * C[b][0] + C[a][1] * C[b][1] + C[a][2] * C[b][2]; };
-  G[0] = f * row(0, 0);
-  G[1] = f * row(1, 1);
-  G[2] = f * row(2, 2);
-  G[3] = f * row(0, 1);
-  G[4] = f * row(0, 2);
-  G[5] = f * row(1, 2);
+  (void)f3;
 }
 
 // per-direction element tables (FP64): Gauss points x[e][q], weights w[e][q]
@@ -240,9 +233,8 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
       g2 += v[a3] * B2[j];    // V1 D2 V3
       g3 += dd[a3] * B1[j];   // V1 V2 D3
     }
-    double J[3][3], G[6];
-    geo_jacobian(a.kind, a.par, tf[ee][0][q1], tf[ee][1][q2], tf[ee][2][q3], J);
-    geo_coefficient(J, G);
+    double G[6];
+    geo_metric(a.kind, a.par, tf[ee][0][q1], tf[ee][1][q2], tf[ee][2][q3], G);
     const double wq = tw[ee][0][q1] * tw[ee][1][q2] * tw[ee][2][q3];
     U[ee * CU + i] = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
     A1[ee * CU + i] = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
@@ -313,8 +305,8 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
 template <int P>
 struct GeoLineCfg {
   static constexpr int L = P * P;                         // lines per element
-  static constexpr int E = L > 32 ? 1 : 64 / L;           // elements per workgroup
-  static constexpr int NT = E * L <= 64 ? 64 : 128;       // lanes
+  static constexpr int NT = P <= 4 ? 64 : (P <= 8 ? 128 : 256);   // lanes
+  static constexpr int E = NT / L;                        // elements per workgroup
   // LDS strides (doubles) of a2 and a3, odd so that lanes on different lines
   // fall on different banks
   static constexpr int S1 = P | 1;
@@ -447,9 +439,8 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
         g2 += vv * b2[j];   // V1 D2 V3
         g3 += dd * b1[j];   // V1 V2 D3
       }
-      double J[3][3], G[6];
-      geo_jacobian(a.kind, a.par, tf[ee][0][la], tf[ee][1][lb], tf[ee][2][q], J);
-      geo_coefficient(J, G);
+      double G[6];
+      geo_metric(a.kind, a.par, tf[ee][0][la], tf[ee][1][lb], tf[ee][2][q], G);
       const double wq = w12 * tw[ee][2][q];
       const double f1 = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
       const double f2 = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
