@@ -99,6 +99,10 @@ WORKLOADS = {
 # faces x = 0 and y = 1, natural conditions elsewhere, i.e. per direction
 # (Dirichlet at 0, Dirichlet at 1) = (1, 0), (0, 1), (0, 0).
 MIXED_CUBE_DIRICHLET = ((1, 0), (0, 1), (0, 0))
+# the thick quarter of annulus: Dirichlet on the bottom face xi_3 = 0 only, and
+# the map's (r_in, r_out, H)
+ANNULUS_DIRICHLET = ((0, 0), (0, 0), (1, 0))
+ANNULUS_PARAMS = (1.0, 2.0, 1.0)
 
 
 def workload_rhs(name: str, p: int | None = None) -> np.ndarray:
