@@ -265,8 +265,30 @@ def mixed_bc(torch, iffd, ps=(3,), n=256, steps=20, solves=10, prec="f32"):
         dom = max(range(npass), key=lambda k: pp[k])
         ach = pb[dom] / (pp[dom] * 1e-3) / 1e9
         lat, st = time_solves(torch, pl, f, solves)
+        # the same preconditioner through a generic basis of S^reg
+        # (eq:reg_eigenvectors: a banded interpolation solve per line)
+        plg = iffd.Plan(3, [n] * 3, [p] * 3, precision=prec,
+                        dirichlet=workloads.MIXED_CUBE_DIRICHLET, basis="generic")
+        zg = torch.empty_like(f)
+        for _ in range(3):
+            plg.apply(f, out=zg)
+        torch.cuda.synchronize()
+        ag, bg = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(int(cpm * 5.0))
+        ag.record()
+        for _ in range(steps):
+            plg.apply(f, out=zg)
+        bg.record()
+        torch.cuda.synchronize()
+        msg = ag.elapsed_time(bg) / steps
+        pl.apply(f, out=z)
+        gdiff = float(((zg - z).norm() / z.norm()).item())
+        del plg, zg
         rows.append({
             "n": n, "p": p, "shape": list(pl.shape), "dofs": N, "dtype": prec,
+            "generic_basis": {"ms_per_apply": round(msg, 5),
+                              "slowdown_vs_special": round(msg / ms, 3),
+                              "rel_diff_vs_special": gdiff},
             "gdof_s": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 5),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),

@@ -221,6 +221,27 @@ typedef struct {
 int iffd_plan_create_general(iffd_plan** out, int d, const int* n, const int* p,
                              const int* dirichlet, const iffd_opts* opts);
 
+/* basis of S^reg of a general plan (iffd_plan_set_basis) */
+#define IFFD_BASIS_SPECIAL  0  /* eq:special_basis: no interpolation solve      */
+#define IFFD_BASIS_GENERIC  1  /* another basis: Q_reg = C^{-1} U D^{-1}        */
+
+/* Host-only, general plans, before iffd_plan_setup (IFFD_E_STATE after;
+ * IFFD_E_UNSUPPORTED for uniform plans; IFFD_E_INVAL for another value).
+ * IFFD_BASIS_GENERIC writes Q_reg through a basis of S^reg that the sine
+ * matrix does not diagonalize (eq:reg_eigenvectors): Q_reg = C^{-1} U D^{-1}
+ * with C_ij = psi_j(x_i) the interpolation matrix at the nodes of Table 1
+ * (banded; its LU factors, without pivoting, are part of the tables), U the
+ * transform of Table 1 and D_jj = ||F_j||_L2 of the interpolants F_j
+ * (eq:Dreg2).  The basis: the special basis of eq:special_basis with each of
+ * its two end blocks replaced by the orthonormal factor Q of the block's QR
+ * factorization (positive diagonal of R).  Every line transform then adds a
+ * banded solve with C^T (forward) or C (backward) per line; P^{-1} r itself
+ * does not depend on the basis (the same space S^reg, the same eigenvalues),
+ * so this variant shows the cost that the special basis removes.  The plan's
+ * tables are rebuilt; a mapped domain set before keeps its map.  Returns
+ * IFFD_E_UNSUPPORTED if C would need pivoting. */
+int iffd_plan_set_basis(iffd_plan* plan, int basis);
+
 /* Per-direction sizes: h_out[k-1] describes direction k, for every plan
  * (uniform plans report Dirichlet ends).  count: capacity of h_out (>= d). */
 int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count);

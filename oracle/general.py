@@ -203,9 +203,84 @@ def factors_route_b(n: int, p: int, D):
                 lam_out=lam_out, Qt=Qt, lam_t=lam_t)
 
 
+# ---- a generic basis of S^reg (eq:reg_eigenvectors) --------------------------
+
+def end_block_sizes(n: int, p: int, D):
+    """(cl, cr): the number of special-basis functions of B_L and B_R (the
+    counts of special_functions)."""
+    D = set(D)
+    cl = p // 2 if (0 in D or p % 2 == 0) else (p + 1) // 2
+    cr = p // 2 if (1 in D or p % 2 == 0) else (p + 1) // 2
+    return cl, cr
+
+
+def generic_vreg(n: int, p: int, D):
+    """A basis of S^reg other than the special one: each end block of the
+    special basis (its cl or cr functions, written on the B-splines they
+    touch) replaced by the orthonormal columns Q of its QR factorization,
+    diagonal of R positive; the interior B-splines are kept.  Returns
+    (V_generic, V_special, (rl, cl, rr, cr))."""
+    V = special_vreg(n, p, D)
+    m, n_reg = V.shape
+    cl, cr = end_block_sizes(n, p, D)
+    tol = 1e-12 * np.abs(V).max()
+    rl = 1 + max([r for r in range(m) if np.abs(V[r, :cl]).max(initial=0.0) > tol], default=-1)
+    rr = m - min([r for r in range(m) if np.abs(V[r, n_reg - cr:]).max(initial=0.0) > tol],
+                 default=m)
+    Vg = V.copy()
+
+    def orth(A):
+        Q, R = np.linalg.qr(A)
+        return Q * np.sign(np.diag(R))
+
+    if cl:
+        Vg[:rl, :cl] = orth(V[:rl, :cl])
+    if cr:
+        Vg[m - rr:, n_reg - cr:] = orth(V[m - rr:, n_reg - cr:])
+    return Vg, V, (rl, cl, rr, cr)
+
+
+def collocation(n: int, p: int, D, V) -> np.ndarray:
+    """C_ij = psi_j(x_i): the basis psi (coefficients V on the B-splines of
+    S_{p,h,D}) at the nodes x_i of Table 1 (the interpolation matrix of
+    eq:reg_eigenvectors, whose C^{-1} interpolates)."""
+    x, _, _ = table1(n, p, D)
+    knots = bspline.open_knots(n, p)
+    return bspline.basis(knots, p, x)[:, kept(n, p, D)] @ V
+
+
+def factors_generic(n: int, p: int, D):
+    """Q_reg = C^{-1} U D^{-1} (eq:reg_eigenvectors) in the generic basis:
+    the columns of C^{-1} U are the coefficients of the interpolants F_j of
+    sin(x alpha_j + beta) at the nodes; D_jj = ||F_j||_L2 (eq:Dreg2, the mass
+    matrix of S^reg); Lambda_reg = D^{-1} U^T C^{-T} V^T K V C^{-1} U D^{-1}
+    (eq:Lambda reg), whose diagonal is kept (the off-diagonal part vanishes,
+    the F_j being the discrete eigenfunctions).  The outlier part is that of
+    route B (S^out does not depend on the basis of S^reg)."""
+    K, M = assemble(n, p, D)
+    Vg, _, sizes = generic_vreg(n, p, D)
+    U = sine_matrix(n, p, D)
+    C = collocation(n, p, D, Vg)
+    W = np.linalg.solve(C, U)
+    VF = Vg @ W
+    Dg = np.sqrt(np.einsum("ij,ij->j", VF, M @ VF))
+    Qreg = W / Dg
+    VQ = Vg @ Qreg
+    Lfull = VQ.T @ K @ VQ
+    lam_reg = np.diag(Lfull).copy()
+    fb = factors_route_b(n, p, D)
+    Vout, Qout, lam_out = fb["V_out"], fb["Q_out"], fb["lam_out"]
+    Qt = np.hstack([VQ, Vout @ Qout]) if Vout.shape[1] else VQ
+    lam_t = np.concatenate([lam_reg, lam_out])
+    return dict(K=K, M=M, V_reg=Vg, C=C, U=U, W=W, D=Dg, Q_reg=Qreg, Lambda_full=Lfull,
+                lam_reg=lam_reg, Qt=Qt, lam_t=lam_t, sizes=sizes)
+
+
 class GeneralPreconditioner:
     """z = P^{-1} r on [0,1]^d with per-direction specs (n_k, p_k, D_k),
-    direction 1 first (the fastest index).  kind: "iffd_a", "iffd_b", "fd"."""
+    direction 1 first (the fastest index).  kind: "iffd_a", "iffd_b", "fd",
+    "iffd_generic" (route B's operator through the generic basis of
+    eq:reg_eigenvectors)."""
 
     def __init__(self, specs, kind: str = "iffd_b"):
         self.specs = [(int(n), int(p), frozenset(D)) for n, p, D in specs]
@@ -217,6 +292,9 @@ class GeneralPreconditioner:
                 lam, Q, _, K, M = factors_route_a(n, p, D)
             elif kind == "iffd_b":
                 f = factors_route_b(n, p, D)
+                lam, Q, K, M = f["lam_t"], f["Qt"], f["K"], f["M"]
+            elif kind == "iffd_generic":
+                f = factors_generic(n, p, D)
                 lam, Q, K, M = f["lam_t"], f["Qt"], f["K"], f["M"]
             elif kind == "fd":
                 K, M = assemble(n, p, D)

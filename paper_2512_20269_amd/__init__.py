@@ -30,6 +30,7 @@ E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
 PREC_F64, PREC_F32, PREC_F16S, PREC_BF16S = 0, 1, 2, 3
 GEOMETRY_NONE, GEOMETRY_BUMP, GEOMETRY_ANNULUS = 0, 1, 2
+BASIS_SPECIAL, BASIS_GENERIC = 0, 1
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
@@ -78,6 +79,7 @@ SIGNATURES = {
     "iffd_plan_query_dirs": (_I, [_P, ctypes.POINTER(_DirInfo), _I]),
     "iffd_plan_read_dir": (_I, [_P, _I, _I, _P, _Z, _P]),
     "iffd_plan_set_geometry": (_I, [_P, _I, _P, _I]),
+    "iffd_plan_set_basis": (_I, [_P, _I]),
     "iffd_plan_setup": (_I, [_P, _P, _Z, _P]),
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
@@ -196,11 +198,14 @@ class Plan:
     geometry: None, or (kind, params) with kind "bump" ({eps}) or "annulus"
     ({r_in, r_out, H}): the system matrix becomes the Galerkin matrix of the
     mapped domain (iffd_plan_set_geometry, d = 3); the preconditioner stays
-    that of A-hat."""
+    that of A-hat.
+    basis: "special" (eq:special_basis) or "generic" (general plans: Q_reg =
+    C^{-1} U D^{-1} with a banded interpolation solve per line,
+    iffd_plan_set_basis)."""
 
     def __init__(self, d: int, n, p, method: str = "fft", precision: str = "f32",
                  max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None,
-                 geometry=None):
+                 geometry=None, basis: str = "special"):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
@@ -217,6 +222,10 @@ class Plan:
         else:
             _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h
+        self.basis = basis
+        if basis != "special":
+            code = {"generic": BASIS_GENERIC}[basis]
+            _check(lib.iffd_plan_set_basis(h, code), "plan_set_basis")
         self.geometry = None
         if geometry is not None:
             kind, params = geometry

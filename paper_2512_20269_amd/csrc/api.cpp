@@ -165,6 +165,10 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
     std::copy(G.AR.begin(), G.AR.end(), blob.begin() + G.o_ar);
     std::copy(G.lam.begin(), G.lam.end(), blob.begin() + G.o_lam);
     std::copy(G.s.begin(), G.s.end(), blob.begin() + G.o_s);
+    if (G.generic) {
+      std::copy(G.LB.begin(), G.LB.begin() + (size_t)G.n_reg * G.bl, blob.begin() + G.o_lb);
+      std::copy(G.UB.begin(), G.UB.end(), blob.begin() + G.o_ub);
+    }
     // band rows padded from 2p+1 to 2pm+1 columns (centred)
     const int bw = 2 * G.p + 1, bwp = 2 * G.pm + 1, sh = G.pm - G.p;
     for (int i = 0; i < G.m; ++i)
@@ -311,6 +315,16 @@ int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, in
   if (P.ready) return fail(IFFD_E_STATE, "set the geometry before iffd_plan_setup");
   std::string err;
   const int rc = build_geometry(P, kind, h_params, nparams, err);
+  if (rc != IFFD_OK) return fail(rc, err);
+  return IFFD_OK;
+}
+
+int iffd_plan_set_basis(iffd_plan* plan, int basis) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  Plan& P = plan->P;
+  if (P.ready) return fail(IFFD_E_STATE, "set the basis before iffd_plan_setup");
+  std::string err;
+  const int rc = set_plan_basis(P, basis, err);
   if (rc != IFFD_OK) return fail(rc, err);
   return IFFD_OK;
 }

@@ -54,6 +54,9 @@ struct GDirDev {
   int m, n_reg, n_out, rl, cl, rr, cr;
   int mir_f, mir_b;  // 2 tau, 2 sig: the index shift of the spectral symmetry
   int wl, wr;        // outlier windows: Vt[q][j] used for j < wl and j >= wr
+  // generic basis of S^reg (eq:reg_eigenvectors): nonzero gb adds the banded
+  // solves with the interpolation matrix C = L U (bands at o_lb, o_ub; see GDir)
+  int gb, bl, bu, o_lb, o_ub;
 };
 
 template <typename T>
@@ -136,8 +139,55 @@ struct GTile {
   const T* SO; // TW: product of their scalings (middle pass)
   int MP;
 
+  // generic basis: w <- C^{-T} w on the folded lines w = X[l][off .. off + n_reg),
+  // one thread per line (C^T = U^T L^T: forward substitution with U^T, then
+  // backward substitution with L^T)
+  __device__ __forceinline__ void solve_ct(const GDirDev<T>& D) const {
+    const int nr = D.n_reg, bl = D.bl, bu = D.bu, off = D.rl - D.cl;
+    const T* LB = D.blob + D.o_lb;
+    const T* UB = D.blob + D.o_ub;
+    for (int l = threadIdx.x; l < C::TW; l += C::NTH) {
+      T* w = X + l * MP + off;
+      for (int i = 0; i < nr; ++i) {
+        T acc = w[i];
+        for (int j = max(0, i - bu); j < i; ++j) acc -= UB[j * (bu + 1) + (i - j)] * w[j];
+        w[i] = acc * UB[i * (bu + 1)];
+      }
+      for (int i = nr - 1; i >= 0; --i) {
+        T acc = w[i];
+        const int je = min(nr - 1, i + bl);
+        for (int j = i + 1; j <= je; ++j) acc -= LB[j * bl + (i - j + bl)] * w[j];
+        w[i] = acc;
+      }
+    }
+  }
+
+  // generic basis: c <- C^{-1} c on the lines c = X[l][off .. off + n_reg)
+  // (L y = c forward, U c = y backward)
+  __device__ __forceinline__ void solve_c(const GDirDev<T>& D) const {
+    const int nr = D.n_reg, bl = D.bl, bu = D.bu, off = D.rl - D.cl;
+    const T* LB = D.blob + D.o_lb;
+    const T* UB = D.blob + D.o_ub;
+    for (int l = threadIdx.x; l < C::TW; l += C::NTH) {
+      T* w = X + l * MP + off;
+      for (int i = 0; i < nr; ++i) {
+        T acc = w[i];
+        for (int j = max(0, i - bl); j < i; ++j) acc -= LB[i * bl + (j - i + bl)] * w[j];
+        w[i] = acc;
+      }
+      for (int i = nr - 1; i >= 0; --i) {
+        T acc = w[i];
+        const int je = min(nr - 1, i + bu);
+        for (int j = i + 1; j <= je; ++j) acc -= UB[i * (bu + 1) + (j - i)] * w[j];
+        w[i] = acc * UB[i * (bu + 1)];
+      }
+    }
+  }
+
   // X[l][0..m) = x  ->  X[l][0..n_reg) = U^T V_reg^T x, YO[l] = Vt x; with MID
-  // both scaled by s_t * SO[l] / (lambda_t + LO[l])
+  // both scaled by s_t * SO[l] / (lambda_t + LO[l]).  A generic basis
+  // (D.gb) writes the folded line in place, X[l][off + s] = (V_reg^T x)_s, and
+  // solves with C^T before the transform.
   template <bool MID>
   __device__ __forceinline__ void forward(const GDirDev<T>& D) const {
     constexpr int TW = C::TW, NTH = C::NTH, NT = C::NT;
@@ -173,6 +223,16 @@ struct GTile {
       }
     }
     __syncthreads();
+    const bool gbas = D.gb != 0;
+    if (gbas) {
+      for (int w = tid; w < TW * nbv; w += NTH) {
+        const int l = w & (TW - 1), k = w / TW;
+        X[l * MP + off + (k < cl ? k : ncr + k - cl)] = GB[l * 8 + k];
+      }
+      __syncthreads();
+      solve_ct(D);
+      __syncthreads();
+    }
     {
       const T* xa = X + la * MP;
       const T* xb = X + lb * MP;
@@ -180,7 +240,8 @@ struct GTile {
       const T* gbb = GB + lb * 8;
       auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
         if (k >= nr) return cpx<T>{T(0), T(0)};
-        const cpx<T> v{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
+        const cpx<T> v = gbas ? cpx<T>{xa[off + k], xb[off + k]}
+                              : cpx<T>{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
         return c_mul(v, TF[k]);
       };
       auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
@@ -225,7 +286,8 @@ struct GTile {
   }
 
   // X[l][0..n_reg) = y_reg and YO[l] = y_out  ->  c = U y_reg at X[l][off + s]
-  // (off = rl - cl), where the interior rows of x = V_reg c read it in place
+  // (off = rl - cl), where the interior rows of x = V_reg c read it in place;
+  // a generic basis (D.gb) then solves with C: c = C^{-1} U y_reg
   __device__ __forceinline__ void backward(const GDirDev<T>& D) const {
     constexpr int NT = C::NT;
     const int nr = D.n_reg, off = D.rl - D.cl;
@@ -262,6 +324,10 @@ struct GTile {
       }
     }
     __syncthreads();
+    if (D.gb) {
+      solve_c(D);
+      __syncthreads();
+    }
   }
 
   // entry r of line l after backward(): x = V_reg c + Vt^T y_out
@@ -426,6 +492,11 @@ GDirDev<T> gen_dir_dev(const Plan& P, const GDir& G) {
   d.mir_b = G.sig2;
   d.wl = f64 ? G.win64[0] : G.win32[0];
   d.wr = f64 ? G.win64[1] : G.win32[1];
+  d.gb = G.generic ? 1 : 0;
+  d.bl = G.bl;
+  d.bu = G.bu;
+  d.o_lb = G.o_lb;
+  d.o_ub = G.o_ub;
   return d;
 }
 

@@ -1087,6 +1087,151 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
   return IFFD_OK;
 }
 
+// Q of the QR factorization (positive diagonal of R) of a rows x cols block
+// (row-major) of full column rank, in place: Gram-Schmidt with a second
+// orthogonalization pass
+void orthonormal_columns(std::vector<double>& A, int rows, int cols) {
+  for (int c = 0; c < cols; ++c) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int c2 = 0; c2 < c; ++c2) {
+        double dot = 0.0;
+        for (int r = 0; r < rows; ++r) dot += A[(size_t)r * cols + c2] * A[(size_t)r * cols + c];
+        for (int r = 0; r < rows; ++r) A[(size_t)r * cols + c] -= dot * A[(size_t)r * cols + c2];
+      }
+    double nrm = 0.0;
+    for (int r = 0; r < rows; ++r) nrm += A[(size_t)r * cols + c] * A[(size_t)r * cols + c];
+    nrm = std::sqrt(nrm);
+    for (int r = 0; r < rows; ++r) A[(size_t)r * cols + c] /= nrm;
+  }
+}
+
+// A generic basis of S^reg for eq:reg_eigenvectors, Q_reg = C^{-1} U D^{-1}:
+// the special basis with each end block (AL, AR) replaced by its orthonormal
+// QR factor, the interior B-splines kept.  C_ij = psi_j(x_i) at the nodes
+// x_i = (i + sig) h of Table 1 is banded; its LU factors (no pivoting) are
+// kept as bands.  D_t = ||F_t||_L2 for the interpolant F_t = V_reg C^{-1} U e_t
+// (eq:Dreg2; s_t = 1 / D_t^2), and Lambda_reg, which does not depend on the
+// basis, is checked against F_t's Rayleigh quotient (eq:Lambda reg2).  The
+// outlier space (and V_out) is the same as for the special basis.
+int make_generic(GDir& G, std::string& err) {
+  const int n = G.n, p = G.p, m = G.m, nr = G.n_reg, nb = n + p, bw = 2 * p + 1;
+  const int cl = G.cl, cr = G.cr, rl = G.rl, rr = G.rr, nint = nr - cl - cr;
+  std::vector<double> AL = G.AL, AR = G.AR;
+  orthonormal_columns(AL, rl, cl);
+  orthonormal_columns(AR, rr, cr);
+  std::vector<double> U(n + 2 * p + 1);
+  for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
+  for (int k = 1; k < n; ++k) U[p + k] = (double)k / n;
+  // the interpolation matrix
+  std::vector<double> C((size_t)nr * nr, 0.0), val, der, brow(m);
+  for (int i = 0; i < nr; ++i) {
+    const double x = (2.0 * i + G.sig2) / (2.0 * n);
+    const int sp = find_span(nb, p, x, U);
+    basis_and_derivative(sp, x, p, U, val, der);
+    std::fill(brow.begin(), brow.end(), 0.0);
+    for (int j = 0; j <= p; ++j) {
+      const int r = sp - p + j - G.dlo;
+      if (r >= 0 && r < m) brow[r] = val[j];
+    }
+    for (int j = 0; j < cl; ++j) {
+      double v = 0.0;
+      for (int r = 0; r < rl; ++r) v += AL[(size_t)r * cl + j] * brow[r];
+      C[(size_t)i * nr + j] = v;
+    }
+    for (int j = 0; j < nint; ++j) C[(size_t)i * nr + cl + j] = brow[rl + j];
+    for (int j = 0; j < cr; ++j) {
+      double v = 0.0;
+      for (int r = 0; r < rr; ++r) v += AR[(size_t)r * cr + j] * brow[m - rr + r];
+      C[(size_t)i * nr + nr - cr + j] = v;
+    }
+  }
+  int bl = 0, bu = 0;
+  double cmax = 0.0;
+  for (int i = 0; i < nr; ++i)
+    for (int j = 0; j < nr; ++j)
+      if (C[(size_t)i * nr + j] != 0.0) {
+        bl = std::max(bl, i - j);
+        bu = std::max(bu, j - i);
+        cmax = std::max(cmax, std::fabs(C[(size_t)i * nr + j]));
+      }
+  // LU without pivoting inside the band (the fill stays in it)
+  for (int k = 0; k < nr; ++k) {
+    const double piv = C[(size_t)k * nr + k];
+    if (!(std::fabs(piv) > 1e-10 * cmax)) {
+      err = "generic basis: the interpolation matrix needs pivoting";
+      return IFFD_E_UNSUPPORTED;
+    }
+    for (int i = k + 1; i <= std::min(nr - 1, k + bl); ++i) {
+      const double l = C[(size_t)i * nr + k] / piv;
+      C[(size_t)i * nr + k] = l;
+      if (l != 0.0)
+        for (int j = k + 1; j <= std::min(nr - 1, k + bu); ++j) C[(size_t)i * nr + j] -= l * C[(size_t)k * nr + j];
+    }
+  }
+  G.bl = bl;
+  G.bu = bu;
+  G.LB.assign((size_t)nr * std::max(bl, 1), 0.0);
+  G.UB.assign((size_t)nr * (bu + 1), 0.0);
+  for (int i = 0; i < nr; ++i) {
+    for (int k = 0; k < bl; ++k) {
+      const int j = i - bl + k;
+      if (j >= 0) G.LB[(size_t)i * bl + k] = C[(size_t)i * nr + j];
+    }
+    G.UB[(size_t)i * (bu + 1)] = 1.0 / C[(size_t)i * nr + i];
+    for (int k = 1; k <= bu; ++k)
+      if (i + k < nr) G.UB[(size_t)i * (bu + 1) + k] = C[(size_t)i * nr + i + k];
+  }
+  // D_t and the eigenvalue check
+  auto band_dot = [&](const std::vector<double>& Bd, const std::vector<double>& v) {
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int o = 0; o < bw; ++o) {
+        const int j = i + o - p;
+        if (j >= 0 && j < m) acc += v[i] * Bd[(size_t)i * bw + o] * v[j];
+      }
+    return acc;
+  };
+  const int per = 8 * n;
+  double lmax = 0.0;
+  for (int t = 0; t < nr; ++t) lmax = std::max(lmax, G.lam[t]);
+  std::vector<double> w(nr), v(m);
+  for (int t = 0; t < nr; ++t) {
+    for (int i = 0; i < nr; ++i) {
+      const long long a = ((long long)(2 * i + G.sig2) * (2 * t + G.tau2) + 2LL * n * G.beta) % per;
+      w[i] = std::sin(2 * kPi * (double)a / per);
+    }
+    for (int i = 0; i < nr; ++i)   // L y = u
+      for (int j = std::max(0, i - bl); j < i; ++j) w[i] -= C[(size_t)i * nr + j] * w[j];
+    for (int i = nr - 1; i >= 0; --i) {   // U w = y
+      for (int j = i + 1; j <= std::min(nr - 1, i + bu); ++j) w[i] -= C[(size_t)i * nr + j] * w[j];
+      w[i] /= C[(size_t)i * nr + i];
+    }
+    for (int r = 0; r < rl; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < cl; ++c) acc += AL[(size_t)r * cl + c] * w[c];
+      v[r] = acc;
+    }
+    for (int i = 0; i < nint; ++i) v[rl + i] = w[cl + i];
+    for (int r = 0; r < rr; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < cr; ++c) acc += AR[(size_t)r * cr + c] * w[nr - cr + c];
+      v[m - rr + r] = acc;
+    }
+    const double sm = band_dot(G.Mb, v), sk = band_dot(G.Kb, v);
+    if (!(sm > 0.0)) { err = "generic basis: an interpolant has no mass"; return IFFD_E_INVAL; }
+    if (std::fabs(sk / sm - G.lam[t]) > 1e-8 * G.lam[t] + 1e-12 * lmax) {
+      err = "generic basis: eigenvalue check failed";
+      return IFFD_E_INVAL;
+    }
+    G.s[t] = 1.0 / sm;
+    G.Dt[t] = std::sqrt(sm);
+  }
+  G.AL = AL;
+  G.AR = AR;
+  G.generic = true;
+  return IFFD_OK;
+}
+
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 void compute_layout_general(Plan& P) {
@@ -1112,6 +1257,8 @@ void compute_layout_general(Plan& P) {
     G.o_s = o;   o += G.m;
     G.o_kb = o;  o += G.m * bw;
     G.o_mb = o;  o += G.m * bw;
+    G.o_lb = o;  o += G.generic ? G.n_reg * G.bl : 0;
+    G.o_ub = o;  o += G.generic ? G.n_reg * (G.bu + 1) : 0;
     G.len = o + (o & 1);
     G.blob64 = take((size_t)8 * G.len);
     G.blob32 = take((size_t)4 * G.len);
@@ -1175,6 +1322,30 @@ int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* 
   P.first64 = P.prec == IFFD_PREC_F32 && pmax >= 5;
   P.lay = TableLayout{};
   compute_layout_general(P);
+  return IFFD_OK;
+}
+
+int set_plan_basis(Plan& P, int basis, std::string& err) {
+  if (basis != IFFD_BASIS_SPECIAL && basis != IFFD_BASIS_GENERIC) { err = "unknown basis"; return IFFD_E_INVAL; }
+  if (!P.gen) { err = "the basis choice needs a general plan (iffd_plan_create_general)"; return IFFD_E_UNSUPPORTED; }
+  if (basis == P.basis) return IFFD_OK;
+  GDir dirs[3];
+  for (int k = 0; k < P.d; ++k) {
+    const GDir& G = P.dirs[k];
+    int rc = build_dir(dirs[k], G.n, G.p, G.dlo, G.dhi, err);
+    if (rc == IFFD_OK && basis == IFFD_BASIS_GENERIC) rc = make_generic(dirs[k], err);
+    if (rc != IFFD_OK) return rc;
+  }
+  for (int k = 0; k < P.d; ++k) P.dirs[k] = dirs[k];
+  P.basis = basis;
+  // the tables of a mapped domain follow the plan's own
+  const int gk = P.geo.kind;
+  double gp[4];
+  for (int i = 0; i < 4; ++i) gp[i] = P.geo.par[i];
+  P.geo = GeoPlan{};
+  P.lay = TableLayout{};
+  compute_layout_general(P);
+  if (gk) return build_geometry(P, gk, gp, 4, err);
   return IFFD_OK;
 }
 

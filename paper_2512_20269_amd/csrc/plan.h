@@ -68,6 +68,13 @@ struct GDir {
   // FP32 blob share them): tw | tf | AL | AR | Vt | lam | s | Kb | Mb (the band
   // tables padded to 2 pm + 1 columns)
   int o_tw = 0, o_tf = 0, o_al = 0, o_ar = 0, o_vt = 0, o_lam = 0, o_s = 0, o_kb = 0, o_mb = 0;
+  // generic basis of S^reg (eq:reg_eigenvectors): the LU factors of the
+  // interpolation matrix C as bands, LB[i][k] = L[i][i - bl + k] (k < bl, unit
+  // diagonal implied), UB[i][0] = 1 / U[i][i], UB[i][k] = U[i][i + k] (1 <= k <= bu)
+  bool generic = false;
+  int bl = 0, bu = 0;
+  std::vector<double> LB, UB;
+  int o_lb = 0, o_ub = 0;
   int len = 0;
   size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
   size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)
@@ -131,6 +138,7 @@ struct Plan {
   // direction 1, the fastest index); n, p, m, n_reg, n_out above then hold
   // direction 1's values
   bool gen = false;
+  int basis = 0;   // IFFD_BASIS_*: the basis of S^reg of general plans
   GDir dirs[3];
 
   GeoPlan geo;
@@ -146,6 +154,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
 int build_plan_general(Plan& P, int d, const int* n, const int* p, const int* dirichlet,
                        const iffd_opts* opts, std::string& err);
 int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& err);
+int set_plan_basis(Plan& P, int basis, std::string& err);
 void compute_layout(Plan& P);
 StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);

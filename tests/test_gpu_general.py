@@ -182,3 +182,65 @@ def test_general_noalloc_equals_apply():
     pl = gen_plan(n, p, dl, "f32")
     r = dev(workloads.uniform_tensor(pl.shape, seed=9))
     assert torch.equal(pl.apply(r), pl.apply_noalloc(r))
+
+
+# ---- the generic basis of eq:reg_eigenvectors (Q_reg = C^{-1} U D^{-1}) -------
+
+@functools.lru_cache(maxsize=None)
+def generic_oracle(specs):
+    return G.GeneralPreconditioner([(n, p, set(D)) for n, p, D in specs], "iffd_generic")
+
+
+@functools.lru_cache(maxsize=None)
+def generic_plan(n, p, dl, prec="f32"):
+    return I.Plan(len(n), list(n), list(p), precision=prec,
+                  dirichlet=[tuple(x) for x in dl], basis="generic")
+
+
+GENERIC_CASES = [
+    # the eight transforms of Table 1 along direction 1 (odd and even p)
+    ((16, 24), (3, 3), ((1, 0), (1, 1))),
+    ((16, 24), (4, 2), ((1, 0), (1, 1))),
+    ((16, 24), (3, 3), ((0, 1), (1, 1))),
+    ((16, 24), (4, 2), ((0, 1), (1, 1))),
+    ((16, 24), (3, 3), ((0, 0), (1, 1))),
+    ((16, 24), (4, 2), ((0, 0), (1, 1))),
+    ((16, 24), (5, 3), ((1, 1), (0, 0))),
+    ((16, 24), (2, 4), ((1, 1), (1, 0))),
+    # 3D mixed, the highest degrees, p = 1, several tiles with ragged tails
+    ((16, 24, 32), (3, 2, 4), ((1, 0), (0, 1), (0, 0))),
+    ((12, 16), (7, 8), ((0, 0), (1, 0))),
+    ((16, 12), (8, 7), ((0, 1), (0, 0))),
+    ((16, 32), (1, 1), ((0, 0), (1, 0))),
+    ((96, 64), (3, 4), ((0, 1), (1, 0))),
+    ((256, 24), (4, 3), ((0, 0), (0, 1))),
+    ((64, 64, 64), (3, 3, 3), ((1, 0), (0, 1), (0, 0))),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,p,dl", GENERIC_CASES)
+def test_generic_basis_apply_matches_oracle(n, p, dl, prec):
+    """The generic-basis plan (banded interpolation solves per line) against
+    the oracle's generic route, which equals route B: P^{-1} r does not depend
+    on the basis of S^reg."""
+    pre = generic_oracle(specs_of(n, p, dl))
+    pl = generic_plan(n, p, dl, prec)
+    assert pl.shape == pre.shape
+    r = workloads.uniform_tensor(pre.shape, seed=sum(n) + 10 * sum(p) + 1)
+    print(f"generic-basis apply n={n} p={p} dirichlet={dl} {prec}", flush=True)
+    z = host(pl.apply(dev(r)))
+    check(z, pre.apply(r), TOL[prec], len(n), max(p), f"generic n={n} p={p} {dl} {prec}")
+
+
+def test_generic_basis_pcg_equals_special():
+    """PCG on the Table 3 pattern (3D, n = 32, p = 2..5) with both bases: the
+    same preconditioner, so the same iterations (FP64 apply) and solutions."""
+    n, dl = (32, 32, 32), workloads.MIXED_CUBE_DIRICHLET
+    for p in (2, 3, 4, 5):
+        f = workloads.uniform_tensor(gen_plan(n, (p,) * 3, dl, "f64").shape, seed=1)
+        us, sts = gen_plan(n, (p,) * 3, dl, "f64").solve(dev(f), rtol=1e-8, maxit=100)
+        ug, stg = generic_plan(n, (p,) * 3, dl, "f64").solve(dev(f), rtol=1e-8, maxit=100)
+        print(f"p={p}: special {sts[0]['iterations']} generic {stg[0]['iterations']}", flush=True)
+        assert stg[0]["converged"] and stg[0]["iterations"] == sts[0]["iterations"]
+        assert rel(host(ug), host(us)) <= 1e-9

@@ -395,3 +395,67 @@ def test_geometry_host_rules():
     _, h3 = host_plan(3, 8, 3, coef_a=0.5)
     assert I.lib.iffd_plan_set_geometry(h3, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_INVAL
     I.lib.iffd_plan_destroy(h3)
+
+
+@pytest.mark.parametrize("n", [16, 24])
+@pytest.mark.parametrize("ends", GEN_ENDS)
+def test_generic_basis_host_tables_match_oracle(n, ends):
+    """iffd_plan_set_basis(IFFD_BASIS_GENERIC) against the oracle's generic
+    route (eq:reg_eigenvectors): the orthonormalized end blocks of V_reg and
+    D_jj = ||F_j||_L2 of the interpolants (eq:Dreg2); the eigenvalues are the
+    special basis's (basis-independent)."""
+    from oracle import general as G
+    D = {e for e, f in zip((0, 1), ends) if f}
+    for p in range(1, 9):
+        if n <= p:
+            continue
+        rc, h = I.create_general(2, [n, 16], [p, 2], [ends, (1, 1)])
+        assert rc == 0
+        lam_special = read_dir(h, 1, 0, n + p)
+        assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == 0, I.lib.iffd_last_error()
+        di = I.query_dirs(h, 2)[0]
+        m, nr = di["m"], di["n_reg"]
+        f = G.factors_generic(n, p, D)
+        _, cl, _, cr = f["sizes"]
+        rl, rr = p - (1 if ends[0] else 0), p - (1 if ends[1] else 0)
+        Vg = f["V_reg"]
+        if cl:
+            AL = read_dir(h, 1, 4, rl * cl).reshape(rl, cl)
+            assert np.abs(AL - Vg[:rl, :cl]).max() < 1e-12, (p, ends)
+        if cr:
+            AR = read_dir(h, 1, 5, rr * cr).reshape(rr, cr)
+            assert np.abs(AR - Vg[m - rr:, nr - cr:]).max() < 1e-12, (p, ends)
+        Dg = read_dir(h, 1, 1, nr)
+        assert np.abs(Dg - f["D"]).max() <= 1e-12 * f["D"].max(), (p, ends)
+        lam = read_dir(h, 1, 0, m)
+        assert np.array_equal(lam[:nr], lam_special[:nr])
+        I.lib.iffd_plan_destroy(h)
+
+
+def test_basis_rules():
+    rc, h = host_plan(3, 16, 3)
+    assert rc == 0
+    assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == I.E_UNSUPPORTED   # uniform plan
+    I.lib.iffd_plan_destroy(h)
+    rc, h = I.create_general(3, [16, 24, 32], [3, 2, 4], [(1, 0), (0, 1), (0, 0)])
+    assert rc == 0
+    info0 = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info0)) == 0
+    AL0 = read_dir(h, 1, 4, 2)
+    assert I.lib.iffd_plan_set_basis(h, 5) == I.E_INVAL
+    assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == 0
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.table_bytes >= info0.table_bytes          # the interpolation bands
+    assert np.linalg.norm(read_dir(h, 1, 4, 2)) == pytest.approx(1.0)   # orthonormal column
+    assert I.lib.iffd_plan_set_basis(h, I.BASIS_SPECIAL) == 0
+    assert np.array_equal(read_dir(h, 1, 4, 2), AL0)
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.table_bytes == info0.table_bytes
+    # a mapped domain keeps its map through a change of basis
+    par = (ctypes.c_double * 3)(1.0, 2.0, 1.0)
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par, 3) == 0
+    assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == 0
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.matvec_ws_bytes == 8 * (16 * 24 * 32) * (4 * 3 * 5)
+    I.lib.iffd_plan_destroy(h)
