@@ -143,3 +143,37 @@ def test_table3_counts_n64():
         f = np.random.default_rng(1).uniform(-1, 1, pre.shape)
         _, it, conv, *_ = krylov.pcg(pre.matvec, pre.apply, f, tol=1e-8)
         assert conv and abs(it - it_p) <= 1, (p, it, it_p)
+
+
+@pytest.mark.parametrize("D", CASES, ids=lambda D: "D" + "".join(map(str, sorted(D))))
+@pytest.mark.parametrize("p", range(1, 9))
+def test_generic_basis_route(p, D):
+    """eq:reg_eigenvectors with two bases of S^reg.  The special basis: its
+    collocation matrix C_s (psi_j at the nodes x_i of Table 1) has the columns
+    of U as eigenvectors (C_s U = U Theta, Theta > 0).  The generic basis (end
+    blocks orthonormalized): U does not diagonalize C, but Q_reg = C^{-1} U
+    D^{-1} gives M-orthonormal eigenvectors (eq:Lambda reg is diagonal) with
+    the same eigenvalues as route B, and the same P^{-1} r."""
+    n = 2 * p + 8
+    f = G.factors_generic(n, p, D)
+    fb = G.factors_route_b(n, p, D)
+    U = f["U"]
+    Vs = G.special_vreg(n, p, D)
+    T = np.linalg.solve(U, G.collocation(n, p, D, Vs) @ U)
+    theta = np.diag(T)
+    assert np.abs(T - np.diag(theta)).max() < 1e-12 and theta.min() > 0
+    Tg = np.linalg.solve(U, f["C"] @ U)
+    cl, cr = G.end_block_sizes(n, p, D)
+    if max(cl, cr) >= 2 or (D != {0, 1} and p >= 2):
+        assert np.abs(Tg - np.diag(np.diag(Tg))).max() > 1e-3   # the solve is needed
+    Vg = f["V_reg"]
+    VQ = Vg @ f["Q_reg"]
+    assert np.abs(VQ.T @ fb["M"] @ VQ - np.eye(VQ.shape[1])).max() < 1e-12
+    Lf = f["Lambda_full"]
+    assert np.abs(Lf - np.diag(np.diag(Lf))).max() < 1e-12 * np.abs(Lf).max()
+    assert np.abs(f["lam_reg"] - fb["lam_reg"]).max() <= 1e-12 * fb["lam_reg"].max()
+    # the same preconditioner (shifted by the identity where D is empty: lambda_0 = 0)
+    r = np.random.default_rng(p).standard_normal(f["Qt"].shape[0])
+    za = f["Qt"] @ ((f["Qt"].T @ r) / (f["lam_t"] + 1.0))
+    zb = fb["Qt"] @ ((fb["Qt"].T @ r) / (fb["lam_t"] + 1.0))
+    assert np.abs(za - zb).max() <= 1e-12 * np.abs(zb).max()
