@@ -22,27 +22,32 @@ def open_knots(n: int, p: int) -> np.ndarray:
     return np.concatenate([np.zeros(p + 1), interior, np.ones(p + 1)])
 
 
-def _degree0(knots: np.ndarray, x: np.ndarray) -> np.ndarray:
+def _degree0(knots: np.ndarray, x: np.ndarray, left: bool = False) -> np.ndarray:
     """Indicator functions of the half-open knot spans [xi_i, xi_{i+1}).
 
     At the right end x = xi_last the half-open rule gives nothing; the value
-    there is taken as the left limit, i.e. the last non-empty span counts."""
+    there is taken as the left limit, i.e. the last non-empty span counts.
+    left=True takes the spans (xi_i, xi_{i+1}] instead: values are then the
+    limits from the left at the knots (a derivative jump at an interior knot
+    is the difference of the two)."""
     nspan = len(knots) - 1
     B = np.zeros((len(x), nspan))
     for i in range(nspan):
         a, b = knots[i], knots[i + 1]
         if b > a:
-            B[:, i] = (x >= a) & (x < b)
-    last = max(i for i in range(nspan) if knots[i + 1] > knots[i])
-    B[x == knots[-1], last] = 1.0
+            B[:, i] = ((x > a) & (x <= b)) if left else ((x >= a) & (x < b))
+    if not left:
+        last = max(i for i in range(nspan) if knots[i + 1] > knots[i])
+        B[x == knots[-1], last] = 1.0
     return B
 
 
-def basis(knots: np.ndarray, p: int, x) -> np.ndarray:
+def basis(knots: np.ndarray, p: int, x, left: bool = False) -> np.ndarray:
     """Values of all degree-p B-splines at the points x, shape (len(x), nb),
-    nb = len(knots) - p - 1, by the Cox-de Boor recursion of Section 2."""
+    nb = len(knots) - p - 1, by the Cox-de Boor recursion of Section 2
+    (left=True: limits from the left at knots)."""
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
-    B = _degree0(knots, x)
+    B = _degree0(knots, x, left)
     for q in range(1, p + 1):
         nb = len(knots) - q - 1
         Bn = np.zeros((len(x), nb))
@@ -57,18 +62,18 @@ def basis(knots: np.ndarray, p: int, x) -> np.ndarray:
     return B
 
 
-def derivative(knots: np.ndarray, p: int, x, k: int) -> np.ndarray:
+def derivative(knots: np.ndarray, p: int, x, k: int, left: bool = False) -> np.ndarray:
     """k-th derivative of all degree-p B-splines at x (shape (len(x), nb)).
 
     Uses the standard derivative formula of the recursion:
     D B_{q,i} = q/(xi_{i+q}-xi_i) B_{q-1,i} - q/(xi_{i+q+1}-xi_{i+1}) B_{q-1,i+1},
     applied k times, with vanishing denominators dropped as in Section 2."""
     if k == 0:
-        return basis(knots, p, x)
+        return basis(knots, p, x, left)
     if k > p:
         x = np.atleast_1d(x)
         return np.zeros((len(x), len(knots) - p - 1))
-    lower = derivative(knots, p - 1, x, k - 1)
+    lower = derivative(knots, p - 1, x, k - 1, left)
     nb = len(knots) - p - 1
     out = np.zeros((lower.shape[0], nb))
     for i in range(nb):
