@@ -242,6 +242,25 @@ int iffd_plan_create_general(iffd_plan** out, int d, const int* n, const int* p,
  * IFFD_E_UNSUPPORTED if C would need pivoting. */
 int iffd_plan_set_basis(iffd_plan* plan, int basis);
 
+/* Host-only, general plans, before iffd_plan_setup (IFFD_E_STATE after).
+ * Reduced regularity (Remark rmk:reduced_regularity, eq:reg_space2): the
+ * breakpoint k / n_d of direction `direction` (1..d) is repeated `mult` times
+ * (1 <= mult <= p_d; mult = 1 restores maximal smoothness), so the spline
+ * space of that direction is C^{p - mult} there and has mult - 1 more
+ * B-splines (m grows by mult - 1; iffd_plan_query_dirs reports it).  S^reg
+ * stays the space of C^{p-1} functions with the end conditions of
+ * eq:reg_space, whose special-basis functions are written on the new
+ * B-splines through the knot-insertion matrix E (Boehm's algorithm: the
+ * identity away from the knot, a small block around it); S^out, its L2
+ * complement, gains mult - 1 functions concentrated around the knot.  The
+ * transforms read and write E^T / E on that window; the operator
+ * (iffd_kron_matvec, PCG) uses K and M of the reduced space.  Valid: the
+ * knot window at least p B-splines away from both end blocks (about 2p
+ * elements from either end; IFFD_E_INVAL otherwise), at most 8 outlier
+ * functions per direction, not with IFFD_BASIS_GENERIC or a mapped domain
+ * (IFFD_E_UNSUPPORTED; set the knot before a mapped domain would need it). */
+int iffd_plan_set_knot(iffd_plan* plan, int direction, int k, int mult);
+
 /* Per-direction sizes: h_out[k-1] describes direction k, for every plan
  * (uniform plans report Dirichlet ends).  count: capacity of h_out (>= d). */
 int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count);

@@ -80,6 +80,7 @@ SIGNATURES = {
     "iffd_plan_read_dir": (_I, [_P, _I, _I, _P, _Z, _P]),
     "iffd_plan_set_geometry": (_I, [_P, _I, _P, _I]),
     "iffd_plan_set_basis": (_I, [_P, _I]),
+    "iffd_plan_set_knot": (_I, [_P, _I, _I, _I]),
     "iffd_plan_setup": (_I, [_P, _P, _Z, _P]),
     "iffd_plan_read": (_I, [_P, _I, _P, _Z, _P]),
     "iffd_plan_destroy": (None, [_P]),
@@ -201,11 +202,14 @@ class Plan:
     that of A-hat.
     basis: "special" (eq:special_basis) or "generic" (general plans: Q_reg =
     C^{-1} U D^{-1} with a banded interpolation solve per line,
-    iffd_plan_set_basis)."""
+    iffd_plan_set_basis).
+    knots: general plans, {direction (1-based): (k, mult)}: the breakpoint
+    k / n of that direction repeated mult times (reduced regularity,
+    iffd_plan_set_knot)."""
 
     def __init__(self, d: int, n, p, method: str = "fft", precision: str = "f32",
                  max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None,
-                 geometry=None, basis: str = "special"):
+                 geometry=None, basis: str = "special", knots=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         opts = _Opts(METHOD_FFT if method == "fft" else METHOD_DENSE_FD,
@@ -213,7 +217,8 @@ class Plan:
                       "bf16s": PREC_BF16S}[precision], max_rhs,
                      float(coef_a))
         self.coef_a = float(coef_a)
-        self.general = dirichlet is not None or hasattr(n, "__len__") or hasattr(p, "__len__")
+        self.general = (dirichlet is not None or hasattr(n, "__len__") or hasattr(p, "__len__")
+                        or bool(knots))
         h = ctypes.c_void_p()
         if self.general:
             dl = dirichlet if dirichlet is not None else [(1, 1)] * d
@@ -222,6 +227,8 @@ class Plan:
         else:
             _check(lib.iffd_plan_create(ctypes.byref(h), d, n, p, ctypes.byref(opts)), "plan_create")
         self._h = h
+        for direction, (kn, mult) in sorted((knots or {}).items()):
+            _check(lib.iffd_plan_set_knot(h, int(direction), int(kn), int(mult)), "plan_set_knot")
         self.basis = basis
         if basis != "special":
             code = {"generic": BASIS_GENERIC}[basis]

@@ -124,6 +124,37 @@ namespace {
 // geometrically away from the two ends; entries below 2^-30 (FP32 apply) or
 // 2^-60 (FP64 apply) of the largest contribute below the working precision
 // to the dots and the rank-n_out update, so only the two end windows are used
+// Three windows for a direction with a repeated knot: the two ends and one
+// around the knot (positions kc0 .. kc1 of the knot window): positions below
+// the midpoint between the left end and the knot go to the left window, those
+// above the midpoint between the knot and the right end to the right one, the
+// rest to [kw0, kw1).  Overlapping windows fall back to every position.
+void outlier_windows3(const std::vector<double>& Vt, int n_out, int m, int kc0, int kc1,
+                      int* win32, int* win64, int* kwin32, int* kwin64) {
+  const int a = kc0 / 2, b = (kc1 + m) / 2;
+  for (int w = 0; w < 2; ++w) {
+    int* win = w == 0 ? win32 : win64;
+    int* kw = w == 0 ? kwin32 : kwin64;
+    win[0] = m; win[1] = m; kw[0] = 0; kw[1] = 0;
+    if (n_out == 0) continue;
+    const double thr = std::ldexp(1.0, w == 0 ? -30 : -60);
+    double mx = 0.0;
+    for (double v : Vt) mx = std::max(mx, std::fabs(v));
+    int lo = 0, hi = m, k0 = m, k1 = 0;
+    for (int j = 0; j < m; ++j)
+      for (int q = 0; q < n_out; ++q)
+        if (std::fabs(Vt[(size_t)q * m + j]) > thr * mx) {
+          if (j < a) lo = std::max(lo, j + 1);
+          else if (j >= b) hi = std::min(hi, j);
+          else { k0 = std::min(k0, j); k1 = std::max(k1, j + 1); }
+        }
+    if (k1 <= k0) { k0 = k1 = lo; }
+    if (lo <= k0 && k1 <= hi && lo < hi) {
+      win[0] = lo; win[1] = hi; kw[0] = k0; kw[1] = k1;
+    }
+  }
+}
+
 void outlier_windows(const std::vector<double>& Vt, int n_out, int m, int* win32, int* win64) {
   for (int w = 0; w < 2; ++w) {
     int* win = w == 0 ? win32 : win64;
@@ -169,6 +200,7 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
       std::copy(G.LB.begin(), G.LB.begin() + (size_t)G.n_reg * G.bl, blob.begin() + G.o_lb);
       std::copy(G.UB.begin(), G.UB.end(), blob.begin() + G.o_ub);
     }
+    std::copy(G.EW.begin(), G.EW.end(), blob.begin() + G.o_ew);
     // band rows padded from 2p+1 to 2pm+1 columns (centred)
     const int bw = 2 * G.p + 1, bwp = 2 * G.pm + 1, sh = G.pm - G.p;
     for (int i = 0; i < G.m; ++i)
@@ -227,7 +259,10 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
                                     ": outlier pencil eigenpairs not finite and positive");
     for (int j = G.n_reg; j < G.m; ++j) G.lam[j] = lam[j];
     G.Vt = vt;
-    outlier_windows(G.Vt, G.n_out, G.m, G.win32, G.win64);
+    if (G.rk)
+      outlier_windows3(G.Vt, G.n_out, G.m, G.wk0, G.wk1 + G.rk, G.win32, G.win64, G.kwin32, G.kwin64);
+    else
+      outlier_windows(G.Vt, G.n_out, G.m, G.win32, G.win64);
   }
   return IFFD_OK;
 }
@@ -315,6 +350,16 @@ int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, in
   if (P.ready) return fail(IFFD_E_STATE, "set the geometry before iffd_plan_setup");
   std::string err;
   const int rc = build_geometry(P, kind, h_params, nparams, err);
+  if (rc != IFFD_OK) return fail(rc, err);
+  return IFFD_OK;
+}
+
+int iffd_plan_set_knot(iffd_plan* plan, int direction, int k, int mult) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  Plan& P = plan->P;
+  if (P.ready) return fail(IFFD_E_STATE, "set the knot before iffd_plan_setup");
+  std::string err;
+  const int rc = set_plan_knot(P, direction, k, mult, err);
   if (rc != IFFD_OK) return fail(rc, err);
   return IFFD_OK;
 }

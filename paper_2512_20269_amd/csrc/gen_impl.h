@@ -57,6 +57,13 @@ struct GDirDev {
   // generic basis of S^reg (eq:reg_eigenvectors): nonzero gb adds the banded
   // solves with the interpolation matrix C = L U (bands at o_lb, o_ub; see GDir)
   int gb, bl, bu, o_lb, o_ub;
+  // reduced regularity (a repeated knot, eq:reg_space2): the line has m
+  // entries on the reduced space's B-splines, mo = m - rk of them on the
+  // maximally smooth space's; E (knot insertion) is the identity below the
+  // old position wk0, a shift by rk from wk1 on, and the block EW (rows
+  // wk0 .. wk1 + rk, columns wk0 .. wk1) in between (wk0 = wk1 = 2^30 without
+  // a knot).  Outlier window [kw0, kw1) around the knot.
+  int rk, wk0, wk1, o_ew, kw0, kw1, mo;
 };
 
 template <typename T>
@@ -79,7 +86,7 @@ struct GPassArgs {
 };
 
 struct GLds {
-  size_t tw, x, f, gb, yo, lb, lo, so, total;
+  size_t tw, x, f, gb, yo, kb, lb, lo, so, total;
 };
 
 __host__ __device__ inline size_t gup16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -94,6 +101,7 @@ __host__ __device__ inline GLds gen_lds(int m) {
   r.f = o;  o = gup16(o + 2 * sizeof(T) * C::FPW * fft_region<L>());
   r.gb = o; o = gup16(o + sizeof(T) * C::TW * 8);
   r.yo = o; o = gup16(o + sizeof(T) * C::TW * 8);
+  r.kb = o; o = gup16(o + sizeof(T) * C::TW * 16);
   r.lb = o; o = gup16(o + sizeof(int) * C::TW);
   r.lo = o; o = gup16(o + sizeof(T) * C::TW);
   r.so = o; o = gup16(o + sizeof(T) * C::TW);
@@ -117,15 +125,6 @@ __device__ __forceinline__ int gen_line(const GPassArgs<T>& a, int q, int& i1, i
   return outer * a.dir.m * a.S + j2 * a.m1 + r;
 }
 
-// g_s of the folded line (forward input of U^T): AL^T x on the first cl
-// entries, AR^T x on the last cr (held in gb), x itself in between
-template <typename T>
-__device__ __forceinline__ T fold_at(const T* x, const T* gb, int s, int cl, int ncr, int off) {
-  if (s < cl) return gb[s];
-  if (s >= ncr) return gb[cl + s - ncr];
-  return x[s + off];
-}
-
 // The transforms of one tile of TW lines held in LDS (X[l][i], row pitch MP).
 // All threads of the workgroup call each step; every step ends with a barrier.
 template <typename T, int L, class C>
@@ -135,6 +134,7 @@ struct GTile {
   cpx<T>* F;   // FPW FFT regions
   T* GB;       // TW x 8: folded end values
   T* YO;       // TW x 8: outlier coefficients
+  T* KB;       // TW x 16: E^T x on the knot window (reduced regularity)
   const T* LO; // TW: sum of the other directions' eigenvalues (middle pass)
   const T* SO; // TW: product of their scalings (middle pass)
   int MP;
@@ -201,9 +201,12 @@ struct GTile {
     const int f = tid / NT, lane = tid - f * NT;
     cpx<T>* buf = F + f * fft_region<L>();
     const int la = 2 * f, lb = 2 * f + 1;
-    // boundary fold values and outlier coefficients
+    // boundary fold values, outlier coefficients and, with a repeated knot,
+    // E^T x on the knot window
     const int nbv = cl + cr;
-    for (int w = tid; w < TW * (nbv + no); w += NTH) {
+    const int nkw = D.rk ? D.wk1 - D.wk0 : 0;
+    const T* EW = D.blob + D.o_ew;
+    for (int w = tid; w < TW * (nbv + no + nkw); w += NTH) {
       const int l = w & (TW - 1), k = w / TW;
       const T* x = X + l * MP;
       T acc = T(0);
@@ -214,12 +217,17 @@ struct GTile {
         const int kk = k - cl;
         for (int r = 0; r < rr; ++r) acc += AR[r * cr + kk] * x[m - rr + r];
         GB[l * 8 + k] = acc;
-      } else {
+      } else if (k < nbv + no) {
         const int q = k - nbv;
         const T* v = Vt + q * m;
         for (int j = 0; j < D.wl; ++j) acc += v[j] * x[j];
+        for (int j = D.kw0; j < D.kw1; ++j) acc += v[j] * x[j];
         for (int j = D.wr; j < m; ++j) acc += v[j] * x[j];
         YO[l * 8 + q] = acc;
+      } else {
+        const int c = k - nbv - no;
+        for (int i = 0; i < nkw + D.rk; ++i) acc += EW[i * nkw + c] * x[D.wk0 + i];
+        KB[l * 16 + c] = acc;
       }
     }
     __syncthreads();
@@ -238,10 +246,23 @@ struct GTile {
       const T* xb = X + lb * MP;
       const T* ga = GB + la * 8;
       const T* gbb = GB + lb * 8;
+      const T* ka = KB + la * 16;
+      const T* kbb = KB + lb * 16;
+      const int wk0 = D.wk0, wk1 = D.wk1, rk = D.rk;
+      // the folded line: end blocks, then x on the old interior positions
+      // through the knot window
+      auto fold = [&](const T* x, const T* g, const T* kw, int s) -> T {
+        if (s < cl) return g[s];
+        if (s >= ncr) return g[cl + s - ncr];
+        const int j = s + off;
+        if (j < wk0) return x[j];
+        if (j >= wk1) return x[j + rk];
+        return kw[j - wk0];
+      };
       auto ld = [&](int k, bool, bool, bool) -> cpx<T> {
         if (k >= nr) return cpx<T>{T(0), T(0)};
         const cpx<T> v = gbas ? cpx<T>{xa[off + k], xb[off + k]}
-                              : cpx<T>{fold_at(xa, ga, k, cl, ncr, off), fold_at(xb, gbb, k, cl, ncr, off)};
+                              : cpx<T>{fold(xa, ga, ka, k), fold(xb, gbb, kbb, k)};
         return c_mul(v, TF[k]);
       };
       auto st = [&](int k, cpx<T> v) { buf[fpad<L>(k)] = v; };
@@ -344,11 +365,18 @@ struct GTile {
     } else if (r >= m - rr) {
       const int rr0 = r - (m - rr);
       v = T(0);
-      for (int c = 0; c < cr; ++c) v += AR[rr0 * cr + c] * x[m - rr + c];
-    } else {
+      for (int c = 0; c < cr; ++c) v += AR[rr0 * cr + c] * x[D.mo - rr + c];
+    } else if (r < D.wk0) {
       v = x[r];
+    } else if (r >= D.wk1 + D.rk) {
+      v = x[r - D.rk];
+    } else {   // E on the knot window
+      const int nkw = D.wk1 - D.wk0;
+      const T* EW = D.blob + D.o_ew + (r - D.wk0) * nkw;
+      v = T(0);
+      for (int c = 0; c < nkw; ++c) v += EW[c] * x[D.wk0 + c];
     }
-    if (r < D.wl || r >= D.wr) {
+    if (r < D.wl || r >= D.wr || (r >= D.kw0 && r < D.kw1)) {
       const T* yo = YO + l * 8;
       for (int q = 0; q < D.n_out; ++q) v += Vt[q * m + r] * yo[q];
     }
@@ -364,6 +392,7 @@ __device__ __forceinline__ GTile<T, L, C> gen_tile(char* smem, const GLds& ly, i
   g.F = reinterpret_cast<cpx<T>*>(smem + ly.f);
   g.GB = reinterpret_cast<T*>(smem + ly.gb);
   g.YO = reinterpret_cast<T*>(smem + ly.yo);
+  g.KB = reinterpret_cast<T*>(smem + ly.kb);
   g.LO = reinterpret_cast<const T*>(smem + ly.lo);
   g.SO = reinterpret_cast<const T*>(smem + ly.so);
   g.MP = m | 1;
@@ -492,6 +521,13 @@ GDirDev<T> gen_dir_dev(const Plan& P, const GDir& G) {
   d.mir_b = G.sig2;
   d.wl = f64 ? G.win64[0] : G.win32[0];
   d.wr = f64 ? G.win64[1] : G.win32[1];
+  d.rk = G.rk;
+  d.wk0 = G.rk ? G.wk0 : (1 << 30);
+  d.wk1 = G.rk ? G.wk1 : (1 << 30);
+  d.o_ew = G.o_ew;
+  d.kw0 = f64 ? G.kwin64[0] : G.kwin32[0];
+  d.kw1 = f64 ? G.kwin64[1] : G.kwin32[1];
+  d.mo = G.mo;
   d.gb = G.generic ? 1 : 0;
   d.bl = G.bl;
   d.bu = G.bu;
@@ -506,7 +542,8 @@ hipError_t gen_launch(const Plan& P, int axis, const void* in, void* out, int nr
                       const double* active, int astride, hipStream_t s) {
   using C = GCfg<T, L>;
   const GDir& G = P.dirs[axis - 1];
-  if (G.L != L || G.n_out > 8 || G.cl + G.cr > 8) return hipErrorInvalidValue;
+  if (G.L != L || G.n_out > 8 || G.cl + G.cr > 8 || (G.rk && G.wk1 - G.wk0 > 16))
+    return hipErrorInvalidValue;
   const bool f64 = sizeof(T) == 8;
   GPassArgs<T> a;
   const char* tb = P.d_tables;

@@ -888,11 +888,53 @@ std::vector<double> complement(const std::vector<double>& A0, int rows, int cols
   return W;
 }
 
-int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
+// Knot insertion (Boehm): inserting x into the knot vector T of degree-p
+// B-splines r times; returns E (row-major, new x old B-splines, full bases)
+// with B^old_j = sum_i E[i][j] B^new_i, and T refined in place.
+std::vector<double> insertion_matrix(std::vector<double>& T, int p, double x, int r, int& nbn) {
+  int nb = (int)T.size() - p - 1;
+  std::vector<double> E((size_t)nb * nb, 0.0);
+  for (int j = 0; j < nb; ++j) E[(size_t)j * nb + j] = 1.0;
+  int nb0 = nb;
+  for (int it = 0; it < r; ++it) {
+    const int s = find_span(nb, p, x, T);
+    std::vector<double> E1((size_t)(nb + 1) * nb, 0.0);   // (nb+1) x nb
+    for (int j = 0; j <= nb; ++j) {
+      if (j <= s - p) {
+        E1[(size_t)j * nb + j] = 1.0;
+      } else if (j <= s) {
+        const double a = (x - T[j]) / (T[j + p] - T[j]);
+        E1[(size_t)j * nb + j] = a;
+        E1[(size_t)j * nb + j - 1] = 1.0 - a;
+      } else {
+        E1[(size_t)j * nb + j - 1] = 1.0;
+      }
+    }
+    std::vector<double> En((size_t)(nb + 1) * nb0, 0.0);
+    for (int i = 0; i <= nb; ++i)
+      for (int k = 0; k < nb; ++k) {
+        const double e = E1[(size_t)i * nb + k];
+        if (e != 0.0)
+          for (int j = 0; j < nb0; ++j) En[(size_t)i * nb0 + j] += e * E[(size_t)k * nb0 + j];
+      }
+    E.swap(En);
+    T.insert(T.begin() + s + 1, x);
+    ++nb;
+  }
+  nbn = nb;
+  return E;
+}
+
+int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err, int kk = 0, int mult = 1) {
   G.n = n; G.p = p; G.dlo = dlo; G.dhi = dhi;
-  const int nb = n + p, bw = 2 * p + 1;
+  const int r = (kk > 0 && mult > 1) ? mult - 1 : 0;
+  G.kk = r ? kk : 0;
+  G.mult = r ? mult : 1;
+  G.rk = r;
+  const int nb = n + p + r, bw = 2 * p + 1;
   const int m = nb - dlo - dhi;
   G.m = m;
+  G.mo = m - r;
   // eq:reg_space_dim
   if ((p % 2) && dlo && dhi) G.n_reg = n - 1;
   else if ((p % 2) && !dlo && !dhi) G.n_reg = n + 1;
@@ -901,15 +943,24 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
   G.L = 2 * n;
   const double h = 1.0 / n;
 
-  // knots, 1-D matrices of the full basis (Sections 2, 3), reduction
+  // knots (the breakpoint kk / n repeated mult times: Remark
+  // rmk:reduced_regularity), 1-D matrices of the full basis (Sections 2, 3),
+  // reduction
   std::vector<double> U(n + 2 * p + 1);
   for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
   for (int k = 1; k < n; ++k) U[p + k] = (double)k / n;
+  const std::vector<double> U0 = U;   // the maximally smooth knots
+  std::vector<double> Efull;          // knot insertion, full bases
+  if (r) {
+    int nbn = 0;
+    Efull = insertion_matrix(U, p, (double)kk / n, r, nbn);
+    if (nbn != nb) { err = "knot insertion size mismatch"; return IFFD_E_INVAL; }
+  }
   std::vector<double> gx, gw, val, der;
   gauss_legendre(p + 1, gx, gw);
   std::vector<double> Kf((size_t)nb * bw, 0.0), Mf((size_t)nb * bw, 0.0);
   for (int e = 0; e < n; ++e) {
-    const int s = p + e;
+    const int s = p + e + (r && e >= kk ? r : 0);
     for (int g = 0; g < p + 1; ++g) {
       const double x = e * h + 0.5 * h * (gx[g] + 1.0), wq = 0.5 * h * gw[g];
       basis_and_derivative(s, x, p, U, val, der);
@@ -935,10 +986,10 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
   // left end of its type: B_j(1 - x) = B_{nb-1-j}(x), Bt_k(1 - x) = Bt_{n+dp-k}(x)
   std::vector<double> Bl, Br;
   int rows, cols;
-  int rc = end_block(n, p, dlo, U, Bl, rows, cols, err);
+  int rc = end_block(n, p, dlo, U0, Bl, rows, cols, err);
   if (rc != IFFD_OK) return rc;
   G.rl = rows; G.cl = cols; G.AL = Bl;
-  rc = end_block(n, p, dhi, U, Br, rows, cols, err);
+  rc = end_block(n, p, dhi, U0, Br, rows, cols, err);
   if (rc != IFFD_OK) return rc;
   G.rr = rows; G.cr = cols;
   G.AR.assign((size_t)rows * cols, 0.0);
@@ -946,17 +997,58 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
     for (int c = 0; c < cols; ++c)
       G.AR[(size_t)(rows - 1 - r) * cols + (cols - 1 - c)] = Br[(size_t)r * cols + c];
   const int nint = G.n_reg - G.cl - G.cr;
-  if (nint < 0 || nint != m - G.rl - G.rr) { err = "special basis does not fit the space"; return IFFD_E_INVAL; }
+  const int mo = G.mo;
+  if (nint < 0 || nint != mo - G.rl - G.rr) { err = "special basis does not fit the space"; return IFFD_E_INVAL; }
+  // the knot window of E on the kept bases: old kept column j is new kept
+  // column j left of the window, j + r right of it
+  if (r) {
+    const int nb0 = nb - r;
+    auto Ek = [&](int i, int j) { return Efull[(size_t)(i + dlo) * nb0 + (j + dlo)]; };
+    int lo = mo, hi = -1;
+    for (int j = 0; j < mo; ++j)
+      for (int i = 0; i < m; ++i) {
+        const double want = (i == j && j < mo) ? 1.0 : 0.0;
+        const double shifted = (i == j + r) ? 1.0 : 0.0;
+        const double e = Ek(i, j);
+        if (e != want && e != shifted) { lo = std::min(lo, j); hi = std::max(hi, j); }
+      }
+    if (hi < lo) { err = "knot insertion without a window"; return IFFD_E_INVAL; }
+    G.wk0 = lo;
+    G.wk1 = hi + 1;
+    for (int j = 0; j < mo; ++j)
+      for (int i = 0; i < m; ++i) {
+        const double e = Ek(i, j);
+        double want;
+        if (j < G.wk0) want = i == j ? 1.0 : 0.0;
+        else if (j >= G.wk1) want = i == j + r ? 1.0 : 0.0;
+        else want = (i >= G.wk0 && i < G.wk1 + r) ? e : 0.0;
+        if (std::fabs(e - want) > 1e-14) { err = "knot insertion outside its window"; return IFFD_E_INVAL; }
+      }
+    if (G.wk0 < G.rl + p || G.wk1 > mo - G.rr - p) {
+      err = "the repeated knot must lie at least 2p elements from both ends";
+      return IFFD_E_INVAL;
+    }
+    const int wr_ = G.wk1 - G.wk0 + r, wc_ = G.wk1 - G.wk0;
+    G.EW.assign((size_t)wr_ * wc_, 0.0);
+    for (int i = 0; i < wr_; ++i)
+      for (int c = 0; c < wc_; ++c) G.EW[(size_t)i * wc_ + c] = Ek(G.wk0 + i, G.wk0 + c);
+  } else {
+    G.wk0 = G.wk1 = 0;
+    G.EW.clear();
+  }
 
   // Table 1 with 0-based indices: x_s = (s + sig) h, alpha_t = (t + tau) pi
   G.sig2 = (p % 2) ? (dlo ? 2 : 0) : 1;
   G.tau2 = (dlo && dhi) ? 2 : ((dlo || dhi) ? 1 : 0);
   G.beta = dlo ? 0 : 1;
 
-  // outlier basis V_out = M^{-1} [W_L; 0; W_R] (Section 4)
+  // outlier basis V_out = M^{-1} [W_L; W_K; W_R] (Section 4): W_K spans the
+  // complement of the knot window's columns of E V_reg (reduced regularity)
   const std::vector<double> WL = complement(G.AL, G.rl, G.cl), WR = complement(G.AR, G.rr, G.cr);
   const int nl = G.rl - G.cl, nr_ = G.rr - G.cr;
-  if (nl + nr_ != G.n_out) { err = "outlier dimension mismatch"; return IFFD_E_INVAL; }
+  const int wrows = r ? G.wk1 - G.wk0 + r : 0, wcols = r ? G.wk1 - G.wk0 : 0;
+  const std::vector<double> WK = r ? complement(G.EW, wrows, wcols) : std::vector<double>();
+  if (nl + r + nr_ != G.n_out) { err = "outlier dimension mismatch"; return IFFD_E_INVAL; }
   std::vector<double> Lb((size_t)m * (p + 1), 0.0);
   auto Lat = [&](int i, int j) -> double& { return Lb[(size_t)i * (p + 1) + (j - i + p)]; };
   for (int i = 0; i < m; ++i)
@@ -974,8 +1066,9 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
   G.Vout.assign((size_t)no * m, 0.0);
   for (int c = 0; c < no; ++c) {
     std::vector<double> b(m, 0.0);
-    if (c < nl) for (int r = 0; r < G.rl; ++r) b[r] = WL[(size_t)r * nl + c];
-    else for (int r = 0; r < G.rr; ++r) b[m - G.rr + r] = WR[(size_t)r * nr_ + (c - nl)];
+    if (c < nl) for (int i = 0; i < G.rl; ++i) b[i] = WL[(size_t)i * nl + c];
+    else if (c < nl + r) for (int i = 0; i < wrows; ++i) b[G.wk0 + i] = WK[(size_t)i * r + (c - nl)];
+    else for (int i = 0; i < G.rr; ++i) b[m - G.rr + i] = WR[(size_t)i * nr_ + (c - nl - r)];
     for (int i = 0; i < m; ++i) {
       double sum = b[i];
       for (int k = std::max(0, i - p); k < i; ++k) sum -= Lat(i, k) * b[k];
@@ -1036,24 +1129,32 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err) {
   G.lam.assign(m, 0.0);
   G.s.assign(m, 1.0);
   G.Dt.assign(nrg, 0.0);
-  std::vector<double> u(nrg), v(m), mv(m);
+  std::vector<double> u(nrg), vo(mo), v(m), mv(m);
   for (int t = 0; t < nrg; ++t) {
     for (int s = 0; s < nrg; ++s) {
       const long long a = ((long long)(2 * s + G.sig2) * (2 * t + G.tau2) + 2LL * n * G.beta) % per;
       u[s] = sintab[a];
     }
-    std::fill(v.begin(), v.end(), 0.0);
-    for (int r = 0; r < G.rl; ++r) {
+    std::fill(vo.begin(), vo.end(), 0.0);
+    for (int i = 0; i < G.rl; ++i) {
       double acc = 0;
-      for (int c = 0; c < G.cl; ++c) acc += G.AL[(size_t)r * G.cl + c] * u[c];
-      v[r] = acc;
+      for (int c = 0; c < G.cl; ++c) acc += G.AL[(size_t)i * G.cl + c] * u[c];
+      vo[i] = acc;
     }
-    for (int i = 0; i < nint; ++i) v[G.rl + i] = u[G.cl + i];
-    for (int r = 0; r < G.rr; ++r) {
+    for (int i = 0; i < nint; ++i) vo[G.rl + i] = u[G.cl + i];
+    for (int i = 0; i < G.rr; ++i) {
       double acc = 0;
-      for (int c = 0; c < G.cr; ++c) acc += G.AR[(size_t)r * G.cr + c] * u[nrg - G.cr + c];
-      v[m - G.rr + r] = acc;
+      for (int c = 0; c < G.cr; ++c) acc += G.AR[(size_t)i * G.cr + c] * u[nrg - G.cr + c];
+      vo[mo - G.rr + i] = acc;
     }
+    // v = E vo on the reduced space's B-splines (the same function)
+    for (int i = 0; i < m; ++i) v[i] = 0.0;
+    for (int j = 0; j < mo; ++j) {
+      if (!r || j < G.wk0) v[j] += vo[j];
+      else if (j >= G.wk1) v[j + r] += vo[j];
+    }
+    for (int i = 0; i < wrows; ++i)
+      for (int c = 0; c < wcols; ++c) v[G.wk0 + i] += G.EW[(size_t)i * wcols + c] * vo[G.wk0 + c];
     band_mv(G.Mb, v.data(), mv.data());
     double sm = 0;
     for (int i = 0; i < m; ++i) sm += v[i] * mv[i];
@@ -1259,6 +1360,7 @@ void compute_layout_general(Plan& P) {
     G.o_mb = o;  o += G.m * bw;
     G.o_lb = o;  o += G.generic ? G.n_reg * G.bl : 0;
     G.o_ub = o;  o += G.generic ? G.n_reg * (G.bu + 1) : 0;
+    G.o_ew = o;  o += (int)G.EW.size();
     G.len = o + (o & 1);
     G.blob64 = take((size_t)8 * G.len);
     G.blob32 = take((size_t)4 * G.len);
@@ -1332,7 +1434,11 @@ int set_plan_basis(Plan& P, int basis, std::string& err) {
   GDir dirs[3];
   for (int k = 0; k < P.d; ++k) {
     const GDir& G = P.dirs[k];
-    int rc = build_dir(dirs[k], G.n, G.p, G.dlo, G.dhi, err);
+    if (basis == IFFD_BASIS_GENERIC && G.rk) {
+      err = "the generic basis is not built for a repeated knot";
+      return IFFD_E_UNSUPPORTED;
+    }
+    int rc = build_dir(dirs[k], G.n, G.p, G.dlo, G.dhi, err, G.kk, G.mult);
     if (rc == IFFD_OK && basis == IFFD_BASIS_GENERIC) rc = make_generic(dirs[k], err);
     if (rc != IFFD_OK) return rc;
   }
@@ -1349,6 +1455,39 @@ int set_plan_basis(Plan& P, int basis, std::string& err) {
   return IFFD_OK;
 }
 
+int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err) {
+  if (!P.gen) { err = "a repeated knot needs a general plan (iffd_plan_create_general)"; return IFFD_E_UNSUPPORTED; }
+  if (direction < 1 || direction > P.d) { err = "direction out of range"; return IFFD_E_INVAL; }
+  GDir& G = P.dirs[direction - 1];
+  if (mult < 1 || mult > G.p) { err = "multiplicity must be in 1..p"; return IFFD_E_INVAL; }
+  if (mult > 1 && (k < 1 || k >= G.n)) { err = "the knot k / n must be an interior breakpoint"; return IFFD_E_INVAL; }
+  if (P.basis == IFFD_BASIS_GENERIC && mult > 1) {
+    err = "the generic basis is not built for a repeated knot";
+    return IFFD_E_UNSUPPORTED;
+  }
+  if (P.geo.kind) {
+    err = "the operator of a mapped domain assumes maximal smoothness (set the knot first)";
+    return IFFD_E_UNSUPPORTED;
+  }
+  GDir nd;
+  int rc = build_dir(nd, G.n, G.p, G.dlo, G.dhi, err, mult > 1 ? k : 0, mult);
+  if (rc != IFFD_OK) return rc;
+  if (nd.n_out > 8) { err = "at most 8 outlier functions per direction"; return IFFD_E_UNSUPPORTED; }
+  int64_t N = 1;
+  for (int j = 0; j < P.d; ++j) N *= (j == direction - 1 ? nd.m : P.dirs[j].m);
+  if (N * (int64_t)P.max_rhs >= (int64_t(1) << 31) || N * 8 >= (int64_t(1) << 31)) {
+    err = "problem too large for 32-bit indexing";
+    return IFFD_E_UNSUPPORTED;
+  }
+  G = nd;
+  P.N = N;
+  const GDir& G1 = P.dirs[0];
+  P.m = G1.m; P.n_reg = G1.n_reg; P.n_out = G1.n_out;
+  P.lay = TableLayout{};
+  compute_layout_general(P);
+  return IFFD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Geometry-mapped system matrix: per-direction element tables
 // ---------------------------------------------------------------------------
@@ -1362,6 +1501,9 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
   if (P.d != 3) { err = "a mapped domain needs d = 3"; return IFFD_E_UNSUPPORTED; }
   if (P.coef_a != 0.0) { err = "a mapped domain replaces coef_a; create the plan with coef_a = 0"; return IFFD_E_INVAL; }
   if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
+  if (P.gen)
+    for (int k = 0; k < P.d; ++k)
+      if (P.dirs[k].rk) { err = "the operator of a mapped domain assumes maximal smoothness"; return IFFD_E_UNSUPPORTED; }
   GeoPlan G;
   G.kind = kind;
   G.base_total = P.geo.kind == 0 ? P.lay.total : P.geo.base_total;

@@ -75,6 +75,17 @@ struct GDir {
   int bl = 0, bu = 0;
   std::vector<double> LB, UB;
   int o_lb = 0, o_ub = 0;
+  // reduced regularity (eq:reg_space2): the breakpoint kk / n repeated mult
+  // times, rk = mult - 1 extra B-splines (m counts them, mo = m - rk does
+  // not).  The knot insertion E (new kept B-splines x old ones) is the
+  // identity on the old columns left of [wk0, wk1) and a shift by rk right of
+  // them; EW holds its rows [wk0, wk1 + rk) x columns [wk0, wk1).  The rk
+  // outlier vectors it adds are concentrated around the knot: outlier window
+  // kwin32 / kwin64 = [kw0, kw1) besides the two end windows.
+  int kk = 0, mult = 1, rk = 0, mo = 0, wk0 = 0, wk1 = 0;
+  std::vector<double> EW;
+  int o_ew = 0;
+  int kwin32[2] = {0, 0}, kwin64[2] = {0, 0};
   int len = 0;
   size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
   size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)
@@ -155,6 +166,7 @@ int build_plan_general(Plan& P, int d, const int* n, const int* p, const int* di
                        const iffd_opts* opts, std::string& err);
 int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& err);
 int set_plan_basis(Plan& P, int basis, std::string& err);
+int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err);
 void compute_layout(Plan& P);
 StateLayout state_layout(const Plan& P, int nslots);
 size_t apply_ws_bytes(const Plan& P, int nrhs);

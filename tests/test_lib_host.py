@@ -459,3 +459,56 @@ def test_basis_rules():
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
     assert info.matvec_ws_bytes == 8 * (16 * 24 * 32) * (4 * 3 * 5)
     I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("ends", GEN_ENDS)
+@pytest.mark.parametrize("p,mult", [(2, 2), (3, 2), (3, 3), (4, 4), (5, 3), (6, 3)])
+def test_repeated_knot_host_tables_match_oracle(p, mult, ends):
+    """iffd_plan_set_knot (reduced regularity, eq:reg_space2) against
+    oracle.reduced: m and n_out grow by mult - 1 (the remark's count), K and M
+    of the reduced space, the regular eigenvalues and Dt unchanged (S^reg and
+    its functions do not change)."""
+    from oracle import reduced as R
+    n = 32
+    k = 13
+    D = {e for e, f in zip((0, 1), ends) if f}
+    rc, h = I.create_general(2, [n, 16], [p, 2], [ends, (1, 1)])
+    assert rc == 0
+    lam0 = read_dir(h, 1, 0, n + p)
+    nr0 = I.query_dirs(h, 2)[0]["n_reg"]
+    Dt0 = read_dir(h, 1, 1, nr0)
+    assert I.lib.iffd_plan_set_knot(h, 1, k, mult) == 0, I.lib.iffd_last_error()
+    di = I.query_dirs(h, 2)[0]
+    m, nr, no = R.dims(n, p, D, mult)
+    assert (di["m"], di["n_reg"], di["n_out"]) == (m, nr, no)
+    K, M = R.assemble(n, p, D, k, mult)
+    bw = 2 * p + 1
+    assert np.abs(band_dense(read_dir(h, 1, 2, m * bw), m, p) - K).max() < 1e-10 * np.abs(K).max()
+    assert np.abs(band_dense(read_dir(h, 1, 3, m * bw), m, p) - M).max() < 1e-13
+    assert np.abs(read_dir(h, 1, 0, m)[:nr] - lam0[:nr]).max() <= 1e-14 * lam0[:nr].max()
+    assert np.abs(read_dir(h, 1, 1, nr) - Dt0).max() <= 1e-12 * Dt0.max()
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.N == m * I.query_dirs(h, 2)[1]["m"]
+    I.lib.iffd_plan_destroy(h)
+
+
+def test_repeated_knot_rules():
+    rc, h = host_plan(3, 32, 3)
+    assert rc == 0
+    assert I.lib.iffd_plan_set_knot(h, 1, 16, 2) == I.E_UNSUPPORTED   # uniform plan
+    I.lib.iffd_plan_destroy(h)
+    rc, h = I.create_general(3, [32, 24, 32], [3, 2, 4], [(1, 0), (0, 1), (0, 0)])
+    assert rc == 0
+    assert I.lib.iffd_plan_set_knot(h, 4, 16, 2) == I.E_INVAL        # direction
+    assert I.lib.iffd_plan_set_knot(h, 1, 16, 4) == I.E_INVAL        # mult > p
+    assert I.lib.iffd_plan_set_knot(h, 1, 32, 2) == I.E_INVAL        # not interior
+    assert I.lib.iffd_plan_set_knot(h, 1, 3, 3) == I.E_INVAL         # too close to an end
+    assert I.lib.iffd_plan_set_knot(h, 1, 16, 3) == 0
+    assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1 + 2
+    assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == I.E_UNSUPPORTED
+    par = (ctypes.c_double * 3)(1.0, 2.0, 1.0)
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par, 3) == I.E_UNSUPPORTED
+    assert I.lib.iffd_plan_set_knot(h, 1, 16, 1) == 0                # back to maximal smoothness
+    assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1
+    I.lib.iffd_plan_destroy(h)
