@@ -284,11 +284,32 @@ def mixed_bc(torch, iffd, ps=(3,), n=256, steps=20, solves=10, prec="f32"):
         pl.apply(f, out=z)
         gdiff = float(((zg - z).norm() / z.norm()).item())
         del plg, zg
+        # reduced regularity: a C^0 plane x_1 = 1/2 (the breakpoint n/2 of
+        # direction 1 repeated p times)
+        plk = iffd.Plan(3, [n] * 3, [p] * 3, precision=prec,
+                        dirichlet=workloads.MIXED_CUBE_DIRICHLET, knots={1: (n // 2, p)})
+        fk = torch.from_numpy(workloads.uniform_tensor(plk.shape, seed=1)).cuda()
+        zk = torch.empty_like(fk)
+        for _ in range(3):
+            plk.apply(fk, out=zk)
+        torch.cuda.synchronize()
+        torch.cuda._sleep(int(cpm * 5.0))
+        ag.record()
+        for _ in range(steps):
+            plk.apply(fk, out=zk)
+        bg.record()
+        torch.cuda.synchronize()
+        msk = ag.elapsed_time(bg) / steps
+        latk, stk = time_solves(torch, plk, fk, solves)
+        del plk, fk, zk
         rows.append({
             "n": n, "p": p, "shape": list(pl.shape), "dofs": N, "dtype": prec,
             "generic_basis": {"ms_per_apply": round(msg, 5),
                               "slowdown_vs_special": round(msg / ms, 3),
                               "rel_diff_vs_special": gdiff},
+            "c0_plane": {"ms_per_apply": round(msk, 5),
+                         "pcg_p50_ms": round(pct(latk, 0.5), 3),
+                         "iterations": stk[0]["iterations"]},
             "gdof_s": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 5),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
