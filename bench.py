@@ -450,6 +450,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
+    ap.add_argument("--serve-iters", type=int, default=2,
+                    help="PCG iterations per shape and round of the solve server")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, no collectives); "
@@ -499,7 +501,7 @@ def main():
         return
     if args.serve:
         res = serving(torch, args.serve_requests, args.serve_warmup,
-                      [float(x) for x in args.serve_fracs.split(",")])
+                      [float(x) for x in args.serve_fracs.split(",")], iters=args.serve_iters)
         print(json.dumps({"metric": "PCG solves/s and p50/p99 latency, serving stream",
                           "unit": "solves/s", "value": res["saturation"]["solves_per_s"],
                           "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
@@ -799,7 +801,8 @@ def main():
                              "iterations": cfst[0]["iterations"]},
                 "iffd_solve_speedup": round(statistics.mean(cflat) / statistics.mean(clat), 3)}
             out["serving"] = serving(torch, args.serve_requests, args.serve_warmup,
-                                     [float(x) for x in args.serve_fracs.split(",")])
+                                     [float(x) for x in args.serve_fracs.split(",")],
+                                     iters=args.serve_iters)
             # ---- the mixed-boundary cube of Table 3 through a general plan ------
             out["mixed_bc"] = mixed_bc(torch, iffd, ps=(3,), n=256, steps=min(args.steps, 50),
                                        solves=max(5, args.solves // 3), prec=args.precision)[0]
