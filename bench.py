@@ -319,7 +319,11 @@ def mixed_bc(torch, iffd, ps=(3,), n=256, steps=20, solves=10, prec="f32"):
                          "apply_alg_GBs": round(sum(pb) / (ms * 1e-3) / 1e9, 1)},
             "pcg": {"solves_per_s": round(1e3 / statistics.mean(lat), 2),
                     "p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
-                    "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"]}})
+                    "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"]},
+            "dense_fd": {"apply_us": round(apfd * 1e3, 2),
+                         "pcg_p50_ms": round(pct(latfd, 0.5), 3),
+                         "iterations": stfd[0]["iterations"],
+                         "iffd_solve_speedup": round(statistics.mean(latfd) / statistics.mean(lat), 3)}})
         del pl, f, z
         torch.cuda.empty_cache()
     return rows
@@ -363,6 +367,13 @@ def annulus(torch, iffd, ps=(3,), n=64, steps=20, solves=5, prec="f32"):
         mv = timed(lambda: pl.matvec(f, out=z))
         ap = timed(lambda: pl.apply(f, out=z))
         lat, st = time_solves(torch, pl, f, solves)
+        # dense FD (exact eigendecompositions) on the same system
+        pfd = iffd.Plan(3, [n] * 3, [p] * 3, method="dense", precision=prec,
+                        dirichlet=workloads.ANNULUS_DIRICHLET,
+                        geometry=("annulus", workloads.ANNULUS_PARAMS))
+        apfd = timed(lambda: pfd.apply(f, out=z))
+        latfd, stfd = time_solves(torch, pfd, f, solves)
+        del pfd
         flops = n ** 3 * geo_flops_per_element(p)
         ach = flops / (mv * 1e-3) / 1e12
         rows.append({
@@ -374,7 +385,11 @@ def annulus(torch, iffd, ps=(3,), n=64, steps=20, solves=5, prec="f32"):
                          "alg_flops_per_launch": flops},
             "pcg": {"solves_per_s": round(1e3 / statistics.mean(lat), 2),
                     "p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
-                    "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"]}})
+                    "iterations": st[0]["iterations"], "relres_true": st[0]["relres_true"]},
+            "dense_fd": {"apply_us": round(apfd * 1e3, 2),
+                         "pcg_p50_ms": round(pct(latfd, 0.5), 3),
+                         "iterations": stfd[0]["iterations"],
+                         "iffd_solve_speedup": round(statistics.mean(latfd) / statistics.mean(lat), 3)}})
         del pl, f, z
         torch.cuda.empty_cache()
     return rows

@@ -214,10 +214,13 @@ typedef struct {
  * {2,3}; per direction 1 <= p <= 8, n > p, n = 2^a or 3*2^a with
  * 8 <= n <= 256 (IFFD_E_UNSUPPORTED otherwise); at least one Dirichlet end
  * (Neumann conditions on every face make the operator singular: the
- * constants; IFFD_E_UNSUPPORTED); opts: method IFFD_METHOD_FFT, apply_prec
- * IFFD_PREC_F32 or IFFD_PREC_F64, coef_a = 0 (IFFD_E_UNSUPPORTED or
- * IFFD_E_INVAL otherwise).  iffd_kron_matvec and the PCG use the operator
- * Ahat = sum_k M_d x .. x K_k x .. x M_1 with each direction's own K, M. */
+ * constants; IFFD_E_UNSUPPORTED); opts: method IFFD_METHOD_FFT or
+ * IFFD_METHOD_DENSE_FD (every direction's own dense eigendecomposition of
+ * (K_k, M_k), the mode products on the matrix cores and the Kronecker-sum
+ * scaling in a kernel of its own), apply_prec IFFD_PREC_F32 or IFFD_PREC_F64,
+ * coef_a = 0 (IFFD_E_UNSUPPORTED or IFFD_E_INVAL otherwise).
+ * iffd_kron_matvec and the PCG use the operator Ahat = sum_k M_d x .. x K_k
+ * x .. x M_1 with each direction's own K, M. */
 int iffd_plan_create_general(iffd_plan** out, int d, const int* n, const int* p,
                              const int* dirichlet, const iffd_opts* opts);
 

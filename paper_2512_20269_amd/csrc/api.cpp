@@ -210,6 +210,17 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
       }
     put<double>(buf, G.blob64, blob);
     put<float>(buf, G.blob32, blob);
+    if (P.method == IFFD_METHOD_DENSE_FD) {
+      std::vector<double> QT((size_t)G.m * G.m);
+      for (int i = 0; i < G.m; ++i)
+        for (int j = 0; j < G.m; ++j) QT[(size_t)j * G.m + i] = G.Qfd[(size_t)i * G.m + j];
+      put<double>(buf, G.fq64, G.Qfd);
+      put<double>(buf, G.fqt64, QT);
+      put<double>(buf, G.flam64, G.lamfd);
+      put<float>(buf, G.fq32, G.Qfd);
+      put<float>(buf, G.fqt32, QT);
+      put<float>(buf, G.flam32, G.lamfd);
+    }
     put<double>(buf, G.ao64, G.Ao);
     put<double>(buf, G.bo64, G.Bo);
     put<double>(buf, G.vout64, G.Vout);
@@ -333,7 +344,9 @@ int iffd_plan_query_dirs(const iffd_plan* plan, iffd_dir_info* h_out, int count)
     if (P.gen) {
       const GDir& G = P.dirs[k];
       I.n = G.n; I.p = G.p; I.dirichlet_lo = G.dlo; I.dirichlet_hi = G.dhi;
-      I.m = G.m; I.n_reg = G.n_reg; I.n_out = G.n_out; I.fft_len = G.L;
+      const bool fft = P.method == IFFD_METHOD_FFT;
+      I.m = G.m; I.n_reg = fft ? G.n_reg : G.m; I.n_out = fft ? G.n_out : 0;
+      I.fft_len = fft ? G.L : 0;
     } else {
       const bool fft = P.method == IFFD_METHOD_FFT;
       I.n = P.n; I.p = P.p; I.dirichlet_lo = 1; I.dirichlet_hi = 1;
@@ -537,7 +550,7 @@ int iffd_plan_read_dir(const iffd_plan* plan, int direction, int what, double* h
   const GDir& G = P.dirs[direction - 1];
   const std::vector<double>* v = nullptr;
   switch (what) {
-    case 0: v = &G.lam; break;
+    case 0: v = P.method == IFFD_METHOD_DENSE_FD ? &G.lamfd : &G.lam; break;
     case 1: v = &G.Dt; break;
     case 2: case 7: v = &G.Kb; break;
     case 3: v = &G.Mb; break;

@@ -552,9 +552,103 @@ static hipError_t fd_apply_f16(const Plan& P, const double* r, double* z, int nr
   return mode_product16<TQ, float, double>(P, 1, false, cur, z, x16, ls, nrhs, 0, a, as, s);
 }
 
+// ---- general plans: every direction its own m_k, Q_k and eigenvalues --------
+
+// one mode product of a general plan along `axis` (1-based): the direction's
+// own Q (or Q^T), lines of length m_k with stride S = m_1 .. m_{k-1}
+template <typename TI, typename TO, typename T>
+static hipError_t mode_product_gen(const Plan& P, int axis, bool fwd, const TI* in, TO* out,
+                                   int nrhs, const double* act, int as, hipStream_t s) {
+  const GDir& G = P.dirs[axis - 1];
+  const bool f64 = sizeof(T) == 8;
+  const T* Q = (const T*)(P.d_tables + (f64 ? G.fq64 : G.fq32));
+  const T* QT = (const T*)(P.d_tables + (f64 ? G.fqt64 : G.fqt32));
+  const int m = G.m;
+  const long long N = P.N;
+  GemmArgs g{};
+  g.active = act;
+  g.astride = as;
+  g.scale_mode = 0;
+  g.m = m;
+  if (axis == 1) {
+    g.M = (int)(N / m); g.N = m; g.K = m;
+    g.lda = m; g.ldb = m; g.ldc = m;
+    g.sA = N; g.sB = 0; g.sC = N;
+    g.batch_per_rhs = 1;
+    return gemm<TI, T, TO, T>(in, fwd ? Q : QT, out, g, nrhs, s);
+  }
+  int S = 1;
+  for (int k = 0; k < axis - 1; ++k) S *= P.dirs[k].m;
+  const int outer = (int)(N / ((long long)S * m));
+  g.M = m; g.N = S; g.K = m;
+  g.lda = m; g.ldb = S; g.ldc = S;
+  g.sA = 0; g.sB = (long long)S * m; g.sC = (long long)S * m;
+  g.batch_per_rhs = outer;
+  return gemm<T, TI, TO, T>(fwd ? QT : Q, in, out, g, outer * nrhs, s);
+}
+
+// x[i1 + m1 (i2 + m2 i3)] /= l1[i1] + l2[i2] (+ l3[i3]): the Kronecker sum of
+// the directions' eigenvalues (eq:exact_diagonalization)
+template <typename T>
+__global__ void __launch_bounds__(256)
+fd_scale_gen(T* __restrict__ x, const T* __restrict__ l1, const T* __restrict__ l2,
+             const T* __restrict__ l3, int m1, int m2, int N, int nrhs,
+             const double* __restrict__ active, int astride) {
+  const long long tot = (long long)N * nrhs;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    const int rhs = (int)(e / N), i = (int)(e - (long long)rhs * N);
+    if (active && active[(size_t)rhs * astride] == 0.0) continue;
+    const int i1 = i % m1, rest = i / m1;
+    const int i2 = rest % m2, i3 = rest / m2;
+    T den = l1[i1] + l2[i2];
+    if (l3) den += l3[i3];
+    x[e] /= den;
+  }
+}
+
+template <typename T>
+static hipError_t fd_apply_gen(const Plan& P, const double* r, double* z, int nrhs, void* ws,
+                               const double* a, int as, hipStream_t s) {
+  const int d = P.d;
+  const size_t N = (size_t)P.N * nrhs;
+  T* t1 = (T*)ws;
+  T* t2 = sizeof(T) == 8 ? (T*)z : t1 + N;  // FP64: ping-pong with z
+  hipError_t e = mode_product_gen<double, T, T>(P, 1, true, r, t1, nrhs, a, as, s);
+  if (e != hipSuccess) return e;
+  T* cur = t1;
+  T* nxt = t2;
+  for (int k = 2; k <= d; ++k) {
+    e = mode_product_gen<T, T, T>(P, k, true, cur, nxt, nrhs, a, as, s);
+    if (e != hipSuccess) return e;
+    std::swap(cur, nxt);
+  }
+  {
+    const bool f64 = sizeof(T) == 8;
+    auto lam = [&](int k) { return (const T*)(P.d_tables + (f64 ? P.dirs[k].flam64 : P.dirs[k].flam32)); };
+    const long long tot = (long long)N;
+    const unsigned nb = (unsigned)std::min<long long>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(fd_scale_gen<T>, dim3(nb), dim3(256), 0, s, cur, lam(0), lam(1),
+                       d == 3 ? lam(2) : (const T*)nullptr, P.dirs[0].m, P.dirs[1].m, (int)P.N,
+                       nrhs, a, as);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int k = d; k >= 2; --k) {
+    e = mode_product_gen<T, T, T>(P, k, false, cur, nxt, nrhs, a, as, s);
+    if (e != hipSuccess) return e;
+    std::swap(cur, nxt);
+  }
+  return mode_product_gen<T, double, T>(P, 1, false, cur, z, nrhs, a, as, s);
+}
+
 hipError_t launch_fd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                            const double* active, int astride, hipStream_t s) {
   if (P.method != IFFD_METHOD_DENSE_FD) return hipErrorInvalidValue;
+  if (P.gen) {
+    if (P.prec == IFFD_PREC_F64) return fd_apply_gen<double>(P, r, z, nrhs, ws, active, astride, s);
+    if (P.prec == IFFD_PREC_F32) return fd_apply_gen<float>(P, r, z, nrhs, ws, active, astride, s);
+    return hipErrorInvalidValue;
+  }
   if (P.prec == IFFD_PREC_F16S) return fd_apply_f16<_Float16>(P, r, z, nrhs, ws, active, astride, s);
   if (P.prec == IFFD_PREC_BF16S) return fd_apply_f16<__bf16>(P, r, z, nrhs, ws, active, astride, s);
   if (P.prec == IFFD_PREC_F64) return fd_apply_t<double>(P, r, z, nrhs, ws, active, astride, s);

@@ -371,6 +371,74 @@ StateLayout state_layout(const Plan& P, int nslots) {
   return s;
 }
 
+// Full generalized eigendecomposition of a banded pencil (K, M) (rows of
+// 2p+1 band entries, m x m): M = L L^T (Cholesky), C = L^{-1} K L^{-T}
+// (cyclic Jacobi), Q = L^{-T} Z, eigenpairs in ascending order; Q^T M Q = I,
+// Q^T K Q = diag(w) (eq:eigendecomposition, the dense FD of Section 3).
+static int dense_pencil(const std::vector<double>& Kb, const std::vector<double>& Mb, int m, int p,
+                        std::vector<double>& Qfd, std::vector<double>& lamfd, std::string& err) {
+  const int bw = 2 * p + 1;
+  // full generalized eigendecomposition of (K, M): M = L L^T, C = L^-1 K L^-T
+  std::vector<double> L((size_t)m * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    for (int i = j; i < std::min(m, j + p + 1); ++i) {
+      double sum = Mb[(size_t)i * bw + (j - i + p)];
+      for (int k = std::max(0, i - p); k < j; ++k) sum -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      if (i == j) {
+        if (!(sum > 0)) { err = "mass matrix not SPD"; return IFFD_E_INVAL; }
+        L[(size_t)j * m + j] = std::sqrt(sum);
+      } else {
+        L[(size_t)i * m + j] = sum / L[(size_t)j * m + j];
+      }
+    }
+  }
+  // X = L^{-1} K (dense), then C = X L^{-T} = (L^{-1} X^T)^T
+  std::vector<double> Kd((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int o = 0; o < bw; ++o) {
+      int j = i + o - p;
+      if (j >= 0 && j < m) Kd[(size_t)i * m + j] = Kb[(size_t)i * bw + o];
+    }
+  auto lower_solve_cols = [&](std::vector<double>& B) {  // B <- L^{-1} B (m x m)
+    for (int c = 0; c < m; ++c)
+      for (int i = 0; i < m; ++i) {
+        double sum = B[(size_t)i * m + c];
+        for (int k = std::max(0, i - p); k < i; ++k) sum -= L[(size_t)i * m + k] * B[(size_t)k * m + c];
+        B[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
+      }
+  };
+  lower_solve_cols(Kd);
+  std::vector<double> T((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) T[(size_t)i * m + j] = Kd[(size_t)j * m + i];
+  lower_solve_cols(T);
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j) {
+      double a = 0.5 * (T[(size_t)i * m + j] + T[(size_t)j * m + i]);
+      T[(size_t)i * m + j] = T[(size_t)j * m + i] = a;
+    }
+  std::vector<double> Z, w;
+  jacobi(m, T, Z, w);
+  // Q = L^{-T} Z (back substitution on each column)
+  std::vector<double> Q = Z;
+  for (int c = 0; c < m; ++c)
+    for (int i = m - 1; i >= 0; --i) {
+      double sum = Q[(size_t)i * m + c];
+      for (int k = i + 1; k < std::min(m, i + p + 1); ++k) sum -= L[(size_t)k * m + i] * Q[(size_t)k * m + c];
+      Q[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
+    }
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
+  Qfd.assign((size_t)m * m, 0.0);
+  lamfd.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    lamfd[j] = w[ord[j]];
+    for (int i = 0; i < m; ++i) Qfd[(size_t)i * m + j] = Q[(size_t)i * m + ord[j]];
+  }
+  return IFFD_OK;
+}
+
 int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return IFFD_E_INVAL; }
   if (p < 1 || p > 8) { err = "p must be in 1..8"; return IFFD_E_INVAL; }
@@ -505,64 +573,8 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   P.s.assign(m, 1.0);
 
   if (P.method == IFFD_METHOD_DENSE_FD) {
-    // full generalized eigendecomposition of (K, M): M = L L^T, C = L^-1 K L^-T
-    std::vector<double> L((size_t)m * m, 0.0);
-    for (int j = 0; j < m; ++j) {
-      for (int i = j; i < std::min(m, j + p + 1); ++i) {
-        double sum = P.Mb[(size_t)i * bw + (j - i + p)];
-        for (int k = std::max(0, i - p); k < j; ++k) sum -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
-        if (i == j) {
-          if (!(sum > 0)) { err = "mass matrix not SPD"; return IFFD_E_INVAL; }
-          L[(size_t)j * m + j] = std::sqrt(sum);
-        } else {
-          L[(size_t)i * m + j] = sum / L[(size_t)j * m + j];
-        }
-      }
-    }
-    // X = L^{-1} K (dense), then C = X L^{-T} = (L^{-1} X^T)^T
-    std::vector<double> Kd((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i)
-      for (int o = 0; o < bw; ++o) {
-        int j = i + o - p;
-        if (j >= 0 && j < m) Kd[(size_t)i * m + j] = P.Kb[(size_t)i * bw + o];
-      }
-    auto lower_solve_cols = [&](std::vector<double>& B) {  // B <- L^{-1} B (m x m)
-      for (int c = 0; c < m; ++c)
-        for (int i = 0; i < m; ++i) {
-          double sum = B[(size_t)i * m + c];
-          for (int k = std::max(0, i - p); k < i; ++k) sum -= L[(size_t)i * m + k] * B[(size_t)k * m + c];
-          B[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
-        }
-    };
-    lower_solve_cols(Kd);
-    std::vector<double> T((size_t)m * m);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) T[(size_t)i * m + j] = Kd[(size_t)j * m + i];
-    lower_solve_cols(T);
-    for (int i = 0; i < m; ++i)
-      for (int j = i + 1; j < m; ++j) {
-        double a = 0.5 * (T[(size_t)i * m + j] + T[(size_t)j * m + i]);
-        T[(size_t)i * m + j] = T[(size_t)j * m + i] = a;
-      }
-    std::vector<double> Z, w;
-    jacobi(m, T, Z, w);
-    // Q = L^{-T} Z (back substitution on each column)
-    std::vector<double> Q = Z;
-    for (int c = 0; c < m; ++c)
-      for (int i = m - 1; i >= 0; --i) {
-        double sum = Q[(size_t)i * m + c];
-        for (int k = i + 1; k < std::min(m, i + p + 1); ++k) sum -= L[(size_t)k * m + i] * Q[(size_t)k * m + c];
-        Q[(size_t)i * m + c] = sum / L[(size_t)i * m + i];
-      }
-    std::vector<int> ord(m);
-    for (int i = 0; i < m; ++i) ord[i] = i;
-    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
-    P.Qfd.assign((size_t)m * m, 0.0);
-    P.lamfd.assign(m, 0.0);
-    for (int j = 0; j < m; ++j) {
-      P.lamfd[j] = w[ord[j]];
-      for (int i = 0; i < m; ++i) P.Qfd[(size_t)i * m + j] = Q[(size_t)i * m + ord[j]];
-    }
+    const int rc = dense_pencil(P.Kb, P.Mb, m, p, P.Qfd, P.lamfd, err);
+    if (rc != IFFD_OK) return rc;
     P.lam = P.lamfd;
     compute_layout(P);
     return IFFD_OK;
@@ -1333,6 +1345,12 @@ int make_generic(GDir& G, std::string& err) {
   return IFFD_OK;
 }
 
+// the dense FD tables of a direction of a dense-FD general plan
+int finish_dir(const Plan& P, GDir& G, std::string& err) {
+  if (P.method != IFFD_METHOD_DENSE_FD) return IFFD_OK;
+  return dense_pencil(G.Kb, G.Mb, G.m, G.p, G.Qfd, G.lamfd, err);
+}
+
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 void compute_layout_general(Plan& P) {
@@ -1364,6 +1382,15 @@ void compute_layout_general(Plan& P) {
     G.len = o + (o & 1);
     G.blob64 = take((size_t)8 * G.len);
     G.blob32 = take((size_t)4 * G.len);
+    if (P.method == IFFD_METHOD_DENSE_FD) {
+      const size_t mm = (size_t)G.m * G.m;
+      G.fq64 = take(8 * mm);
+      G.fqt64 = take(8 * mm);
+      G.flam64 = take((size_t)8 * G.m);
+      G.fq32 = take(4 * mm);
+      G.fqt32 = take(4 * mm);
+      G.flam32 = take((size_t)4 * G.m);
+    }
     G.ao64 = take((size_t)8 * G.n_out * G.n_out);
     G.bo64 = take((size_t)8 * G.n_out * G.n_out);
     G.vout64 = take((size_t)8 * G.n_out * G.m);
@@ -1386,7 +1413,7 @@ int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* 
     P.max_rhs = opts->max_rhs;
     P.coef_a = opts->coef_a;
   }
-  if (P.method != IFFD_METHOD_FFT) { err = "general plans support the IFFD method only"; return IFFD_E_UNSUPPORTED; }
+  if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
   if (P.prec != IFFD_PREC_F32 && P.prec != IFFD_PREC_F64) { err = "general plans take IFFD_PREC_F32 or IFFD_PREC_F64"; return IFFD_E_INVAL; }
   if (P.coef_a != 0.0) { err = "general plans take coef_a = 0 (the Kronecker-sum operator)"; return IFFD_E_UNSUPPORTED; }
   if (P.max_rhs < 1) { err = "max_rhs must be >= 1"; return IFFD_E_INVAL; }
@@ -1412,7 +1439,8 @@ int build_plan_general(Plan& P, int d, const int* nv, const int* pv, const int* 
   P.d = d;
   P.N = 1;
   for (int k = 0; k < d; ++k) {
-    const int rc = build_dir(P.dirs[k], nv[k], pv[k], dirichlet[2 * k], dirichlet[2 * k + 1], err);
+    int rc = build_dir(P.dirs[k], nv[k], pv[k], dirichlet[2 * k], dirichlet[2 * k + 1], err);
+    if (rc == IFFD_OK) rc = finish_dir(P, P.dirs[k], err);
     if (rc != IFFD_OK) return rc;
     P.N *= P.dirs[k].m;
   }
@@ -1440,6 +1468,7 @@ int set_plan_basis(Plan& P, int basis, std::string& err) {
     }
     int rc = build_dir(dirs[k], G.n, G.p, G.dlo, G.dhi, err, G.kk, G.mult);
     if (rc == IFFD_OK && basis == IFFD_BASIS_GENERIC) rc = make_generic(dirs[k], err);
+    if (rc == IFFD_OK) rc = finish_dir(P, dirs[k], err);
     if (rc != IFFD_OK) return rc;
   }
   for (int k = 0; k < P.d; ++k) P.dirs[k] = dirs[k];
@@ -1471,6 +1500,7 @@ int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err) {
   }
   GDir nd;
   int rc = build_dir(nd, G.n, G.p, G.dlo, G.dhi, err, mult > 1 ? k : 0, mult);
+  if (rc == IFFD_OK) rc = finish_dir(P, nd, err);
   if (rc != IFFD_OK) return rc;
   if (nd.n_out > 8) { err = "at most 8 outlier functions per direction"; return IFFD_E_UNSUPPORTED; }
   int64_t N = 1;

@@ -86,6 +86,11 @@ struct GDir {
   std::vector<double> EW;
   int o_ew = 0;
   int kwin32[2] = {0, 0}, kwin64[2] = {0, 0};
+  // dense FD of a general plan (IFFD_METHOD_DENSE_FD): this direction's full
+  // eigendecomposition Q^T K Q = diag(lamfd), Q^T M Q = I, and the byte
+  // offsets of Q, Q^T and lamfd in the tables (FP64 and FP32 copies)
+  std::vector<double> Qfd, lamfd;
+  size_t fq64 = 0, fqt64 = 0, flam64 = 0, fq32 = 0, fqt32 = 0, flam32 = 0;
   int len = 0;
   size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
   size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)

@@ -244,3 +244,37 @@ def test_generic_basis_pcg_equals_special():
         print(f"p={p}: special {sts[0]['iterations']} generic {stg[0]['iterations']}", flush=True)
         assert stg[0]["converged"] and stg[0]["iterations"] == sts[0]["iterations"]
         assert rel(host(ug), host(us)) <= 1e-9
+
+
+# ---- dense FD on general plans (each direction its own Q_k, Lambda_k) --------
+
+FD_CASES = [CASES[0], CASES[3], CASES[4], CASES[8], CASES[9], CASES[12], CASES[15], CASES[18]]
+
+
+@functools.lru_cache(maxsize=None)
+def fd_oracle(specs):
+    return G.GeneralPreconditioner([(n, p, set(D)) for n, p, D in specs], "fd")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,p,dl", FD_CASES)
+def test_general_dense_fd_matches_oracle(n, p, dl, prec):
+    """Classical FD (eq:exact_diagonalization) with per-direction sizes and
+    ends: the matrix-core mode products and the Kronecker-sum scaling against
+    the oracle's dense FD."""
+    pre = fd_oracle(specs_of(n, p, dl))
+    pl = I.Plan(len(n), list(n), list(p), method="dense", precision=prec,
+                dirichlet=[tuple(x) for x in dl])
+    r = workloads.uniform_tensor(pre.shape, seed=sum(n) + 3)
+    z = host(pl.apply(dev(r)))
+    check(z, pre.apply(r), TOL[prec], len(n), max(p), f"general FD n={n} p={p} {dl} {prec}")
+
+
+def test_general_dense_fd_with_a_repeated_knot():
+    from oracle import reduced as Rd
+    n, p, dl, kn = (32, 24), (3, 2), ((1, 0), (0, 1)), {1: (16, 3)}
+    pre = Rd.ReducedPreconditioner([(32, 3, {0}, (16, 3)), (24, 2, {1}, None)], "fd")
+    pl = I.Plan(2, list(n), list(p), method="dense", precision="f64",
+                dirichlet=[tuple(x) for x in dl], knots=kn)
+    r = workloads.uniform_tensor(pre.shape, seed=9)
+    check(host(pl.apply(dev(r))), pre.apply(r), 1e-12, 2, 3, "FD with a repeated knot")

@@ -171,6 +171,39 @@ def test_table4_iffd_counts_on_gpu(n):
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("p", [2, 3])
+def test_annulus_fd_pcg_matches_oracle(p):
+    """Dense FD (exact eigendecompositions) preconditioning the annulus
+    operator: the oracle's FD PCG iterations, FP64."""
+    n = (16, 16, 16)
+    specs = plan_specs(n, (p,) * 3, BOTTOM)
+    op = geo_oracle(specs, ANNULUS)
+    pre = G.GeneralPreconditioner([(a, b, set(D)) for a, b, D in specs], "fd")
+    pl = make_plan(n, (p,) * 3, BOTTOM, ANNULUS, method="dense", prec="f64")
+    f = workloads.uniform_tensor(pl.shape, seed=1)
+    _, it_o, conv_o, hist, *_ = krylov.pcg(op.matvec, pre.apply, f, tol=1e-8, maxit=200)
+    _, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+    print(f"annulus FD n={n} p={p}: {st[0]['iterations']} (oracle {it_o})", flush=True)
+    assert conv_o and st[0]["converged"] and st[0]["iterations"] == it_o
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_table4_fd_counts_on_gpu(n):
+    """Table 4's FD column (exact eigendecompositions, FP32 mode products on
+    the matrix cores): within +-1 of the printed counts for p = 2..5."""
+    g = json.load(open(os.path.join(HERE, "golden", "table4_annulus.json")))
+    printed = g["fd"][g["n"].index(n)]
+    for p, it_p in zip(g["p"], printed):
+        pl = make_plan((n,) * 3, (p,) * 3, BOTTOM, ANNULUS, method="dense", prec="f32")
+        f = workloads.uniform_tensor(pl.shape, seed=1)
+        _, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+        s = st[0]
+        print(f"Table 4 n={n} p={p}: FD {s['iterations']} (printed {it_p})", flush=True)
+        assert s["converged"] and abs(s["iterations"] - it_p) <= 1
+        del pl
+        torch.cuda.empty_cache()
+
+
 def test_geometry_state_rules():
     pl = make_plan(8, 2, None, ("bump", (0.05,)))
     rc = I.lib.iffd_plan_set_geometry(pl._h, I.GEOMETRY_NONE, None, 0)

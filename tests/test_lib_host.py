@@ -330,7 +330,7 @@ def test_general_host_tables_match_oracle(n, ends):
     ([16, 16], [9, 3], [(1, 0), (0, 1)], None, I.E_INVAL),
     ([16, 8], [3, 8], [(1, 0), (0, 1)], None, I.E_INVAL),              # n <= p
     ([16, 16], [3, 3], [(2, 0), (0, 1)], None, I.E_INVAL),
-    ([16, 16], [3, 3], [(1, 0), (0, 1)], (I.METHOD_DENSE_FD, I.PREC_F32), I.E_UNSUPPORTED),
+    ([16, 16], [3, 3], [(1, 0), (0, 1)], (I.METHOD_DENSE_FD, I.PREC_F16S), I.E_INVAL),
     ([16, 16], [3, 3], [(1, 0), (0, 1)], (I.METHOD_FFT, I.PREC_F16S), I.E_INVAL),
 ])
 def test_invalid_general_plans_rejected(n, p, dl, opts, code):
@@ -512,3 +512,26 @@ def test_repeated_knot_rules():
     assert I.lib.iffd_plan_set_knot(h, 1, 16, 1) == 0                # back to maximal smoothness
     assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1
     I.lib.iffd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("ends", GEN_ENDS)
+def test_general_dense_fd_eigenvalues_match_oracle(ends):
+    """Dense FD on a general plan: every direction's eigenvalues of (K_k, M_k)
+    (its own size and ends) against the oracle's Jacobi eigensolver."""
+    from oracle import eig
+    from oracle import general as G
+    D = {e for e, f in zip((0, 1), ends) if f}
+    for p in (2, 3, 5):
+        n = 24
+        rc, h = I.create_general(2, [n, 16], [p, 2], [ends, (1, 1)],
+                                 I._Opts(I.METHOD_DENSE_FD, I.PREC_F32, 1, 0.0))
+        assert rc == 0, I.lib.iffd_last_error()
+        di = I.query_dirs(h, 2)[0]
+        m = di["m"]
+        assert (di["n_reg"], di["n_out"], di["fft_len"]) == (m, 0, 0)
+        K, M = G.assemble(n, p, D)
+        lam_o, _ = eig.gen_eigh(K, M)
+        lam = read_dir(h, 1, 0, m)
+        scale = max(abs(lam_o).max(), 1.0)
+        assert np.abs(np.sort(lam) - np.sort(lam_o)).max() <= 1e-9 * scale, (p, ends)
+        I.lib.iffd_plan_destroy(h)
