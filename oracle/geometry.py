@@ -89,29 +89,57 @@ def coefficient(kind: str, params, X: np.ndarray) -> np.ndarray:
     return det[:, None, None] * Ji @ np.transpose(Ji, (0, 2, 1))
 
 
-def element_tables(n: int, p: int):
+def first_function(e: int, knot) -> int:
+    """Full index of the first of the p+1 B-splines that are nonzero on element
+    e: e, or e + mult - 1 past a breakpoint k/n repeated mult times."""
+    if knot is None:
+        return e
+    k, mult = knot
+    return e + (mult - 1 if e >= k else 0)
+
+
+def element_tables(n: int, p: int, knot=None):
     """Per element e of one direction: the Gauss points (p+1), weights, and the
-    values and derivatives of the p+1 B-splines e .. e+p (full basis) there."""
-    knots = bspline.open_knots(n, p)
+    values and derivatives of the p+1 B-splines nonzero there (full basis;
+    knot = (k, mult) repeats the breakpoint k/n, Remark rmk:reduced_regularity)."""
+    if knot is None:
+        knots = bspline.open_knots(n, p)
+    else:
+        knots = np.sort(np.concatenate([bspline.open_knots(n, p),
+                                        np.full(knot[1] - 1, knot[0] / n)]))
     gx, gw = np.polynomial.legendre.leggauss(p + 1)
     pts, wts, val, der = [], [], [], []
     for e in range(n):
         a, b = e / n, (e + 1) / n
         xq = 0.5 * (a + b) + 0.5 * (b - a) * gx
+        f = first_function(e, knot)
         pts.append(xq)
         wts.append(0.5 * (b - a) * gw)
-        val.append(bspline.basis(knots, p, xq)[:, e:e + p + 1])
-        der.append(bspline.derivative(knots, p, xq, 1)[:, e:e + p + 1])
+        val.append(bspline.basis(knots, p, xq)[:, f:f + p + 1])
+        der.append(bspline.derivative(knots, p, xq, 1)[:, f:f + p + 1])
     return np.array(pts), np.array(wts), np.array(val), np.array(der)
+
+
+def _spec(s):
+    return (s[0], s[1], s[2], s[3] if len(s) > 3 else None)
 
 
 def assemble(specs, kind: str, params) -> sp.csr_matrix:
     """A over the kept tensor-product B-splines, index i1 + m1 i2 + m1 m2 i3
-    (direction 1 fastest), specs = [(n_k, p_k, D_k)] for k = 1, 2, 3."""
+    (direction 1 fastest), specs = [(n_k, p_k, D_k[, knot_k])] for k = 1, 2, 3
+    (knot_k = (k, mult) or None)."""
     assert len(specs) == 3
-    tabs = [element_tables(n, p) for n, p, _ in specs]
-    nfull = [n + p for n, p, _ in specs]
-    keep = [kept(n, p, D) for n, p, D in specs]
+    specs = [_spec(s) for s in specs]
+    tabs = [element_tables(n, p, kt) for n, p, _, kt in specs]
+    nfull = [n + p + (kt[1] - 1 if kt else 0) for n, p, _, kt in specs]
+    keep = []
+    for (n, p, D, kt), nb in zip(specs, nfull):
+        idx = np.arange(nb)
+        if 0 in D:
+            idx = idx[1:]
+        if 1 in D:
+            idx = idx[:-1]
+        keep.append(idx)
     red = []
     for k in range(3):
         r = -np.ones(nfull[k], dtype=np.int64)
@@ -119,7 +147,7 @@ def assemble(specs, kind: str, params) -> sp.csr_matrix:
         red.append(r)
     m = [len(kk) for kk in keep]
     rows, cols, vals = [], [], []
-    (n1, p1, _), (n2, p2, _), (n3, p3, _) = specs
+    (n1, p1, _, kt1), (n2, p2, _, kt2), (n3, p3, _, kt3) = specs
     for e3 in range(n3):
         for e2 in range(n2):
             for e1 in range(n1):
@@ -145,9 +173,9 @@ def assemble(specs, kind: str, params) -> sp.csr_matrix:
                 Gg = np.einsum("qkl,qlj->qkj", G, grad)
                 loc = grad.reshape(-1, nl).T @ Gg.reshape(-1, nl)
                 # local -> reduced global indices
-                i3 = red[2][e3 + np.arange(p3 + 1)]
-                i2 = red[1][e2 + np.arange(p2 + 1)]
-                i1 = red[0][e1 + np.arange(p1 + 1)]
+                i3 = red[2][first_function(e3, kt3) + np.arange(p3 + 1)]
+                i2 = red[1][first_function(e2, kt2) + np.arange(p2 + 1)]
+                i1 = red[0][first_function(e1, kt1) + np.arange(p1 + 1)]
                 I3, I2, I1 = np.meshgrid(i3, i2, i1, indexing="ij")
                 ok = (I3 >= 0) & (I2 >= 0) & (I1 >= 0)
                 gidx = (I1 + m[0] * I2 + m[0] * m[1] * I3).reshape(-1)
@@ -167,10 +195,12 @@ class GeometryOperator:
     """y = A x for a tensor of shape (m_3, m_2, m_1)."""
 
     def __init__(self, specs, kind: str, params):
-        self.specs = [(int(n), int(p), frozenset(D)) for n, p, D in specs]
+        self.specs = [(int(s[0]), int(s[1]), frozenset(s[2]),
+                       None if len(s) < 4 or s[3] is None else tuple(s[3])) for s in specs]
         self.kind, self.params = kind, tuple(float(v) for v in params)
         self.A = assemble(self.specs, kind, self.params)
-        self.shape = tuple(len(kept(n, p, D)) for n, p, D in reversed(self.specs))
+        self.shape = tuple(len(kept(n, p, D)) + (kt[1] - 1 if kt else 0)
+                           for n, p, D, kt in reversed(self.specs))
 
     def matvec(self, X: np.ndarray) -> np.ndarray:
         X = np.asarray(X, dtype=np.float64)

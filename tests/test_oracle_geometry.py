@@ -164,3 +164,81 @@ def test_table4_annulus_n16_p2():
     i, j = gold["n"].index(n), gold["p"].index(p)
     assert abs(its["fd"] - gold["fd"][i][j]) <= 1, its
     assert abs(its["iffd_b"] - gold["iffd"][i][j]) <= 1, its
+
+
+def _restriction(n, p, D, knot):
+    """E with B^smooth_j = sum_i E_ij B^knot_i on the kept functions of one
+    direction: the smooth spline space is a subspace of the space with the
+    repeated breakpoint, so a least-squares fit at 7 points per element is
+    exact."""
+    from oracle import bspline, reduced as R
+    xs = (np.arange(7 * n) + 0.5) / (7 * n)
+    Bs = bspline.basis(bspline.open_knots(n, p), p, xs)[:, R.kept(n + p, D)]
+    Bk = bspline.basis(R.knots(n, p, *knot), p, xs)[:, R.kept(n + p + knot[1] - 1, D)]
+    E, *_ = np.linalg.lstsq(Bk, Bs, rcond=None)
+    assert np.abs(Bk @ E - Bs).max() < 1e-12
+    return E
+
+
+@pytest.mark.parametrize("p,mult", [(2, 2), (3, 2), (3, 3)])
+def test_repeated_knot_identity_map_gives_reduced_A_hat(p, mult):
+    """With a breakpoint of multiplicity mult (Remark rmk:reduced_regularity)
+    the identity map gives the Kronecker sum of the reduced space's exact
+    one-dimensional K and M (assembled there over the whole basis, not per
+    element): a wrong first function past the breakpoint fails it."""
+    from oracle import reduced as R
+    n = 8
+    specs = [(n, p, {0, 1}, (4, mult)), (n, 2, {0}, None), (n + 1, p, set(), (3, mult))]
+    A = Gm.GeometryOperator(specs, "bump", [0.0])
+    X = np.random.default_rng(mult).standard_normal(A.shape)
+    (K1, M1), (K2, M2), (K3, M3) = [R.assemble(nk, pk, D, *kt) if kt else _smooth_km(nk, pk, D)
+                                    for nk, pk, D, kt in specs]
+    Ahat = (np.kron(M3, np.kron(M2, K1)) + np.kron(M3, np.kron(K2, M1))
+            + np.kron(K3, np.kron(M2, M1)))
+    ref = (Ahat @ X.reshape(-1)).reshape(A.shape)
+    assert A.shape == (M3.shape[0], M2.shape[0], M1.shape[0])
+    assert np.abs(A.matvec(X) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _smooth_km(n, p, D):
+    """K and M of the maximally smooth space by Gauss-Legendre over the whole
+    basis (exact for the polynomial integrands)."""
+    from oracle import bspline, reduced as R
+    kn = bspline.open_knots(n, p)
+    gx, gw = np.polynomial.legendre.leggauss(p + 1)
+    K = np.zeros((n + p, n + p))
+    M = np.zeros((n + p, n + p))
+    for e in range(n):
+        xq = (e + 0.5 + 0.5 * gx) / n
+        wq = 0.5 * gw / n
+        B = bspline.basis(kn, p, xq)
+        dB = bspline.derivative(kn, p, xq, 1)
+        M += (B * wq[:, None]).T @ B
+        K += (dB * wq[:, None]).T @ dB
+    kk = R.kept(n + p, D)
+    return K[np.ix_(kk, kk)], M[np.ix_(kk, kk)]
+
+
+@pytest.mark.parametrize("kind,par", [("bump", (0.05,)), ("annulus", ANNULUS)])
+def test_repeated_knot_contains_smooth_operator(kind, par):
+    """The maximally smooth space is a subspace of the space with a repeated
+    breakpoint, and A is the same bilinear form on both: E^T A_knot E =
+    A_smooth for any map, E the (Kronecker) inclusion of the coefficients."""
+    n, p = 6, 3
+    D = [{0, 1}, {0}, {0}]
+    knots = [(3, 3), None, (2, 2)]
+    Ak = Gm.GeometryOperator([(n, p, D[k], knots[k]) for k in range(3)], kind, par)
+    As = Gm.GeometryOperator([(n, p, D[k]) for k in range(3)], kind, par)
+    Es = []
+    for k in range(3):
+        if knots[k] is None:
+            Es.append(np.eye(n + p - len(D[k])))
+        else:
+            Es.append(_restriction(n, p, D[k], knots[k]))
+    E = np.kron(Es[2], np.kron(Es[1], Es[0]))
+    lhs = E.T @ (Ak.A @ E)
+    ref = As.A.toarray()
+    assert np.abs(lhs - ref).max() <= 1e-12 * np.abs(ref).max()
+    # and the knot space is strictly larger: A_knot is SPD on it
+    w = np.linalg.eigvalsh(Ak.A.toarray())
+    assert w.min() > 0
