@@ -173,6 +173,10 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
  *                          (0,1) and weights 1, 1/sqrt(2), 1 (the thick quarter
  *                          of annulus of Section 7).
  *   IFFD_GEOMETRY_NONE     restores A-hat.
+ * On a general plan with a repeated knot (iffd_plan_set_knot) the element
+ * tables use the refined knot vector and the p+1 B-splines nonzero on element
+ * e start at e, or at e + mult - 1 past the knot, so A is the mapped
+ * operator of the reduced-regularity space (Remark rmk:reduced_regularity).
  * The operator needs a workspace of 8 * n1 n2 n3 (p1+1)(p2+1)(p3+1) bytes per
  * right-hand side (iffd_plan_info.matvec_ws_bytes, included in the PCG
  * state sizes). */
@@ -260,8 +264,8 @@ int iffd_plan_set_basis(iffd_plan* plan, int basis);
  * (iffd_kron_matvec, PCG) uses K and M of the reduced space.  Valid: the
  * knot window at least p B-splines away from both end blocks (about 2p
  * elements from either end; IFFD_E_INVAL otherwise), at most 8 outlier
- * functions per direction, not with IFFD_BASIS_GENERIC or a mapped domain
- * (IFFD_E_UNSUPPORTED; set the knot before a mapped domain would need it). */
+ * functions per direction, not with IFFD_BASIS_GENERIC (IFFD_E_UNSUPPORTED).
+ * A mapped domain set before is rebuilt on the new space. */
 int iffd_plan_set_knot(iffd_plan* plan, int direction, int k, int mult);
 
 /* Per-direction sizes: h_out[k-1] describes direction k, for every plan

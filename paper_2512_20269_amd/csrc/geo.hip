@@ -107,7 +107,22 @@ struct GeoDir {
   const double* V;
   const double* D;
   int n, P, lo, m;   // elements, p + 1, full index of kept entry 0 (Dirichlet at 0), kept
+  int kk, rk;        // breakpoint kk / n repeated rk + 1 times (rk = 0: none)
 };
+
+// full index of the first B-spline nonzero on element e: past a breakpoint of
+// multiplicity rk + 1 the rk extra functions come first
+__device__ __forceinline__ int geo_first(const GeoDir& g, int e) {
+  return e + (e >= g.kk ? g.rk : 0);
+}
+// the element on which full function gi is local function a, or a value
+// outside 0 .. n - 1 when there is none
+__device__ __forceinline__ int geo_elem(const GeoDir& g, int gi, int a) {
+  const int e = gi - a;
+  if (e < g.kk) return e;
+  const int e2 = e - g.rk;
+  return e2 >= g.kk ? e2 : -1;
+}
 
 struct GeoArgs {
   GeoDir d[3];
@@ -181,7 +196,8 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
     const int el = el0 + ee;
     const int e1 = el % d1.n, e2 = (el / d1.n) % d2.n, e3 = el / (d1.n * d2.n);
     const int a1 = i % P1, a2 = (i / P1) % P2, a3 = i / (P1 * P2);
-    const int r1 = e1 + a1 - d1.lo, r2 = e2 + a2 - d2.lo, r3 = e3 + a3 - d3.lo;
+    const int r1 = geo_first(d1, e1) + a1 - d1.lo, r2 = geo_first(d2, e2) + a2 - d2.lo,
+              r3 = geo_first(d3, e3) + a3 - d3.lo;
     const bool ok = r1 >= 0 && r1 < d1.m && r2 >= 0 && r2 < d2.m && r3 >= 0 && r3 < d3.m;
     U[ee * CU + i] = ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
   }
@@ -357,7 +373,8 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
     int e1, e2, e3;
     coords(el0 + ee, e1, e2, e3);
     const int a1 = i % P, a2 = (i / P) % P, a3 = i / PP;
-    const int r1 = e1 + a1 - d1.lo, r2 = e2 + a2 - d2.lo, r3 = e3 + a3 - d3.lo;
+    const int r1 = geo_first(d1, e1) + a1 - d1.lo, r2 = geo_first(d2, e2) + a2 - d2.lo,
+              r3 = geo_first(d3, e3) + a3 - d3.lo;
     const bool ok = r1 >= 0 && r1 < d1.m && r2 >= 0 && r2 < d2.m && r3 >= 0 && r3 < d3.m;
     X0[ee * ES + a1 + S1 * a2 + S2 * a3] =
         ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
@@ -526,16 +543,16 @@ geo_gather_uni(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a
     const int g1 = r1 + d1.lo, g2 = r2 + d2.lo, g3 = r3 + d3.lo;   // full indices
     double s = 0.0;
     for (int a3 = 0; a3 < P; ++a3) {
-      const int e3 = g3 - a3;
+      const int e3 = geo_elem(d3, g3, a3);
       if (e3 < 0 || e3 >= d3.n) continue;
       for (int a2 = 0; a2 < P; ++a2) {
-        const int e2 = g2 - a2;
+        const int e2 = geo_elem(d2, g2, a2);
         if (e2 < 0 || e2 >= d2.n) continue;
         const double* row = lr + (size_t)((a3 * P + a2) * P) * nel + (size_t)d1.n * (e2 + (size_t)d2.n * e3);
         double v[P];
 #pragma unroll
         for (int a1 = 0; a1 < P; ++a1) {
-          const int e1 = g1 - a1;
+          const int e1 = geo_elem(d1, g1, a1);
           const bool ok = e1 >= 0 && e1 < d1.n;
           v[a1] = row[(size_t)a1 * nel + (ok ? e1 : 0)];
           v[a1] = ok ? v[a1] : 0.0;
@@ -586,15 +603,15 @@ geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, in
     const int g1 = r1 + d1.lo, g2 = r2 + d2.lo, g3 = r3 + d3.lo;   // full indices
     double s = 0.0;
     for (int a3 = 0; a3 < d3.P; ++a3) {
-      const int e3 = g3 - a3;
+      const int e3 = geo_elem(d3, g3, a3);
       if (e3 < 0 || e3 >= d3.n) continue;
       for (int a2 = 0; a2 < d2.P; ++a2) {
-        const int e2 = g2 - a2;
+        const int e2 = geo_elem(d2, g2, a2);
         if (e2 < 0 || e2 >= d2.n) continue;
         const double* row = lr + (size_t)((a3 * d2.P + a2) * d1.P) * a.nel +
                             (size_t)d1.n * (e2 + (size_t)d2.n * e3);
         for (int a1 = 0; a1 < d1.P; ++a1) {
-          const int e1 = g1 - a1;
+          const int e1 = geo_elem(d1, g1, a1);
           if (e1 >= 0 && e1 < d1.n) s += row[(size_t)a1 * a.nel + e1];
         }
       }
@@ -633,6 +650,8 @@ static GeoArgs geo_args(const Plan& P) {
     a.d[k].P = g.P;
     a.d[k].lo = g.lo;
     a.d[k].m = g.m;
+    a.d[k].kk = g.kk;
+    a.d[k].rk = g.rk;
   }
   a.kind = P.geo.kind;
   for (int i = 0; i < 4; ++i) a.par[i] = P.geo.par[i];

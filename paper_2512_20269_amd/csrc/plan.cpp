@@ -1494,10 +1494,6 @@ int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err) {
     err = "the generic basis is not built for a repeated knot";
     return IFFD_E_UNSUPPORTED;
   }
-  if (P.geo.kind) {
-    err = "the operator of a mapped domain assumes maximal smoothness (set the knot first)";
-    return IFFD_E_UNSUPPORTED;
-  }
   GDir nd;
   int rc = build_dir(nd, G.n, G.p, G.dlo, G.dhi, err, mult > 1 ? k : 0, mult);
   if (rc == IFFD_OK) rc = finish_dir(P, nd, err);
@@ -1513,8 +1509,14 @@ int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err) {
   P.N = N;
   const GDir& G1 = P.dirs[0];
   P.m = G1.m; P.n_reg = G1.n_reg; P.n_out = G1.n_out;
+  // the tables of a mapped domain follow the new space
+  const int gk = P.geo.kind;
+  double gp[4];
+  for (int i = 0; i < 4; ++i) gp[i] = P.geo.par[i];
+  P.geo = GeoPlan{};
   P.lay = TableLayout{};
   compute_layout_general(P);
+  if (gk) return build_geometry(P, gk, gp, 4, err);
   return IFFD_OK;
 }
 
@@ -1531,9 +1533,6 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
   if (P.d != 3) { err = "a mapped domain needs d = 3"; return IFFD_E_UNSUPPORTED; }
   if (P.coef_a != 0.0) { err = "a mapped domain replaces coef_a; create the plan with coef_a = 0"; return IFFD_E_INVAL; }
   if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
-  if (P.gen)
-    for (int k = 0; k < P.d; ++k)
-      if (P.dirs[k].rk) { err = "the operator of a mapped domain assumes maximal smoothness"; return IFFD_E_UNSUPPORTED; }
   GeoPlan G;
   G.kind = kind;
   G.base_total = P.geo.kind == 0 ? P.lay.total : P.geo.base_total;
@@ -1553,14 +1552,15 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
   int o = 0;
   for (int k = 0; k < 3; ++k) {
     GeoPlanDir& g = G.dir[k];
-    int n, p, lo, m;
+    int n, p, lo, m, kk = 0, rk = 0;
     if (P.gen) {
       n = P.dirs[k].n; p = P.dirs[k].p; lo = P.dirs[k].dlo; m = P.dirs[k].m;
+      if (P.dirs[k].rk) { kk = P.dirs[k].kk; rk = P.dirs[k].rk; }
     } else {
       n = P.n; p = P.p; lo = 1; m = P.m;
     }
     if (p + 1 > 9) { err = "p <= 8"; return IFFD_E_INVAL; }
-    g.n = n; g.P = p + 1; g.lo = lo; g.m = m;
+    g.n = n; g.P = p + 1; g.lo = lo; g.m = m; g.kk = kk; g.rk = rk;
     g.o_x = o; o += n * g.P;
     g.o_w = o; o += n * g.P;
     g.o_v = o; o += n * g.P * g.P;
@@ -1570,14 +1570,18 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
   std::vector<double> gx, gw, val, der;
   for (int k = 0; k < 3; ++k) {
     GeoPlanDir& g = G.dir[k];
-    const int n = g.n, p = g.P - 1, nb = n + p;
-    std::vector<double> U(n + 2 * p + 1);
-    for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[n + p + i] = 1.0; }
-    for (int j = 1; j < n; ++j) U[p + j] = (double)j / n;
+    const int n = g.n, p = g.P - 1;
+    // open knots with the breakpoint kk / n repeated rk more times
+    std::vector<double> U;
+    for (int i = 0; i <= p; ++i) U.push_back(0.0);
+    for (int j = 1; j < n; ++j)
+      for (int r = 0; r <= (j == g.kk ? g.rk : 0); ++r) U.push_back((double)j / n);
+    for (int i = 0; i <= p; ++i) U.push_back(1.0);
     gauss_legendre(p + 1, gx, gw);
     const double h = 1.0 / n;
     for (int e = 0; e < n; ++e) {
-      const int s = p + e;   // span of element e: B-splines e .. e+p
+      // span of element e: B-splines f .. f+p, f = e (+ rk past the breakpoint)
+      const int s = p + e + (e >= g.kk ? g.rk : 0);
       for (int q = 0; q <= p; ++q) {
         const double x = e * h + 0.5 * h * (gx[q] + 1.0);
         G.tab[(size_t)g.o_x + e * g.P + q] = x;
@@ -1589,7 +1593,6 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
         }
       }
     }
-    (void)nb;
   }
   G.off = (G.base_total + 255) & ~(size_t)255;
   P.lay.total = G.off + (((size_t)8 * o + 255) & ~(size_t)255);

@@ -101,6 +101,7 @@ struct GDir {
 // every element there (element offsets inside the tables at `off`)
 struct GeoPlanDir {
   int n = 0, P = 0, lo = 0, m = 0;   // elements, p + 1, full index of kept entry 0, kept
+  int kk = 0, rk = 0;                 // breakpoint kk / n repeated rk + 1 times
   int o_x = 0, o_w = 0, o_v = 0, o_d = 0;
 };
 struct GeoPlan {

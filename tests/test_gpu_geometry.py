@@ -204,6 +204,62 @@ def test_table4_fd_counts_on_gpu(n):
         torch.cuda.empty_cache()
 
 
+# (n, p, ends, {direction: (k, mult)}, geometry): a repeated breakpoint
+# (Remark rmk:reduced_regularity) under a map, through both element kernels
+KNOT_CASES = [
+    ((12, 8, 16), (2, 3, 2), BOTTOM, {1: (6, 2), 3: (8, 2)}, ANNULUS),
+    ((12, 12, 12), (3, 3, 3), BOTTOM, {2: (6, 3)}, ANNULUS),
+    ((12, 12, 12), (3, 3, 3), ((1, 0), (0, 1), (0, 0)), {1: (6, 2), 3: (6, 3)}, ("bump", (0.06,))),
+    ((16, 12, 12), (4, 4, 4), BOTTOM, {1: (8, 4)}, ANNULUS),
+]
+
+
+def knot_specs(n, p, dl, knots):
+    return [(nk, pk, set(DSET[tuple(dk)]), knots.get(k + 1))
+            for k, (nk, pk, dk) in enumerate(zip(n, p, dl))]
+
+
+def knot_plan(n, p, dl, knots, geometry, method="fft", prec="f64", max_rhs=1):
+    return I.Plan(3, list(n), list(p), method=method, precision=prec, max_rhs=max_rhs,
+                  dirichlet=[tuple(x) for x in dl], geometry=geometry, knots=knots)
+
+
+@pytest.mark.parametrize("n,p,dl,knots,geometry", KNOT_CASES)
+def test_geometry_matvec_with_repeated_knot_matches_oracle(n, p, dl, knots, geometry):
+    op = Gm.GeometryOperator(knot_specs(n, p, dl, knots), geometry[0], geometry[1])
+    pl = knot_plan(n, p, dl, knots, geometry, max_rhs=2)
+    assert pl.shape == op.shape
+    X = np.stack([workloads.uniform_tensor(pl.shape, seed=s) for s in (8, 9)])
+    y = host(pl.matvec(dev(X)))
+    yo = op.matvec(X)
+    e2, emax = rel(y, yo), float(np.abs(y - yo).max() / np.abs(yo).max())
+    print(f"geometry {geometry[0]} n={n} p={p} knots={knots}: rel2 {e2:.2e} max {emax:.2e}",
+          flush=True)
+    assert e2 <= 1e-13 and emax <= 1e-13
+
+
+@pytest.mark.parametrize("method,kind", [("fft", "iffd_b"), ("dense", "fd")])
+def test_annulus_pcg_with_c0_plane_matches_oracle(method, kind):
+    """The thick quarter of annulus with a C^0 plane at xi_1 = 1/2 (the
+    breakpoint repeated p times): PCG with IFFD on the reduced space (the
+    knot's extra outlier functions) or dense FD, against the oracle's PCG
+    with the same preconditioner, FP64: the same iteration count."""
+    from oracle import reduced as R
+    n, p, knots = (16, 16, 16), (3, 3, 3), {1: (8, 3)}
+    specs = knot_specs(n, p, BOTTOM, knots)
+    op = Gm.GeometryOperator(specs, *ANNULUS)
+    pre = R.ReducedPreconditioner(specs, kind)
+    pl = knot_plan(n, p, BOTTOM, knots, ANNULUS, method=method)
+    f = workloads.uniform_tensor(pl.shape, seed=1)
+    uo, it_o, conv_o, hist, *_ = krylov.pcg(op.matvec, pre.apply, f, tol=1e-8, maxit=200)
+    u, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+    s = st[0]
+    print(f"annulus C^0 plane {method}: {s['iterations']} iterations (oracle {it_o})", flush=True)
+    assert conv_o and s["converged"]
+    assert s["iterations"] == it_o
+    assert rel(host(u), uo) <= 1e-9
+
+
 def test_geometry_state_rules():
     pl = make_plan(8, 2, None, ("bump", (0.05,)))
     rc = I.lib.iffd_plan_set_geometry(pl._h, I.GEOMETRY_NONE, None, 0)

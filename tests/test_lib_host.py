@@ -507,10 +507,20 @@ def test_repeated_knot_rules():
     assert I.lib.iffd_plan_set_knot(h, 1, 16, 3) == 0
     assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1 + 2
     assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == I.E_UNSUPPORTED
+    # a mapped domain takes the knot, before or after it is set
+    info0, info = I._Info(), I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info0)) == 0
     par = (ctypes.c_double * 3)(1.0, 2.0, 1.0)
-    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par, 3) == I.E_UNSUPPORTED
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par, 3) == 0
     assert I.lib.iffd_plan_set_knot(h, 1, 16, 1) == 0                # back to maximal smoothness
     assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1
+    assert I.lib.iffd_plan_set_knot(h, 1, 16, 3) == 0
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.matvec_ws_bytes == 8 * (32 * 24 * 32) * (4 * 3 * 5)   # the elements stay
+    assert info.table_bytes > info0.table_bytes
+    assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_NONE, None, 0) == 0
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert info.table_bytes == info0.table_bytes
     I.lib.iffd_plan_destroy(h)
 
 
