@@ -108,6 +108,8 @@ struct GeoDir {
   const double* D;
   int n, P, lo, m;   // elements, p + 1, full index of kept entry 0 (Dirichlet at 0), kept
   int kk, rk;        // breakpoint kk / n repeated rk + 1 times (rk = 0: none)
+  int ulo, uhi;      // elements ulo..uhi hold one table (the basis is translation
+                     // invariant there); ulo > uhi: none
 };
 
 // full index of the first B-spline nonzero on element e: past a breakpoint of
@@ -323,11 +325,17 @@ struct GeoLineCfg {
   static constexpr int L = P * P;                         // lines per element
   static constexpr int NT = P <= 4 ? 64 : (P <= 8 ? 128 : 256);   // lanes
   static constexpr int E = NT / L;                        // elements per workgroup
-  // LDS strides (doubles) of a2 and a3, odd so that lanes on different lines
-  // fall on different banks
-  static constexpr int S1 = P | 1;
-  static constexpr int S2 = (S1 * P) | 1;
-  static constexpr int ES = (S2 * P) | 1;                 // per element
+  // LDS strides (doubles) of a2, a3 and of the elements: padded so that the
+  // lanes of one access (P^2 lines of each of E elements, along any of the three
+  // directions) spread over the banks; the padded values come from a search
+  // over S1 in [P, P+8], S2 and ES up to 16 and 32 past their minimum, scored by
+  // the most lanes on one bank in groups of 16 and 32 lanes (16 and 32 banks
+  // of 8 bytes); where the best needs more LDS (P = 6, 7, 9: fewer waves per
+  // compute unit, measured slower at P = 6) the odd strides stay
+  static constexpr int S1 = P == 2 ? 3 : P == 4 ? 5 : P == 8 ? 9 : (P | 1);
+  static constexpr int S2 = P == 2 ? 6 : P == 4 ? 20 : P == 8 ? 72 : (S1 * P) | 1;
+  static constexpr int ES = P == 2 ? 12 : P == 4 ? 80 : P == 8 ? 576 : (S2 * P) | 1;
+  static_assert(S1 >= P && S2 >= S1 * P && ES >= S2 * P, "strides must not overlap");
 };
 
 template <int P>
@@ -338,43 +346,55 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
   constexpr int E = C::E, L = C::L, NT = C::NT, S1 = C::S1, S2 = C::S2, ES = C::ES;
   constexpr int PP = P * P, CU = P * P * P;
   __shared__ double X0[E * ES], X1[E * ES], X2[E * ES];
-  __shared__ double tv[E][3][PP], td[E][3][PP];
-  __shared__ double tw[E][3][P], tf[E][3][P][4];
+  __shared__ double tv[E][PP], td[E][PP];        // direction 1, per element
+  __shared__ double tw1[E][P], tf1[E][P][4];
+  __shared__ double tw23[2][P], tf23[2][P][4];   // directions 2 and 3, one element each
   const int rhs = blockIdx.y;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
   const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
   const int tid = threadIdx.x;
-  const int el0 = xcd_linear(blockIdx.x, gridDim.x) * E;
-  const int ne = min(E, a.nel - el0);
-  auto coords = [&](int el, int& e1, int& e2, int& e3) {
-    e1 = el % d1.n;
-    e2 = (el / d1.n) % d2.n;
-    e3 = el / (d1.n * d2.n);
-  };
-  for (int t = tid; t < ne * 3 * PP; t += NT) {
-    const int ee = t / (3 * PP), r = t - ee * 3 * PP, k = r / PP, j = r - k * PP;
-    int e[3];
-    coords(el0 + ee, e[0], e[1], e[2]);
-    const GeoDir& g = a.d[k];
-    tv[ee][k][j] = g.V[(size_t)e[k] * PP + j];
-    td[ee][k][j] = g.D[(size_t)e[k] * PP + j];
+  // a workgroup takes up to E consecutive elements of one row along xi_1: they
+  // share e2 and e3, so the tables of directions 2 and 3 are the same for the
+  // whole wave and are read with scalar loads, not from LDS
+  const int bpr = (d1.n + E - 1) / E;
+  const int b = xcd_linear(blockIdx.x, gridDim.x);
+  const int row = b / bpr;
+  const int e10 = (b - row * bpr) * E;
+  const int ne = min(E, d1.n - e10);
+  const int e2 = row % d2.n, e3 = row / d2.n;
+  const int el0 = row * d1.n + e10;
+  // direction 1's tables: where every element of the workgroup lies in the
+  // translation-invariant range they are one table, read with scalar loads;
+  // otherwise per element from LDS
+  const bool u1 = e10 >= d1.ulo && e10 + ne - 1 <= d1.uhi;
+  const double* V1 = d1.V + (size_t)(u1 ? d1.ulo : 0) * PP;
+  const double* D1 = d1.D + (size_t)(u1 ? d1.ulo : 0) * PP;
+  const double* V2 = d2.V + (size_t)e2 * PP;
+  const double* D2 = d2.D + (size_t)e2 * PP;
+  const double* V3 = d3.V + (size_t)e3 * PP;
+  const double* D3 = d3.D + (size_t)e3 * PP;
+  if (!u1)
+    for (int t = tid; t < ne * PP; t += NT) {
+      tv[0][t] = d1.V[(size_t)e10 * PP + t];
+      td[0][t] = d1.D[(size_t)e10 * PP + t];
+    }
+  for (int t = tid; t < ne * P; t += NT) {
+    tw1[0][t] = d1.w[(size_t)e10 * P + t];
+    geo_factors(a.kind, a.par, 0, d1.x[(size_t)e10 * P + t], tf1[0][t]);
   }
-  for (int t = tid; t < ne * 3 * P; t += NT) {
-    const int ee = t / (3 * P), r = t - ee * 3 * P, k = r / P, q = r - k * P;
-    int e[3];
-    coords(el0 + ee, e[0], e[1], e[2]);
-    const GeoDir& g = a.d[k];
-    tw[ee][k][q] = g.w[(size_t)e[k] * P + q];
-    geo_factors(a.kind, a.par, k, g.x[(size_t)e[k] * P + q], tf[ee][k][q]);
+  if (tid < 2 * P) {
+    const int k = tid / P, q = tid - k * P;
+    const GeoDir& g = k ? d3 : d2;
+    const int e = k ? e3 : e2;
+    tw23[k][q] = g.w[(size_t)e * P + q];
+    geo_factors(a.kind, a.par, k + 1, g.x[(size_t)e * P + q], tf23[k][q]);
   }
   const double* xr = x + (size_t)rhs * a.N;
+  const int f2 = geo_first(d2, e2) - d2.lo, f3 = geo_first(d3, e3) - d3.lo;
   for (int t = tid; t < ne * CU; t += NT) {
     const int ee = t / CU, i = t - ee * CU;
-    int e1, e2, e3;
-    coords(el0 + ee, e1, e2, e3);
     const int a1 = i % P, a2 = (i / P) % P, a3 = i / PP;
-    const int r1 = geo_first(d1, e1) + a1 - d1.lo, r2 = geo_first(d2, e2) + a2 - d2.lo,
-              r3 = geo_first(d3, e3) + a3 - d3.lo;
+    const int r1 = geo_first(d1, e10 + ee) + a1 - d1.lo, r2 = f2 + a2, r3 = f3 + a3;
     const bool ok = r1 >= 0 && r1 < d1.m && r2 >= 0 && r2 < d2.m && r3 >= 0 && r3 < d3.m;
     X0[ee * ES + a1 + S1 * a2 + S2 * a3] =
         ok ? xr[(size_t)r1 + (size_t)d1.m * (r2 + (size_t)d2.m * r3)] : 0.0;
@@ -391,7 +411,8 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
   // (this lane owns the line, so reading and rewriting it in place is safe),
   // and only the unrolled inner index lives in registers.
   // stage 1: line (a2, a3) = (la, lb) along a1
-  if (live) {
+  auto stage1 = [&](const double* V, const double* D) {
+    if (!live) return;
     const int o = S1 * la + S2 * lb;
     double u[P];
 #pragma unroll
@@ -401,13 +422,17 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       double s = 0.0, w = 0.0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        s += tv[ee][0][q * P + j] * u[j];
-        w += td[ee][0][q * P + j] * u[j];
+        s += V[q * P + j] * u[j];
+        w += D[q * P + j] * u[j];
       }
       Y0[o + q] = s;
       Y1[o + q] = w;
     }
-  }
+  };
+  if (u1)
+    stage1(V1, D1);
+  else
+    stage1(tv[ee], td[ee]);
   __syncthreads();
   // stage 2: line (q1, a3) = (la, lb) along a2
   if (live) {
@@ -423,7 +448,7 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       double s = 0.0, w = 0.0, v = 0.0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double vv = tv[ee][1][q * P + j], dd = td[ee][1][q * P + j];
+        const double vv = V2[q * P + j], dd = D2[q * P + j];
         s += vv * u1[j];
         w += dd * u1[j];
         v += vv * u2[j];
@@ -445,26 +470,26 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       b3[j] = Y2[o + S2 * j];
       c1[j] = c2[j] = c3[j] = 0.0;
     }
-    const double w12 = tw[ee][0][la] * tw[ee][1][lb];
+    const double w12 = tw1[ee][la] * tw23[0][lb];
 #pragma unroll 1
     for (int q = 0; q < P; ++q) {
       double g1 = 0.0, g2 = 0.0, g3 = 0.0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double vv = tv[ee][2][q * P + j], dd = td[ee][2][q * P + j];
+        const double vv = V3[q * P + j], dd = D3[q * P + j];
         g1 += vv * b3[j];   // D1 V2 V3
         g2 += vv * b2[j];   // V1 D2 V3
         g3 += dd * b1[j];   // V1 V2 D3
       }
       double G[6];
-      geo_metric(a.kind, a.par, tf[ee][0][la], tf[ee][1][lb], tf[ee][2][q], G);
-      const double wq = w12 * tw[ee][2][q];
+      geo_metric(a.kind, a.par, tf1[ee][la], tf23[0][lb], tf23[1][q], G);
+      const double wq = w12 * tw23[1][q];
       const double f1 = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
       const double f2 = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
       const double f3 = wq * (G[4] * g1 + G[5] * g2 + G[2] * g3);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double vv = tv[ee][2][q * P + j], dd = td[ee][2][q * P + j];
+        const double vv = V3[q * P + j], dd = D3[q * P + j];
         c1[j] += vv * f1;
         c2[j] += vv * f2;
         c3[j] += dd * f3;
@@ -489,7 +514,7 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       const double c1 = Y0[o + S1 * q], c2 = Y1[o + S1 * q], c3 = Y2[o + S1 * q];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double vv = tv[ee][1][q * P + j], dd = td[ee][1][q * P + j];
+        const double vv = V2[q * P + j], dd = D2[q * P + j];
         s1[j] += vv * c1;
         s2[j] += dd * c2 + vv * c3;
       }
@@ -502,7 +527,8 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
   }
   __syncthreads();
   // stage 5: line (a2, a3) = (la, lb) along q1 -> a1, to loc[(rhs nloc + i) nel + el]
-  if (live) {
+  auto stage5 = [&](const double* V, const double* D) {
+    if (!live) return;
     const int o = S1 * la + S2 * lb;
     double s[P];
 #pragma unroll
@@ -512,12 +538,16 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       const double y1 = Y0[o + q], y2 = Y1[o + q];
 #pragma unroll
       for (int j = 0; j < P; ++j)
-        s[j] += td[ee][0][q * P + j] * y1 + tv[ee][0][q * P + j] * y2;
+        s[j] += D[q * P + j] * y1 + V[q * P + j] * y2;
     }
     double* out = loc + ((size_t)rhs * CU + (size_t)P * ln) * a.nel + el0 + ee;
 #pragma unroll
     for (int j = 0; j < P; ++j) out[(size_t)j * a.nel] = s[j];
-  }
+  };
+  if (u1)
+    stage5(V1, D1);
+  else
+    stage5(tv[ee], td[ee]);
 }
 
 // the gather for P_1 = P_2 = P_3 = P: the same fixed order, every load of a
@@ -652,6 +682,8 @@ static GeoArgs geo_args(const Plan& P) {
     a.d[k].m = g.m;
     a.d[k].kk = g.kk;
     a.d[k].rk = g.rk;
+    a.d[k].ulo = g.ulo;
+    a.d[k].uhi = g.uhi;
   }
   a.kind = P.geo.kind;
   for (int i = 0; i < 4; ++i) a.par[i] = P.geo.par[i];
@@ -679,7 +711,8 @@ static void launch_geo_element(const GeoArgs& a, const double* x, double* loc, d
   const bool uni = a.d[0].P == PM && a.d[1].P == PM && a.d[2].P == PM;
   if (uni) {
     constexpr int E = GeoLineCfg<PM>::E, NT = GeoLineCfg<PM>::NT;
-    const unsigned nwg = (unsigned)((a.nel + E - 1) / E);
+    // whole rows along xi_1, E elements per workgroup
+    const unsigned nwg = (unsigned)((a.d[0].n + E - 1) / E * a.d[1].n * a.d[2].n);
     hipLaunchKernelGGL(geo_element_lines<PM>, dim3(nwg, (unsigned)nrhs), dim3(NT), 0, s, x, loc,
                        a, act, as);
     hipLaunchKernelGGL(geo_gather_uni<PM>, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,

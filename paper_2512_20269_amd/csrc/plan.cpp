@@ -1593,6 +1593,20 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
         }
       }
     }
+    // On the uniform knots the p+1 B-splines of elements p .. n-1-p are
+    // translates of one another (their knot windows are uniform), so their
+    // tables agree up to rounding: they get the table of element p exactly,
+    // and the element kernel reads it once for a whole run of such elements.
+    if (g.rk == 0 && n - 1 - p >= p) {
+      g.ulo = p;
+      g.uhi = n - 1 - p;
+      const size_t PP = (size_t)g.P * g.P;
+      for (int e = g.ulo + 1; e <= g.uhi; ++e)
+        for (size_t j = 0; j < PP; ++j) {
+          G.tab[(size_t)g.o_v + e * PP + j] = G.tab[(size_t)g.o_v + g.ulo * PP + j];
+          G.tab[(size_t)g.o_d + e * PP + j] = G.tab[(size_t)g.o_d + g.ulo * PP + j];
+        }
+    }
   }
   G.off = (G.base_total + 255) & ~(size_t)255;
   P.lay.total = G.off + (((size_t)8 * o + 255) & ~(size_t)255);

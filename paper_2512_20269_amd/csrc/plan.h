@@ -102,6 +102,7 @@ struct GDir {
 struct GeoPlanDir {
   int n = 0, P = 0, lo = 0, m = 0;   // elements, p + 1, full index of kept entry 0, kept
   int kk = 0, rk = 0;                 // breakpoint kk / n repeated rk + 1 times
+  int ulo = 0, uhi = -1;              // elements with one shared table (none: ulo > uhi)
   int o_x = 0, o_w = 0, o_v = 0, o_d = 0;
 };
 struct GeoPlan {
