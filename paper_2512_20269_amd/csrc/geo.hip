@@ -471,6 +471,11 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       c1[j] = c2[j] = c3[j] = 0.0;
     }
     const double w12 = tw1[ee][la] * tw23[0][lb];
+    // the annulus map is a prism over xi_3 (its G does not depend on xi_3):
+    // G of the line's points is computed once
+    const bool prism = a.kind == IFFD_GEOMETRY_ANNULUS;
+    double G[6];
+    if (prism) geo_metric(a.kind, a.par, tf1[ee][la], tf23[0][lb], tf23[1][0], G);
 #pragma unroll 1
     for (int q = 0; q < P; ++q) {
       double g1 = 0.0, g2 = 0.0, g3 = 0.0;
@@ -481,8 +486,7 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
         g2 += vv * b2[j];   // V1 D2 V3
         g3 += dd * b1[j];   // V1 V2 D3
       }
-      double G[6];
-      geo_metric(a.kind, a.par, tf1[ee][la], tf23[0][lb], tf23[1][q], G);
+      if (!prism) geo_metric(a.kind, a.par, tf1[ee][la], tf23[0][lb], tf23[1][q], G);
       const double wq = w12 * tw23[1][q];
       const double f1 = wq * (G[0] * g1 + G[3] * g2 + G[4] * g3);
       const double f2 = wq * (G[3] * g1 + G[1] * g2 + G[5] * g3);
