@@ -25,6 +25,13 @@ available; these stand in for them):
              circle as a rational quadratic (control points (1,0), (1,1),
              (0,1), weights 1, 1/sqrt(2), 1), the exact NURBS form of the
              circle.
+  "plate"    a quarter of a square plate [0, L]^2 with a hole of radius R at
+             the corner, extruded to height H: F(xi) = ((1 - xi_2) R c(xi_1)
+             + xi_2 o(xi_1), H xi_3), c the quarter circle as above and o the
+             plate's two outer sides at constant speed, (L, 0) -> (L, L) ->
+             (0, L), with the corner at xi_1 = 1/2.  F is only C^0 across the
+             plane xi_1 = 1/2 (from the corner to the hole), the setting of
+             Section 7's plate with hole (a C^0 line of the parametrization).
   "linear"   F(xi) = B xi for a fixed 3 x 3 matrix B (pins only).
 """
 
@@ -72,6 +79,30 @@ def jacobian(kind: str, params, X: np.ndarray) -> np.ndarray:
         J[:, 1, 0] = (r_out - r_in) * c2
         J[:, 0, 1] = r * dc1
         J[:, 1, 1] = r * dc2
+        J[:, 2, 2] = H
+    elif kind == "plate":
+        R, Lp, H = (float(v) for v in params)
+        t = X[:, 0]
+        s = X[:, 1]
+        w = 1.0 / np.sqrt(2.0)
+        b0, b1, b2 = (1 - t) ** 2, 2 * t * (1 - t), t ** 2
+        db0, db1, db2 = -2 * (1 - t), 2 - 4 * t, 2 * t
+        den = b0 + w * b1 + b2
+        dden = db0 + w * db1 + db2
+        n1, n2 = b0 + w * b1, w * b1 + b2
+        dn1, dn2 = db0 + w * db1, w * db1 + db2
+        c1, c2 = n1 / den, n2 / den
+        dc1 = (dn1 * den - n1 * dden) / den ** 2
+        dc2 = (dn2 * den - n2 * dden) / den ** 2
+        first = t < 0.5   # on the side x = L, else on the side y = L
+        o1 = np.where(first, Lp, 2 * Lp * (1 - t))
+        o2 = np.where(first, 2 * Lp * t, Lp)
+        do1 = np.where(first, 0.0, -2 * Lp)
+        do2 = np.where(first, 2 * Lp, 0.0)
+        J[:, 0, 0] = (1 - s) * R * dc1 + s * do1
+        J[:, 1, 0] = (1 - s) * R * dc2 + s * do2
+        J[:, 0, 1] = o1 - R * c1
+        J[:, 1, 1] = o2 - R * c2
         J[:, 2, 2] = H
     elif kind == "linear":
         Bm = np.asarray(params, dtype=np.float64).reshape(3, 3)

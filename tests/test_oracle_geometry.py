@@ -55,6 +55,21 @@ def annulus_map(par, X):
     return np.stack([r * c[:, 0], r * c[:, 1], H * X[:, 2]], axis=1)
 
 
+PLATE = (1.0, 2.0, 1.0)   # hole radius R, plate side L, height H
+
+
+def plate_map(par, X):
+    """(1 - xi_2) R c(xi_1) + xi_2 o(xi_1), o walking the two outer sides
+    (L, 0) -> (L, L) -> (0, L) at constant speed; x_3 = H xi_3."""
+    R, Lp, H = par
+    t, s = X[:, 0], X[:, 1]
+    c = circle_arc(t)
+    o = np.where((t < 0.5)[:, None], np.stack([np.full_like(t, Lp), 2 * Lp * t], axis=1),
+                 np.stack([2 * Lp * (1 - t), np.full_like(t, Lp)], axis=1))
+    xy = (1 - s)[:, None] * R * c + s[:, None] * o
+    return np.stack([xy[:, 0], xy[:, 1], H * X[:, 2]], axis=1)
+
+
 def fd_jacobian(F, X, h=1e-6):
     J = np.zeros((X.shape[0], 3, 3))
     for k in range(3):
@@ -74,6 +89,28 @@ def test_maps_jacobians_against_differences():
     c = circle_arc(t)
     assert np.abs(np.hypot(c[:, 0], c[:, 1]) - 1).max() < 1e-15   # a quarter of the unit circle
     assert np.allclose(c[0], [1, 0]) and np.allclose(c[-1], [0, 1])
+    # the plate: away from its C^0 plane xi_1 = 1/2 (differences must not
+    # straddle the corner)
+    Xp = X[np.abs(X[:, 0] - 0.5) > 0.01]
+    Jp = Gm.jacobian("plate", PLATE, Xp)
+    assert np.abs(Jp - fd_jacobian(lambda Y: plate_map(PLATE, Y), Xp)).max() < 1e-8
+    # its faces: the hole xi_2 = 0 on the circle of radius R, xi_2 = 1 on the
+    # sides x = L or y = L with the corner at xi_1 = 1/2
+    e = np.linspace(0, 1, 41)
+    hole = plate_map(PLATE, np.stack([e, 0 * e, 0 * e], axis=1))
+    side = plate_map(PLATE, np.stack([e, 0 * e + 1, 0 * e], axis=1))
+    assert np.abs(np.hypot(hole[:, 0], hole[:, 1]) - PLATE[0]).max() < 1e-14
+    assert np.abs(np.maximum(side[:, 0], side[:, 1]) - PLATE[1]).max() < 1e-14
+    assert np.allclose(side[20, :2], [PLATE[1], PLATE[1]])
+    # the derivative along xi_1 jumps across the plane: only C^0 there
+    Jl = Gm.jacobian("plate", PLATE, np.array([[0.5 - 1e-12, 0.7, 0.3]]))
+    Jr = Gm.jacobian("plate", PLATE, np.array([[0.5 + 1e-12, 0.7, 0.3]]))
+    assert np.abs(Jl[0, :2, 0] - Jr[0, :2, 0]).max() > 1.0
+    assert np.abs(Jl[0, :, 1:] - Jr[0, :, 1:]).max() < 1e-9
+    # no fold: det J keeps one sign over the cube (negative: xi_1 runs along
+    # the arc, xi_2 outwards)
+    Xg = np.random.default_rng(1).uniform(0, 1, (400, 3))
+    assert np.linalg.det(Gm.jacobian("plate", PLATE, Xg)).max() < -0.1
     # G is |det J| (J^T J)^{-1}: symmetric positive definite
     Gq = Gm.coefficient("annulus", ANNULUS, X)
     assert np.abs(Gq - np.transpose(Gq, (0, 2, 1))).max() < 1e-14
@@ -127,7 +164,22 @@ def test_annulus_energies():
     assert abs(e1 - vol / (r_out - r_in) ** 2) < 1e-6 * vol
 
 
-@pytest.mark.parametrize("kind,par", [("bump", [0.08]), ("annulus", ANNULUS)])
+def test_plate_energy():
+    """The energy of u = x_3 = H xi_3 over the plate with a hole is its
+    volume (L^2 - pi R^2 / 4) H, up to the quadrature error of the rational
+    map; n_1 even puts the corner plane on a breakpoint."""
+    R, Lp, H = PLATE
+    vol = (Lp ** 2 - np.pi * R ** 2 / 4) * H
+    n, p = 6, 2
+    A = Gm.GeometryOperator([(n, p, set())] * 3, "plate", PLATE)
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    g = np.array([knots[i + 1:i + p + 1].mean() for i in range(n + p)])
+    G3 = np.broadcast_to(g[:, None, None], A.shape)
+    e3 = float(np.vdot(H * G3, A.matvec(H * G3)))
+    assert abs(e3 - vol) < 1e-5 * vol
+
+
+@pytest.mark.parametrize("kind,par", [("bump", [0.08]), ("annulus", ANNULUS), ("plate", PLATE)])
 def test_section3_bound(kind, par):
     n, p = 4, 2
     specs = [(n, p, {0, 1}), (n, p, {0, 1}), (n, p, {0})]
@@ -219,7 +271,7 @@ def _smooth_km(n, p, D):
     return K[np.ix_(kk, kk)], M[np.ix_(kk, kk)]
 
 
-@pytest.mark.parametrize("kind,par", [("bump", (0.05,)), ("annulus", ANNULUS)])
+@pytest.mark.parametrize("kind,par", [("bump", (0.05,)), ("annulus", ANNULUS), ("plate", PLATE)])
 def test_repeated_knot_contains_smooth_operator(kind, par):
     """The maximally smooth space is a subspace of the space with a repeated
     breakpoint, and A is the same bilinear form on both: E^T A_knot E =
