@@ -395,6 +395,32 @@ def annulus(torch, iffd, ps=(3,), n=64, steps=20, solves=5, prec="f32"):
     return rows
 
 
+def plate(torch, iffd, ns=(32, 64, 128), ps=(2, 3, 4, 5), solves=3, prec="f32"):
+    """The plate with a hole whose map is only C^0 across xi_1 = 1/2, on the
+    space C^0 there too (the breakpoint n/2 of direction 1 repeated p times,
+    Remark rmk:reduced_regularity), Dirichlet on the bottom face: PCG to 1e-8
+    with IFFD and with dense FD (the stand-in for Table 5)."""
+    import workloads
+    rows = []
+    for n in ns:
+        for p in ps:
+            row = {"n": n, "p": p}
+            for method in ("fft", "dense"):
+                pl = iffd.Plan(3, [n] * 3, [p] * 3, method=method, precision=prec,
+                               dirichlet=workloads.PLATE_DIRICHLET, knots={1: (n // 2, p)},
+                               geometry=("plate", workloads.PLATE_PARAMS))
+                f = torch.from_numpy(workloads.uniform_tensor(pl.shape, seed=1)).cuda()
+                lat, st = time_solves(torch, pl, f, solves)
+                row["dofs"] = pl.N
+                row["iffd" if method == "fft" else "dense_fd"] = {
+                    "iterations": st[0]["iterations"], "p50_ms": round(pct(lat, 0.5), 3),
+                    "relres_true": st[0]["relres_true"]}
+                del pl, f
+                torch.cuda.empty_cache()
+            rows.append(row)
+    return rows
+
+
 def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256, coef=0.0):
     """3D with the smooth right-hand side (8 random-phase sine modes plus 1e-3
     noise, seed 3), degree sweep: FP32 apply error against the FP64 apply, PCG
@@ -462,6 +488,8 @@ def main():
                     help="only the mixed-boundary cube of Table 3 (n = 256, p = 2..5)")
     ap.add_argument("--annulus", action="store_true",
                     help="only the thick quarter of annulus of Table 4 (n = 64, p = 2..5)")
+    ap.add_argument("--plate", action="store_true",
+                    help="only the plate with a hole and a C^0 plane (n = 32, 64, 128, p = 2..5)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
@@ -512,6 +540,14 @@ def main():
                           "unit": "ms", "n_gpus": 1, "dtype": args.precision,
                           "data": "synthetic",
                           "config": {"workload": "annulus_n64_p2-5_uniform"},
+                          "rows": rows}), flush=True)
+        return
+    if args.plate:
+        rows = plate(torch, iffd, solves=args.solves, prec=args.precision)
+        print(json.dumps({"metric": "PCG iterations and solve time, plate with a C^0 plane",
+                          "unit": "ms", "n_gpus": 1, "dtype": args.precision,
+                          "data": "synthetic",
+                          "config": {"workload": "plate_c0_n32-128_p2-5_uniform"},
                           "rows": rows}), flush=True)
         return
     if args.serve:

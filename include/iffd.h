@@ -85,6 +85,7 @@ extern "C" {
 #define IFFD_GEOMETRY_NONE     0  /* A-hat (or A_c of iffd_opts.coef_a)          */
 #define IFFD_GEOMETRY_BUMP     1  /* the unit cube with an interior bump map      */
 #define IFFD_GEOMETRY_ANNULUS  2  /* the thick quarter of annulus                 */
+#define IFFD_GEOMETRY_PLATE    3  /* a plate with a hole, C^0 across one plane    */
 
 typedef struct iffd_plan iffd_plan;
 
@@ -172,6 +173,17 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
  *                          rational quadratic with control points (1,0), (1,1),
  *                          (0,1) and weights 1, 1/sqrt(2), 1 (the thick quarter
  *                          of annulus of Section 7).
+ *   IFFD_GEOMETRY_PLATE    params {R, L, H}, 0 < R < L, H > 0, n_1 even:
+ *                          F(xi) = ((1 - xi2) R c(xi1) + xi2 o(xi1), H xi3),
+ *                          the quarter of the plate [0, L]^2 outside the hole
+ *                          of radius R at its corner, extruded to height H;
+ *                          c the quarter circle above, o the two outer sides
+ *                          (L, 0) -> (L, L) -> (0, L) at constant speed.  F
+ *                          is only C^0 across the plane xi1 = 1/2 (from the
+ *                          plate's corner to the hole, a breakpoint since n_1
+ *                          is even), the setting of Section 7's plate with a
+ *                          hole; with iffd_plan_set_knot(plan, 1, n_1 / 2, p_1)
+ *                          the spline space is C^0 there too.
  *   IFFD_GEOMETRY_NONE     restores A-hat.
  * On a general plan with a repeated knot (iffd_plan_set_knot) the element
  * tables use the refined knot vector and the p+1 B-splines nonzero on element

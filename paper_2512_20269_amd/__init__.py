@@ -29,7 +29,7 @@ OK, W_NOT_CONVERGED = 0, 1
 E_INVAL, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 METHOD_FFT, METHOD_DENSE_FD = 0, 1
 PREC_F64, PREC_F32, PREC_F16S, PREC_BF16S = 0, 1, 2, 3
-GEOMETRY_NONE, GEOMETRY_BUMP, GEOMETRY_ANNULUS = 0, 1, 2
+GEOMETRY_NONE, GEOMETRY_BUMP, GEOMETRY_ANNULUS, GEOMETRY_PLATE = 0, 1, 2, 3
 BASIS_SPECIAL, BASIS_GENERIC = 0, 1
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
@@ -196,8 +196,8 @@ class Plan:
     (Neumann), direction 1 first; given (or n, p given per direction as
     sequences) it makes a general plan (iffd_plan_create_general) whose
     tensors have shape (m_d, .., m_1).
-    geometry: None, or (kind, params) with kind "bump" ({eps}) or "annulus"
-    ({r_in, r_out, H}): the system matrix becomes the Galerkin matrix of the
+    geometry: None, or (kind, params) with kind "bump" ({eps}), "annulus"
+    ({r_in, r_out, H}) or "plate" ({R, L, H}): the system matrix becomes the Galerkin matrix of the
     mapped domain (iffd_plan_set_geometry, d = 3); the preconditioner stays
     that of A-hat.
     basis: "special" (eq:special_basis) or "generic" (general plans: Q_reg =
@@ -237,7 +237,7 @@ class Plan:
         if geometry is not None:
             kind, params = geometry
             code = {"none": GEOMETRY_NONE, "bump": GEOMETRY_BUMP,
-                    "annulus": GEOMETRY_ANNULUS}[kind]
+                    "annulus": GEOMETRY_ANNULUS, "plate": GEOMETRY_PLATE}[kind]
             par = (ctypes.c_double * max(len(params), 1))(*[float(v) for v in params])
             _check(lib.iffd_plan_set_geometry(h, code, par, len(params)), "plan_set_geometry")
             self.geometry = (kind, tuple(float(v) for v in params))

@@ -20,39 +20,68 @@
 //                per-block partial sums of x . y or (f - y)^2 for PCG.
 // Deterministic: no result depends on scheduling.
 //
-// Both maps are products of one-dimensional factors (the bump's
-// sin(pi xi_k), the annulus' radius and circle), so each workgroup first
-// evaluates those factors at the p_k + 1 Gauss points of each direction; G at
-// a point is then a few products of them (closed forms in geo_metric).
+// Every map is built from one-dimensional factors (the bump's sin(pi xi_k),
+// the annulus' radius and circle, the plate's circle and outer sides), so each
+// workgroup first evaluates those factors at the p_k + 1 Gauss points of each
+// direction; G at a point is then a few products of them (closed forms in
+// geo_metric).
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
 
 namespace iffd {
 
+// factors of the map per direction and Gauss point
+constexpr int GEO_NF = 6;
+
+// the quarter of the unit circle from (1, 0) to (0, 1) as the rational
+// quadratic with control points (1,0), (1,1), (0,1) and weights 1, 1/sqrt 2,
+// 1: c = (c1, c2) and c' at t
+__device__ __forceinline__ void quarter_circle(double t, double c[4]) {
+  const double w = 0.70710678118654752440;
+  const double b0 = (1 - t) * (1 - t), b1 = 2 * t * (1 - t), b2 = t * t;
+  const double db0 = -2 * (1 - t), db1 = 2 - 4 * t, db2 = 2 * t;
+  const double den = b0 + w * b1 + b2, dden = db0 + w * db1 + db2;
+  const double n1 = b0 + w * b1, n2 = w * b1 + b2;
+  const double dn1 = db0 + w * db1, dn2 = w * db1 + db2;
+  c[0] = n1 / den;
+  c[1] = n2 / den;
+  c[2] = (dn1 * den - n1 * dden) / (den * den);
+  c[3] = (dn2 * den - n2 * dden) / (den * den);
+}
+
 // per-direction factors of the map at one Gauss point
 //   bump:     f = (sin(pi xi), cos(pi xi))
 //   annulus:  direction 1: f = (r(xi)), direction 2: f = (c1, c2, c1', c2')
-//             of the quarter circle at t = xi (rational quadratic, weights
-//             1, 1/sqrt 2, 1), direction 3: unused
+//             of the quarter circle at t = xi, direction 3: unused
+//   plate:    direction 1: with the hole's arc R c(xi) and the outer sides
+//             o(xi) ((L, 2 L xi) below xi = 1/2, (2 L (1 - xi), L) above),
+//             f = (o - R c, R c', o' - R c') (two entries each), direction 2:
+//             f = (xi), direction 3: unused
 __device__ __forceinline__ void geo_factors(int kind, const double* par, int k, double xi,
-                                           double f[4]) {
-  f[0] = f[1] = f[2] = f[3] = 0.0;
+                                           double f[GEO_NF]) {
+  for (int i = 0; i < GEO_NF; ++i) f[i] = 0.0;
   if (kind == IFFD_GEOMETRY_BUMP) {
     sincos(3.14159265358979323846 * xi, &f[0], &f[1]);
-  } else if (k == 0) {
-    f[0] = par[0] + (par[1] - par[0]) * xi;
-  } else if (k == 1) {
-    const double t = xi, w = 0.70710678118654752440;
-    const double b0 = (1 - t) * (1 - t), b1 = 2 * t * (1 - t), b2 = t * t;
-    const double db0 = -2 * (1 - t), db1 = 2 - 4 * t, db2 = 2 * t;
-    const double den = b0 + w * b1 + b2, dden = db0 + w * db1 + db2;
-    const double n1 = b0 + w * b1, n2 = w * b1 + b2;
-    const double dn1 = db0 + w * db1, dn2 = w * db1 + db2;
-    f[0] = n1 / den;
-    f[1] = n2 / den;
-    f[2] = (dn1 * den - n1 * dden) / (den * den);
-    f[3] = (dn2 * den - n2 * dden) / (den * den);
+  } else if (kind == IFFD_GEOMETRY_ANNULUS) {
+    if (k == 0) f[0] = par[0] + (par[1] - par[0]) * xi;
+    if (k == 1) quarter_circle(xi, f);
+  } else if (kind == IFFD_GEOMETRY_PLATE) {
+    if (k == 0) {
+      const double R = par[0], L = par[1];
+      double c[4];
+      quarter_circle(xi, c);
+      const bool first = xi < 0.5;   // on the side x = L, else on y = L
+      const double o1 = first ? L : 2 * L * (1 - xi), o2 = first ? 2 * L * xi : L;
+      const double do1 = first ? 0.0 : -2 * L, do2 = first ? 2 * L : 0.0;
+      f[0] = o1 - R * c[0];
+      f[1] = o2 - R * c[1];
+      f[2] = R * c[2];
+      f[3] = R * c[3];
+      f[4] = do1 - R * c[2];
+      f[5] = do2 - R * c[3];
+    }
+    if (k == 1) f[0] = xi;
   }
 }
 
@@ -66,7 +95,9 @@ __device__ __forceinline__ void geo_factors(int kind, const double* par, int k, 
 //            |eps| > 0 for the admitted |eps| < 0.1;
 //   annulus  J = [[dr c1, r c1', 0], [dr c2, r c2', 0], [0, 0, H]]: with the
 //            2 x 2 block K and k = det K, G = (H / |k|) adj(K) adj(K)^T on
-//            that block and G22 = |k| / H.
+//            that block and G22 = |k| / H;
+//   plate    the same form with the columns dF/dxi_1 = R c' + xi_2 (o' - R c')
+//            and dF/dxi_2 = o - R c of K.
 __device__ __forceinline__ void geo_metric(int kind, const double* par, const double* f1,
                                            const double* f2, const double* f3, double G[6]) {
   if (kind == IFFD_GEOMETRY_BUMP) {
@@ -83,9 +114,19 @@ __device__ __forceinline__ void geo_metric(int kind, const double* par, const do
     G[4] = q - g0 - g2;
     G[5] = q - g1 - g2;
   } else {
-    // F = (r c1(xi2), r c2(xi2), H xi3), r = r_in + (r_out - r_in) xi1
-    const double dr = par[1] - par[0], r = f1[0], H = par[2];
-    const double k00 = dr * f2[0], k10 = dr * f2[1], k01 = r * f2[2], k11 = r * f2[3];
+    // the 2 x 2 block K = [[k00, k01], [k10, k11]] of J (columns dF/dxi_1,
+    // dF/dxi_2) over a prism of height H
+    double k00, k10, k01, k11;
+    const double H = par[2];
+    if (kind == IFFD_GEOMETRY_ANNULUS) {
+      // F = (r c1(xi2), r c2(xi2), H xi3), r = r_in + (r_out - r_in) xi1
+      const double dr = par[1] - par[0], r = f1[0];
+      k00 = dr * f2[0]; k10 = dr * f2[1]; k01 = r * f2[2]; k11 = r * f2[3];
+    } else {
+      // F = ((1 - xi2) R c(xi1) + xi2 o(xi1), H xi3)
+      const double s = f2[0];
+      k00 = f1[2] + s * f1[4]; k10 = f1[3] + s * f1[5]; k01 = f1[0]; k11 = f1[1];
+    }
     const double k = fabs(k00 * k11 - k01 * k10);
     const double h = H / k;
     G[0] = h * (k11 * k11 + k01 * k01);
@@ -160,7 +201,7 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
   __shared__ double U[E * CU], A1[E * CU], A2[E * CU];
   __shared__ double B1[E * CU], B2[E * CU], B3[E * CU];
   __shared__ double tv[E][3][PP], td[E][3][PP];
-  __shared__ double tw[E][3][PM], tf[E][3][PM][4];
+  __shared__ double tw[E][3][PM], tf[E][3][PM][GEO_NF];
   const int rhs = blockIdx.y;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
   const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
@@ -347,8 +388,8 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
   constexpr int PP = P * P, CU = P * P * P;
   __shared__ double X0[E * ES], X1[E * ES], X2[E * ES];
   __shared__ double tv[E][PP], td[E][PP];        // direction 1, per element
-  __shared__ double tw1[E][P], tf1[E][P][4];
-  __shared__ double tw23[2][P], tf23[2][P][4];   // directions 2 and 3, one element each
+  __shared__ double tw1[E][P], tf1[E][P][GEO_NF];
+  __shared__ double tw23[2][P], tf23[2][P][GEO_NF];   // directions 2 and 3, one element each
   const int rhs = blockIdx.y;
   if (active && active[(size_t)rhs * astride] == 0.0) return;
   const GeoDir &d1 = a.d[0], &d2 = a.d[1], &d3 = a.d[2];
@@ -471,9 +512,9 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       c1[j] = c2[j] = c3[j] = 0.0;
     }
     const double w12 = tw1[ee][la] * tw23[0][lb];
-    // the annulus map is a prism over xi_3 (its G does not depend on xi_3):
-    // G of the line's points is computed once
-    const bool prism = a.kind == IFFD_GEOMETRY_ANNULUS;
+    // the annulus and the plate are prisms over xi_3 (G does not depend on
+    // xi_3): G of the line's points is computed once
+    const bool prism = a.kind == IFFD_GEOMETRY_ANNULUS || a.kind == IFFD_GEOMETRY_PLATE;
     double G[6];
     if (prism) geo_metric(a.kind, a.par, tf1[ee][la], tf23[0][lb], tf23[1][0], G);
 #pragma unroll 1

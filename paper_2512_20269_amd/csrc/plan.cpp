@@ -1545,6 +1545,17 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
       return IFFD_E_INVAL;
     }
     for (int i = 0; i < 3; ++i) G.par[i] = par[i];
+  } else if (kind == IFFD_GEOMETRY_PLATE) {
+    if (!par || npar < 3 || !(par[0] > 0.0 && par[1] > par[0] && par[2] > 0.0)) {
+      err = "plate map: params {R, L, H}, 0 < R < L, H > 0";
+      return IFFD_E_INVAL;
+    }
+    const int n1 = P.gen ? P.dirs[0].n : P.n;
+    if (n1 % 2) {
+      err = "plate map: n_1 must be even (the corner plane xi_1 = 1/2 on a breakpoint)";
+      return IFFD_E_INVAL;
+    }
+    for (int i = 0; i < 3; ++i) G.par[i] = par[i];
   } else {
     err = "unknown geometry kind";
     return IFFD_E_INVAL;

@@ -31,6 +31,7 @@ from test_gpu_parity import dev, host, rel  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 DSET = {(1, 1): {0, 1}, (1, 0): {0}, (0, 1): {1}, (0, 0): set()}
 ANNULUS = ("annulus", (1.0, 2.0, 1.0))
+PLATE = ("plate", workloads.PLATE_PARAMS)
 BOTTOM = ((0, 0), (0, 0), (1, 0))   # Dirichlet on the face xi_3 = 0 only
 
 
@@ -72,6 +73,9 @@ MATVEC_CASES = [
     ((8, 8, 8), (4, 4, 4), ((1, 0), (0, 1), (0, 0)), ("bump", (-0.04,)), "fft"),
     ((8, 8, 8), (6, 6, 6), BOTTOM, ANNULUS, "fft"),
     ((8, 8, 8), (7, 7, 7), ((0, 0), (1, 1), (0, 1)), ("bump", (0.09,)), "fft"),
+    # the plate with a hole (C^0 map across xi_1 = 1/2) on the smooth space
+    ((8, 8, 8), (3, 3, 3), BOTTOM, PLATE, "fft"),
+    ((12, 8, 16), (2, 4, 3), BOTTOM, PLATE, "dense"),
 ]
 
 
@@ -211,6 +215,9 @@ KNOT_CASES = [
     ((12, 12, 12), (3, 3, 3), BOTTOM, {2: (6, 3)}, ANNULUS),
     ((12, 12, 12), (3, 3, 3), ((1, 0), (0, 1), (0, 0)), {1: (6, 2), 3: (6, 3)}, ("bump", (0.06,))),
     ((16, 12, 12), (4, 4, 4), BOTTOM, {1: (8, 4)}, ANNULUS),
+    # the plate with the space C^0 across its corner plane, as its map
+    ((12, 8, 16), (3, 2, 2), BOTTOM, {1: (6, 3)}, PLATE),
+    ((16, 12, 12), (4, 4, 4), BOTTOM, {1: (8, 4)}, PLATE),
 ]
 
 
@@ -258,6 +265,58 @@ def test_annulus_pcg_with_c0_plane_matches_oracle(method, kind):
     assert conv_o and s["converged"]
     assert s["iterations"] == it_o
     assert rel(host(u), uo) <= 1e-9
+
+
+@pytest.mark.parametrize("method,kind", [("fft", "iffd_b"), ("dense", "fd")])
+def test_plate_c0_pcg_matches_oracle(method, kind):
+    """The plate with a hole, its map only C^0 across xi_1 = 1/2 and the
+    spline space C^0 there too (the breakpoint repeated p times, Remark
+    rmk:reduced_regularity): PCG with IFFD on the reduced space or dense FD
+    against the oracle's PCG, FP64: the same iteration count."""
+    from oracle import reduced as R
+    n, p, knots = (16, 16, 16), (3, 3, 3), {1: (8, 3)}
+    specs = knot_specs(n, p, BOTTOM, knots)
+    op = Gm.GeometryOperator(specs, *PLATE)
+    pre = R.ReducedPreconditioner(specs, kind)
+    pl = knot_plan(n, p, BOTTOM, knots, PLATE, method=method)
+    f = workloads.uniform_tensor(pl.shape, seed=1)
+    uo, it_o, conv_o, hist, *_ = krylov.pcg(op.matvec, pre.apply, f, tol=1e-8, maxit=200)
+    u, st = pl.solve(dev(f), rtol=1e-8, maxit=200)
+    s = st[0]
+    print(f"plate C^0 {method}: {s['iterations']} iterations (oracle {it_o})", flush=True)
+    assert conv_o and s["converged"]
+    assert s["iterations"] == it_o
+    assert rel(host(u), uo) <= 1e-9
+
+
+def test_plate_c0_counts_robust_on_gpu():
+    """The plate with a hole and a C^0 space across its corner plane (a
+    stand-in for Table 5, whose plate comes from a geometry file that is not
+    available): PCG iterations to 1e-8 with IFFD (FP32 apply) and dense FD
+    for n = 32, 64, 128 and p = 2..5.  As in Table 5 the counts barely move
+    with n (at most 3 apart for each p and method) and IFFD needs nearly the
+    iterations of FD: Table 5 has IFFD within 7% of FD; this geometry is not
+    the paper's, and IFFD is allowed 15% (observed up to 11%, at p = 2)."""
+    counts = {}
+    for n in (32, 64, 128):
+        for p in (2, 3, 4, 5):
+            for method in ("fft", "dense"):
+                pl = knot_plan((n,) * 3, (p,) * 3, BOTTOM, {1: (n // 2, p)}, PLATE,
+                               method=method, prec="f32")
+                f = workloads.uniform_tensor(pl.shape, seed=1)
+                _, st = pl.solve(dev(f), rtol=1e-8, maxit=300)
+                assert st[0]["converged"], (n, p, method)
+                counts[n, p, method] = st[0]["iterations"]
+                del pl, f
+                torch.cuda.empty_cache()
+            print(f"plate C^0 n={n} p={p}: FD {counts[n, p, 'dense']} / IFFD {counts[n, p, 'fft']}",
+                  flush=True)
+    for p in (2, 3, 4, 5):
+        for method in ("fft", "dense"):
+            c = [counts[n, p, method] for n in (32, 64, 128)]
+            assert max(c) - min(c) <= 3, (p, method, c)
+        for n in (32, 64, 128):
+            assert counts[n, p, "fft"] <= 1.15 * counts[n, p, "dense"], (n, p)
 
 
 def test_geometry_state_rules():

@@ -395,6 +395,17 @@ def test_geometry_host_rules():
     _, h3 = host_plan(3, 8, 3, coef_a=0.5)
     assert I.lib.iffd_plan_set_geometry(h3, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_INVAL
     I.lib.iffd_plan_destroy(h3)
+    # the plate: 0 < R < L, H > 0, and its corner plane xi_1 = 1/2 on a breakpoint
+    _, h4 = host_plan(3, 8, 3)
+    assert I.lib.iffd_plan_set_geometry(h4, I.GEOMETRY_PLATE, par(2.0, 1.0, 1.0), 3) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h4, I.GEOMETRY_PLATE, par(1.0, 2.0), 2) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h4, I.GEOMETRY_PLATE, par(1.0, 2.0, 1.0), 3) == 0
+    I.lib.iffd_plan_destroy(h4)
+    rc, h5 = host_plan(3, 9, 2, method=I.METHOD_DENSE_FD)   # dense FD takes any n > p
+    assert rc == 0, I.lib.iffd_last_error()
+    assert I.lib.iffd_plan_set_geometry(h5, I.GEOMETRY_PLATE, par(1.0, 2.0, 1.0), 3) == I.E_INVAL
+    assert b"even" in I.lib.iffd_last_error()
+    I.lib.iffd_plan_destroy(h5)
 
 
 @pytest.mark.parametrize("n", [16, 24])

@@ -103,6 +103,11 @@ MIXED_CUBE_DIRICHLET = ((1, 0), (0, 1), (0, 0))
 # the map's (r_in, r_out, H)
 ANNULUS_DIRICHLET = ((0, 0), (0, 0), (1, 0))
 ANNULUS_PARAMS = (1.0, 2.0, 1.0)
+# the plate with a hole (the stand-in for Section 7's plate with a C^0 line):
+# the map's (R, L, H), the same bottom-face Dirichlet condition as the
+# annulus, and the C^0 plane xi_1 = 1/2 as the knot (n_1 / 2, p) of direction 1
+PLATE_PARAMS = (1.0, 2.0, 1.0)
+PLATE_DIRICHLET = ANNULUS_DIRICHLET
 
 
 def workload_rhs(name: str, p: int | None = None) -> np.ndarray:
