@@ -302,6 +302,22 @@ def mixed_bc(torch, iffd, ps=(3,), n=256, steps=20, solves=10, prec="f32"):
         msk = ag.elapsed_time(bg) / steps
         latk, stk = time_solves(torch, plk, fk, solves)
         del plk, fk, zk
+        # dense FD (every direction's exact eigendecomposition) on the same system
+        pfd = iffd.Plan(3, [n] * 3, [p] * 3, method="dense", precision=prec,
+                        dirichlet=workloads.MIXED_CUBE_DIRICHLET)
+        zf = torch.empty_like(f)
+        for _ in range(3):
+            pfd.apply(f, out=zf)
+        torch.cuda.synchronize()
+        torch.cuda._sleep(int(cpm * 5.0))
+        ag.record()
+        for _ in range(steps):
+            pfd.apply(f, out=zf)
+        bg.record()
+        torch.cuda.synchronize()
+        apfd = ag.elapsed_time(bg) / steps
+        latfd, stfd = time_solves(torch, pfd, f, solves)
+        del pfd, zf
         rows.append({
             "n": n, "p": p, "shape": list(pl.shape), "dofs": N, "dtype": prec,
             "generic_basis": {"ms_per_apply": round(msg, 5),
