@@ -21,9 +21,9 @@
 // Deterministic: no result depends on scheduling.
 //
 // Every map is built from one-dimensional factors (the bump's sin(pi xi_k),
-// the annulus' radius and circle, the plate's circle and outer sides), so each
-// workgroup first evaluates those factors at the p_k + 1 Gauss points of each
-// direction; G at a point is then a few products of them (closed forms in
+// the annulus' radius and circle, the plate's circle and outer sides): the
+// host tabulates them at the p_k + 1 Gauss points of every element and
+// direction, and G at a point is a few products of them (closed forms in
 // geo_metric).
 #include <hip/hip_runtime.h>
 
@@ -31,59 +31,15 @@
 
 namespace iffd {
 
-// factors of the map per direction and Gauss point
-constexpr int GEO_NF = 6;
-
-// the quarter of the unit circle from (1, 0) to (0, 1) as the rational
-// quadratic with control points (1,0), (1,1), (0,1) and weights 1, 1/sqrt 2,
-// 1: c = (c1, c2) and c' at t
-__device__ __forceinline__ void quarter_circle(double t, double c[4]) {
-  const double w = 0.70710678118654752440;
-  const double b0 = (1 - t) * (1 - t), b1 = 2 * t * (1 - t), b2 = t * t;
-  const double db0 = -2 * (1 - t), db1 = 2 - 4 * t, db2 = 2 * t;
-  const double den = b0 + w * b1 + b2, dden = db0 + w * db1 + db2;
-  const double n1 = b0 + w * b1, n2 = w * b1 + b2;
-  const double dn1 = db0 + w * db1, dn2 = w * db1 + db2;
-  c[0] = n1 / den;
-  c[1] = n2 / den;
-  c[2] = (dn1 * den - n1 * dden) / (den * den);
-  c[3] = (dn2 * den - n2 * dden) / (den * den);
-}
-
-// per-direction factors of the map at one Gauss point
+// factors of the map per direction and Gauss point, tabulated on the host
+// with the element tables (geo_map_factors in plan.cpp):
 //   bump:     f = (sin(pi xi), cos(pi xi))
 //   annulus:  direction 1: f = (r(xi)), direction 2: f = (c1, c2, c1', c2')
 //             of the quarter circle at t = xi, direction 3: unused
 //   plate:    direction 1: with the hole's arc R c(xi) and the outer sides
-//             o(xi) ((L, 2 L xi) below xi = 1/2, (2 L (1 - xi), L) above),
-//             f = (o - R c, R c', o' - R c') (two entries each), direction 2:
-//             f = (xi), direction 3: unused
-__device__ __forceinline__ void geo_factors(int kind, const double* par, int k, double xi,
-                                           double f[GEO_NF]) {
-  for (int i = 0; i < GEO_NF; ++i) f[i] = 0.0;
-  if (kind == IFFD_GEOMETRY_BUMP) {
-    sincos(3.14159265358979323846 * xi, &f[0], &f[1]);
-  } else if (kind == IFFD_GEOMETRY_ANNULUS) {
-    if (k == 0) f[0] = par[0] + (par[1] - par[0]) * xi;
-    if (k == 1) quarter_circle(xi, f);
-  } else if (kind == IFFD_GEOMETRY_PLATE) {
-    if (k == 0) {
-      const double R = par[0], L = par[1];
-      double c[4];
-      quarter_circle(xi, c);
-      const bool first = xi < 0.5;   // on the side x = L, else on y = L
-      const double o1 = first ? L : 2 * L * (1 - xi), o2 = first ? 2 * L * xi : L;
-      const double do1 = first ? 0.0 : -2 * L, do2 = first ? 2 * L : 0.0;
-      f[0] = o1 - R * c[0];
-      f[1] = o2 - R * c[1];
-      f[2] = R * c[2];
-      f[3] = R * c[3];
-      f[4] = do1 - R * c[2];
-      f[5] = do2 - R * c[3];
-    }
-    if (k == 1) f[0] = xi;
-  }
-}
+//             o(xi), f = (o - R c, R c', o' - R c') (two entries each),
+//             direction 2: f = (xi), direction 3: unused
+constexpr int GEO_NF = GEO_FACTORS;
 
 // G = |det J| J^{-1} J^{-T} at one point from the factors of the three
 // directions, stored G00 G11 G22 G01 G02 G12 (symmetric), in closed form for
@@ -144,6 +100,7 @@ __device__ __forceinline__ void geo_metric(int kind, const double* par, const do
 // D[e][q][a] of the B-splines e .. e+p (full basis) at them
 struct GeoDir {
   const double* x;
+  const double* F;   // F[e][q][GEO_NF]: the map's factors at the points
   const double* w;
   const double* V;
   const double* D;
@@ -229,7 +186,8 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
     const int ek = k == 0 ? el % d1.n : (k == 1 ? (el / d1.n) % d2.n : el / (d1.n * d2.n));
     if (UNI || q < g.P) {
       tw[ee][k][q] = g.w[(size_t)ek * g.P + q];
-      geo_factors(a.kind, a.par, k, g.x[(size_t)ek * g.P + q], tf[ee][k][q]);
+#pragma unroll
+      for (int i = 0; i < GEO_NF; ++i) tf[ee][k][q][i] = g.F[((size_t)ek * g.P + q) * GEO_NF + i];
     }
   }
   // local coefficients U[a3][a2][a1] (0 for dropped B-splines)
@@ -421,14 +379,16 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
     }
   for (int t = tid; t < ne * P; t += NT) {
     tw1[0][t] = d1.w[(size_t)e10 * P + t];
-    geo_factors(a.kind, a.par, 0, d1.x[(size_t)e10 * P + t], tf1[0][t]);
+#pragma unroll
+    for (int i = 0; i < GEO_NF; ++i) tf1[0][t][i] = d1.F[((size_t)e10 * P + t) * GEO_NF + i];
   }
   if (tid < 2 * P) {
     const int k = tid / P, q = tid - k * P;
     const GeoDir& g = k ? d3 : d2;
     const int e = k ? e3 : e2;
     tw23[k][q] = g.w[(size_t)e * P + q];
-    geo_factors(a.kind, a.par, k + 1, g.x[(size_t)e * P + q], tf23[k][q]);
+#pragma unroll
+    for (int i = 0; i < GEO_NF; ++i) tf23[k][q][i] = g.F[((size_t)e * P + q) * GEO_NF + i];
   }
   const double* xr = x + (size_t)rhs * a.N;
   const int f2 = geo_first(d2, e2) - d2.lo, f3 = geo_first(d3, e3) - d3.lo;
@@ -718,6 +678,7 @@ static GeoArgs geo_args(const Plan& P) {
   for (int k = 0; k < 3; ++k) {
     const GeoPlanDir& g = P.geo.dir[k];
     a.d[k].x = t + g.o_x;
+    a.d[k].F = t + g.o_f;
     a.d[k].w = t + g.o_w;
     a.d[k].V = t + g.o_v;
     a.d[k].D = t + g.o_d;

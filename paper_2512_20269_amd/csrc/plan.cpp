@@ -1523,6 +1523,58 @@ int set_plan_knot(Plan& P, int direction, int k, int mult, std::string& err) {
 // ---------------------------------------------------------------------------
 // Geometry-mapped system matrix: per-direction element tables
 // ---------------------------------------------------------------------------
+// the quarter of the unit circle from (1, 0) to (0, 1) as the rational
+// quadratic with control points (1,0), (1,1), (0,1) and weights 1, 1/sqrt 2,
+// 1: c = (c1, c2) and c' at t
+static void quarter_circle(double t, double c[4]) {
+  const double w = 0.70710678118654752440;
+  const double b0 = (1 - t) * (1 - t), b1 = 2 * t * (1 - t), b2 = t * t;
+  const double db0 = -2 * (1 - t), db1 = 2 - 4 * t, db2 = 2 * t;
+  const double den = b0 + w * b1 + b2, dden = db0 + w * db1 + db2;
+  const double n1 = b0 + w * b1, n2 = w * b1 + b2;
+  const double dn1 = db0 + w * db1, dn2 = w * db1 + db2;
+  c[0] = n1 / den;
+  c[1] = n2 / den;
+  c[2] = (dn1 * den - n1 * dden) / (den * den);
+  c[3] = (dn2 * den - n2 * dden) / (den * den);
+}
+
+// one-dimensional factors of the map along direction k at xi (the element
+// kernels form G from them, closed forms in geo.hip):
+//   bump     f = (sin(pi xi), cos(pi xi))
+//   annulus  direction 1: (r(xi)); direction 2: (c1, c2, c1', c2') at t = xi
+//   plate    direction 1: (o - R c, R c', o' - R c') with the hole's arc R c
+//            and the outer sides o ((L, 2 L xi) below xi = 1/2, (2 L (1 - xi),
+//            L) above); direction 2: (xi)
+static void geo_map_factors(int kind, const double* par, int k, double xi,
+                            double f[GEO_FACTORS]) {
+  for (int i = 0; i < GEO_FACTORS; ++i) f[i] = 0.0;
+  if (kind == IFFD_GEOMETRY_BUMP) {
+    const double pi = 3.14159265358979323846;
+    f[0] = std::sin(pi * xi);
+    f[1] = std::cos(pi * xi);
+  } else if (kind == IFFD_GEOMETRY_ANNULUS) {
+    if (k == 0) f[0] = par[0] + (par[1] - par[0]) * xi;
+    if (k == 1) quarter_circle(xi, f);
+  } else if (kind == IFFD_GEOMETRY_PLATE) {
+    if (k == 0) {
+      const double R = par[0], L = par[1];
+      double c[4];
+      quarter_circle(xi, c);
+      const bool first = xi < 0.5;   // on the side x = L, else on y = L
+      const double o1 = first ? L : 2 * L * (1 - xi), o2 = first ? 2 * L * xi : L;
+      const double do1 = first ? 0.0 : -2 * L, do2 = first ? 2 * L : 0.0;
+      f[0] = o1 - R * c[0];
+      f[1] = o2 - R * c[1];
+      f[2] = R * c[2];
+      f[3] = R * c[3];
+      f[4] = do1 - R * c[2];
+      f[5] = do2 - R * c[3];
+    }
+    if (k == 1) f[0] = xi;
+  }
+}
+
 int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& err) {
   if (P.geo.kind == 0) P.geo.base_total = P.lay.total;
   if (kind == IFFD_GEOMETRY_NONE) {
@@ -1576,6 +1628,7 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
     g.o_w = o; o += n * g.P;
     g.o_v = o; o += n * g.P * g.P;
     g.o_d = o; o += n * g.P * g.P;
+    g.o_f = o; o += n * g.P * GEO_FACTORS;
   }
   G.tab.assign((size_t)o, 0.0);
   std::vector<double> gx, gw, val, der;
@@ -1597,6 +1650,7 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
         const double x = e * h + 0.5 * h * (gx[q] + 1.0);
         G.tab[(size_t)g.o_x + e * g.P + q] = x;
         G.tab[(size_t)g.o_w + e * g.P + q] = 0.5 * h * gw[q];
+        geo_map_factors(kind, G.par, k, x, &G.tab[(size_t)g.o_f + ((size_t)e * g.P + q) * GEO_FACTORS]);
         basis_and_derivative(s, x, p, U, val, der);
         for (int a = 0; a <= p; ++a) {
           G.tab[(size_t)g.o_v + ((size_t)e * g.P + q) * g.P + a] = val[a];

@@ -99,11 +99,13 @@ struct GDir {
 // Geometry-mapped system matrix (iffd_plan_set_geometry): per direction the
 // Gauss points, weights, and the values and derivatives of the p+1 B-splines of
 // every element there (element offsets inside the tables at `off`)
+// factors of a map per direction and Gauss point (the element tables' F)
+#define GEO_FACTORS 6
 struct GeoPlanDir {
   int n = 0, P = 0, lo = 0, m = 0;   // elements, p + 1, full index of kept entry 0, kept
   int kk = 0, rk = 0;                 // breakpoint kk / n repeated rk + 1 times
   int ulo = 0, uhi = -1;              // elements with one shared table (none: ulo > uhi)
-  int o_x = 0, o_w = 0, o_v = 0, o_d = 0;
+  int o_x = 0, o_w = 0, o_v = 0, o_d = 0, o_f = 0;
 };
 struct GeoPlan {
   int kind = 0;   // IFFD_GEOMETRY_*
