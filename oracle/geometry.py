@@ -33,6 +33,11 @@ available; these stand in for them):
              plane xi_1 = 1/2 (from the corner to the hole), the setting of
              Section 7's plate with hole (a C^0 line of the parametrization).
   "linear"   F(xi) = B xi for a fixed 3 x 3 matrix B (pins only).
+
+In 2D (two specs, points with two coordinates) the maps are their cross
+sections: the annulus and the plate without xi_3 (params (r_in, r_out) and
+(R, L); a third value is ignored), the bump F = xi + eps sin(pi xi_1)
+sin(pi xi_2) (1, 1), and "linear" with a 2 x 2 matrix.
 """
 
 from __future__ import annotations
@@ -45,8 +50,10 @@ from .general import kept
 
 
 def jacobian(kind: str, params, X: np.ndarray) -> np.ndarray:
-    """J at the points X (npts x 3): J[q, i, k] = d F_i / d xi_k."""
+    """J at the points X (npts x d, d = 2 or 3): J[q, i, k] = d F_i / d xi_k."""
     X = np.asarray(X, dtype=np.float64)
+    if X.shape[1] == 2:
+        return _jacobian2(kind, params, X)
     npt = X.shape[0]
     J = np.zeros((npt, 3, 3))
     if kind == "bump":
@@ -112,8 +119,29 @@ def jacobian(kind: str, params, X: np.ndarray) -> np.ndarray:
     return J
 
 
+def _jacobian2(kind: str, params, X: np.ndarray) -> np.ndarray:
+    """The 2D maps: the cross sections of the 3D ones."""
+    npt = X.shape[0]
+    if kind == "bump":
+        eps = float(params[0])
+        s, c = np.sin(np.pi * X), np.cos(np.pi * X)
+        grad = np.stack([np.pi * c[:, 0] * s[:, 1], np.pi * s[:, 0] * c[:, 1]], axis=1)
+        J = np.zeros((npt, 2, 2))
+        for i in range(2):
+            J[:, i, i] = 1.0
+            J[:, i, :] += eps * grad
+        return J
+    if kind in ("annulus", "plate"):
+        p3 = (float(params[0]), float(params[1]), 1.0)
+        X3 = np.concatenate([X, np.zeros((npt, 1))], axis=1)
+        return jacobian(kind, p3, X3)[:, :2, :2]
+    if kind == "linear":
+        return np.broadcast_to(np.asarray(params, dtype=np.float64).reshape(2, 2), (npt, 2, 2)).copy()
+    raise ValueError(kind)
+
+
 def coefficient(kind: str, params, X: np.ndarray) -> np.ndarray:
-    """G = |det J| J^{-1} J^{-T} at the points X (npts x 3 x 3)."""
+    """G = |det J| J^{-1} J^{-T} at the points X (npts x d x d)."""
     J = jacobian(kind, params, X)
     Ji = np.linalg.inv(J)
     det = np.abs(np.linalg.det(J))
@@ -155,10 +183,59 @@ def _spec(s):
     return (s[0], s[1], s[2], s[3] if len(s) > 3 else None)
 
 
+def assemble2(specs, kind: str, params) -> sp.csr_matrix:
+    """The 2D A over the kept tensor-product B-splines, index i1 + m1 i2,
+    specs = [(n_k, p_k, D_k[, knot_k])] for k = 1, 2."""
+    specs = [_spec(s) for s in specs]
+    tabs = [element_tables(n, p, kt) for n, p, _, kt in specs]
+    red, m = [], []
+    for n, p, D, kt in specs:
+        nb = n + p + (kt[1] - 1 if kt else 0)
+        idx = np.arange(nb)
+        if 0 in D:
+            idx = idx[1:]
+        if 1 in D:
+            idx = idx[:-1]
+        r = -np.ones(nb, dtype=np.int64)
+        r[idx] = np.arange(len(idx))
+        red.append(r)
+        m.append(len(idx))
+    rows, cols, vals = [], [], []
+    (n1, p1, _, kt1), (n2, p2, _, kt2) = specs
+    for e2 in range(n2):
+        for e1 in range(n1):
+            x1, w1, V1, D1 = (t[e1] for t in tabs[0])
+            x2, w2, V2, D2 = (t[e2] for t in tabs[1])
+            # points ordered (q2, q1)
+            X = np.stack(np.meshgrid(x2, x1, indexing="ij")[::-1], axis=-1).reshape(-1, 2)
+            W = np.outer(w2, w1).reshape(-1)
+            G = coefficient(kind, params, X) * W[:, None, None]
+            # gradients of the local functions (a2, a1) at the points (q2, q1)
+            g1 = np.einsum("jb,ic->jibc", V2, D1)
+            g2 = np.einsum("jb,ic->jibc", D2, V1)
+            nq, nl = X.shape[0], (p1 + 1) * (p2 + 1)
+            grad = np.stack([g1.reshape(nq, nl), g2.reshape(nq, nl)], axis=1)
+            loc = grad.reshape(-1, nl).T @ np.einsum("qkl,qlj->qkj", G, grad).reshape(-1, nl)
+            i2 = red[1][first_function(e2, kt2) + np.arange(p2 + 1)]
+            i1 = red[0][first_function(e1, kt1) + np.arange(p1 + 1)]
+            I2, I1 = np.meshgrid(i2, i1, indexing="ij")
+            okf = ((I2 >= 0) & (I1 >= 0)).reshape(-1)
+            li = np.nonzero(okf)[0]
+            gi = (I1 + m[0] * I2).reshape(-1)[li]
+            rows.append(np.repeat(gi, len(gi)))
+            cols.append(np.tile(gi, len(gi)))
+            vals.append(loc[np.ix_(li, li)].reshape(-1))
+    N = m[0] * m[1]
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N)).tocsr()
+
+
 def assemble(specs, kind: str, params) -> sp.csr_matrix:
     """A over the kept tensor-product B-splines, index i1 + m1 i2 + m1 m2 i3
     (direction 1 fastest), specs = [(n_k, p_k, D_k[, knot_k])] for k = 1, 2, 3
-    (knot_k = (k, mult) or None)."""
+    (knot_k = (k, mult) or None); two specs give the 2D matrix."""
+    if len(specs) == 2:
+        return assemble2(specs, kind, params)
     assert len(specs) == 3
     specs = [_spec(s) for s in specs]
     tabs = [element_tables(n, p, kt) for n, p, _, kt in specs]
@@ -235,7 +312,7 @@ class GeometryOperator:
 
     def matvec(self, X: np.ndarray) -> np.ndarray:
         X = np.asarray(X, dtype=np.float64)
-        lead = X.shape[:-3]
+        lead = X.shape[:-len(self.shape)]
         Xf = X.reshape(-1, int(np.prod(self.shape)))
         Y = (self.A @ Xf.T).T
         return Y.reshape(lead + self.shape)

@@ -294,3 +294,125 @@ def test_repeated_knot_contains_smooth_operator(kind, par):
     # and the knot space is strictly larger: A_knot is SPD on it
     w = np.linalg.eigvalsh(Ak.A.toarray())
     assert w.min() > 0
+
+
+# ---- 2D: the cross sections of the maps ------------------------------------
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_2d_identity_map_gives_A_hat(p):
+    specs = [(6, p, {0, 1}), (7, p, {0})]
+    A = Gm.GeometryOperator(specs, "bump", [0.0])
+    Ahat = G.GeneralPreconditioner(specs, "fd")
+    X = np.random.default_rng(p).standard_normal(A.shape)
+    ref = Ahat.matvec(X)
+    assert A.shape == Ahat.shape
+    assert np.abs(A.matvec(X) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_2d_linear_map_energy(p):
+    """u = a . (B xi) over B([0,1]^2): energy |a|^2 |det B| (a transposed or
+    inverted G, or points in the wrong order, fail it)."""
+    B = np.array([[1.3, 0.4], [-0.3, 0.9]])
+    n = 4
+    A = Gm.GeometryOperator([(n, p, set()), (n + 1, p, set())], "linear", B.reshape(-1))
+    g1 = greville(n, p)
+    g2 = greville(n + 1, p)
+    G2, G1 = np.meshgrid(g2, g1, indexing="ij")
+    a = np.array([0.7, -1.1])
+    c = a @ B
+    U = c[0] * G1 + c[1] * G2
+    e = float(np.vdot(U, A.matvec(U)))
+    exact = float(a @ a) * abs(np.linalg.det(B))
+    assert abs(e - exact) <= 1e-12 * exact
+    assert np.abs(A.matvec(np.ones(A.shape))).max() < 1e-12
+
+
+def greville(n, p):
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    return np.array([knots[i + 1:i + p + 1].mean() for i in range(n + p)])
+
+
+def test_2d_maps():
+    """The 2D maps' Jacobians against differences of their cross sections,
+    the annulus' radial energy (area / (r_out - r_in)^2), one sign of det J
+    on the plate, and its C^0 line xi_1 = 1/2."""
+    X = np.random.default_rng(2).uniform(0.05, 0.95, (40, 2))
+    X3 = np.concatenate([X, np.zeros((40, 1))], axis=1)
+    Ja = Gm.jacobian("annulus", ANNULUS[:2], X)
+    Fa = lambda Y: annulus_map(ANNULUS, np.concatenate([Y, np.zeros((len(Y), 1))], axis=1))[:, :2]
+    assert np.abs(Ja - fd_jacobian2(Fa, X)).max() < 1e-8
+    Xp = X[np.abs(X[:, 0] - 0.5) > 0.01]
+    Fp = lambda Y: plate_map(PLATE, np.concatenate([Y, np.zeros((len(Y), 1))], axis=1))[:, :2]
+    assert np.abs(Gm.jacobian("plate", PLATE[:2], Xp) - fd_jacobian2(Fp, Xp)).max() < 1e-8
+    Jb = Gm.jacobian("bump", [0.07], X)
+    Fb = lambda Y: Y + 0.07 * (np.sin(np.pi * Y[:, 0]) * np.sin(np.pi * Y[:, 1]))[:, None]
+    assert np.abs(Jb - fd_jacobian2(Fb, X)).max() < 1e-8
+    assert np.linalg.det(Gm.jacobian("plate", PLATE[:2], X)).max() < -0.1
+    # the annulus' radial coordinate u = xi_1: |grad u| = 1 / (r_out - r_in)
+    r_in, r_out, _ = ANNULUS
+    n, p = 6, 2
+    A = Gm.GeometryOperator([(n, p, set())] * 2, "annulus", ANNULUS[:2])
+    g = greville(n, p)
+    U = np.broadcast_to(g[None, :], A.shape)
+    area = np.pi / 4 * (r_out ** 2 - r_in ** 2)
+    assert abs(float(np.vdot(U, A.matvec(U))) - area / (r_out - r_in) ** 2) < 1e-6 * area
+    del X3
+
+
+def fd_jacobian2(F, X, h=1e-6):
+    J = np.zeros((X.shape[0], 2, 2))
+    for k in range(2):
+        E = np.zeros(2)
+        E[k] = h
+        J[:, :, k] = (F(X + E) - F(X - E)) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("kind,par", [("bump", [0.08]), ("annulus", ANNULUS[:2]), ("plate", PLATE[:2])])
+def test_2d_section3_bound_and_c0_inclusion(kind, par):
+    n, p = 6, 2
+    specs = [(n, p, {0, 1}), (n, p, {0})]
+    A = Gm.GeometryOperator(specs, kind, par).A.toarray()
+    Ahat = G.GeneralPreconditioner(specs, "fd")
+    N = A.shape[0]
+    Ah = np.stack([Ahat.matvec(e.reshape(Ahat.shape)).reshape(-1) for e in np.eye(N)], axis=1)
+    assert np.abs(A - A.T).max() < 1e-13 * np.abs(A).max()
+    lam = sla.eigh(A, Ah, eigvals_only=True)
+    pts = [Gm.element_tables(nk, pk)[0].reshape(-1) for nk, pk, _ in specs]
+    Xq = np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).reshape(-1, 2)
+    ev = np.linalg.eigvalsh(Gm.coefficient(kind, par, Xq))
+    assert lam.min() >= ev.min() * (1 - 1e-10) and lam.max() <= ev.max() * (1 + 1e-10)
+    # the smooth space inside the space with a C^0 line xi_1 = 1/2
+    kn = (3, p)
+    Ak = Gm.GeometryOperator([(n, p, {0, 1}, kn), (n, p, {0}, None)], kind, par)
+    E = np.kron(np.eye(n + p - 1), _restriction(n, p, {0, 1}, kn))
+    assert np.abs(E.T @ (Ak.A @ E) - A).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_annulus_energy_of_xi1_squared(d):
+    """u = xi_1^2 (in the space for p >= 2) on the annulus, where G varies
+    with xi_1 and xi_2: its energy against int (2 xi_1)^2 G_00 dxi by a fine
+    tensor Gauss rule.  Unlike the constant-gradient energies this pairs each
+    element's gradients with G at the right points (swapped point coordinates
+    fail it)."""
+    from oracle import bspline
+    n, p = 5, 2
+    par = ANNULUS[:2] if d == 2 else ANNULUS
+    A = Gm.GeometryOperator([(n, p, set())] * d, "annulus", par)
+    xs = np.linspace(0, 1, 61)
+    B = bspline.basis(bspline.open_knots(n, p), p, xs)
+    c1 = np.linalg.lstsq(B, xs ** 2, rcond=None)[0]
+    assert np.abs(B @ c1 - xs ** 2).max() < 1e-13
+    U = c1
+    for _ in range(d - 1):
+        U = np.multiply.outer(np.ones(n + p), U)   # constant along xi_2 (, xi_3)
+    e = float(np.vdot(U, A.matvec(U)))
+    gx, gw = np.polynomial.legendre.leggauss(40)
+    t, w = 0.5 * (gx + 1), 0.5 * gw
+    T1, T2 = np.meshgrid(t, t, indexing="ij")
+    X = np.stack([T1.reshape(-1), T2.reshape(-1)] + ([np.zeros(T1.size)] if d == 3 else []), axis=1)
+    G00 = Gm.coefficient("annulus", par, X)[:, 0, 0]
+    exact = float(np.sum(np.outer(w, w).reshape(-1) * (2 * X[:, 0]) ** 2 * G00))
+    assert abs(e - exact) < 1e-6 * exact
