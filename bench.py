@@ -411,20 +411,23 @@ def annulus(torch, iffd, ps=(3,), n=64, steps=20, solves=5, prec="f32"):
     return rows
 
 
-def plate(torch, iffd, ns=(32, 64, 128), ps=(2, 3, 4, 5), solves=3, prec="f32"):
+def plate(torch, iffd, d=3, ns=(32, 64, 128), ps=(2, 3, 4, 5), solves=3, prec="f32"):
     """The plate with a hole whose map is only C^0 across xi_1 = 1/2, on the
     space C^0 there too (the breakpoint n/2 of direction 1 repeated p times,
-    Remark rmk:reduced_regularity), Dirichlet on the bottom face: PCG to 1e-8
-    with IFFD and with dense FD (the stand-in for Table 5)."""
+    Remark rmk:reduced_regularity): PCG to 1e-8 with IFFD and with dense FD
+    (the stand-in for Table 5).  3D: extruded, Dirichlet on the bottom face;
+    2D: the plate itself, Dirichlet on the whole boundary."""
     import workloads
     rows = []
     for n in ns:
         for p in ps:
-            row = {"n": n, "p": p}
+            row = {"d": d, "n": n, "p": p}
             for method in ("fft", "dense"):
-                pl = iffd.Plan(3, [n] * 3, [p] * 3, method=method, precision=prec,
-                               dirichlet=workloads.PLATE_DIRICHLET, knots={1: (n // 2, p)},
-                               geometry=("plate", workloads.PLATE_PARAMS))
+                pl = iffd.Plan(d, [n] * d, [p] * d, method=method, precision=prec,
+                               dirichlet=(workloads.PLATE_DIRICHLET if d == 3
+                                          else ((1, 1), (1, 1))),
+                               knots={1: (n // 2, p)},
+                               geometry=("plate", workloads.PLATE_PARAMS[:d]))
                 f = torch.from_numpy(workloads.uniform_tensor(pl.shape, seed=1)).cuda()
                 lat, st = time_solves(torch, pl, f, solves)
                 row["dofs"] = pl.N
@@ -505,7 +508,8 @@ def main():
     ap.add_argument("--annulus", action="store_true",
                     help="only the thick quarter of annulus of Table 4 (n = 64, p = 2..5)")
     ap.add_argument("--plate", action="store_true",
-                    help="only the plate with a hole and a C^0 plane (n = 32, 64, 128, p = 2..5)")
+                    help="only the plate with a hole and a C^0 line: 2D n = 64, 128, 256 and "
+                         "3D n = 32, 64, 128, p = 2..5")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-fracs", default="0.25,0.5,0.75,0.9")
@@ -559,11 +563,14 @@ def main():
                           "rows": rows}), flush=True)
         return
     if args.plate:
-        rows = plate(torch, iffd, solves=args.solves, prec=args.precision)
-        print(json.dumps({"metric": "PCG iterations and solve time, plate with a C^0 plane",
+        rows = plate(torch, iffd, d=2, ns=(64, 128, 256), solves=args.solves,
+                     prec=args.precision)
+        rows += plate(torch, iffd, d=3, solves=args.solves, prec=args.precision)
+        print(json.dumps({"metric": "PCG iterations and solve time, plate with a C^0 line "
+                                    "(2D) or plane (3D)",
                           "unit": "ms", "n_gpus": 1, "dtype": args.precision,
                           "data": "synthetic",
-                          "config": {"workload": "plate_c0_n32-128_p2-5_uniform"},
+                          "config": {"workload": "plate_c0_2d_n64-256_3d_n32-128_p2-5_uniform"},
                           "rows": rows}), flush=True)
         return
     if args.serve:

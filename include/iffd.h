@@ -162,7 +162,10 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
  * with Gauss-Legendre rules of p_k + 1 points per element and direction,
  * applied matrix-free (per element sum factorization, then a fixed-order
  * gather).  The preconditioners stay those of A-hat, whose condition number
- * against A is bounded by the extremes of G (Section 3).  d = 3, coef_a = 0.
+ * against A is bounded by the extremes of G (Section 3).  d = 2 or 3,
+ * coef_a = 0.  In 2D the maps are the cross sections below (the annulus and
+ * the plate without xi3, params {r_in, r_out} and {R, L}; the bump with
+ * phi = sin(pi xi1) sin(pi xi2)).
  *   IFFD_GEOMETRY_BUMP     params {eps}, |eps| < 0.1: F(xi) = xi + eps phi(xi)
  *                          (1, 1, 1), phi = sin(pi xi1) sin(pi xi2) sin(pi xi3):
  *                          the unit cube with a non-separable parametrization

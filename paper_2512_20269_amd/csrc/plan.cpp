@@ -1582,7 +1582,7 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
     P.geo = GeoPlan{};
     return IFFD_OK;
   }
-  if (P.d != 3) { err = "a mapped domain needs d = 3"; return IFFD_E_UNSUPPORTED; }
+  if (P.d != 2 && P.d != 3) { err = "a mapped domain needs d = 2 or 3"; return IFFD_E_UNSUPPORTED; }
   if (P.coef_a != 0.0) { err = "a mapped domain replaces coef_a; create the plan with coef_a = 0"; return IFFD_E_INVAL; }
   if (P.method != IFFD_METHOD_FFT && P.method != IFFD_METHOD_DENSE_FD) { err = "bad method"; return IFFD_E_INVAL; }
   GeoPlan G;
@@ -1592,14 +1592,17 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
     if (!par || npar < 1 || !(std::fabs(par[0]) < 0.1)) { err = "bump map: params {eps}, |eps| < 0.1"; return IFFD_E_INVAL; }
     G.par[0] = par[0];
   } else if (kind == IFFD_GEOMETRY_ANNULUS) {
-    if (!par || npar < 3 || !(par[0] > 0.0 && par[1] > par[0] && par[2] > 0.0)) {
-      err = "annulus map: params {r_in, r_out, H}, 0 < r_in < r_out, H > 0";
+    // 2D: the cross section {r_in, r_out} (the prism's H is 1 and unused)
+    if (!par || npar < P.d || !(par[0] > 0.0 && par[1] > par[0] && (P.d == 2 || par[2] > 0.0))) {
+      err = P.d == 3 ? "annulus map: params {r_in, r_out, H}, 0 < r_in < r_out, H > 0"
+                     : "annulus map (2D): params {r_in, r_out}, 0 < r_in < r_out";
       return IFFD_E_INVAL;
     }
-    for (int i = 0; i < 3; ++i) G.par[i] = par[i];
+    for (int i = 0; i < 3; ++i) G.par[i] = i < 2 || P.d == 3 ? par[i] : 1.0;
   } else if (kind == IFFD_GEOMETRY_PLATE) {
-    if (!par || npar < 3 || !(par[0] > 0.0 && par[1] > par[0] && par[2] > 0.0)) {
-      err = "plate map: params {R, L, H}, 0 < R < L, H > 0";
+    if (!par || npar < P.d || !(par[0] > 0.0 && par[1] > par[0] && (P.d == 2 || par[2] > 0.0))) {
+      err = P.d == 3 ? "plate map: params {R, L, H}, 0 < R < L, H > 0"
+                     : "plate map (2D): params {R, L}, 0 < R < L";
       return IFFD_E_INVAL;
     }
     const int n1 = P.gen ? P.dirs[0].n : P.n;
@@ -1607,16 +1610,21 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
       err = "plate map: n_1 must be even (the corner plane xi_1 = 1/2 on a breakpoint)";
       return IFFD_E_INVAL;
     }
-    for (int i = 0; i < 3; ++i) G.par[i] = par[i];
+    for (int i = 0; i < 3; ++i) G.par[i] = i < 2 || P.d == 3 ? par[i] : 1.0;
   } else {
     err = "unknown geometry kind";
     return IFFD_E_INVAL;
   }
+  // In 2D the third direction is a single element with one point, V = 1,
+  // D = 0 and w = 1 (factors (1, 0, ..)): the 3D operator then is the 2D one
+  // (no xi_3 derivative, the bump's third gradient entry 0, the prisms' H 1).
   int o = 0;
   for (int k = 0; k < 3; ++k) {
     GeoPlanDir& g = G.dir[k];
     int n, p, lo, m, kk = 0, rk = 0;
-    if (P.gen) {
+    if (k >= P.d) {
+      n = 1; p = 0; lo = 0; m = 1;
+    } else if (P.gen) {
       n = P.dirs[k].n; p = P.dirs[k].p; lo = P.dirs[k].dlo; m = P.dirs[k].m;
       if (P.dirs[k].rk) { kk = P.dirs[k].kk; rk = P.dirs[k].rk; }
     } else {
@@ -1635,6 +1643,16 @@ int build_geometry(Plan& P, int kind, const double* par, int npar, std::string& 
   for (int k = 0; k < 3; ++k) {
     GeoPlanDir& g = G.dir[k];
     const int n = g.n, p = g.P - 1;
+    if (k >= P.d) {   // the 2D plan's dummy direction
+      G.tab[(size_t)g.o_x] = 0.5;
+      G.tab[(size_t)g.o_w] = 1.0;
+      G.tab[(size_t)g.o_v] = 1.0;
+      G.tab[(size_t)g.o_d] = 0.0;
+      G.tab[(size_t)g.o_f] = 1.0;
+      g.ulo = 0;
+      g.uhi = -1;
+      continue;
+    }
     // open knots with the breakpoint kk / n repeated rk more times
     std::vector<double> U;
     for (int i = 0; i <= p; ++i) U.push_back(0.0);

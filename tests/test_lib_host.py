@@ -389,8 +389,15 @@ def test_geometry_host_rules():
     assert info.table_bytes == info0.table_bytes
     assert info.matvec_ws_bytes == info0.matvec_ws_bytes
     I.lib.iffd_plan_destroy(h)
+    # 2D: the cross sections, two parameters for the annulus and the plate
     _, h2 = host_plan(2, 8, 3)
-    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_UNSUPPORTED
+    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_BUMP, par(0.01), 1) == 0
+    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_ANNULUS, par(2.0, 1.0), 2) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_ANNULUS, par(1.0), 1) == I.E_INVAL
+    assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_PLATE, par(1.0, 2.0), 2) == 0
+    info2 = I._Info()
+    assert I.lib.iffd_plan_query(h2, ctypes.byref(info2)) == 0
+    assert info2.matvec_ws_bytes == 8 * 8 ** 2 * 4 ** 2
     I.lib.iffd_plan_destroy(h2)
     _, h3 = host_plan(3, 8, 3, coef_a=0.5)
     assert I.lib.iffd_plan_set_geometry(h3, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_INVAL
