@@ -136,9 +136,11 @@ struct GeoArgs {
 constexpr int GEO_T = 256;     // gather threads per block
 constexpr int GEO_MAXP = 9;    // p <= 8
 
-template <int PM>
+// PM3: the capacity along xi_3 (PM, or 1 for a 2D plan's one-point third
+// direction, which then packs more elements into a workgroup)
+template <int PM, int PM3 = PM>
 struct GeoCfg {
-  static constexpr int CUBE = PM * PM * PM;
+  static constexpr int CUBE = PM * PM * PM3;
   // lanes: one per local index up to 256 (one to four wavefronts)
   static constexpr int NT = CUBE <= 64 ? 64 : (CUBE <= 128 ? 128 : 256);
   static constexpr int E = 2 * CUBE > NT ? 1 : NT / CUBE;   // elements per workgroup
@@ -149,11 +151,11 @@ struct GeoCfg {
 // the E * nloc (element, local index) pairs; every stage ends in a barrier.
 // UNI: P_1 = P_2 = P_3 = PM, known at compile time (every index split by a
 // constant); otherwise the P_k <= PM come from the plan.
-template <int PM, bool UNI>
-__global__ void __launch_bounds__(GeoCfg<PM>::NT)
+template <int PM, bool UNI, int PM3 = PM>
+__global__ void __launch_bounds__((GeoCfg<PM, PM3>::NT))
 geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
             const double* __restrict__ active, int astride) {
-  using C = GeoCfg<PM>;
+  using C = GeoCfg<PM, PM3>;
   constexpr int E = C::E, CU = C::CUBE, PP = C::PP, NT = C::NT;
   __shared__ double U[E * CU], A1[E * CU], A2[E * CU];
   __shared__ double B1[E * CU], B2[E * CU], B3[E * CU];
@@ -722,6 +724,13 @@ static void launch_geo_element(const GeoArgs& a, const double* x, double* loc, d
     hipLaunchKernelGGL(geo_element_lines<PM>, dim3(nwg, (unsigned)nrhs), dim3(NT), 0, s, x, loc,
                        a, act, as);
     hipLaunchKernelGGL(geo_gather_uni<PM>, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,
+                       (const double*)loc, y, a, nb, x, fres, part, npart, act, as);
+  } else if (a.d[2].P == 1) {   // 2D: the one-point third direction
+    constexpr int E = GeoCfg<PM, 1>::E, NT = GeoCfg<PM, 1>::NT;
+    const unsigned nwg = (unsigned)((a.nel + E - 1) / E);
+    hipLaunchKernelGGL((geo_element<PM, false, 1>), dim3(nwg, (unsigned)nrhs), dim3(NT), 0, s, x,
+                       loc, a, act, as);
+    hipLaunchKernelGGL(geo_gather, dim3((unsigned)(nb * nrhs)), dim3(GEO_T), 0, s,
                        (const double*)loc, y, a, nb, x, fres, part, npart, act, as);
   } else {
     constexpr int E = GeoCfg<PM>::E, NT = GeoCfg<PM>::NT;
