@@ -406,3 +406,26 @@ def test_2d_plate_c0_counts_robust_on_gpu():
             assert max(c) - min(c) <= 3, (p, method, c)
         for n in (64, 128, 256):
             assert counts[n, p, "fft"] <= 1.15 * counts[n, p, "dense"], (n, p)
+
+
+@pytest.mark.parametrize("n,p,geometry,method", [
+    (16, 3, ("bump", (0.05,)), "fft"),
+    (16, 2, ("annulus", (1.0, 2.0)), "fft"),
+    (24, 4, ("plate", (1.0, 2.0)), "dense"),
+])
+def test_2d_uniform_plan_geometry_matches_oracle(n, p, geometry, method):
+    """2D mapped domains on a uniform plan (Dirichlet on every side, one n
+    and p), operator and FP64 PCG iterations against the oracle."""
+    specs = [(n, p, {0, 1})] * 2
+    op = Gm.GeometryOperator(specs, *geometry)
+    pl = I.Plan(2, n, p, method=method, precision="f64", geometry=geometry)
+    assert pl.shape == op.shape
+    X = workloads.uniform_tensor(pl.shape, seed=7)
+    y, yo = host(pl.matvec(dev(X))), op.matvec(X)
+    assert rel(y, yo) <= 1e-13
+    pre = G.GeneralPreconditioner([(n, p, {0, 1})] * 2, "iffd_b" if method == "fft" else "fd")
+    _, it_o, conv_o, *_ = krylov.pcg(op.matvec, pre.apply, X, tol=1e-8, maxit=300)
+    _, st = pl.solve(dev(X), rtol=1e-8, maxit=300)
+    print(f"2D uniform {geometry[0]} n={n} p={p} {method}: {st[0]['iterations']} (oracle {it_o})",
+          flush=True)
+    assert conv_o and st[0]["converged"] and st[0]["iterations"] == it_o
