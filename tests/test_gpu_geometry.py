@@ -429,3 +429,27 @@ def test_2d_uniform_plan_geometry_matches_oracle(n, p, geometry, method):
     print(f"2D uniform {geometry[0]} n={n} p={p} {method}: {st[0]['iterations']} (oracle {it_o})",
           flush=True)
     assert conv_o and st[0]["converged"] and st[0]["iterations"] == it_o
+
+
+@pytest.mark.parametrize("geometry,d", [(ANNULUS, 3), (PLATE, 3), (("plate", (1.0, 2.0)), 2)])
+def test_fd_kappa_within_section3_bound(geometry, d):
+    """Section 3: with FD (the exact inverse of A-hat) the preconditioned
+    operator's spectrum lies inside the extremes of G over the quadrature
+    points, so the PCG's Lanczos estimate of kappa(A-hat^{-1} A) is at most
+    max G / min G (eigenvalues of G at every Gauss point, from the oracle's
+    map)."""
+    n, p = 16, 2
+    dl = BOTTOM if d == 3 else ((1, 1), (1, 1))
+    specs = [(n, p, set(DSET[tuple(x)])) for x in dl]
+    pl = I.Plan(d, [n] * d, [p] * d, method="dense", precision="f64",
+                dirichlet=[tuple(x) for x in dl], geometry=geometry)
+    f = workloads.uniform_tensor(pl.shape, seed=3)
+    _, st = pl.solve(dev(f), rtol=1e-10, maxit=300)
+    pts = [Gm.element_tables(nk, pk)[0].reshape(-1) for nk, pk, _ in specs]
+    X = np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).reshape(-1, d)
+    ev = np.linalg.eigvalsh(Gm.coefficient(geometry[0], geometry[1], X))
+    bound = ev.max() / ev.min()
+    print(f"{geometry[0]} {d}D: kappa_est {st[0]['kappa_est']:.3f}, Section 3 bound {bound:.3f}",
+          flush=True)
+    assert st[0]["converged"]
+    assert 1.0 < st[0]["kappa_est"] <= bound * (1 + 1e-6)
