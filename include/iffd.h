@@ -267,7 +267,8 @@ int iffd_plan_set_basis(iffd_plan* plan, int basis);
 /* Host-only, general plans, before iffd_plan_setup (IFFD_E_STATE after).
  * Reduced regularity (Remark rmk:reduced_regularity, eq:reg_space2): the
  * breakpoint k / n_d of direction `direction` (1..d) is repeated `mult` times
- * (1 <= mult <= p_d; mult = 1 restores maximal smoothness), so the spline
+ * (1 <= mult <= p_d; mult = 1 restores maximal smoothness; one knot per
+ * direction: a later call on the same direction replaces it), so the spline
  * space of that direction is C^{p - mult} there and has mult - 1 more
  * B-splines (m grows by mult - 1; iffd_plan_query_dirs reports it).  S^reg
  * stays the space of C^{p-1} functions with the end conditions of

@@ -205,7 +205,7 @@ class Plan:
     iffd_plan_set_basis).
     knots: general plans, {direction (1-based): (k, mult)}: the breakpoint
     k / n of that direction repeated mult times (reduced regularity,
-    iffd_plan_set_knot)."""
+    iffd_plan_set_knot; one knot per direction)."""
 
     def __init__(self, d: int, n, p, method: str = "fft", precision: str = "f32",
                  max_rhs: int = 1, device=None, coef_a: float = 0.0, dirichlet=None,
