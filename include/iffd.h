@@ -192,9 +192,9 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
  * tables use the refined knot vector and the p+1 B-splines nonzero on element
  * e start at e, or at e + mult - 1 past the knot, so A is the mapped
  * operator of the reduced-regularity space (Remark rmk:reduced_regularity).
- * The operator needs a workspace of 8 * n1 n2 n3 (p1+1)(p2+1)(p3+1) bytes per
- * right-hand side (iffd_plan_info.matvec_ws_bytes, included in the PCG
- * state sizes). */
+ * The operator needs a workspace of 8 * ls (p1+1)(p2+1)(p3+1) bytes per
+ * right-hand side, ls = n1 n2 n3 rounded up to a multiple of 64, plus 32
+ * (iffd_plan_info.matvec_ws_bytes, included in the PCG state sizes). */
 int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, int nparams);
 
 /* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan.

@@ -131,9 +131,12 @@ struct GeoArgs {
   int N;      // kept coefficients per right-hand side
   int nloc;   // P1 P2 P3
   int nel;    // n1 n2 n3
+  int ls;     // workspace stride of one local index: nel padded to an odd
+              // multiple of 32 doubles (256 bytes), so that the (p+1)^3 streams
+              // of a workgroup do not start on the same HBM channel
 };
 
-constexpr int GEO_T = 256;     // gather threads per block
+constexpr int GEO_T = 1024;    // gather threads per block (its block count is the PCG partial count)
 constexpr int GEO_MAXP = 9;    // p <= 8
 
 // PM3: the capacity along xi_3 (PM, or 1 for a 2D plan's one-point third
@@ -295,8 +298,8 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
   }
   __syncthreads();
   // back along direction 1: the element's contribution to its local functions,
-  // stored at loc[(rhs nloc + i) nel + el]
-  double* out = loc + (size_t)rhs * nloc * a.nel;
+  // stored at loc[(rhs nloc + i) ls + el]
+  double* out = loc + (size_t)rhs * nloc * a.ls;
   for (int t = tid; t < items; t += NT) {
     const int ee = t / nloc, i = t - ee * nloc;
     const int a1 = i % P1, rest = i / P1;
@@ -304,7 +307,7 @@ geo_element(const double* __restrict__ x, double* __restrict__ loc, GeoArgs a,
     const double* y2 = A2 + ee * CU + rest * P1;
     double s = 0.0;
     for (int q1 = 0; q1 < P1; ++q1) s += td[ee][0][q1 * P1 + a1] * y1[q1] + tv[ee][0][q1 * P1 + a1] * y2[q1];
-    out[(size_t)i * a.nel + el0 + ee] = s;
+    out[(size_t)i * a.ls + el0 + ee] = s;
   }
 }
 
@@ -533,7 +536,7 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
     }
   }
   __syncthreads();
-  // stage 5: line (a2, a3) = (la, lb) along q1 -> a1, to loc[(rhs nloc + i) nel + el]
+  // stage 5: line (a2, a3) = (la, lb) along q1 -> a1, to loc[(rhs nloc + i) ls + el]
   auto stage5 = [&](const double* V, const double* D) {
     if (!live) return;
     const int o = S1 * la + S2 * lb;
@@ -547,9 +550,9 @@ geo_element_lines(const double* __restrict__ x, double* __restrict__ loc, GeoArg
       for (int j = 0; j < P; ++j)
         s[j] += D[q * P + j] * y1 + V[q * P + j] * y2;
     }
-    double* out = loc + ((size_t)rhs * CU + (size_t)P * ln) * a.nel + el0 + ee;
+    double* out = loc + ((size_t)rhs * CU + (size_t)P * ln) * a.ls + el0 + ee;
 #pragma unroll
-    for (int j = 0; j < P; ++j) out[(size_t)j * a.nel] = s[j];
+    for (int j = 0; j < P; ++j) out[(size_t)j * a.ls] = s[j];
   };
   if (u1)
     stage5(V1, D1);
@@ -572,7 +575,7 @@ geo_gather_uni(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a
   const int c = (a.N + nblk - 1) / nblk;
   const int lo = min(a.N, blk * c), hi = min(a.N, lo + c);
   const size_t ro = (size_t)rhs * a.N;
-  const size_t nel = (size_t)a.nel;
+  const size_t nel = (size_t)a.ls;   // the stride of one local index
   const double* lr = loc + (size_t)rhs * (P * P * P) * nel;
   double dot = 0.0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += GEO_T) {
@@ -633,7 +636,7 @@ geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, in
   const int c = (a.N + nblk - 1) / nblk;
   const int lo = min(a.N, blk * c), hi = min(a.N, lo + c);
   const size_t ro = (size_t)rhs * a.N;
-  const double* lr = loc + (size_t)rhs * a.nloc * a.nel;
+  const double* lr = loc + (size_t)rhs * a.nloc * a.ls;
   double dot = 0.0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += GEO_T) {
     const int r1 = i % d1.m, r2 = (i / d1.m) % d2.m, r3 = i / (d1.m * d2.m);
@@ -645,11 +648,11 @@ geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, in
       for (int a2 = 0; a2 < d2.P; ++a2) {
         const int e2 = geo_elem(d2, g2, a2);
         if (e2 < 0 || e2 >= d2.n) continue;
-        const double* row = lr + (size_t)((a3 * d2.P + a2) * d1.P) * a.nel +
+        const double* row = lr + (size_t)((a3 * d2.P + a2) * d1.P) * a.ls +
                             (size_t)d1.n * (e2 + (size_t)d2.n * e3);
         for (int a1 = 0; a1 < d1.P; ++a1) {
           const int e1 = geo_elem(d1, g1, a1);
-          if (e1 >= 0 && e1 < d1.n) s += row[(size_t)a1 * a.nel + e1];
+          if (e1 >= 0 && e1 < d1.n) s += row[(size_t)a1 * a.ls + e1];
         }
       }
     }
@@ -673,6 +676,8 @@ geo_gather(const double* __restrict__ loc, double* __restrict__ y, GeoArgs a, in
     part[(size_t)rhs * npart + blk] = s2;
   }
 }
+
+static int geo_local_stride(int nel) { return (nel + 63) / 64 * 64 + 32; }
 
 static GeoArgs geo_args(const Plan& P) {
   GeoArgs a;
@@ -698,6 +703,7 @@ static GeoArgs geo_args(const Plan& P) {
   a.N = (int)P.N;
   a.nloc = a.d[0].P * a.d[1].P * a.d[2].P;
   a.nel = a.d[0].n * a.d[1].n * a.d[2].n;
+  a.ls = geo_local_stride(a.nel);
   return a;
 }
 
@@ -707,7 +713,7 @@ size_t geo_matvec_ws_bytes(const Plan& P, int nrhs) {
     nel *= (size_t)P.geo.dir[k].n;
     nloc *= (size_t)P.geo.dir[k].P;
   }
-  return 8 * nel * nloc * (size_t)nrhs;
+  return 8 * (size_t)geo_local_stride((int)nel) * nloc * (size_t)nrhs;
 }
 
 int geo_matvec_blocks(const Plan& P) { return pcg_blocks(P); }

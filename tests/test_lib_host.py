@@ -364,9 +364,16 @@ def test_general_plan_sizes_and_errors():
     I.lib.iffd_plan_destroy(h)
 
 
+def geo_ls(nel):
+    """The operator workspace's stride per local index: the element count
+    padded to an odd multiple of 32 doubles."""
+    return (nel + 63) // 64 * 64 + 32
+
+
 def test_geometry_host_rules():
     """iffd_plan_set_geometry: the kinds and their parameter ranges, d = 3,
-    coef_a = 0, the operator workspace 8 n1 n2 n3 (p+1)^3 bytes per RHS, and
+    coef_a = 0, the operator workspace 8 ls (p+1)^3 bytes per RHS (ls: the
+    element count padded to an odd multiple of 32), and
     IFFD_GEOMETRY_NONE restoring the table size."""
     par = lambda *v: (ctypes.c_double * len(v))(*v)
     rc, h = host_plan(3, 8, 3, max_rhs=2)
@@ -382,7 +389,7 @@ def test_geometry_host_rules():
     assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par(1.0, 2.0, 1.0), 3) == 0
     info = I._Info()
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
-    assert info.matvec_ws_bytes == 8 * 8 ** 3 * 4 ** 3 * 2
+    assert info.matvec_ws_bytes == 8 * geo_ls(8 ** 3) * 4 ** 3 * 2
     assert info.table_bytes > info0.table_bytes
     assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_NONE, None, 0) == 0
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
@@ -397,7 +404,7 @@ def test_geometry_host_rules():
     assert I.lib.iffd_plan_set_geometry(h2, I.GEOMETRY_PLATE, par(1.0, 2.0), 2) == 0
     info2 = I._Info()
     assert I.lib.iffd_plan_query(h2, ctypes.byref(info2)) == 0
-    assert info2.matvec_ws_bytes == 8 * 8 ** 2 * 4 ** 2
+    assert info2.matvec_ws_bytes == 8 * geo_ls(8 ** 2) * 4 ** 2
     I.lib.iffd_plan_destroy(h2)
     _, h3 = host_plan(3, 8, 3, coef_a=0.5)
     assert I.lib.iffd_plan_set_geometry(h3, I.GEOMETRY_BUMP, par(0.01), 1) == I.E_INVAL
@@ -475,7 +482,7 @@ def test_basis_rules():
     assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_ANNULUS, par, 3) == 0
     assert I.lib.iffd_plan_set_basis(h, I.BASIS_GENERIC) == 0
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
-    assert info.matvec_ws_bytes == 8 * (16 * 24 * 32) * (4 * 3 * 5)
+    assert info.matvec_ws_bytes == 8 * geo_ls(16 * 24 * 32) * (4 * 3 * 5)
     I.lib.iffd_plan_destroy(h)
 
 
@@ -534,7 +541,7 @@ def test_repeated_knot_rules():
     assert I.query_dirs(h, 3)[0]["m"] == 32 + 3 - 1
     assert I.lib.iffd_plan_set_knot(h, 1, 16, 3) == 0
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
-    assert info.matvec_ws_bytes == 8 * (32 * 24 * 32) * (4 * 3 * 5)   # the elements stay
+    assert info.matvec_ws_bytes == 8 * geo_ls(32 * 24 * 32) * (4 * 3 * 5)   # the elements stay
     assert info.table_bytes > info0.table_bytes
     assert I.lib.iffd_plan_set_geometry(h, I.GEOMETRY_NONE, None, 0) == 0
     assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
