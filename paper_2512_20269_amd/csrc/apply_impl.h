@@ -96,7 +96,7 @@ struct Cfg {
 __host__ __device__ inline size_t up16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct LdsMap {
-  size_t x, blob, g, co, lo, so, lb, dm, pd, total;
+  size_t x, blob, g, co, lo, so, lb, dm, total;
 };
 
 template <typename T, int L, int V>
@@ -115,8 +115,6 @@ __host__ __device__ inline LdsMap lds_map(int m, int n, int n_out, int half, int
   r.so = off;  off = up16(off + sizeof(T) * C::TW);
   r.lb = off;  off = up16(off + sizeof(int) * C::TW);
   r.dm = off;  off = up16(off + sizeof(T) * 2 * C::NTH);
-  // per-wave partial outlier dots of the strided tiles: [waves][n_out][TW]
-  r.pd = off;  off = up16(off + sizeof(T) * ((C::NTH + 63) / 64) * (n_out > 0 ? n_out : 1) * C::TW);
   r.total = off;
   return r;
 }
@@ -488,44 +486,14 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
 
   if (MODE == PASS_FWD || MODE == PASS_MID) {
     // ---- outlier dots; boundary fold into the g slots ----------------------
-    // strided tiles (S > 1): each thread forms partial dots over the rows it
-    // loaded (rows j0 + k JS of line l) inside the two windows; the partials
-    // of the lanes that share a line are summed by shuffles within each wave
-    // and across waves after the next barrier, in a fixed order
-    constexpr bool REGDOT = NTH % TW == 0;
-    const bool regdot = REGDOT && S > 1 && n_out > 0;
-    T* PD = reinterpret_cast<T*>(smem + mp.pd);
-    if (regdot) {
-      constexpr int JS = REGDOT ? NTH / TW : 1;
-      const int l = t & (TW - 1), j0 = t >> LTW;
-      const int cnt = j0 < m ? (m - j0 + JS - 1) / JS : 0;
-      const int kl = min(cnt, j0 < g.wl ? (g.wl - 1 - j0) / JS + 1 : 0);
-      const int kr = max(kl, g.wr <= j0 ? 0 : (g.wr - j0 + JS - 1) / JS);
-      T acc[MAXO];
-#pragma unroll
-      for (int q = 0; q < MAXO; ++q) acc[q] = T(0);
-      auto row = [&](int k) {
-        const int j = j0 + k * JS;
-        const T x = X[l * MP + j];
-#pragma unroll
-        for (int q = 0; q < MAXO; ++q)
-          if (q < n_out) acc[q] += VT[q * m + j] * x;
-      };
-      for (int k = 0; k < kl; ++k) row(k);
-      for (int k = kr; k < cnt; ++k) row(k);
-      constexpr int WL = NTH < 64 ? NTH : 64;   // lanes of a wave
-#pragma unroll
-      for (int q = 0; q < MAXO; ++q) {
-        if (q < n_out) {
-          T a = acc[q];
-          for (int o = TW; o < WL; o <<= 1) a += __shfl_xor(a, o);
-          if ((t & 63) < TW) PD[((t >> 6) * n_out + q) * TW + l] = a;
-        }
-      }
-    } else if (n_out > 0) {
-      // 1 << tl threads per dot (chosen on the host), every thread runs the
-      // same number of rounds so the shuffles see all lanes; the dot runs over
-      // the window entries u < nw, entry j = u (left) or u - wl + wr (right)
+    // 1 << tl threads per dot (chosen on the host) within one wave read the
+    // window entries of their line from the tile in LDS and sum by shuffles,
+    // so no partial crosses a wave (per-wave partials of a strided tile summed
+    // across waves measured slower: that sum ran on a few lanes between two
+    // barriers).  Every thread runs the same number of rounds so the shuffles
+    // see all lanes; the dot runs over the window entries u < nw, entry
+    // j = u (left) or u - wl + wr (right).
+    if (n_out > 0) {
       const int tl = g.tpd_log, tpd = 1 << tl;
       const int ndots = TW * n_out;
       const int per = NTH >> tl;
@@ -576,17 +544,7 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       const int pos = c < half ? c0 + c : m - nbd + (c - half);
       X[l * MP + pos] = GB[l * GW + c];
     }
-    if (regdot) {   // the strided tiles' partial dots, summed wave by wave
-      constexpr int NWV = (NTH + 63) / 64;
-      for (int e = t; e < TW * n_out; e += NTH) {
-        const int l = e & (TW - 1), q = e >> LTW;
-        T sum = T(0);
-#pragma unroll
-        for (int w = 0; w < NWV; ++w) sum += PD[(w * n_out + q) * TW + l];
-        if (MODE == PASS_MID) sum *= fac(l, n_reg + q);   // the outliers take the same scaling
-        CO[l * n_out + q] = sum;
-      }
-    } else if (MODE == PASS_MID) {   // the outlier coefficients take the same scaling
+    if (MODE == PASS_MID) {   // the outlier coefficients take the same scaling
       for (int e = t; e < TW * n_out; e += NTH) {
         const int l = e & (TW - 1), q = e >> LTW;
         CO[l * n_out + q] *= fac(l, n_reg + q);
