@@ -206,7 +206,8 @@ struct GTile {
     const int nbv = cl + cr;
     const int nkw = D.rk ? D.wk1 - D.wk0 : 0;
     const T* EW = D.blob + D.o_ew;
-    for (int w = tid; w < TW * (nbv + no + nkw); w += NTH) {
+    // the short ones (end blocks, knot window) one thread each
+    for (int w = tid; w < TW * (nbv + nkw); w += NTH) {
       const int l = w & (TW - 1), k = w / TW;
       const T* x = X + l * MP;
       T acc = T(0);
@@ -217,17 +218,37 @@ struct GTile {
         const int kk = k - cl;
         for (int r = 0; r < rr; ++r) acc += AR[r * cr + kk] * x[m - rr + r];
         GB[l * 8 + k] = acc;
-      } else if (k < nbv + no) {
-        const int q = k - nbv;
-        const T* v = Vt + q * m;
-        for (int j = 0; j < D.wl; ++j) acc += v[j] * x[j];
-        for (int j = D.kw0; j < D.kw1; ++j) acc += v[j] * x[j];
-        for (int j = D.wr; j < m; ++j) acc += v[j] * x[j];
-        YO[l * 8 + q] = acc;
       } else {
-        const int c = k - nbv - no;
+        const int c = k - nbv;
         for (int i = 0; i < nkw + D.rk; ++i) acc += EW[i * nkw + c] * x[D.wk0 + i];
         KB[l * 16 + c] = acc;
+      }
+    }
+    // the outlier dots over their windows (tens of entries): tpd adjacent
+    // lanes of one wave per dot, summed by shuffles in a fixed order; every
+    // thread runs every round so that the shuffles see all lanes
+    if (no > 0) {
+      const int ndots = TW * no;
+      int tpd = 1;
+      while (tpd < 64 && ndots * tpd * 2 <= NTH) tpd *= 2;
+      const int per = NTH / tpd;
+      const int rounds = (ndots + per - 1) / per;
+      const int sub = tid & (tpd - 1);
+      const int nl = D.wl, nk = D.kw1 - D.kw0, nw = D.wl + nk + (m - D.wr);
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int di = tid / tpd + rd * per;
+        T acc = T(0);
+        if (di < ndots) {
+          const int l = di & (TW - 1), q = di / TW;
+          const T* x = X + l * MP;
+          const T* v = Vt + q * m;
+          for (int u = sub; u < nw; u += tpd) {
+            const int j = u < nl ? u : (u < nl + nk ? D.kw0 + (u - nl) : D.wr + (u - nl - nk));
+            acc += v[j] * x[j];
+          }
+        }
+        for (int o = 1; o < tpd; o <<= 1) acc += __shfl_xor(acc, o);
+        if (sub == 0 && di < ndots) YO[(di & (TW - 1)) * 8 + di / TW] = acc;
       }
     }
     __syncthreads();
