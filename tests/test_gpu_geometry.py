@@ -453,3 +453,16 @@ def test_fd_kappa_within_section3_bound(geometry, d):
           flush=True)
     assert st[0]["converged"]
     assert 1.0 < st[0]["kappa_est"] <= bound * (1 + 1e-6)
+
+
+def test_2d_geometry_matvec_is_deterministic_and_batched():
+    """The 2D operator (one-point third direction, PM^2 items per workgroup):
+    a batch member's result equals its single right-hand side result bit for
+    bit, and repeated calls agree bit for bit."""
+    n, p, dl, knots = (24, 16), (3, 2), ((1, 1), (0, 1)), {1: (12, 3)}
+    pl = plan2(n, p, dl, knots, ("plate", (1.0, 2.0)), max_rhs=3)
+    X = np.stack([workloads.uniform_tensor(pl.shape, seed=s) for s in (21, 22, 23)])
+    y3 = host(pl.matvec(dev(X)))
+    y1 = host(pl.matvec(dev(X[2:3])))
+    assert np.array_equal(y3[2:3], y1)
+    assert np.array_equal(y3, host(pl.matvec(dev(X))))
