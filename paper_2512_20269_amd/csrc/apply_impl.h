@@ -799,7 +799,15 @@ __device__ __forceinline__ void line_pass_body(const Tin* __restrict__ in, Tout*
       const unsigned vo = (unsigned)(base + j0 * S) * sizeof(Tout);
       const int cnt = (m - j0 + JS - 1) / JS;
       const int step = JS * S * (int)sizeof(Tout);
-      for (int k = 0; k < cnt; ++k)
+      // rows k < kl and k >= kr lie in the outlier windows; the rows between
+      // are stored as they are
+      const int kl = MODE == PASS_FWD ? 0 : min(cnt, j0 < g.wl ? (g.wl - 1 - j0) / JS + 1 : 0);
+      const int kr = MODE == PASS_FWD ? 0 : max(kl, g.wr <= j0 ? 0 : (g.wr - j0 + JS - 1) / JS);
+      for (int k = 0; k < kl; ++k)
+        buf_st<Tout>((Tout)value(l, j0 + k * JS, co), rs, vo + (unsigned)(k * step));
+      for (int k = kl; k < kr; ++k)
+        buf_st<Tout>((Tout)X[l * MP + j0 + k * JS], rs, vo + (unsigned)(k * step));
+      for (int k = max(kr, kl); k < cnt; ++k)
         buf_st<Tout>((Tout)value(l, j0 + k * JS, co), rs, vo + (unsigned)(k * step));
     }
   } else {
