@@ -883,6 +883,9 @@ def main():
             # ---- the mapped domain of Table 4 (thick quarter of annulus) --------
             out["annulus"] = annulus(torch, iffd, ps=(3,), n=64, steps=min(args.steps, 20),
                                      solves=max(3, args.solves // 5), prec=args.precision)[0]
+            # ---- the plate with a C^0 line (Table 5's setting, 2D) -------------
+            out["plate"] = plate(torch, iffd, d=2, ns=(256,), ps=(3,),
+                                 solves=max(3, args.solves // 5), prec=args.precision)[0]
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
