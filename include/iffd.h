@@ -156,7 +156,7 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
 
 /* Host-only, before iffd_plan_setup (IFFD_E_STATE after).  Makes the plan's
  * system matrix (iffd_kron_matvec, the PCG entry points) the Galerkin matrix of
- * the Poisson problem on Omega = F([0,1]^3) pulled back to the parameter cube
+ * the Poisson problem on Omega = F([0,1]^d) pulled back to the parameter cube
  * (Section 2):
  *   A_ij = int grad B_i^T G grad B_j dxi,  G = |det J| J^{-1} J^{-T},  J = dF/dxi,
  * with Gauss-Legendre rules of p_k + 1 points per element and direction,
@@ -194,7 +194,8 @@ int iffd_plan_create(iffd_plan** out, int d, int n, int p, const iffd_opts* opts
  * operator of the reduced-regularity space (Remark rmk:reduced_regularity).
  * The operator needs a workspace of 8 * ls (p1+1)(p2+1)(p3+1) bytes per
  * right-hand side, ls = n1 n2 n3 rounded up to a multiple of 64, plus 32
- * (iffd_plan_info.matvec_ws_bytes, included in the PCG state sizes). */
+ * (in 2D n3 = 1 and p3 + 1 = 1; iffd_plan_info.matvec_ws_bytes, included in
+ * the PCG state sizes). */
 int iffd_plan_set_geometry(iffd_plan* plan, int kind, const double* h_params, int nparams);
 
 /* Sizes and dimensions of a plan.  Host-only, never fails on a valid plan.
