@@ -440,6 +440,55 @@ def plate(torch, iffd, d=3, ns=(32, 64, 128), ps=(2, 3, 4, 5), solves=3, prec="f
     return rows
 
 
+def small2d(torch, iffd, ns=(32, 64, 96), p=3, batches=(1, 16, 64, 256, 1024), inner=20,
+            outer=10):
+    """2D FP32 applies of small problems (uniform Dirichlet, p = 3), replayed
+    from HIP graphs of `inner` applies each (so no host work per apply): the
+    small 2-D route (dense Qt, two launches of LDS products) against the
+    three line passes, per batch size, and the route the automatic choice
+    takes for a plan of that batch capacity."""
+    import workloads
+
+    rows = []
+    for n in ns:
+        for b in batches:
+            if n >= 96 and b > 256:
+                continue
+            pl = iffd.Plan(2, n, p, precision="f32", max_rhs=b)
+            auto = pl.route(b)
+            R = workloads.batched_uniform_rhs(2, n, p, list(range(b)))
+            r = torch.from_numpy(R if b > 1 else R[0]).cuda()
+            z = torch.empty_like(r)
+            row = {"n": n, "p": p, "m": pl.shape[0], "nrhs": b, "auto": auto}
+            for rt in ("dense2d", "passes"):
+                pl.set_route(rt)
+                cap = torch.cuda.Stream()
+                cap.wait_stream(torch.cuda.current_stream())
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.stream(cap):
+                    pl.apply(r, out=z)
+                    torch.cuda.synchronize()
+                    with torch.cuda.graph(g, stream=cap):
+                        for _ in range(inner):
+                            pl.apply(r, out=z)
+                torch.cuda.current_stream().wait_stream(cap)
+                g.replay()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(outer):
+                    g.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / (inner * outer)
+                row[rt + "_us"] = round(us, 2)
+                row[rt + "_gdof_s"] = round(b * pl.shape[0] * pl.shape[1] / (us * 1e-6) / 1e9, 2)
+            pl.set_route("auto")
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return rows
+
+
 def sweep_p(torch, ps=(2, 3, 4, 6, 8), n=256, coef=0.0):
     """3D with the smooth right-hand side (8 random-phase sine modes plus 1e-3
     noise, seed 3), degree sweep: FP32 apply error against the FP64 apply, PCG
@@ -489,6 +538,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB with a plain elementwise kernel "
                          "(reference dispatch for HBM byte counters)")
+    ap.add_argument("--small2d", action="store_true",
+                    help="only the small 2D applies (dense route vs line passes, graph-replayed)")
     ap.add_argument("--sweep-p", action="store_true",
                     help="only the 3D n=256 degree sweep (smooth right-hand side)")
     ap.add_argument("--sweep-n", default="",
@@ -561,6 +612,12 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "annulus_n64_p2-5_uniform"},
                           "rows": rows}), flush=True)
+        return
+    if args.small2d:
+        rows = small2d(torch, iffd)
+        print(json.dumps({"metric": "2D FP32 apply of small problems, graph-replayed", "unit": "us",
+                          "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "square_n32-96_p3_small"}, "rows": rows}))
         return
     if args.plate:
         rows = plate(torch, iffd, d=2, ns=(64, 128, 256), solves=args.solves,
@@ -886,6 +943,8 @@ def main():
             # ---- the plate with a C^0 line (Table 5's setting, 2D) -------------
             out["plate"] = plate(torch, iffd, d=2, ns=(256,), ps=(3,),
                                  solves=max(3, args.solves // 5), prec=args.precision)[0]
+            # ---- small 2D problems: the dense route against the line passes ------
+            out["small2d"] = small2d(torch, iffd, ns=(64,), batches=(1, 64, 1024))
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")

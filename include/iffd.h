@@ -405,6 +405,39 @@ int iffd_plan_set_variant(iffd_plan* plan, int pass, int variant);
 int iffd_plan_get_variant(const iffd_plan* plan, int pass);
 int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int reps, void* stream);
 
+/* Small 2-D route of the IFFD apply (eq:preconditioner with Qt of Sections 4
+ * and 6 held densely).  A 2-D plan of the FFT method with an FP32 apply whose
+ * directions all have m <= 128 (and p <= 4, where the input may be rounded
+ * to FP32 before the first product) also keeps, in its tables, each
+ * direction's Qt = [V_reg U Dt^{-1}, V_out Q_out] as a dense FP32 m x m array
+ * and its eigenvalues.  iffd_precond_apply (and iffd_precond_apply_noalloc,
+ * and the plain preconditioner applies of iffd_pcg_solve) can then compute
+ *   Z = Qt_1 ((Qt_1^T R Qt_2) / (lam_1[a] + lam_2[b])) Qt_2^T
+ * as two launches of LDS products: the same P^{-1} r to FP32 rounding, at
+ * 4 m^3 multiply-adds per right-hand side instead of the transforms'
+ * O(m^2 (log m + p)), but without the line passes' barrier chains, which is
+ * what a small apply waits on.  iffd_apply_pass always runs the passes.
+ *   IFFD_ROUTE_AUTO     the dense route where the plan has its tables and
+ *                       max_rhs m_1 m_2 (m_1 + m_2) <= 2^25 (about 500
+ *                       right-hand sides at m = 33, 60 at m = 65, 18 at
+ *                       m = 97; larger batches fill the chip with the line
+ *                       passes), else the passes (the default).  The route
+ *                       depends on the plan only, never on nrhs, so a
+ *                       right-hand side gets the same bits alone and in any
+ *                       batch of the plan;
+ *   IFFD_ROUTE_PASSES   always the line passes;
+ *   IFFD_ROUTE_DENSE2D  always the dense route.
+ * iffd_plan_set_route is host-only; it returns IFFD_E_UNSUPPORTED for
+ * IFFD_ROUTE_DENSE2D on a plan without the dense tables and IFFD_E_INVAL for
+ * another value.  iffd_plan_get_route returns the route an apply of nrhs
+ * (>= 1) right-hand sides takes (IFFD_ROUTE_PASSES or IFFD_ROUTE_DENSE2D),
+ * or a negative status.  Both are valid before and after iffd_plan_setup. */
+#define IFFD_ROUTE_AUTO     0
+#define IFFD_ROUTE_PASSES   1
+#define IFFD_ROUTE_DENSE2D  2
+int iffd_plan_set_route(iffd_plan* plan, int route);
+int iffd_plan_get_route(const iffd_plan* plan, int nrhs);
+
 /* ---- stepped PCG on resident state (continuous batching) -----------------
  * A state buffer holds `nslots` independent PCG solves of one plan: bytes =
  * state_bytes_fixed + nslots * state_bytes_per_slot.  Slots are independent:

@@ -31,6 +31,7 @@ METHOD_FFT, METHOD_DENSE_FD = 0, 1
 PREC_F64, PREC_F32, PREC_F16S, PREC_BF16S = 0, 1, 2, 3
 GEOMETRY_NONE, GEOMETRY_BUMP, GEOMETRY_ANNULUS, GEOMETRY_PLATE = 0, 1, 2, 3
 BASIS_SPECIAL, BASIS_GENERIC = 0, 1
+ROUTE_AUTO, ROUTE_PASSES, ROUTE_DENSE2D = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # IFFD_NOALLOC_SCRATCH_BYTES
 
 TABLE_LAM, TABLE_DT, TABLE_KBAND, TABLE_MBAND, TABLE_V0, TABLE_V1, TABLE_VT = range(7)
@@ -91,6 +92,8 @@ SIGNATURES = {
     "iffd_plan_set_variant": (_I, [_P, _I, _I]),
     "iffd_plan_get_variant": (_I, [_P, _I]),
     "iffd_plan_tune": (_I, [_P, _P, _Z, _I, _P]),
+    "iffd_plan_set_route": (_I, [_P, _I]),
+    "iffd_plan_get_route": (_I, [_P, _I]),
     "iffd_apply_pass": (_I, [_P, _I, _P, _P, _I, _P, _Z, _P]),
     "iffd_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_Stats), _P, _Z, _P]),
     "iffd_pcg_state_init": (_I, [_P, _P, _Z, _I, _P]),
@@ -334,6 +337,19 @@ class Plan:
 
     def variants(self):
         return [lib.iffd_plan_get_variant(self._h, k) for k in range(self.n_passes())]
+
+    def set_route(self, route):
+        """ROUTE_AUTO, ROUTE_PASSES or ROUTE_DENSE2D (or "auto", "passes",
+        "dense2d"): how iffd_precond_apply runs a 2-D plan's apply."""
+        if isinstance(route, str):
+            route = {"auto": ROUTE_AUTO, "passes": ROUTE_PASSES, "dense2d": ROUTE_DENSE2D}[route]
+        _check(lib.iffd_plan_set_route(self._h, int(route)), "plan_set_route")
+
+    def route(self, nrhs: int = 1) -> str:
+        """The route an apply of nrhs right-hand sides takes: "passes" or "dense2d"."""
+        rc = lib.iffd_plan_get_route(self._h, int(nrhs))
+        _check(rc if rc < 0 else 0, "plan_get_route")
+        return "dense2d" if rc == ROUTE_DENSE2D else "passes"
 
     def tune(self, reps: int = 20, stream=None):
         """Time both FFT shapes of every pass on the device and keep the faster."""

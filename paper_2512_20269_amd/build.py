@@ -33,7 +33,7 @@ SOURCES = ["plan.cpp", "api.cpp", "apply.hip",
            "apply_lg_fwd.hip", "apply_lg_bwd.hip", "apply_lg_mid.hip",
            "gen.hip", "gen_la.hip", "gen_lb.hip", "gen_lc.hip", "gen_ld.hip", "gen_le.hip",
            "gen_lf.hip", "gen_lg.hip",
-           "setup.hip", "matvec.hip", "mvroll.hip", "geo.hip", "pcg.hip", "dense.hip", "noalloc.hip"]
+           "setup.hip", "matvec.hip", "mvroll.hip", "geo.hip", "pcg.hip", "dense.hip", "dense2d.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

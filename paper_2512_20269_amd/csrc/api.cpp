@@ -10,6 +10,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "dense2d.h"
 #include "launch.h"
 #include "pcg_state.h"
 #include "plan.h"
@@ -185,6 +186,37 @@ hipError_t upload_geometry(const Plan& P, void* d_tables, hipStream_t s) {
                         hipMemcpyHostToDevice, s);
 }
 
+// Dense Qt = [V_reg U Dt^{-1}, V_out Q_out] of one direction in FP32, row i
+// = dof i, column a = mode a (regular modes, then the Q_out-rotated outlier
+// vectors), and its eigenvalues lam, for the small 2-D route; written once at
+// setup with synchronous copies.
+int put_dense_dir(char* b, size_t dq, size_t dl, int m, int n_reg, const std::vector<double>& Qreg,
+                  const std::vector<double>& Vt, const std::vector<double>& lam) {
+  std::vector<float> q((size_t)m * m), l(m);
+  for (int i = 0; i < m; ++i)
+    for (int a = 0; a < m; ++a)
+      q[(size_t)i * m + a] = (float)(a < n_reg ? Qreg[(size_t)a * m + i] : Vt[(size_t)(a - n_reg) * m + i]);
+  for (int a = 0; a < m; ++a) l[a] = (float)lam[a];
+  hipError_t e = hipMemcpy(b + dq, q.data(), 4 * q.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b + dl, l.data(), 4 * l.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "dense Qt upload");
+  return IFFD_OK;
+}
+
+int upload_dense2d(const Plan& P, char* b) {
+  if (!P.gen) {
+    if (P.Vt.size() != (size_t)P.n_out * P.m) return fail(IFFD_E_STATE, "outlier vectors missing");
+    return put_dense_dir(b, P.lay.dq32, P.lay.dlam32, P.m, P.n_reg, P.Qreg, P.Vt, P.lam);
+  }
+  for (int k = 0; k < 2; ++k) {
+    const GDir& G = P.dirs[k];
+    if (G.Vt.size() != (size_t)G.n_out * G.m) return fail(IFFD_E_STATE, "outlier vectors missing");
+    const int rc = put_dense_dir(b, G.dq32, G.dlam32, G.m, G.n_reg, G.Qreg, G.Vt, G.lam);
+    if (rc != IFFD_OK) return rc;
+  }
+  return IFFD_OK;
+}
+
 int setup_general(Plan& P, void* d_tables, hipStream_t s) {
   std::vector<char> buf(P.lay.total, 0);
   for (int k = 0; k < P.d; ++k) {
@@ -275,6 +307,7 @@ int setup_general(Plan& P, void* d_tables, hipStream_t s) {
     else
       outlier_windows(G.Vt, G.n_out, G.m, G.win32, G.win64);
   }
+  if (P.dense2d) return upload_dense2d(P, b);
   return IFFD_OK;
 }
 
@@ -537,6 +570,10 @@ int iffd_plan_setup(iffd_plan* plan, void* d_tables, size_t table_bytes, void* s
                     hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "blob upload");
   }
+  if (P.dense2d) {
+    const int rc = upload_dense2d(P, (char*)d_tables);
+    if (rc != IFFD_OK) return rc;
+  }
   P.ready = true;
   return IFFD_OK;
 }
@@ -643,6 +680,24 @@ int iffd_plan_get_variant(const iffd_plan* plan, int pass) {
   if (pass < 0 || pass >= 2 * plan->P.d - 1) return fail(IFFD_E_INVAL, "pass out of range");
   if (plan->P.gen) return 1;
   return plan->P.variant[pass];
+}
+
+int iffd_plan_set_route(iffd_plan* plan, int route) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  if (route != IFFD_ROUTE_AUTO && route != IFFD_ROUTE_PASSES && route != IFFD_ROUTE_DENSE2D)
+    return fail(IFFD_E_INVAL, "unknown route");
+  if (route == IFFD_ROUTE_DENSE2D && !plan->P.dense2d)
+    return fail(IFFD_E_UNSUPPORTED,
+                "the dense 2-D route needs d = 2, the FFT method, an FP32 apply with p <= 4 and m <= 128");
+  plan->P.route = route;
+  return IFFD_OK;
+}
+
+int iffd_plan_get_route(const iffd_plan* plan, int nrhs) {
+  if (!plan) return fail(IFFD_E_INVAL, "null argument");
+  if (nrhs < 1) return fail(IFFD_E_INVAL, "nrhs out of range");
+  if (plan->P.method != IFFD_METHOD_FFT) return IFFD_ROUTE_PASSES;
+  return dense2d_route(plan->P, nrhs);
 }
 
 int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int reps, void* stream) {

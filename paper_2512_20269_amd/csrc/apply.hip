@@ -1,6 +1,7 @@
 // IFFD apply: dispatch of the line passes (apply_impl.h) over FFT lengths and
 // the sequence of passes that forms z = P^{-1} r.
 #include "apply_impl.h"
+#include "dense2d.h"
 
 namespace iffd {
 
@@ -101,6 +102,8 @@ hipError_t launch_iffd_pass(const Plan& P, int pass, const double* r, double* z,
 hipError_t launch_iffd_apply(const Plan& P, const double* r, double* z, int nrhs, void* ws,
                              const double* a, int as, hipStream_t s, const PassHook* last,
                              const PassHook* first) {
+  if (!last && !first && dense2d_route(P, nrhs) == IFFD_ROUTE_DENSE2D)
+    return launch_dense2d(P, r, z, nrhs, ws, a, as, s);
   for (int k = 0; k < 2 * P.d - 1; ++k) {
     hipError_t e = launch_iffd_pass(P, k, r, z, nrhs, ws, a, as, s, last, first);
     if (e != hipSuccess) return e;

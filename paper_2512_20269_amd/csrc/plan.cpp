@@ -257,6 +257,18 @@ bool fft_len_supported(int L) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// the small 2-D route needs both directions' dense Qt in FP32 with the input
+// rounded to FP32 before its first product (so not where first64 is set)
+static bool dense2d_ok(const Plan& P) {
+  if (P.d != 2 || P.method != IFFD_METHOD_FFT || P.prec != IFFD_PREC_F32 || P.first64) return false;
+  if (!P.gen) return P.m <= kDenseMax && P.Qreg.size() == (size_t)P.n_reg * P.m;
+  for (int k = 0; k < 2; ++k) {
+    const GDir& G = P.dirs[k];
+    if (G.m > kDenseMax || G.Qreg.size() != (size_t)G.n_reg * G.m) return false;
+  }
+  return true;
+}
+
 void compute_layout(Plan& P) {
   TableLayout& t = P.lay;
   {
@@ -316,6 +328,9 @@ void compute_layout(Plan& P) {
   t.qfd16 = take(f16 ? 2 * mm : 8);
   t.qtfd16 = take(f16 ? 2 * mm : 8);
   t.qs16 = take(8);
+  P.dense2d = dense2d_ok(P);
+  t.dq32 = take(P.dense2d ? 4 * (size_t)m * m : 8);
+  t.dlam32 = take(P.dense2d ? 4 * (size_t)m : 8);
   t.stat64 = take(8);
   t.blob64 = take(8 * (size_t)P.blob_len);
   t.blob32 = take(4 * (size_t)P.blob_len);
@@ -733,6 +748,7 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
   std::vector<double> sintab(period);
   for (int k = 0; k < period; ++k) sintab[k] = (double)std::sin(2 * kPi * k / period);
   P.Dt.assign(nr, 0.0);
+  P.Qreg.assign(m <= kDenseMax ? (size_t)nr * m : 0, 0.0);
   std::vector<double> u(nr), v(m), mv(m);
   for (int j = 1; j <= nr; ++j) {
     for (int i = 1; i <= nr; ++i) {
@@ -755,6 +771,8 @@ int build_plan(Plan& P, int d, int n, int p, const iffd_opts* opts, std::string&
     double sm = 0;
     for (int i = 0; i < m; ++i) sm += v[i] * mv[i];
     P.Dt[j - 1] = std::sqrt(sm);
+    if (!P.Qreg.empty())
+      for (int i = 0; i < m; ++i) P.Qreg[(size_t)(j - 1) * m + i] = v[i] / P.Dt[j - 1];
     P.lam[j - 1] = lambda_reg_closed(n, p, j);
     P.s[j - 1] = 1.0 / sm;
   }
@@ -1141,6 +1159,7 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err, int kk 
   G.lam.assign(m, 0.0);
   G.s.assign(m, 1.0);
   G.Dt.assign(nrg, 0.0);
+  G.Qreg.assign(m <= kDenseMax ? (size_t)nrg * m : 0, 0.0);
   std::vector<double> u(nrg), vo(mo), v(m), mv(m);
   for (int t = 0; t < nrg; ++t) {
     for (int s = 0; s < nrg; ++s) {
@@ -1171,6 +1190,8 @@ int build_dir(GDir& G, int n, int p, int dlo, int dhi, std::string& err, int kk 
     double sm = 0;
     for (int i = 0; i < m; ++i) sm += v[i] * mv[i];
     G.Dt[t] = std::sqrt(sm);
+    if (!G.Qreg.empty())
+      for (int i = 0; i < m; ++i) G.Qreg[(size_t)t * m + i] = v[i] / G.Dt[t];
     G.s[t] = 1.0 / sm;
     G.lam[t] = lambda_reg_half(n, p, 2 * t + G.tau2);
   }
@@ -1308,6 +1329,7 @@ int make_generic(GDir& G, std::string& err) {
   double lmax = 0.0;
   for (int t = 0; t < nr; ++t) lmax = std::max(lmax, G.lam[t]);
   std::vector<double> w(nr), v(m);
+  G.Qreg.assign(m <= kDenseMax ? (size_t)nr * m : 0, 0.0);
   for (int t = 0; t < nr; ++t) {
     for (int i = 0; i < nr; ++i) {
       const long long a = ((long long)(2 * i + G.sig2) * (2 * t + G.tau2) + 2LL * n * G.beta) % per;
@@ -1338,6 +1360,8 @@ int make_generic(GDir& G, std::string& err) {
     }
     G.s[t] = 1.0 / sm;
     G.Dt[t] = std::sqrt(sm);
+    if (!G.Qreg.empty())
+      for (int i = 0; i < m; ++i) G.Qreg[(size_t)t * m + i] = v[i] / G.Dt[t];
   }
   G.AL = AL;
   G.AR = AR;
@@ -1362,6 +1386,8 @@ void compute_layout_general(Plan& P) {
   };
   int pm = 1;
   for (int k = 0; k < P.d; ++k) pm = std::max(pm, P.dirs[k].p);
+  P.dense2d = dense2d_ok(P);
+  const bool dense = P.dense2d;
   for (int k = 0; k < P.d; ++k) {
     GDir& G = P.dirs[k];
     G.pm = pm;
@@ -1390,6 +1416,11 @@ void compute_layout_general(Plan& P) {
       G.fq32 = take(4 * mm);
       G.fqt32 = take(4 * mm);
       G.flam32 = take((size_t)4 * G.m);
+    }
+    G.dq32 = G.dlam32 = 0;
+    if (dense) {
+      G.dq32 = take((size_t)4 * G.m * G.m);
+      G.dlam32 = take((size_t)4 * G.m);
     }
     G.ao64 = take((size_t)8 * G.n_out * G.n_out);
     G.bo64 = take((size_t)8 * G.n_out * G.n_out);

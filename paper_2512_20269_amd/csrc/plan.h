@@ -21,6 +21,7 @@ struct TableLayout {
   size_t lam32, s32, v0_32, v1_32, vt32, twl32, twp32;
   size_t qfd32, qtfd32, lamfd32;
   size_t qfd16, qtfd16, qs16;  // dense FD in FP16: Q / s_Q, Q^T / s_Q, s_Q (FP32)
+  size_t dq32, dlam32;         // small 2-D route: dense Qt (m x m, row = dof) and lam, FP32
   size_t stat64;  // setup status word written by the outlier setup kernel (0 = ok)
   size_t unit64;  // general 2D plans: the third direction's band rows, K = 0 and M = 1
   size_t total;
@@ -41,6 +42,7 @@ struct StateLayout {
 };
 
 constexpr int kHist = 256;  // alpha/beta history kept per slot for Lanczos
+constexpr int kDenseMax = 128;  // largest m of the small 2-D route (its LDS tiles)
 
 // One direction of a general plan (iffd_plan_create_general): its own n, p and
 // boundary conditions.  The spline space drops B_0 when x = 0 is a Dirichlet
@@ -91,6 +93,12 @@ struct GDir {
   // offsets of Q, Q^T and lamfd in the tables (FP64 and FP32 copies)
   std::vector<double> Qfd, lamfd;
   size_t fq64 = 0, fqt64 = 0, flam64 = 0, fq32 = 0, fqt32 = 0, flam32 = 0;
+  // dense form of Qt = [V_reg U Dt^{-1}, V_out Q_out] for the small 2-D route:
+  // row t < n_reg holds V_reg U e_t / Dt_t (m values, kept while building when
+  // m <= kDenseMax), and the byte offsets of Qt (FP32, row i = dof i) and of
+  // lam (FP32) in the tables
+  std::vector<double> Qreg;
+  size_t dq32 = 0, dlam32 = 0;
   int len = 0;
   size_t blob64 = 0, blob32 = 0;            // byte offsets of the blobs in the table buffer
   size_t ao64 = 0, bo64 = 0, vout64 = 0, stat64 = 0;  // outlier setup inputs / status (FP64)
@@ -153,6 +161,15 @@ struct Plan {
   // rounded to FP32 before its first transform (set for p >= 5, where the
   // mass matrices' small eigenvalues amplify that rounding)
   bool first64 = false;
+
+  // small 2-D route (IFFD_ROUTE_DENSE2D): both directions' Qt held densely
+  // and applied as two launches of LDS products instead of the three line
+  // passes.  dense2d: the plan qualifies (d = 2, FFT method, FP32 apply
+  // without first64, every m <= kDenseMax); route: IFFD_ROUTE_*; Qreg: as
+  // GDir::Qreg for uniform plans
+  bool dense2d = false;
+  int route = 0;
+  std::vector<double> Qreg;
 
   // general plans: per-direction n, p and boundary conditions (dirs[0] is
   // direction 1, the fastest index); n, p, m, n_reg, n_out above then hold

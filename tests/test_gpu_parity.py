@@ -106,10 +106,19 @@ APPLY_CASES = [(2, 8, 3), (2, 16, 2), (2, 16, 3), (2, 24, 4), (2, 12, 5), (2, 32
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("d,n,p", APPLY_CASES)
 def test_apply_matches_oracle(d, n, p, prec):
+    """Plans with the small 2-D route (FP32, p <= 4, m <= 128) are checked
+    on both routes."""
     r = workloads.uniform_rhs(d, n, p, seed=100 * d + n + p)
-    z = host(plan(d, n, p, prec).apply(dev(r)))
+    pl = plan(d, n, p, prec)
     zo = oracle(d, n, p).apply(r)
-    check(z, zo, TOL[prec], d, p, f"apply d={d} n={n} p={p} {prec}")
+    routes = ("dense2d", "passes") if pl.route() == "dense2d" else ("auto",)
+    try:
+        for rt in routes:
+            pl.set_route(rt)
+            z = host(pl.apply(dev(r)))
+            check(z, zo, TOL[prec], d, p, f"apply d={d} n={n} p={p} {prec} {rt}")
+    finally:
+        pl.set_route("auto")
 
 
 @pytest.mark.parametrize("d,n,p", [(2, 16, 3), (2, 64, 3), (3, 16, 3), (3, 12, 4), (3, 24, 8),
@@ -306,6 +315,7 @@ def test_fft_variants_and_tuner(d, n, p):
     zo = oracle(d, n, p).apply(r)
     for prec in ("f64", "f32"):
         pl = I.Plan(d, n, p, precision=prec)
+        pl.set_route("passes")
         for v in (0, 1, 2, 3, 4):
             for k in range(pl.n_passes()):
                 pl.set_variant(k, v)

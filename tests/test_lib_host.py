@@ -570,3 +570,69 @@ def test_general_dense_fd_eigenvalues_match_oracle(ends):
         scale = max(abs(lam_o).max(), 1.0)
         assert np.abs(np.sort(lam) - np.sort(lam_o)).max() <= 1e-9 * scale, (p, ends)
         I.lib.iffd_plan_destroy(h)
+
+
+def _route(h, nrhs):
+    return I.lib.iffd_plan_get_route(h, nrhs)
+
+
+def test_dense2d_route_rules():
+    """The small 2-D route: which plans hold the dense Qt tables, the automatic
+    choice by batch size, the setter's errors, and the table bytes it adds
+    (one FP32 m x m array and m eigenvalues per direction)."""
+    rc, h = host_plan(2, 64, 3)
+    assert rc == 0, I.lib.iffd_last_error()
+    m = O.dims(64, 3)[0]
+    assert _route(h, 1) == I.ROUTE_DENSE2D and _route(h, 4096) == I.ROUTE_DENSE2D
+    # the automatic choice looks at the plan's batch capacity only
+    for max_rhs, want in ((61, I.ROUTE_DENSE2D), (62, I.ROUTE_PASSES)):
+        rc, hb = host_plan(2, 64, 3, max_rhs=max_rhs)
+        assert rc == 0 and m * m * 2 * m * 61 <= 2 ** 25 < m * m * 2 * m * 62
+        assert _route(hb, 1) == want and _route(hb, max_rhs) == want
+        assert I.lib.iffd_plan_set_route(hb, I.ROUTE_DENSE2D) == 0
+        assert _route(hb, 1) == I.ROUTE_DENSE2D
+        I.lib.iffd_plan_destroy(hb)
+    assert I.lib.iffd_plan_set_route(h, I.ROUTE_PASSES) == 0
+    assert _route(h, 1) == I.ROUTE_PASSES
+    assert I.lib.iffd_plan_set_route(h, I.ROUTE_DENSE2D) == 0
+    assert _route(h, 7) == I.ROUTE_DENSE2D
+    assert I.lib.iffd_plan_set_route(h, 3) == I.E_INVAL
+    assert I.lib.iffd_plan_set_route(h, -1) == I.E_INVAL
+    assert _route(h, 0) == I.E_INVAL
+    info = I._Info()
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    dense_bytes = info.table_bytes
+    I.lib.iffd_plan_destroy(h)
+    # the same plan with the passes only (FP64 apply) has no dense tables
+    rc, h = host_plan(2, 64, 3, prec=I.PREC_F64)
+    assert rc == 0
+    assert _route(h, 1) == I.ROUTE_PASSES
+    assert I.lib.iffd_plan_set_route(h, I.ROUTE_DENSE2D) == I.E_UNSUPPORTED
+    assert I.lib.iffd_plan_set_route(h, I.ROUTE_AUTO) == 0
+    I.lib.iffd_plan_destroy(h)
+    rc, h = host_plan(2, 64, 3)
+    assert I.lib.iffd_plan_query(h, ctypes.byref(info)) == 0
+    assert dense_bytes == info.table_bytes
+    I.lib.iffd_plan_destroy(h)
+    # not eligible: 3-D, m > 128, p >= 5 in FP32, dense FD
+    for d, n, p, method in [(3, 16, 3, I.METHOD_FFT), (2, 128, 3, I.METHOD_FFT),
+                            (2, 64, 5, I.METHOD_FFT), (2, 64, 3, I.METHOD_DENSE_FD)]:
+        rc, h = host_plan(d, n, p, method)
+        assert rc == 0, (d, n, p)
+        assert _route(h, 1) == I.ROUTE_PASSES, (d, n, p, method)
+        assert I.lib.iffd_plan_set_route(h, I.ROUTE_DENSE2D) == I.E_UNSUPPORTED
+        I.lib.iffd_plan_destroy(h)
+    # the largest FFT size below the limit: n = 96, m = 98 at p = 4
+    rc, h = host_plan(2, 96, 4)
+    assert rc == 0 and O.dims(96, 4)[0] == 98 and _route(h, 1) == I.ROUTE_DENSE2D
+    I.lib.iffd_plan_destroy(h)
+    # general 2-D plans: per-direction sizes and ends, a repeated knot
+    rc, h = I.create_general(2, [48, 32], [3, 4], [(1, 0), (0, 1)])
+    assert rc == 0, I.lib.iffd_last_error()
+    assert _route(h, 1) == I.ROUTE_DENSE2D
+    assert I.lib.iffd_plan_set_knot(h, 1, 24, 2) == 0, I.lib.iffd_last_error()
+    assert _route(h, 1) == I.ROUTE_DENSE2D
+    I.lib.iffd_plan_destroy(h)
+    rc, h = I.create_general(2, [48, 128], [3, 3], [(1, 1), (1, 1)])
+    assert rc == 0 and _route(h, 1) == I.ROUTE_PASSES
+    I.lib.iffd_plan_destroy(h)
