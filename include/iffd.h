@@ -418,8 +418,8 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
  * O(m^2 (log m + p)), but without the line passes' barrier chains, which is
  * what a small apply waits on.  iffd_apply_pass always runs the passes.
  *   IFFD_ROUTE_AUTO     the dense route where the plan has its tables and
- *                       max_rhs m_1 m_2 (m_1 + m_2) <= 2^25 (about 500
- *                       right-hand sides at m = 33, 60 at m = 65, 18 at
+ *                       max_rhs m_1 m_2 (m_1 + m_2) <= 2^24 (233
+ *                       right-hand sides at m = 33, 30 at m = 65, 9 at
  *                       m = 97; larger batches fill the chip with the line
  *                       passes), else the passes (the default).  The route
  *                       depends on the plan only, never on nrhs, so a

@@ -22,10 +22,10 @@ size_t dense2d_lds_b(int m1);
 
 // IFFD_ROUTE_AUTO takes the dense route when a full batch of the plan is at
 // most this many multiply-adds per product pair (max_rhs m1 m2 (m1 + m2)):
-// measured on the FP32 apply, the dense route wins up to about 500
-// right-hand sides at m = 33, 60 at m = 65 and 20 at m = 97, where a batch
-// of line passes starts to fill the chip.
-constexpr double kDenseAutoWork = 33554432.0;   // 2^25
+// measured on the FP32 apply, the dense route wins up to about 160
+// right-hand sides at m = 33, 70 at m = 65 and 35 at m = 97, where a batch
+// of line passes starts to fill the chip; the bound keeps below all three.
+constexpr double kDenseAutoWork = 16777216.0;   // 2^24
 
 // the route an apply takes: IFFD_ROUTE_DENSE2D or IFFD_ROUTE_PASSES.  It is
 // a property of the plan (its max_rhs), not of the batch size of a call, so

@@ -14,7 +14,7 @@
 //   launch B: each workgroup takes 8 rows j of Z: Z[j][:] = V[:, j]^T Qt_1^T,
 //             written in FP64.
 // Every product runs from LDS: the left operand k-major with the 8 slice rows
-// contiguous (one 8-byte read gives a wave its two rows), the right operand
+// contiguous (a wave reads its row's entry as one broadcast), the right operand
 // with an odd row stride so that the 64 lanes of a wave, one column each,
 // read 64 different banks in either orientation.
 #include "dense2d.h"
@@ -23,8 +23,8 @@ namespace iffd {
 
 namespace {
 
-constexpr int kSl = 8;     // slice rows per workgroup (4 waves x 2 rows)
-constexpr int kNt = 256;
+constexpr int kSl = 8;     // slice rows per workgroup (8 waves x 1 row)
+constexpr int kNt = 512;
 
 // the k-major operands are read two floats at a time: their LDS regions start
 // at an even float offset
@@ -47,8 +47,8 @@ struct D2Args {
 // Copies n elements of one source into LDS: load(e) reads element e (its
 // index clamped into the source, so every load is issued unconditionally),
 // put(e, x) stores it for e < n.  Each thread issues kInflight loads before
-// its first store, so a workgroup waits for about n / (256 kInflight) load
-// latencies instead of n / 256.
+// its first store, so a workgroup waits for about n / (kNt kInflight) load
+// latencies instead of n / kNt.
 constexpr int kInflight = 16;
 template <typename Load, typename Put>
 __device__ __forceinline__ void stage(int n, Load load, Put put) {
@@ -73,33 +73,25 @@ __device__ __forceinline__ int div_small(int e, float inv) {
 
 // C(a, c) = sum_k A[k kSl + a] B(c, k) for the 8 rows a of a slice and the
 // columns c < nc <= 128, with B(c, k) = B[c ldb + k] (CK) or B[k ldb + c].
-// Wave w computes rows 2w and 2w + 1, lane l the columns l and l + 64; out(a,
-// c, value) receives each result once.
+// Wave w computes row w, lane l the columns l and l + 64 (two waves per SIMD
+// hide each other's LDS latency); out(a, c, value) receives each result once.
 template <bool CK, typename F>
 __device__ __forceinline__ void lds_product(const float* A, const float* B, int ldb, int K, int nc,
                                             F out) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c0 = lane, c1 = lane + 64;
   const int r0 = c0 < nc ? c0 : 0, r1 = c1 < nc ? c1 : 0;   // idle lanes read column 0
-  float x00 = 0.f, x10 = 0.f, x01 = 0.f, x11 = 0.f;
+  float x0 = 0.f, x1 = 0.f;
 #pragma unroll 4
   for (int k = 0; k < K; ++k) {
-    const float2 a = *(const float2*)(A + k * kSl + 2 * w);
+    const float a = A[k * kSl + w];
     const float b0 = CK ? B[r0 * ldb + k] : B[k * ldb + r0];
     const float b1 = CK ? B[r1 * ldb + k] : B[k * ldb + r1];
-    x00 += a.x * b0;
-    x10 += a.y * b0;
-    x01 += a.x * b1;
-    x11 += a.y * b1;
+    x0 += a * b0;
+    x1 += a * b1;
   }
-  if (c0 < nc) {
-    out(2 * w, c0, x00);
-    out(2 * w + 1, c0, x10);
-  }
-  if (c1 < nc) {
-    out(2 * w, c1, x01);
-    out(2 * w + 1, c1, x11);
-  }
+  if (c0 < nc) out(w, c0, x0);
+  if (c1 < nc) out(w, c1, x1);
 }
 
 __global__ void __launch_bounds__(kNt) dense2d_a(D2Args g) {

@@ -585,9 +585,9 @@ def test_dense2d_route_rules():
     m = O.dims(64, 3)[0]
     assert _route(h, 1) == I.ROUTE_DENSE2D and _route(h, 4096) == I.ROUTE_DENSE2D
     # the automatic choice looks at the plan's batch capacity only
-    for max_rhs, want in ((61, I.ROUTE_DENSE2D), (62, I.ROUTE_PASSES)):
+    for max_rhs, want in ((30, I.ROUTE_DENSE2D), (31, I.ROUTE_PASSES)):
         rc, hb = host_plan(2, 64, 3, max_rhs=max_rhs)
-        assert rc == 0 and m * m * 2 * m * 61 <= 2 ** 25 < m * m * 2 * m * 62
+        assert rc == 0 and m * m * 2 * m * 30 <= 2 ** 24 < m * m * 2 * m * 31
         assert _route(hb, 1) == want and _route(hb, max_rhs) == want
         assert I.lib.iffd_plan_set_route(hb, I.ROUTE_DENSE2D) == 0
         assert _route(hb, 1) == I.ROUTE_DENSE2D
