@@ -19,6 +19,7 @@
 // slot that stops in this iteration still gets it (flag S_RUN).
 // rz alternates between two record entries by iteration parity so that no
 // kernel reads a value another block of the same kernel overwrites.
+#include "dense2d.h"
 #include "launch.h"
 #include "pcg_state.h"
 
@@ -395,8 +396,17 @@ hipError_t pcg_status_dev(const Plan& P, const char* st, int nslots, double* out
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// the preconditioner without fused PCG steps: dense FD or the line passes of a
-// general plan (the r . z and residual updates then run as kernels of their own)
+// PCG steps fused into the apply's line passes: uniform plans of the FFT
+// method, unless their applies take the small 2-D route (whose two launches
+// carry no PCG work; such plans then run the unfused steps below)
+static inline bool fused_steps(const Plan& P, int nslots) {
+  return P.method == IFFD_METHOD_FFT && !P.gen &&
+         dense2d_route(P, nslots) != IFFD_ROUTE_DENSE2D;
+}
+
+// the preconditioner without fused PCG steps: dense FD, the line passes of a
+// general plan, or the small 2-D route (the r . z and residual updates then
+// run as kernels of their own)
 static hipError_t plain_apply(const Plan& P, const double* r, double* z, int nslots, void* ws,
                               const double* a, int as, hipStream_t s) {
   return P.method == IFFD_METHOD_FFT ? launch_iffd_apply(P, r, z, nslots, ws, a, as, s)
@@ -437,7 +447,7 @@ hipError_t pcg_begin_dev(const Plan& P, char* st, int nslots, const int* h_slots
   // p = z = P^{-1} r for the new slots only, written straight into p (IFFD:
   // r . z partials from its last pass)
   int nrz = nb;
-  if (P.method == IFFD_METHOD_FFT && !P.gen) {
+  if (fused_steps(P, nslots)) {
     const PassHook hk{r, part, nb, 0};
     e = launch_iffd_apply(P, r, p, nslots, L.ws ? st + L.ws : nullptr, scal + S_NEW, kScal, s,
                           &hk);
@@ -472,7 +482,7 @@ hipError_t pcg_iterate_dev(const Plan& P, char* st, int nslots, int k, hipStream
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pcg_alpha, dim3(nslots), dim3(VT), 0, s, scal, part2, nmv, nb, nslots);
     int nrz = nb;
-    if (P.method == IFFD_METHOD_FFT && !P.gen) {
+    if (fused_steps(P, nslots)) {
       // the apply's first pass takes r <- r - alpha q on its way in (r.r
       // partials), the residual test follows it, so the other passes skip the
       // slots that converged; r.z partials come from the last pass
