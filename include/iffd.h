@@ -410,8 +410,9 @@ int iffd_plan_tune(iffd_plan* plan, void* d_scratch, size_t scratch_bytes, int r
  * directions all have m <= 128 (and p <= 4, where the input may be rounded
  * to FP32 before the first product) also keeps, in its tables, each
  * direction's Qt = [V_reg U Dt^{-1}, V_out Q_out] as a dense FP32 m x m array
- * and its eigenvalues.  iffd_precond_apply (and iffd_precond_apply_noalloc,
- * and the plain preconditioner applies of iffd_pcg_solve) can then compute
+ * and its eigenvalues.  iffd_precond_apply, iffd_precond_apply_noalloc and
+ * the preconditioner applies of iffd_pcg_solve and the stepped PCG (whose
+ * residual update and r . z then run as kernels of their own) can compute
  *   Z = Qt_1 ((Qt_1^T R Qt_2) / (lam_1[a] + lam_2[b])) Qt_2^T
  * as two launches of LDS products: the same P^{-1} r to FP32 rounding, at
  * 4 m^3 multiply-adds per right-hand side instead of the transforms'
