@@ -82,13 +82,18 @@ __device__ __forceinline__ void lds_product(const float* A, const float* B, int 
   const int c0 = lane, c1 = lane + 64;
   const int r0 = c0 < nc ? c0 : 0, r1 = c1 < nc ? c1 : 0;   // idle lanes read column 0
   float x0 = 0.f, x1 = 0.f;
+  if (nc > 64) {
 #pragma unroll 4
-  for (int k = 0; k < K; ++k) {
-    const float a = A[k * kSl + w];
-    const float b0 = CK ? B[r0 * ldb + k] : B[k * ldb + r0];
-    const float b1 = CK ? B[r1 * ldb + k] : B[k * ldb + r1];
-    x0 += a * b0;
-    x1 += a * b1;
+    for (int k = 0; k < K; ++k) {
+      const float a = A[k * kSl + w];
+      const float b0 = CK ? B[r0 * ldb + k] : B[k * ldb + r0];
+      const float b1 = CK ? B[r1 * ldb + k] : B[k * ldb + r1];
+      x0 += a * b0;
+      x1 += a * b1;
+    }
+  } else {   // one column per lane (the same branch for the whole workgroup)
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) x0 += A[k * kSl + w] * (CK ? B[r0 * ldb + k] : B[k * ldb + r0]);
   }
   if (c0 < nc) out(w, c0, x0);
   if (c1 < nc) out(w, c1, x1);
